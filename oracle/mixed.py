@@ -1,0 +1,82 @@
+"""FP64 iterative refinement around a reduced-precision GMRES (GMRES-IR). Test infrastructure.
+
+Outer loop in FP64: r = b - M x; stop when ||r||/||b|| <= tol; otherwise solve M d = r
+approximately with an inner GMRES whose sigma product runs in FP32 (and, optionally, with the
+three-body term's operands rounded to bfloat16), then x += d. The inner Arnoldi, Givens
+rotations and least-squares solves stay in FP64. (Carson & Higham's GMRES-IR scheme.)
+
+The reduced-precision sigma is emulated with float32 copies of the operator blocks and
+float32 arithmetic; bfloat16 rounding is round-to-nearest-even on the float32 bit pattern.
+"""
+from __future__ import annotations
+
+import copy
+
+import numpy as np
+
+from . import sigma as sg
+from . import solve as so
+
+
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Round float32 values to the nearest bfloat16 (ties to even), returned as float32."""
+    a = np.ascontiguousarray(x, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = (u + 0x7FFF + lsb) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).reshape(a.shape)
+
+
+def f32_hbar(hb):
+    h = copy.copy(hb)
+    for name in ("Fov", "Foo", "Fvv", "Woooo", "Wooov", "Wovvo", "Wovoo", "oovv", "t2"):
+        setattr(h, name, getattr(hb, name).astype(np.float32))
+    return h
+
+
+def sigma_reduced(h32, x: np.ndarray, bf16_3body: bool) -> np.ndarray:
+    """sigma in float32 (complex64) arithmetic; three-body operands optionally in bf16."""
+    xr = x.real.astype(np.float32)
+    xi = x.imag.astype(np.float32)
+    out = []
+    for part in (xr, xi):
+        parts = sg.sigma_parts(h32, part)
+        if bf16_3body:
+            o, v = h32.o, h32.v
+            _, r2 = sg.unpack(bf16_round(part), o, v)
+            tau = np.einsum("klcd,...klc->...d", bf16_round(h32.oovv), r2).astype(np.float32)
+            t9 = -0.5 * np.einsum("ijad,...d->...ija", bf16_round(h32.t2), bf16_round(tau))
+            parts["T9"] = sg.pack(np.zeros(part.shape[:-1] + (o,), np.float32), t9.astype(np.float32))
+        out.append(sum(parts.values()).astype(np.float32))
+    return out[0].astype(np.float64) + 1j * out[1].astype(np.float64)
+
+
+class ReducedOperator(so.Operator):
+    def __init__(self, hb, bf16_3body: bool):
+        super().__init__(hb)
+        self.h32 = f32_hbar(hb)
+        self.bf16 = bf16_3body
+
+    def hbar(self, x):
+        self.nmatvec += 1
+        return sigma_reduced(self.h32, x, self.bf16)
+
+
+def gmres_ir(hb, b, omega, eta, tol=1e-8, inner_tol=1e-4, inner_maxit=100, restart=50,
+             max_outer=30, bf16_3body=True):
+    """Returns (x, outer steps, total inner iterations, final FP64 relative residual)."""
+    op64 = so.Operator(hb)
+    lo = ReducedOperator(hb, bf16_3body)
+    shift = omega - 1j * eta
+    x = np.zeros(op64.D, dtype=complex)
+    bn = np.linalg.norm(b)
+    inner_total = 0
+    for outer in range(max_outer + 1):
+        r = b - (op64.hbar(x) + shift * x)
+        rel = np.linalg.norm(r) / bn
+        if rel <= tol or outer == max_outer:
+            return x, outer, inner_total, rel
+        d, its, _ = so.gmres(lo, r, omega, eta, tol=inner_tol, restart=restart, maxit=inner_maxit)
+        inner_total += its
+        x = x + d
+    return x, max_outer, inner_total, rel

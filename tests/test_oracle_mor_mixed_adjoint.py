@@ -1,0 +1,124 @@
+"""Pins of the oracle's reduced-order model, mixed-precision refinement and adjoint gradient."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import adjoint as oadj
+from oracle import hbar as ohbar
+from oracle import mixed as omix
+from oracle import mor as omor
+from oracle import sigma as osig
+from oracle import solve as osolve
+
+
+@pytest.fixture(scope="module")
+def model():
+    o, v = 6, 10
+    p = synth.make_problem(o, v, 31)
+    hb = ohbar.build_hbar_from_problem(p)
+    H = osolve.dense_hbar(hb)
+    lam = np.sort(np.linalg.eigvals(H).real)
+    ps = np.array([o - 2, o - 1])
+    B = np.stack([osig.b_vector(o, v, q) for q in ps], 1)
+    C = np.stack([osig.c_vector(o, v, p.t1, p.t2, p.l1, p.l2, q) for q in ps], 0)
+    return p, hb, H, lam, ps, B, C
+
+
+def test_rom_interpolates_at_sampled_frequencies(model):
+    p, hb, H, lam, ps, B, C = model
+    eta = 0.01
+    wk = np.linspace(-lam[0] - 0.3, -lam[0] + 0.3, 3)
+    rom = omor.ROM(hb, ps, eta, C, omor.dense_solver(H, B, eta))
+    rom.extend(wk, 1e-12)
+    Gh, res = rom.eval(wk)
+    G = osolve.green(C, osolve.dense_solve(H, wk, B, eta))
+    assert np.abs(Gh - G).max() < 1e-10 * np.abs(G).max()
+    assert res.max() < 1e-10
+    # between samples the model is an approximation: non-zero residual
+    _, res_mid = rom.eval(0.5 * (wk[:-1] + wk[1:]))
+    assert res_mid.max() > 1e-8
+
+
+def test_rom_full_order_is_exact(model):
+    p, hb, H, lam, ps, B, C = model
+    eta = 0.02
+    D = H.shape[0]
+    rom = omor.ROM(hb, ps, eta, C, omor.dense_solver(H, B, eta))
+    # any orthonormal basis of the whole space: the reduced model is the full model
+    rom.extend([-1.0], 1e-12)
+    Q, _ = np.linalg.qr(np.concatenate([rom.S, np.random.default_rng(5).standard_normal((D, D))], 1))
+    rom.S = Q[:, :D]
+    rom.HS = osig.sigma(hb, rom.S.T).T
+    assert rom.m == D
+    om = np.linspace(-4, 0, 9)
+    Gh, res = rom.eval(om)
+    G = osolve.green(C, osolve.dense_solve(H, om, B, eta))
+    assert np.abs(Gh - G).max() < 1e-9 * np.abs(G).max()
+
+
+def test_rom_basis_rotation_invariance(model):
+    p, hb, H, lam, ps, B, C = model
+    eta = 0.01
+    rom = omor.ROM(hb, ps, eta, C, omor.dense_solver(H, B, eta))
+    rom.extend(np.linspace(-2.0, -1.0, 3), 1e-12)
+    om = np.linspace(-2.2, -0.8, 7)
+    G1, r1 = rom.eval(om)
+    Q, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((rom.m, rom.m)))
+    rom.S = rom.S @ Q
+    rom.HS = rom.HS @ Q
+    G2, r2 = rom.eval(om)
+    assert np.abs(G1 - G2).max() < 1e-10 * np.abs(G1).max()
+    assert np.abs(r1 - r2).max() < 1e-8
+
+
+def test_refinement_reaches_threshold(model):
+    p, hb, H, lam, ps, B, C = model
+    eta = 0.01
+    lo, hi = -lam[0] - 0.4, -lam[0] + 0.2
+    rom = omor.ROM(hb, ps, eta, C, omor.dense_solver(H, B, eta))
+    rom.extend(np.linspace(lo, hi, 3), 1e-10)
+    grid = np.linspace(lo, hi, 121)
+    rounds, rmax = omor.refine(rom, grid, lo, hi, 2, 1e-6, 10_000, 50, 1e-10)
+    assert rmax <= 1e-6 and rounds >= 1
+    G = osolve.green(C, osolve.dense_solve(H, grid, B, eta))
+    Gh, _ = rom.eval(grid)
+    assert np.abs(Gh - G).max() < 1e-4 * np.abs(G).max()
+
+
+def test_bf16_rounding():
+    x = np.array([1.0, 1.00390625, 1.005859375, -3.0e-8, 65504.0], dtype=np.float32)
+    r = omix.bf16_round(x)
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == np.float32(1.0078125)
+    assert np.all(np.abs(r - x) <= np.abs(x) * 2.0 ** -8)
+
+
+def test_gmres_ir_reaches_fp64_tolerance(model):
+    p, hb, H, lam, ps, B, C = model
+    om, eta = -lam[0] + 0.05, 0.005
+    x, outer, inner, rel = omix.gmres_ir(hb, B[:, 1].astype(complex), om, eta, tol=1e-10)
+    assert rel <= 1e-10 and outer >= 2
+    xd = np.linalg.solve(osolve.shifted(H, om, eta), B[:, 1].astype(complex))
+    assert np.abs(x - xd).max() < 1e-8 * np.abs(xd).max()
+
+
+def test_adjoint_gradient_matches_finite_differences(model):
+    p, hb, H, lam, ps, B, C = model
+    o, v = p.o, p.v
+    eta = 0.02
+    om = np.linspace(-lam[0] - 0.2, -lam[0] + 0.2, 9)
+    w = oadj.trapezoid_weights(om)
+    g = oadj.gradient_dense(H, om, w, B, C, eta, o, v)
+    h = 1e-5
+    for r in (0, o - 1, o + 2):
+        ep, em = p.eps.copy(), p.eps.copy()
+        ep[r] += h
+        em[r] -= h
+        Jp = oadj.objective_dense(osolve.dense_hbar(oadj.rebuild_with_eps(p, ep)), om, w, B, C, eta)
+        Jm = oadj.objective_dense(osolve.dense_hbar(oadj.rebuild_with_eps(p, em)), om, w, B, C, eta)
+        fd = (Jp - Jm) / (2 * h)
+        assert abs(fd - g[r]) < 1e-6 * max(1.0, abs(fd)), (r, fd, g[r])
+    # and D_r is exactly dH/deps_r
+    ep = p.eps.copy()
+    ep[1] += 1.0
+    dH = osolve.dense_hbar(oadj.rebuild_with_eps(p, ep)) - H
+    assert np.abs(dH - np.diag(oadj.d_eps_diagonal(o, v, 1))).max() < 1e-12
