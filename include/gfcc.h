@@ -1,0 +1,208 @@
+/*
+ * gfcc.h -- C ABI of the MI355X IP-GFCC solver library (libgfcc.so).
+ *
+ * The library computes the retarded coupled-cluster Green's function in the ionisation
+ * (N-1 electron) sector by solving the shifted linear systems of the GFCC method
+ *   ( omega - i*eta + Hbar_N ) X_p(omega) = b_p                  (Peng et al., Eq. xplin)
+ *   G_qp(omega) = c_q^T X_p(omega)                                (Eq. gfcclineqn)
+ *   A(omega)    = (1/pi) sum_p Im G_pp(omega)                     (spectral function)
+ * and by projecting them onto a reduced-order model (Eq. model, Methodology section).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Orbitals: spin orbitals; o occupied (indices i,j,k,l,m,n < o), v virtual (a..f < v).
+ * Vector space of X_p (Eq. xp): D = o + o(o-1)/2 * v. Packed layout of one vector:
+ *   x[i]                           one-hole amplitude x^i, 0 <= i < o
+ *   x[o + pi(i,j)*v + a]           two-hole-one-particle amplitude x^{ij}_a, i < j,
+ *   pi(i,j) = i*o - i*(i+1)/2 + (j - i - 1)   (lexicographic pairs, a fastest).
+ * Complex vectors are interleaved complex128 (re, im), as torch.complex128 stores them.
+ * Integral blocks: full antisymmetrised spin-orbital blocks <pq||rs>, row-major, named by
+ *   occupancy; e.g. ovvo[m][b][e][j] = <m b || e j>. They must satisfy
+ *   <pq||rs> = -<qp||rs> = -<pq||sr> = <rs||pq>.
+ * Amplitudes: t1[i][a], t2[i][j][a][b] (antisymmetric in ij and in ab), l1, l2 likewise
+ *   (Lambda stored in the same index order as T).
+ * Pointers: unless marked "host", every array argument is a DEVICE pointer on the context's
+ *   device. The caller owns all buffers passed in; the context owns the operator it builds.
+ * Streams: all work is enqueued on the stream given to gfcc_create. Entry points that
+ *   return host results synchronise that stream before returning.
+ * Errors: no exception crosses the ABI. Every call returns a gfcc_status; on failure
+ *   gfcc_last_error(ctx) holds a message. Inputs are validated before any kernel launch.
+ * Threads: a context must not be used from two host threads at once.
+ */
+#ifndef GFCC_H
+#define GFCC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gfcc_ctx gfcc_ctx;
+typedef struct gfcc_mor gfcc_mor;
+
+typedef enum {
+  GFCC_OK = 0,
+  GFCC_EINVAL = 1,      /* bad argument (sizes, indices, null pointers, non-finite data) */
+  GFCC_ENOMEM = 2,      /* device allocation failed or a size limit was exceeded */
+  GFCC_EHIP = 3,        /* a HIP runtime call failed */
+  GFCC_ENOCONV = 4,     /* an iterative solve stopped at maxit above its tolerance */
+  GFCC_EBREAKDOWN = 5,  /* a shifted operator is exactly singular for some right-hand side */
+  GFCC_ESTATE = 6       /* called in the wrong state (e.g. no operator built yet) */
+} gfcc_status;
+
+/* Arithmetic of the sigma product (H-bar times a block of vectors). */
+enum {
+  GFCC_FP64 = 0,            /* all terms in FP64 (MFMA f64) */
+  GFCC_FP32 = 1,            /* all terms in FP32 (MFMA f32, FP32 accumulation) */
+  GFCC_FP32_BF16_3BODY = 2  /* FP32, with the three-body T2*<kl||cd> term on BF16 MFMA */
+};
+
+/* Bit mask for build_hbar_operands: which operator copies to keep on the device. */
+enum {
+  GFCC_KEEP_FP64 = 1,       /* always kept */
+  GFCC_KEEP_FP32 = 2,       /* FP32 copies (and BF16 three-body operands) for mixed solves */
+  GFCC_KEEP_TRANSPOSE = 4   /* transposed copies for fast H-bar^T products (adjoint) */
+};
+
+/* Dimension D of the packed IP vector space for o occupied and v virtual spin orbitals. */
+int64_t gfcc_dim(int o, int v);
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream` (a hipStream_t; NULL
+ * means the device's null stream). */
+gfcc_status gfcc_create(gfcc_ctx** ctx, int device, void* hip_stream);
+
+/* Free the context, its operator and all device memory it owns. NULL is accepted. */
+gfcc_status gfcc_destroy(gfcc_ctx* ctx);
+
+/* Message of the last failed call on ctx ("" if none). Valid until the next call on ctx. */
+const char* gfcc_last_error(const gfcc_ctx* ctx);
+
+/*
+ * build_hbar_operands -- form the similarity-transformed Hamiltonian blocks that the sigma
+ * product needs (the transform Hbar = e^{-T} H e^{T} defined under Eq. gfxn1) and keep them
+ * on the device.
+ *
+ * eps [o+v] orbital energies (the Fock matrix is diag(eps)); t1 [o][v]; t2 [o][o][v][v];
+ * l1 [o][v]; l2 [o][o][v][v]; oooo [o][o][o][o]; ooov [o][o][o][v]; oovv [o][o][v][v];
+ * ovvo [o][v][v][o]; ovvv [o][v][v][v]. All FP64, device pointers, read only during the
+ * call. precision_mask: GFCC_KEEP_* bits. Replaces any operator built before.
+ * Errors: EINVAL for o < 2, v < 1, null pointers or non-finite entries (checked on the
+ * device); ENOMEM if the operator does not fit.
+ */
+gfcc_status build_hbar_operands(gfcc_ctx* ctx, int o, int v, const double* eps,
+                                const double* t1, const double* t2, const double* l1,
+                                const double* l2, const double* oooo, const double* ooov,
+                                const double* oovv, const double* ovvo, const double* ovvv,
+                                int precision_mask);
+
+/*
+ * sigma_apply -- y = Hbar_N x (transpose = 0) or y = Hbar_N^T x (transpose = 1) for nrhs
+ * complex vectors: x, y are complex128 [nrhs][D] (device). This is the connected part of
+ * Hbar_N acting on X_p (Eq. xplin), the product every Krylov iteration needs.
+ * precision: GFCC_FP64, GFCC_FP32 or GFCC_FP32_BF16_3BODY (the latter two need
+ * GFCC_KEEP_FP32 at build time; transpose needs GFCC_KEEP_TRANSPOSE for speed but works
+ * without it). x and y must not overlap. ESTATE if no operator is built.
+ */
+gfcc_status sigma_apply(gfcc_ctx* ctx, int nrhs, const void* x, void* y, int transpose,
+                        int precision);
+
+/*
+ * gfcc_solve -- solve Eq. xplin at every (omega_w, p_k) and form G (Eq. gfcclineqn).
+ *
+ * omega [nw] (host), p [np] (host; occupied orbitals 0 <= p < o, distinct), eta > 0.
+ * transpose = 0: (omega - i eta + Hbar_N) X = b_p with b_p = e_p (the occupied-orbital
+ *   right-hand side), and G_out[w][q][p] = c_q^T X_p for q, p in the p set.
+ * transpose = 1: (omega - i eta + Hbar_N^T) Y = c_p (the adjoint systems); since
+ *   b_p^T Y_q = c_q^T X_p, G_out[w][q][p] is filled from b_p^T Y_q: the same G as the
+ *   forward solve, up to the solve tolerance.
+ * precision: GFCC_FP64 (right-preconditioned restarted GMRES with CGS2 Arnoldi, Jacobi
+ *   preconditioner) or GFCC_FP32 / GFCC_FP32_BF16_3BODY (FP64 iterative refinement around
+ *   an inner GMRES whose sigma product runs in that precision; the stopping test is always
+ *   the FP64 true relative residual).
+ * tol: relative residual ||b - M x|| / ||b||. maxit: max iterations per right-hand side
+ *   (inner+outer). restart: Krylov restart length (1..200). block: number of right-hand
+ *   sides solved together (0 = library default).
+ * X_out: optional complex128 [nw][np][D] (device) or NULL. G_out: complex128 [nw][np][np]
+ *   (device). iters_out, resid_out: host arrays [nw*np] or NULL.
+ * Returns ENOCONV (after filling every output with the best iterate) if some right-hand side
+ * did not reach tol; EBREAKDOWN if a shifted operator is exactly singular on a Krylov space.
+ */
+gfcc_status gfcc_solve(gfcc_ctx* ctx, int nw, const double* omega, int np, const int* p,
+                       double eta, double tol, int maxit, int restart, int block,
+                       int precision, int transpose, void* X_out, void* G_out,
+                       int* iters_out, double* resid_out);
+
+/*
+ * gfcc_grad_eps -- adjoint gradient of J = sum_w weight_w A(omega_w) with respect to the
+ * orbital energies eps (amplitudes held fixed):
+ *   dJ/deps_r = (1/pi) sum_w weight_w sum_k Im( - Y_k^T D_r X_k ),
+ * where X are forward solutions, Y adjoint solutions (both complex128 [nw][np][D] device, as
+ * written by gfcc_solve) and D_r = dHbar_N/deps_r is diagonal in the packed basis.
+ * weight [nw] (host). grad_out [o+v] (host).
+ */
+gfcc_status gfcc_grad_eps(gfcc_ctx* ctx, int nw, const double* weight, int np, const void* X,
+                          const void* Y, double* grad_out);
+
+/*
+ * mor_build -- first reduced-order model (Eq. model): full solves at omega_k [nk] (host)
+ * for orbitals p [np] (host), then a real orthonormal basis S of span{Re X_p(omega_k),
+ * Im X_p(omega_k)} (CGS2, columns whose norm falls below defl_tol times their original norm
+ * are dropped), Hbar S, and the projected Hhat = S^T Hbar S, bhat = S^T b, chat = S^T c.
+ * The model owns its device memory; it stays valid while ctx lives.
+ */
+gfcc_status mor_build(gfcc_ctx* ctx, int nk, const double* omega_k, int np, const int* p,
+                      double eta, double solve_tol, double defl_tol, gfcc_mor** model);
+
+/*
+ * mor_refine -- adaptive refinement (the strategy described after Eq. model): evaluate the
+ * relative full-space residual of the reduced solutions on grid [nw] (host) restricted to
+ * [wmin, wmax]; while its maximum exceeds resid_tol, add up to per_round midpoints of the
+ * sampled-frequency intervals with the largest residual, solve there in full and extend S.
+ * Stops at resid_tol, at max_order basis columns or after max_rounds. rounds_out (host)
+ * receives the rounds run, max_resid_out (host) the final maximum residual.
+ */
+gfcc_status mor_refine(gfcc_mor* model, int nw, const double* grid, double wmin, double wmax,
+                       int per_round, double resid_tol, int max_order, int max_rounds,
+                       int* rounds_out, double* max_resid_out);
+
+/*
+ * mor_eval -- reduced Green's function at omega [nw] (host): Ghat_qp = chat_q^T xhat_p with
+ * ((omega - i eta) I + Hhat) xhat_p = bhat_p. G_out complex128 [nw][np][np] (device);
+ * resid_out [nw] (host, may be NULL): max over p of the relative full-space residual.
+ */
+gfcc_status mor_eval(gfcc_mor* model, int nw, const double* omega, void* G_out,
+                     double* resid_out);
+
+/* Model facts: order m (columns of S), sampled frequencies (host array of cap entries). */
+gfcc_status mor_info(const gfcc_mor* model, int* m_out, int* nk_out, double* omega_k_out,
+                     int cap);
+
+/* Free a model. NULL is accepted. */
+gfcc_status mor_destroy(gfcc_mor* model);
+
+/*
+ * spectral_function -- A(omega_w) = (1/pi) sum_p Im G[w][p][p] for G complex128
+ * [nw][np][np] (device if is_device, else host). A_out [nw] (host). The sign makes the
+ * peaks positive for the operator (omega - i eta + Hbar_N).
+ */
+gfcc_status spectral_function(int nw, int np, const void* G, int is_device, double* A_out);
+
+/*
+ * Inspection (tests and profiling).
+ * gfcc_export: copy a built operator block to a device buffer dst (FP64):
+ *   0 Foo [o][o] (F_mi), 1 Fov [o][v] (F_me), 2 Fvv [v][v] (F_ae),
+ *   3 Woooo [o][o][o][o] (W_mnij), 4 Wooov [o][o][o][v] (W_mnie),
+ *   5 Wovvo [o][v][v][o] (W_mbej), 6 Wovoo [o][v][o][o] (W_mbij), 7 diag [D].
+ * gfcc_timer: accumulated device time (ms, from HIP events on the context stream) and launch
+ *   count of kernel family `which` since the last reset (0: the ovvo contraction of sigma,
+ *   1: whole sigma products); reset = 1 clears after reading.
+ */
+gfcc_status gfcc_export(gfcc_ctx* ctx, int which, void* dst);
+gfcc_status gfcc_timer(gfcc_ctx* ctx, int which, int enable, int reset, double* ms_out,
+                       int64_t* launches_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GFCC_H */

@@ -1,0 +1,216 @@
+// Internal declarations shared by the HIP sources of libgfcc.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/gfcc.h"
+
+namespace gfcc {
+
+// ---------------------------------------------------------------------------------------
+// errors: internal code throws gfcc::Error; every extern "C" entry point catches it.
+struct Error : std::runtime_error {
+  gfcc_status status;
+  Error(gfcc_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define GFCC_HIP(call)                                                                  \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw ::gfcc::Error(GFCC_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define GFCC_REQUIRE(cond, status, msg)                  \
+  do {                                                   \
+    if (!(cond)) throw ::gfcc::Error((status), (msg));   \
+  } while (0)
+
+#define GFCC_LAUNCH_CHECK() GFCC_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------------------
+// device memory owned by the library (RAII, freed with hipFree).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) return;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw Error(GFCC_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
+    }
+    bytes = n;
+  }
+  // grow-only reuse (scratch/workspace)
+  void ensure(size_t n) {
+    if (n > bytes) alloc(n);
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Pair index of i<j in the packed 2h1p layout (lexicographic).
+__host__ __device__ inline int64_t pair_of(int i, int j, int o) {
+  return (int64_t)i * o - (int64_t)i * (i + 1) / 2 + (j - i - 1);
+}
+
+// ---------------------------------------------------------------------------------------
+// The device-resident operator. Row-major matrices acting on D-major vector blocks
+// X[D][nc] (nc real columns; a complex right-hand side occupies two adjacent columns).
+//
+//   sigma_1h   = W1 . X                                (o x D)
+//   sigma_2h1p = W4c . [X_1h ; tau]  +  Woo (x) I_v . X_2h1p  +  antisym( Weff . unpack(X_2h1p) )
+//   tau        = Vp^T . X_2h1p                         (v x nc)
+// with
+//   W1[i][k]            = -F_ki,   W1[i][o+(kl)v+d] = -W_klid + d_ik F_ld - d_il F_kd
+//   W4c[(ij)a][k]       = -W_kaij, W4c[(ij)a][o+d]  = -t_ij^ad
+//   Woo[(ij)][(kl)]     = W_klij
+//   Vp[(kl)c][d]        = <kl||cd>
+//   Weff[(i,a)][(m,e)]  = W_maei - d_ae F_mi + 1/2 d_mi F_ae
+// so that every sigma term is a dense contraction.
+template <typename T> struct OpPieces {
+  DevBuf W1, W4c, Woo, Vp, Weff;
+  DevBuf W4, T2p;          // split form of W4c (mixed precision: T2p may be bf16)
+};
+
+struct Operator {
+  bool built = false;
+  int o = 0, v = 0;
+  int64_t D = 0, P = 0, PV = 0, OV = 0;
+  int keep = 0;
+  OpPieces<double> f64;
+  OpPieces<float> f32;
+  DevBuf Vp_bf16, T2p_bf16;     // bf16 three-body operands (mixed precision)
+  DevBuf WeffT, W1T, W4cT, WooT, VpT;  // transposed copies (adjoint)
+  DevBuf diag;                  // [D] diagonal of Hbar_N
+  DevBuf Crows;                 // [o][D] c_q rows for all occupied q
+  DevBuf pairlut;               // [o*o] int: +(pair+1) for i<j, -(pair+1) for i>j, 0 on i==j
+  // blocks kept for export
+  DevBuf Foo, Fov, Fvv, Woooo, Wooov, Wovvo, Wovoo;
+};
+
+struct TimerSlot {
+  bool enabled = false;
+  double ms = 0.0;
+  int64_t launches = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+};
+
+}  // namespace gfcc
+
+struct gfcc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  gfcc::Operator op;
+  // scratch, grow-only
+  gfcc::DevBuf ws_gemm;     // split-K partials
+  gfcc::DevBuf ws_a, ws_b, ws_c, ws_d, ws_e;
+  gfcc::TimerSlot timers[2];
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace gfcc {
+
+// Grow a context-owned scratch buffer. Work already queued on the context stream may still
+// read the old allocation, so the stream is drained before it is released.
+inline void ws_ensure(gfcc_ctx* ctx, DevBuf& b, size_t n) {
+  if (n <= b.bytes) return;
+  GFCC_HIP(hipStreamSynchronize(ctx->stream));
+  b.alloc(n);
+}
+
+// ------------------------------------------------------------------------------ GEMM
+// C[M][N] = alpha * op(A)[M][K] . op(B)[K][N] + beta * C, row-major, batched by strides.
+// op(A) = A ([M][K], lda) or A^T (A stored [K][M], lda); op(B) likewise.
+// beta == 0 never reads C.
+template <typename T>
+void gemm(gfcc_ctx* ctx, bool transA, bool transB, int M, int N, int K, T alpha, const T* A,
+          int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc, int batch = 1,
+          int64_t sA = 0, int64_t sB = 0, int64_t sC = 0);
+
+// The ovvo contraction of sigma: Z[(i,a)][(j,c)] = sum_(m,e) Weff[(i,a)][(m,e)] * r_mj^e[c],
+// where r is read from the packed 2h1p block X2[(pair,e)][c] (ld = ldx) through pairlut.
+// transW: use Weff^T (the transpose product). Z is [o*v][o*nc].
+template <typename T>
+void gemm_ovvo(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, const T* X2,
+               int64_t ldx, const int* pairlut, T* Z);
+
+// bf16 x bf16 -> fp32 GEMM (three-body term of the mixed-precision sigma).
+void gemm_bf16(gfcc_ctx* ctx, bool transA, int M, int N, int K, float alpha,
+               const __hip_bfloat16* A, int64_t lda, const __hip_bfloat16* B, int64_t ldb,
+               float beta, float* C, int64_t ldc);
+
+// ------------------------------------------------------------------- tensor utilities
+// dst[i0][i1][i2][i3] (contiguous, dims d[]) = alpha * src[i0*s0 + i1*s1 + i2*s2 + i3*s3]
+//   + beta * dst   (beta == 0 never reads dst)
+void permute4(gfcc_ctx* ctx, const double* src, const int64_t d[4], const int64_t s[4],
+              double* dst, double alpha = 1.0, double beta = 0.0);
+void fill(gfcc_ctx* ctx, double* p, int64_t n, double val);
+void fill_f(gfcc_ctx* ctx, float* p, int64_t n, float val);
+void cast_f64_f32(gfcc_ctx* ctx, const double* s, float* d, int64_t n);
+void cast_f64_bf16(gfcc_ctx* ctx, const double* s, __hip_bfloat16* d, int64_t n);
+void cast_f32_f64(gfcc_ctx* ctx, const float* s, double* d, int64_t n);
+void cast_f32_bf16(gfcc_ctx* ctx, const float* s, __hip_bfloat16* d, int64_t n);
+void transpose2d(gfcc_ctx* ctx, const double* src, int64_t rows, int64_t cols, double* dst);
+// complex128 transpose: dst[c*ldd + r] = src[r*lds + c] for r < rows, c < cols
+void ctranspose(gfcc_ctx* ctx, const void* src, int64_t rows, int64_t cols, int64_t lds,
+                void* dst, int64_t ldd);
+// count of non-finite entries of a device array (synchronises)
+int64_t count_nonfinite(gfcc_ctx* ctx, const double* p, int64_t n);
+
+// -------------------------------------------------------------------- sigma products
+// Y[D][nc] = Hbar_N X[D][nc] (or Hbar_N^T). Real columns; X and Y D-major with ld = nc.
+void sigma_block_f64(gfcc_ctx* ctx, int nc, const double* X, double* Y, bool transpose);
+void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, bool bf16_3body);
+
+// event-timed launch helpers
+void timer_begin(gfcc_ctx* ctx, int which, hipEvent_t* ev);
+void timer_end(gfcc_ctx* ctx, int which, hipEvent_t ev0);
+void timers_collect(gfcc_ctx* ctx);
+
+inline unsigned blocks_for(int64_t n, int threads) {
+  int64_t b = (n + threads - 1) / threads;
+  if (b > (1 << 30)) b = 1 << 30;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace gfcc
+
+// Wrap an extern "C" body: converts exceptions to status codes and records the message.
+#define GFCC_API_BEGIN(ctx) try {
+#define GFCC_API_END(ctx)                                              \
+  }                                                                    \
+  catch (const ::gfcc::Error& e) {                                     \
+    if (ctx) (ctx)->last_error = e.what();                             \
+    return e.status;                                                   \
+  }                                                                    \
+  catch (const std::exception& e) {                                    \
+    if (ctx) (ctx)->last_error = e.what();                             \
+    return GFCC_EINVAL;                                                \
+  }                                                                    \
+  return GFCC_OK;

@@ -1,0 +1,334 @@
+// Dense contractions on CDNA4 matrix cores (MFMA) for FP64 and FP32.
+//
+// One workgroup = 4 wavefronts (2 x 2) computes a 128 x 128 tile of C; each wavefront owns a
+// 64 x 64 sub-tile held as 4 x 4 accumulators of the 16x16x4 MFMA (f64 or f32). K advances in
+// slabs of 16: global -> registers (prefetched one slab ahead) -> LDS (k-major, padded) ->
+// MFMA operands. Ragged edges are zero-filled on load and masked on store.
+//
+// The B operand has three modes: row-major [K][N], transposed ([N][K]), or the gather used by
+// the ovvo term of the IP sigma product, which expands the packed antisymmetric 2h1p block
+// on the fly (r_mj^e = +-X2[pair(m,j)][e], zero for m == j).
+#include "common.h"
+
+namespace gfcc {
+namespace {
+
+constexpr int BM = 128, BN = 128, BK = 16, NT = 256;
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef double C4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ C4 op(double a, double b, C4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static constexpr int PAD = 2;
+  // output element q of lane l sits at row (l/16) + 4q, column l%16
+  static __device__ __forceinline__ int row(int lane, int q) { return (lane >> 4) + 4 * q; }
+};
+template <> struct Mfma<float> {
+  typedef float C4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ C4 op(float a, float b, C4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static constexpr int PAD = 4;
+  // output element q of lane l sits at row 4(l/16) + q, column l%16
+  static __device__ __forceinline__ int row(int lane, int q) { return 4 * (lane >> 4) + q; }
+};
+
+enum BMode { B_ROW = 0, B_TRANS = 1, B_OVVO = 2 };
+
+template <typename T> struct Params {
+  int M, N, K;
+  const T* A; int64_t lda, sA;
+  const T* B; int64_t ldb, sB;
+  T* C; int64_t ldc, sC;
+  T alpha, beta;
+  int kchunk;          // split-K chunk (multiple of BK); splits = gridDim.z
+  int mtiles, ntiles;
+  // ovvo gather
+  const int* lut; int o, v, nc;
+};
+
+template <typename T, bool TA, int BMODE, bool SPLIT>
+__global__ __launch_bounds__(NT) void gemm_kernel(Params<T> p) {
+  using M4 = Mfma<T>;
+  using C4 = typename M4::C4;
+  constexpr int PAD = M4::PAD;
+  __shared__ T As[BK][BM + PAD];
+  __shared__ T Bs[BK][BN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  const int tile = blockIdx.x;
+  const int mt = tile % p.mtiles, nt = tile / p.mtiles;
+  const int m0 = mt * BM, n0 = nt * BN;
+  const int64_t bidx = blockIdx.y;
+  const T* __restrict__ A = p.A + bidx * p.sA;
+  const T* __restrict__ B = p.B + bidx * p.sB;
+
+  int kbeg = 0, kend = p.K;
+  if (SPLIT) {
+    kbeg = blockIdx.z * p.kchunk;
+    kend = min(p.K, kbeg + p.kchunk);
+  }
+
+  // ---- per-thread load coordinates
+  // A row-major [M][K]: k = tid%16, rows tid/16 + 16r ; A^T [K][M]: m = tid%128, k = tid/128 + 2r
+  // B row-major / gather: n = tid%128, k = tid/128 + 2r ; B^T [N][K]: k = tid%16, n = tid/16+16r
+  const int a_c0 = TA ? (tid % BM) : (tid % BK);
+  const int a_r0 = TA ? (tid / BM) : (tid / BK);
+  const int b_c0 = (BMODE == B_TRANS) ? (tid % BK) : (tid % BN);
+  const int b_r0 = (BMODE == B_TRANS) ? (tid / BK) : (tid / BN);
+
+  // gather mode: fixed column -> (j, c)
+  int g_j = 0, g_c = 0;
+  bool g_nok = false;
+  if (BMODE == B_OVVO) {
+    int n = n0 + b_c0;
+    g_nok = n < p.N;
+    if (g_nok) {
+      g_j = n / p.nc;
+      g_c = n - g_j * p.nc;
+    }
+  }
+
+  T ra[8], rb[8];
+
+  auto load_tile = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      int m, k;
+      if (TA) { m = m0 + a_c0; k = k0 + a_r0 + 2 * r; }
+      else    { k = k0 + a_c0; m = m0 + a_r0 + 16 * r; }
+      T val = T(0);
+      if (m < p.M && k < kend) val = TA ? A[(int64_t)k * p.lda + m] : A[(int64_t)m * p.lda + k];
+      ra[r] = val;
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      T val = T(0);
+      if (BMODE == B_TRANS) {
+        int k = k0 + b_c0, n = n0 + b_r0 + 16 * r;
+        if (n < p.N && k < kend) val = B[(int64_t)n * p.ldb + k];
+      } else if (BMODE == B_ROW) {
+        int k = k0 + b_r0 + 2 * r, n = n0 + b_c0;
+        if (n < p.N && k < kend) val = B[(int64_t)k * p.ldb + n];
+      } else {
+        int k = k0 + b_r0 + 2 * r;
+        if (g_nok && k < kend) {
+          int m = k / p.v;
+          int e = k - m * p.v;
+          int s = p.lut[m * p.o + g_j];
+          if (s != 0) {
+            int64_t pr = (s > 0 ? s : -s) - 1;
+            T x = B[(pr * p.v + e) * p.ldb + g_c];
+            val = s > 0 ? x : -x;
+          }
+        }
+      }
+      rb[r] = val;
+    }
+  };
+  auto store_tile = [&]() {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (TA) As[a_r0 + 2 * r][a_c0] = ra[r];
+      else    As[a_c0][a_r0 + 16 * r] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (BMODE == B_TRANS) Bs[b_c0][b_r0 + 16 * r] = rb[r];
+      else                  Bs[b_r0 + 2 * r][b_c0] = rb[r];
+    }
+  };
+
+  C4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = C4{0, 0, 0, 0};
+
+  if (kbeg < kend) {
+    load_tile(kbeg);
+    store_tile();
+    __syncthreads();
+    const int row_l = lane & 15, kq = lane >> 4;
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+      const bool more = k0 + BK < kend;
+      if (more) load_tile(k0 + BK);
+#pragma unroll
+      for (int s = 0; s < BK / 4; ++s) {
+        T af[4], bf[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) af[i] = As[s * 4 + kq][wm * 64 + i * 16 + row_l];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bf[j] = Bs[s * 4 + kq][wn * 64 + j * 16 + row_l];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = M4::op(af[i], bf[j], acc[i][j]);
+      }
+      __syncthreads();
+      if (more) {
+        store_tile();
+        __syncthreads();
+      }
+    }
+  }
+
+  // ---- epilogue (per-type output layout of the 16x16 block, see Mfma<T>::row)
+  T* __restrict__ C = p.C + bidx * p.sC;
+  if (SPLIT) C += (int64_t)blockIdx.z * p.sC;  // partial buffer: one [M][N] slab per split
+  const int col_l = lane & 15;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + wn * 64 + j * 16 + col_l;
+      if (n >= p.N) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + wm * 64 + i * 16 + M4::row(lane, q);
+        if (m >= p.M) continue;
+        T* dst = C + (int64_t)m * p.ldc + n;
+        if (SPLIT) {
+          *dst = acc[i][j][q];
+        } else {
+          T val = p.alpha * acc[i][j][q];
+          if (p.beta != T(0)) val += p.beta * *dst;
+          *dst = val;
+        }
+      }
+    }
+}
+
+// Sum split-K partials: C = alpha * sum_z part[z] + beta * C
+template <typename T>
+__global__ void splitk_reduce(const T* __restrict__ part, int splits, int M, int N,
+                              int64_t pstride, T* __restrict__ C, int64_t ldc, T alpha, T beta) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)M * N) return;
+  int m = (int)(idx / N), n = (int)(idx % N);
+  T s = T(0);
+  for (int z = 0; z < splits; ++z) s += part[z * pstride + idx];
+  T* dst = C + (int64_t)m * ldc + n;
+  T val = alpha * s;
+  if (beta != T(0)) val += beta * *dst;
+  *dst = val;
+}
+
+template <typename T, bool TA, int BMODE>
+void launch(gfcc_ctx* ctx, Params<T> p, int batch, int splits) {
+  dim3 grid(p.mtiles * p.ntiles, batch, splits);
+  if (splits > 1)
+    hipLaunchKernelGGL((gemm_kernel<T, TA, BMODE, true>), grid, dim3(NT), 0, ctx->stream, p);
+  else
+    hipLaunchKernelGGL((gemm_kernel<T, TA, BMODE, false>), grid, dim3(NT), 0, ctx->stream, p);
+  GFCC_LAUNCH_CHECK();
+}
+
+template <typename T>
+void dispatch(gfcc_ctx* ctx, bool ta, int bmode, Params<T> p, int batch, int splits) {
+  if (ta) {
+    if (bmode == B_ROW) launch<T, true, B_ROW>(ctx, p, batch, splits);
+    else if (bmode == B_TRANS) launch<T, true, B_TRANS>(ctx, p, batch, splits);
+    else launch<T, true, B_OVVO>(ctx, p, batch, splits);
+  } else {
+    if (bmode == B_ROW) launch<T, false, B_ROW>(ctx, p, batch, splits);
+    else if (bmode == B_TRANS) launch<T, false, B_TRANS>(ctx, p, batch, splits);
+    else launch<T, false, B_OVVO>(ctx, p, batch, splits);
+  }
+}
+
+// choose a split-K factor so that small-output, long-K products still fill the chip
+inline int choose_splits(int tiles, int batch, int K, int* kchunk) {
+  int splits = 1;
+  const int64_t work = (int64_t)tiles * batch;
+  if (work < 512 && K >= 4 * BK * 8) {
+    int64_t want = (1024 + work - 1) / work;
+    int64_t maxs = K / (BK * 8);
+    splits = (int)std::min<int64_t>(want, maxs);
+    if (splits < 1) splits = 1;
+  }
+  int64_t chunk = ((int64_t)K + splits - 1) / splits;
+  chunk = (chunk + BK - 1) / BK * BK;
+  splits = (int)(((int64_t)K + chunk - 1) / chunk);
+  *kchunk = (int)chunk;
+  return splits;
+}
+
+template <typename T>
+void gemm_impl(gfcc_ctx* ctx, bool transA, int bmode, int M, int N, int K, T alpha, const T* A,
+               int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc, int batch,
+               int64_t sA, int64_t sB, int64_t sC, const int* lut, int o, int v, int nc) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  if (K <= 0) {  // C = beta * C
+    GFCC_REQUIRE(batch == 1, GFCC_EINVAL, "gemm: K == 0 with batch > 1 unsupported");
+    Params<T> p{};
+    p.M = M; p.N = N; p.K = 0; p.A = A; p.B = B; p.C = C; p.lda = lda; p.ldb = ldb;
+    p.ldc = ldc; p.alpha = alpha; p.beta = beta; p.mtiles = (M + BM - 1) / BM;
+    p.ntiles = (N + BN - 1) / BN; p.lut = lut; p.o = o; p.v = v; p.nc = nc;
+    dispatch<T>(ctx, transA, bmode, p, 1, 1);
+    return;
+  }
+  Params<T> p{};
+  p.M = M; p.N = N; p.K = K;
+  p.A = A; p.lda = lda; p.sA = sA;
+  p.B = B; p.ldb = ldb; p.sB = sB;
+  p.alpha = alpha; p.beta = beta;
+  p.mtiles = (M + BM - 1) / BM;
+  p.ntiles = (N + BN - 1) / BN;
+  p.lut = lut; p.o = o; p.v = v; p.nc = nc;
+  const int64_t tiles = (int64_t)p.mtiles * p.ntiles;
+  GFCC_REQUIRE(tiles < (1LL << 31), GFCC_EINVAL, "gemm: too many tiles");
+  int kchunk = K;
+  int splits = batch == 1 ? choose_splits((int)tiles, batch, K, &kchunk) : 1;
+  if (splits <= 1) {
+    p.C = C; p.ldc = ldc; p.sC = sC; p.kchunk = K;
+    dispatch<T>(ctx, transA, bmode, p, batch, 1);
+    return;
+  }
+  const int64_t slab = (int64_t)M * N;
+  ws_ensure(ctx, ctx->ws_gemm, (size_t)slab * splits * sizeof(T));
+  T* part = ctx->ws_gemm.as<T>();
+  p.C = part; p.ldc = N; p.sC = slab; p.kchunk = kchunk;
+  dispatch<T>(ctx, transA, bmode, p, 1, splits);
+  hipLaunchKernelGGL(splitk_reduce<T>, dim3(blocks_for(slab, 256)), dim3(256), 0, ctx->stream,
+                     part, splits, M, N, slab, C, ldc, alpha, beta);
+  GFCC_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+template <typename T>
+void gemm(gfcc_ctx* ctx, bool transA, bool transB, int M, int N, int K, T alpha, const T* A,
+          int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc, int batch,
+          int64_t sA, int64_t sB, int64_t sC) {
+  gemm_impl<T>(ctx, transA, transB ? B_TRANS : B_ROW, M, N, K, alpha, A, lda, B, ldb, beta, C,
+               ldc, batch, sA, sB, sC, nullptr, 0, 1, 1);
+}
+
+template void gemm<double>(gfcc_ctx*, bool, bool, int, int, int, double, const double*, int64_t,
+                           const double*, int64_t, double, double*, int64_t, int, int64_t,
+                           int64_t, int64_t);
+template void gemm<float>(gfcc_ctx*, bool, bool, int, int, int, float, const float*, int64_t,
+                          const float*, int64_t, float, float*, int64_t, int, int64_t, int64_t,
+                          int64_t);
+
+template <typename T>
+void gemm_ovvo(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, const T* X2,
+               int64_t ldx, const int* pairlut, T* Z) {
+  const int OV = o * v;
+  gemm_impl<T>(ctx, transW, B_OVVO, OV, o * nc, OV, T(1), W, OV, X2, ldx, T(0), Z,
+               (int64_t)o * nc, 1, 0, 0, 0, pairlut, o, v, nc);
+}
+
+template void gemm_ovvo<double>(gfcc_ctx*, bool, int, int, int, const double*, const double*,
+                                int64_t, const int*, double*);
+template void gemm_ovvo<float>(gfcc_ctx*, bool, int, int, int, const float*, const float*,
+                               int64_t, const int*, float*);
+
+}  // namespace gfcc

@@ -1,0 +1,222 @@
+// The IP sigma product y = Hbar_N x on a block of vectors (Eq. xplin's operator).
+//
+// Vectors are stored D-major: X[D][nc] with nc real columns (complex right-hand sides are
+// interleaved column pairs), so every term is a matrix product whose N dimension runs over
+// the right-hand sides:
+//   sigma_1h   = W1 . X
+//   tau        = Vp^T . X_2h1p                 (three-body intermediate, v x nc)
+//   sigma_2h1p = W4c . [X_1h ; tau] + (Woo (x) I_v) . X_2h1p + antisym(Weff . r)
+// where r_mj^e is the antisymmetric expansion of the packed 2h1p block, generated inside
+// the ovvo product (gemm_ovvo), and antisym(Z)_(i<j),a = Z[(i,a)][j] - Z[(j,a)][i].
+// The transpose product uses the same pieces with transposed A operands.
+#include "common.h"
+
+namespace gfcc {
+namespace {
+
+template <typename T>
+__global__ void antisym_add_kernel(const T* __restrict__ Z, int o, int v, int nc,
+                                   T* __restrict__ Y2) {
+  const int64_t P = (int64_t)o * (o - 1) / 2;
+  const int64_t n = P * v * nc;
+  const int64_t ldz = (int64_t)o * nc;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t t = idx;
+    int c = (int)(t % nc); t /= nc;
+    int a = (int)(t % v); t /= v;
+    int64_t pr = t;
+    // pair -> (i, j)
+    int i = 0;
+    int64_t base = 0;
+    while (i < o - 1 && pr >= base + (o - 1 - i)) { base += o - 1 - i; ++i; }
+    int j = (int)(i + 1 + (pr - base));
+    T zij = Z[((int64_t)i * v + a) * ldz + (int64_t)j * nc + c];
+    T zji = Z[((int64_t)j * v + a) * ldz + (int64_t)i * nc + c];
+    Y2[idx] += zij - zji;
+  }
+}
+
+template <typename T>
+__global__ void add_kernel(T* __restrict__ y, const T* __restrict__ x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += x[i];
+}
+
+// complex (16-byte element) transpose: dst[c][r] = src[r][c], src is [rows][cols]
+__global__ void ctranspose_kernel(const double2* __restrict__ src, int64_t rows, int64_t cols,
+                                  int64_t lds, double2* __restrict__ dst, int64_t ldd) {
+  __shared__ double2 tile[16][17];
+  int64_t c0 = (int64_t)blockIdx.x * 16, r0 = (int64_t)blockIdx.y * 16;
+  int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  {
+    int64_t r = r0 + ty, c = c0 + tx;
+    if (r < rows && c < cols) tile[ty][tx] = src[r * lds + c];
+  }
+  __syncthreads();
+  {
+    int64_t c = c0 + ty, r = r0 + tx;
+    if (r < rows && c < cols) dst[c * ldd + r] = tile[tx][ty];
+  }
+}
+
+inline unsigned grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+void ctranspose(gfcc_ctx* ctx, const void* src, int64_t rows, int64_t cols, int64_t lds,
+                void* dst, int64_t ldd) {
+  if (rows == 0 || cols == 0) return;
+  int64_t gy = (rows + 15) / 16, gx = (cols + 15) / 16;
+  GFCC_REQUIRE(gy < 65536 && gx < (1LL << 31), GFCC_EINVAL, "ctranspose: shape too large");
+  hipLaunchKernelGGL(ctranspose_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0,
+                     ctx->stream, (const double2*)src, rows, cols, lds, (double2*)dst, ldd);
+  GFCC_LAUNCH_CHECK();
+}
+
+void sigma_block_f64(gfcc_ctx* ctx, int nc, const double* X, double* Y, bool transpose) {
+  Operator& op = ctx->op;
+  GFCC_REQUIRE(op.built, GFCC_ESTATE, "sigma: no operator built");
+  const int o = op.o, v = op.v;
+  const int64_t D = op.D, P = op.P, PV = op.PV, OV = op.OV;
+  const OpPieces<double>& f = op.f64;
+  const double* X1 = X;
+  const double* X2 = X + (int64_t)o * nc;
+  double* Y1 = Y;
+  double* Y2 = Y + (int64_t)o * nc;
+  ws_ensure(ctx, ctx->ws_a, sizeof(double) * (size_t)(o + v) * nc);
+  ws_ensure(ctx, ctx->ws_b, sizeof(double) * (size_t)OV * o * nc);
+  double* S = ctx->ws_a.as<double>();
+  double* Z = ctx->ws_b.as<double>();
+  hipEvent_t e_all = nullptr, e_ovvo = nullptr;
+  timer_begin(ctx, 1, &e_all);
+  if (!transpose) {
+    gemm<double>(ctx, false, false, o, nc, (int)D, 1.0, f.W1.as<double>(), D, X, nc, 0.0, Y1, nc);
+    GFCC_HIP(hipMemcpyAsync(S, X1, sizeof(double) * (size_t)o * nc, hipMemcpyDeviceToDevice,
+                            ctx->stream));
+    gemm<double>(ctx, true, false, v, nc, (int)PV, 1.0, f.Vp.as<double>(), v, X2, nc, 0.0,
+                 S + (int64_t)o * nc, nc);
+    gemm<double>(ctx, false, false, (int)PV, nc, o + v, 1.0, f.W4c.as<double>(), o + v, S, nc,
+                 0.0, Y2, nc);
+    gemm<double>(ctx, false, false, (int)P, v * nc, (int)P, 1.0, f.Woo.as<double>(), P, X2,
+                 (int64_t)v * nc, 1.0, Y2, (int64_t)v * nc);
+  } else {
+    gemm<double>(ctx, true, false, (int)D, nc, o, 1.0, f.W1.as<double>(), D, X1, nc, 0.0, Y, nc);
+    gemm<double>(ctx, true, false, o + v, nc, (int)PV, 1.0, f.W4c.as<double>(), o + v, X2, nc,
+                 0.0, S, nc);
+    hipLaunchKernelGGL(add_kernel<double>, dim3(grid_for((int64_t)o * nc)), dim3(256), 0,
+                       ctx->stream, Y1, S, (int64_t)o * nc);
+    GFCC_LAUNCH_CHECK();
+    gemm<double>(ctx, false, false, (int)PV, nc, v, 1.0, f.Vp.as<double>(), v,
+                 S + (int64_t)o * nc, nc, 1.0, Y2, nc);
+    gemm<double>(ctx, true, false, (int)P, v * nc, (int)P, 1.0, f.Woo.as<double>(), P, X2,
+                 (int64_t)v * nc, 1.0, Y2, (int64_t)v * nc);
+  }
+  timer_begin(ctx, 0, &e_ovvo);
+  gemm_ovvo<double>(ctx, transpose, o, v, nc, f.Weff.as<double>(), X2, nc,
+                    op.pairlut.as<int>(), Z);
+  timer_end(ctx, 0, e_ovvo);
+  hipLaunchKernelGGL(antisym_add_kernel<double>, dim3(grid_for(PV * nc)), dim3(256), 0,
+                     ctx->stream, Z, o, v, nc, Y2);
+  GFCC_LAUNCH_CHECK();
+  timer_end(ctx, 1, e_all);
+}
+
+void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, bool bf16_3body) {
+  Operator& op = ctx->op;
+  GFCC_REQUIRE(op.built, GFCC_ESTATE, "sigma: no operator built");
+  GFCC_REQUIRE(op.keep & GFCC_KEEP_FP32, GFCC_ESTATE,
+               "sigma: FP32 operator copies were not kept at build time");
+  const int o = op.o, v = op.v;
+  const int64_t D = op.D, P = op.P, PV = op.PV, OV = op.OV;
+  const OpPieces<float>& f = op.f32;
+  const float* X1 = X;
+  const float* X2 = X + (int64_t)o * nc;
+  float* Y1 = Y;
+  float* Y2 = Y + (int64_t)o * nc;
+  ws_ensure(ctx, ctx->ws_a, sizeof(float) * (size_t)(o + v) * nc);
+  ws_ensure(ctx, ctx->ws_b, sizeof(float) * (size_t)OV * o * nc);
+  float* S = ctx->ws_a.as<float>();
+  float* Z = ctx->ws_b.as<float>();
+  hipEvent_t e_all = nullptr, e_ovvo = nullptr;
+  timer_begin(ctx, 1, &e_all);
+  gemm<float>(ctx, false, false, o, nc, (int)D, 1.0f, f.W1.as<float>(), D, X, nc, 0.0f, Y1, nc);
+  if (!bf16_3body) {
+    GFCC_HIP(hipMemcpyAsync(S, X1, sizeof(float) * (size_t)o * nc, hipMemcpyDeviceToDevice,
+                            ctx->stream));
+    gemm<float>(ctx, true, false, v, nc, (int)PV, 1.0f, f.Vp.as<float>(), v, X2, nc, 0.0f,
+                S + (int64_t)o * nc, nc);
+    gemm<float>(ctx, false, false, (int)PV, nc, o + v, 1.0f, f.W4c.as<float>(), o + v, S, nc,
+                0.0f, Y2, nc);
+  } else {
+    // three-body term on bf16 matrix cores: tau = Vp^T X2, Y2 = W4 X1 + (-t2) tau
+    ws_ensure(ctx, ctx->ws_c, sizeof(__hip_bfloat16) * (size_t)PV * nc);
+    ws_ensure(ctx, ctx->ws_d, sizeof(__hip_bfloat16) * (size_t)v * nc + sizeof(float) * (size_t)v * nc);
+    __hip_bfloat16* X2b = ctx->ws_c.as<__hip_bfloat16>();
+    float* tau = reinterpret_cast<float*>(ctx->ws_d.as<char>());
+    __hip_bfloat16* taub =
+        reinterpret_cast<__hip_bfloat16*>(ctx->ws_d.as<char>() + sizeof(float) * (size_t)v * nc);
+    cast_f32_bf16(ctx, X2, X2b, PV * nc);
+    gemm_bf16(ctx, true, v, nc, (int)PV, 1.0f, op.Vp_bf16.as<__hip_bfloat16>(), v, X2b, nc, 0.0f,
+              tau, nc);
+    cast_f32_bf16(ctx, tau, taub, (int64_t)v * nc);
+    gemm<float>(ctx, false, false, (int)PV, nc, o, 1.0f, f.W4.as<float>(), o, X1, nc, 0.0f, Y2, nc);
+    gemm_bf16(ctx, false, (int)PV, nc, v, 1.0f, op.T2p_bf16.as<__hip_bfloat16>(), v, taub, nc,
+              1.0f, Y2, nc);
+  }
+  gemm<float>(ctx, false, false, (int)P, v * nc, (int)P, 1.0f, f.Woo.as<float>(), P, X2,
+              (int64_t)v * nc, 1.0f, Y2, (int64_t)v * nc);
+  timer_begin(ctx, 0, &e_ovvo);
+  gemm_ovvo<float>(ctx, false, o, v, nc, f.Weff.as<float>(), X2, nc, op.pairlut.as<int>(), Z);
+  timer_end(ctx, 0, e_ovvo);
+  hipLaunchKernelGGL(antisym_add_kernel<float>, dim3(grid_for(PV * nc)), dim3(256), 0,
+                     ctx->stream, Z, o, v, nc, Y2);
+  GFCC_LAUNCH_CHECK();
+  timer_end(ctx, 1, e_all);
+}
+
+}  // namespace gfcc
+
+extern "C" gfcc_status sigma_apply(gfcc_ctx* ctx, int nrhs, const void* x, void* y,
+                                   int transpose, int precision) {
+  if (!ctx) return GFCC_EINVAL;
+  GFCC_API_BEGIN(ctx)
+  using namespace gfcc;
+  GFCC_REQUIRE(ctx->op.built, GFCC_ESTATE, "sigma_apply: no operator built");
+  GFCC_REQUIRE(nrhs >= 0, GFCC_EINVAL, "sigma_apply: nrhs < 0");
+  if (nrhs == 0) return GFCC_OK;
+  GFCC_REQUIRE(x && y, GFCC_EINVAL, "sigma_apply: null pointer");
+  GFCC_REQUIRE(precision == GFCC_FP64 || precision == GFCC_FP32 ||
+                   precision == GFCC_FP32_BF16_3BODY,
+               GFCC_EINVAL, "sigma_apply: unknown precision");
+  GFCC_REQUIRE(!(transpose && precision != GFCC_FP64), GFCC_EINVAL,
+               "sigma_apply: the transpose product is FP64 only");
+  GFCC_REQUIRE(x != y, GFCC_EINVAL, "sigma_apply: x and y must not overlap");
+  const int64_t D = ctx->op.D;
+  const int nc = 2 * nrhs;
+  DevBuf bx, by;
+  bx.alloc(sizeof(double) * (size_t)D * nc);
+  by.alloc(sizeof(double) * (size_t)D * nc);
+  // [nrhs][D] complex -> [D][nrhs] complex
+  ctranspose(ctx, x, nrhs, D, D, bx.p, nrhs);
+  if (precision == GFCC_FP64) {
+    sigma_block_f64(ctx, nc, bx.as<double>(), by.as<double>(), transpose != 0);
+  } else {
+    DevBuf fx, fy;
+    fx.alloc(sizeof(float) * (size_t)D * nc);
+    fy.alloc(sizeof(float) * (size_t)D * nc);
+    cast_f64_f32(ctx, bx.as<double>(), fx.as<float>(), D * nc);
+    sigma_block_f32(ctx, nc, fx.as<float>(), fy.as<float>(), precision == GFCC_FP32_BF16_3BODY);
+    cast_f32_f64(ctx, fy.as<float>(), by.as<double>(), D * nc);
+    GFCC_HIP(hipStreamSynchronize(ctx->stream));
+  }
+  ctranspose(ctx, by.p, D, nrhs, nrhs, y, D);
+  GFCC_HIP(hipStreamSynchronize(ctx->stream));
+  timers_collect(ctx);
+  GFCC_API_END(ctx)
+}

@@ -1,0 +1,867 @@
+// Shifted linear solves of the GFCC method (Eq. xplin) for many (omega, p) at once.
+//
+// Right-hand sides are processed in blocks of nb; a block's vectors are stored D-major as
+// complex128 [D][nb], so the sigma product of the whole block is one set of matrix products
+// (sigma.hip). Each right-hand side runs its own restarted GMRES on
+//   M(omega) x = b,  M(omega) = (omega - i eta) I + Hbar_N,
+// right-preconditioned by the Jacobi matrix diag(M(omega)). Arnoldi uses classical
+// Gram-Schmidt with one full re-orthogonalisation pass (CGS2). Givens rotations, the
+// convergence test and the triangular solve run on the device, one thread per right-hand side.
+// Every restart cycle begins with the explicit FP64 residual b - M x, which is also the final
+// stopping test. With a reduced-precision sigma inside the cycle this is FP64 iterative
+// refinement around a low-precision GMRES (GMRES-IR).
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace gfcc {
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  double s = fabs(b.x) + fabs(b.y);
+  double ar = a.x / s, ai = a.y / s, br = b.x / s, bi = b.y / s;
+  double d = br * br + bi * bi;
+  return make_double2((ar * br + ai * bi) / d, (ai * br - ar * bi) / d);
+}
+
+constexpr int JG = 16;  // basis vectors per dot pass
+
+// partial[blk][jj][r] = sum over this block's rows of conj(V_j[d][r]) * W[d][r], j = j0 + jj
+__global__ __launch_bounds__(256) void dots_kernel(const double2* __restrict__ V, int64_t vstride,
+                                                   int j0, int nj, const double2* __restrict__ W,
+                                                   int64_t D, int nb, double2* __restrict__ partial) {
+  __shared__ double2 red[256];
+  const int RB = nb < 256 ? nb : 256;
+  const int lanes = 256 / RB;
+  const int t = threadIdx.x;
+  const int rl = t % RB, rowlane = t / RB;
+  const int r = blockIdx.y * RB + rl;
+  const bool live = rowlane < lanes && r < nb;
+  double2 acc[JG];
+#pragma unroll
+  for (int jj = 0; jj < JG; ++jj) acc[jj] = make_double2(0.0, 0.0);
+  const int64_t rows_per_blk = (D + gridDim.x - 1) / gridDim.x;
+  const int64_t d0 = (int64_t)blockIdx.x * rows_per_blk;
+  const int64_t d1 = min(D, d0 + rows_per_blk);
+  if (live) {
+    for (int64_t d = d0 + rowlane; d < d1; d += lanes) {
+      double2 w = W[d * nb + r];
+#pragma unroll
+      for (int jj = 0; jj < JG; ++jj) {
+        if (jj < nj) {
+          double2 p = cconjmul(V[(int64_t)(j0 + jj) * vstride + d * nb + r], w);
+          acc[jj].x += p.x;
+          acc[jj].y += p.y;
+        }
+      }
+    }
+  }
+  for (int jj = 0; jj < nj; ++jj) {
+    red[t] = live ? acc[jj] : make_double2(0.0, 0.0);
+    __syncthreads();
+    if (rowlane == 0 && r < nb) {
+      double2 s = red[t];
+      for (int q = 1; q < lanes; ++q) {
+        double2 x = red[t + q * RB];
+        s.x += x.x;
+        s.y += x.y;
+      }
+      partial[((int64_t)blockIdx.x * JG + jj) * nb + r] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// h[(j0+jj)][r] (+)= sum_blk partial[blk][jj][r]
+__global__ void dots_reduce(const double2* __restrict__ partial, int nblk, int j0, int nj, int nb,
+                            double2* __restrict__ h) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nj * nb) return;
+  int jj = idx / nb, r = idx % nb;
+  double2 s = make_double2(0.0, 0.0);
+  for (int b = 0; b < nblk; ++b) {
+    double2 x = partial[((int64_t)b * JG + jj) * nb + r];
+    s.x += x.x;
+    s.y += x.y;
+  }
+  h[(int64_t)(j0 + jj) * nb + r] = s;
+}
+
+// W[d][r] -= sum_{j<=k} V_j[d][r] * h[j][r]
+__global__ void update_kernel(const double2* __restrict__ V, int64_t vstride, int nj,
+                              const double2* __restrict__ h, int64_t D, int nb,
+                              double2* __restrict__ W) {
+  const int64_t n = D * nb;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx % nb);
+    double2 w = W[idx];
+    for (int j = 0; j < nj; ++j) {
+      double2 p = cmul(V[(int64_t)j * vstride + idx], h[(int64_t)j * nb + r]);
+      w.x -= p.x;
+      w.y -= p.y;
+    }
+    W[idx] = w;
+  }
+}
+
+// nrm partial: sum |W[d][r]|^2
+__global__ __launch_bounds__(256) void norm_kernel(const double2* __restrict__ W, int64_t D, int nb,
+                                                   double* __restrict__ partial) {
+  __shared__ double red[256];
+  const int RB = nb < 256 ? nb : 256;
+  const int lanes = 256 / RB;
+  const int t = threadIdx.x;
+  const int rl = t % RB, rowlane = t / RB;
+  const int r = blockIdx.y * RB + rl;
+  const bool live = rowlane < lanes && r < nb;
+  double acc = 0.0;
+  const int64_t rows_per_blk = (D + gridDim.x - 1) / gridDim.x;
+  const int64_t d0 = (int64_t)blockIdx.x * rows_per_blk;
+  const int64_t d1 = min(D, d0 + rows_per_blk);
+  if (live)
+    for (int64_t d = d0 + rowlane; d < d1; d += lanes) {
+      double2 w = W[d * nb + r];
+      acc += w.x * w.x + w.y * w.y;
+    }
+  red[t] = live ? acc : 0.0;
+  __syncthreads();
+  if (rowlane == 0 && r < nb) {
+    double s = red[t];
+    for (int q = 1; q < lanes; ++q) s += red[t + q * RB];
+    partial[(int64_t)blockIdx.x * nb + r] = s;
+  }
+}
+
+__global__ void norm_reduce(const double* __restrict__ partial, int nblk, int nb,
+                            double* __restrict__ out) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nb) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * nb + r];
+  out[r] = sqrt(s);
+}
+
+// U[d][r] = V[d][r] / (diag[d] + z[r])
+__global__ void precond_kernel(const double2* __restrict__ V, const double* __restrict__ diag,
+                               const double2* __restrict__ z, int64_t D, int nb,
+                               double2* __restrict__ U) {
+  const int64_t n = D * nb;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx % nb);
+    const int64_t d = idx / nb;
+    double2 zz = z[r];
+    U[idx] = cdiv(V[idx], make_double2(diag[d] + zz.x, zz.y));
+  }
+}
+
+// W[d][r] = S[d][r] + z[r] * U[d][r]   (S may alias W)
+__global__ void shift_kernel(const double2* S, const double2* __restrict__ U,
+                             const double2* __restrict__ z, int64_t D, int nb, double2* W) {
+  const int64_t n = D * nb;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx % nb);
+    double2 p = cmul(z[r], U[idx]);
+    double2 s = S[idx];
+    W[idx] = make_double2(s.x + p.x, s.y + p.y);
+  }
+}
+
+// R = B - S  (S = M X, shift included)
+__global__ void residual_kernel(const double2* __restrict__ B, const double2* __restrict__ S,
+                                int64_t n, double2* __restrict__ R) {
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    double2 b = B[idx], s = S[idx];
+    R[idx] = make_double2(b.x - s.x, b.y - s.y);
+  }
+}
+
+// a += b (complex, n entries)
+__global__ void cadd_kernel(double2* __restrict__ a, const double2* __restrict__ b, int64_t n) {
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    a[idx].x += b[idx].x;
+    a[idx].y += b[idx].y;
+  }
+}
+
+// V0 = R / beta (zero for inactive)
+__global__ void scale_kernel(const double2* __restrict__ W, const double* __restrict__ inv,
+                             int64_t D, int nb, double2* __restrict__ V) {
+  const int64_t n = D * nb;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx % nb);
+    double s = inv[r];
+    double2 w = W[idx];
+    V[idx] = make_double2(w.x * s, w.y * s);
+  }
+}
+
+struct BlockState {
+  double2* H;      // [nb][m][m+1]  column k of RHS r at H + (r*m + k)*(m+1)
+  double2* cs;     // [nb][m]
+  double2* sn;     // [nb][m]
+  double2* g;      // [nb][m+1]
+  int* active;     // [nb]
+  int* kend;       // [nb] steps taken this cycle
+  int* its;        // [nb] total iterations
+  int* brk;        // [nb] singular least-squares flag
+  double* resest;  // [nb]
+  double* thresh;  // [nb] inner stopping threshold (absolute)
+  double* inv;     // [nb] 1/||w|| for the new basis vector
+};
+
+// one thread per RHS: Hessenberg column k, Givens rotation, residual estimate, flags
+__global__ void arnoldi_finish_kernel(const double2* __restrict__ h, const double* __restrict__ hn,
+                                      int k, int m, int nb, int maxit, BlockState s) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nb) return;
+  if (!s.active[r]) {
+    s.inv[r] = 0.0;
+    return;
+  }
+  double2* col = s.H + ((int64_t)r * m + k) * (m + 1);
+  for (int i = 0; i <= k; ++i) col[i] = h[(int64_t)i * nb + r];
+  double nrm = hn[r];
+  col[k + 1] = make_double2(nrm, 0.0);
+  double2* cs = s.cs + (int64_t)r * m;
+  double2* sn = s.sn + (int64_t)r * m;
+  for (int i = 0; i < k; ++i) {  // previous rotations
+    double2 a = col[i], b = col[i + 1];
+    double2 t1 = cconjmul(cs[i], a), t2 = cconjmul(sn[i], b);
+    double2 u1 = cmul(sn[i], a), u2 = cmul(cs[i], b);
+    col[i] = make_double2(t1.x + t2.x, t1.y + t2.y);
+    col[i + 1] = make_double2(u2.x - u1.x, u2.y - u1.y);
+  }
+  double2 a = col[k], b = col[k + 1];
+  double den = hypot(hypot(a.x, a.y), hypot(b.x, b.y));
+  double2* g = s.g + (int64_t)r * (m + 1);
+  s.its[r] += 1;
+  s.kend[r] = k + 1;
+  if (den == 0.0) {  // singular least-squares problem
+    s.brk[r] = 1;
+    s.active[r] = 0;
+    s.inv[r] = 0.0;
+    s.kend[r] = k;  // exclude the singular column
+    return;
+  }
+  double2 c = make_double2(a.x / den, a.y / den), sv = make_double2(b.x / den, b.y / den);
+  cs[k] = c;
+  sn[k] = sv;
+  col[k] = make_double2(den, 0.0);
+  col[k + 1] = make_double2(0.0, 0.0);
+  double2 gk = g[k];
+  double2 ng = cmul(sv, gk);
+  g[k + 1] = make_double2(-ng.x, -ng.y);
+  g[k] = cconjmul(c, gk);
+  double est = hypot(g[k + 1].x, g[k + 1].y);
+  s.resest[r] = est;
+  bool stop = est <= s.thresh[r] || nrm == 0.0 || s.its[r] >= maxit || k + 1 == m;
+  s.inv[r] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
+  if (stop) s.active[r] = 0;
+}
+
+// y = H(0:kend,0:kend)^{-1} g(0:kend), written to yout[j][r] (zero beyond kend)
+__global__ void ysolve_kernel(int m, int nb, BlockState s, const int* __restrict__ used,
+                              double2* __restrict__ yout) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nb) return;
+  int ke = used[r] ? s.kend[r] : 0;
+  const double2* H = s.H + (int64_t)r * m * (m + 1);
+  const double2* g = s.g + (int64_t)r * (m + 1);
+  for (int j = ke; j < m; ++j) yout[(int64_t)j * nb + r] = make_double2(0.0, 0.0);
+  for (int i = ke - 1; i >= 0; --i) {
+    double2 acc = g[i];
+    for (int j = i + 1; j < ke; ++j) {
+      double2 p = cmul(H[(int64_t)j * (m + 1) + i], yout[(int64_t)j * nb + r]);
+      acc.x -= p.x;
+      acc.y -= p.y;
+    }
+    yout[(int64_t)i * nb + r] = cdiv(acc, H[(int64_t)i * (m + 1) + i]);
+  }
+}
+
+// X[d][r] += (sum_j V_j[d][r] y[j][r]) / (diag[d] + z[r])
+__global__ void xupdate_kernel(const double2* __restrict__ V, int64_t vstride, int nj,
+                               const double2* __restrict__ y, const double* __restrict__ diag,
+                               const double2* __restrict__ z, int64_t D, int nb,
+                               double2* __restrict__ X) {
+  const int64_t n = D * nb;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx % nb);
+    const int64_t d = idx / nb;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j = 0; j < nj; ++j) {
+      double2 p = cmul(V[(int64_t)j * vstride + idx], y[(int64_t)j * nb + r]);
+      acc.x += p.x;
+      acc.y += p.y;
+    }
+    double2 zz = z[r];
+    double2 u = cdiv(acc, make_double2(diag[d] + zz.x, zz.y));
+    double2 x = X[idx];
+    X[idx] = make_double2(x.x + u.x, x.y + u.y);
+  }
+}
+
+// right-hand sides: forward b = e_p, transpose b = c_p (row p of Crows)
+__global__ void rhs_kernel(const int* __restrict__ prow, const double* __restrict__ Crows,
+                           int transpose, int64_t D, int nb, double2* __restrict__ B) {
+  const int64_t n = D * nb;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx % nb);
+    const int64_t d = idx / nb;
+    const int p = prow[r];
+    double val = 0.0;
+    if (p >= 0) val = transpose ? Crows[(int64_t)p * D + d] : (d == p ? 1.0 : 0.0);
+    B[idx] = make_double2(val, 0.0);
+  }
+}
+
+// Gq[k][r] = sum_d Crows[q_k][d] X[d][r]  computed by gemm; here the transpose variant:
+// Gq[k][r] = X[q_k][r]
+__global__ void gather_rows_kernel(const double2* __restrict__ X, const int* __restrict__ q, int nq,
+                                   int nb, double2* __restrict__ out) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nq * nb) return;
+  int k = idx / nb, r = idx % nb;
+  out[idx] = X[(int64_t)q[k] * nb + r];
+}
+
+// G_out[w][qk][pk] = Gq[qk][r] for the block's right-hand sides r -> (w, pk). The adjoint
+// systems give b_q^T Y_p = G_pq, stored transposed so both directions fill G in one layout.
+__global__ void scatter_G_kernel(const double2* __restrict__ Gq, int nq, int nb, int r0,
+                                 int nrhs_total, int np, int transpose, double2* __restrict__ G) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nq * nb) return;
+  int k = idx / nb, r = idx % nb;
+  int gr = r0 + r;
+  if (gr >= nrhs_total) return;
+  int w = gr / np, pk = gr % np;
+  if (transpose) G[((int64_t)w * np + pk) * np + k] = Gq[idx];
+  else G[((int64_t)w * np + k) * np + pk] = Gq[idx];
+}
+
+__global__ void copy_rows_kernel(const double* __restrict__ C, const int* __restrict__ q, int nq,
+                                 int64_t D, double* __restrict__ out) {
+  const int64_t n = (int64_t)nq * D;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int k = (int)(idx / D);
+    int64_t d = idx - (int64_t)k * D;
+    out[idx] = C[(int64_t)q[k] * D + d];
+  }
+}
+
+__global__ void f64_to_f32_kernel(const double* __restrict__ s, float* __restrict__ d, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = (float)s[i];
+}
+__global__ void f32_to_f64_kernel(const float* __restrict__ s, double* __restrict__ d, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = (double)s[i];
+}
+
+inline unsigned gridn(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 16384) b = 16384;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+template <typename T> T* carve(char*& cur, int64_t n) {
+  T* p = reinterpret_cast<T*>(cur);
+  cur += ((n * (int64_t)sizeof(T) + 255) / 256) * 256;
+  return p;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// Block GMRES driver
+struct GmresBlock {
+  gfcc_ctx* ctx = nullptr;
+  int64_t D = 0;
+  int nb = 0, m = 0;
+  int precision = GFCC_FP64;
+  bool transpose = false;
+  DevBuf mem, mem_f32;
+  double2 *V, *W, *U, *X, *B, *Hh, *Hh2, *Y, *z;
+  double *nrm, *part_n;
+  double2* part_h;
+  int *used, *prow;
+  float *Uf = nullptr, *Sf = nullptr;
+  BlockState s;
+  int nblk_rows = 1, nbrows_y = 1;
+
+  void setup(gfcc_ctx* c, int nb_, int m_, int prec, bool tr) {
+    ctx = c;
+    D = ctx->op.D;
+    nb = nb_;
+    m = m_;
+    precision = prec;
+    transpose = tr;
+    const int64_t vec = D * nb;
+    nblk_rows = (int)std::min<int64_t>(1024, std::max<int64_t>(1, vec / 4096));
+    const int RB = nb < 256 ? nb : 256;
+    nbrows_y = (nb + RB - 1) / RB;
+    int64_t bytes = 0;
+    auto add = [&](int64_t n, int64_t sz) { bytes += ((n * sz + 255) / 256) * 256; };
+    add(vec * (m + 1), 16);                                   // V
+    for (int i = 0; i < 4; ++i) add(vec, 16);                 // W U X B
+    add((int64_t)(m + 1) * nb, 16); add((int64_t)(m + 1) * nb, 16);  // Hh Hh2
+    add((int64_t)m * nb, 16);                                 // Y
+    add(nb, 16);                                              // z
+    add(nb, 8);                                               // nrm
+    add((int64_t)nblk_rows * nb, 8);                          // part_n
+    add((int64_t)nblk_rows * JG * nb, 16);                    // part_h
+    add(nb, 4); add(nb, 4);                                   // used prow
+    add((int64_t)nb * m * (m + 1), 16);                       // H
+    add((int64_t)nb * m, 16); add((int64_t)nb * m, 16);       // cs sn
+    add((int64_t)nb * (m + 1), 16);                           // g
+    for (int i = 0; i < 4; ++i) add(nb, 4);
+    for (int i = 0; i < 3; ++i) add(nb, 8);
+    mem.ensure((size_t)bytes);
+    char* cur = mem.as<char>();
+    V = carve<double2>(cur, vec * (m + 1));
+    W = carve<double2>(cur, vec);
+    U = carve<double2>(cur, vec);
+    X = carve<double2>(cur, vec);
+    B = carve<double2>(cur, vec);
+    Hh = carve<double2>(cur, (int64_t)(m + 1) * nb);
+    Hh2 = carve<double2>(cur, (int64_t)(m + 1) * nb);
+    Y = carve<double2>(cur, (int64_t)m * nb);
+    z = carve<double2>(cur, nb);
+    nrm = carve<double>(cur, nb);
+    part_n = carve<double>(cur, (int64_t)nblk_rows * nb);
+    part_h = carve<double2>(cur, (int64_t)nblk_rows * JG * nb);
+    used = carve<int>(cur, nb);
+    prow = carve<int>(cur, nb);
+    s.H = carve<double2>(cur, (int64_t)nb * m * (m + 1));
+    s.cs = carve<double2>(cur, (int64_t)nb * m);
+    s.sn = carve<double2>(cur, (int64_t)nb * m);
+    s.g = carve<double2>(cur, (int64_t)nb * (m + 1));
+    s.active = carve<int>(cur, nb);
+    s.kend = carve<int>(cur, nb);
+    s.its = carve<int>(cur, nb);
+    s.brk = carve<int>(cur, nb);
+    s.resest = carve<double>(cur, nb);
+    s.thresh = carve<double>(cur, nb);
+    s.inv = carve<double>(cur, nb);
+    if (precision != GFCC_FP64) {
+      mem_f32.ensure(sizeof(float) * (size_t)vec * 2 * 2);
+      Uf = mem_f32.as<float>();
+      Sf = Uf + vec * 2;
+    }
+  }
+
+  hipStream_t st() const { return ctx->stream; }
+
+  // out[r] = ||Wv[:, r]||
+  void norms(const double2* Wv, double* out) {
+    hipLaunchKernelGGL(norm_kernel, dim3(nblk_rows, nbrows_y), dim3(256), 0, st(), Wv, D, nb, part_n);
+    GFCC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(norm_reduce, dim3(blocks_for(nb, 256)), dim3(256), 0, st(), part_n,
+                       nblk_rows, nb, out);
+    GFCC_LAUNCH_CHECK();
+  }
+
+  // h[j][r] = V_j^H W for j in [0, nj)
+  void dots(int nj, double2* h) {
+    for (int j0 = 0; j0 < nj; j0 += JG) {
+      int cnt = std::min(JG, nj - j0);
+      hipLaunchKernelGGL(dots_kernel, dim3(nblk_rows, nbrows_y), dim3(256), 0, st(), V, D * nb,
+                         j0, cnt, W, D, nb, part_h);
+      GFCC_LAUNCH_CHECK();
+      hipLaunchKernelGGL(dots_reduce, dim3(blocks_for((int64_t)cnt * nb, 256)), dim3(256), 0,
+                         st(), part_h, nblk_rows, j0, cnt, nb, h);
+      GFCC_LAUNCH_CHECK();
+    }
+  }
+
+  // Wv = M(omega) Uv = sigma(Uv) + z Uv ; sigma in FP64 when fp64 is set, else in the
+  // block's precision
+  void apply_M(const double2* Uv, double2* Wv, bool fp64) {
+    const int nc = 2 * nb;
+    if (fp64 || precision == GFCC_FP64) {
+      sigma_block_f64(ctx, nc, reinterpret_cast<const double*>(Uv), reinterpret_cast<double*>(Wv),
+                      transpose);
+    } else {
+      const int64_t n = D * nc;
+      hipLaunchKernelGGL(f64_to_f32_kernel, dim3(gridn(n)), dim3(256), 0, st(),
+                         reinterpret_cast<const double*>(Uv), Uf, n);
+      GFCC_LAUNCH_CHECK();
+      sigma_block_f32(ctx, nc, Uf, Sf, precision == GFCC_FP32_BF16_3BODY);
+      hipLaunchKernelGGL(f32_to_f64_kernel, dim3(gridn(n)), dim3(256), 0, st(), Sf,
+                         reinterpret_cast<double*>(Wv), n);
+      GFCC_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(shift_kernel, dim3(gridn(D * nb)), dim3(256), 0, st(), Wv, Uv, z, D, nb, Wv);
+    GFCC_LAUNCH_CHECK();
+  }
+};
+
+// Solve the systems of right-hand sides [r0, r0+nb) (global index r = w*np + k). On return
+// gb.X holds the solutions (D-major block).
+static void solve_block(GmresBlock& gb, const double* omega, const int* pset, int np, int nrhs,
+                        int r0, double eta, double tol, int maxit, std::vector<int>& its_out,
+                        std::vector<double>& res_out, std::vector<int>& brk_out) {
+  gfcc_ctx* ctx = gb.ctx;
+  const int nb = gb.nb, m = gb.m;
+  const int64_t D = gb.D;
+  hipStream_t st = ctx->stream;
+  std::vector<double2> hz(nb);
+  std::vector<int> hp(nb);
+  for (int r = 0; r < nb; ++r) {
+    int gr = r0 + r;
+    if (gr < nrhs) {
+      hz[r] = make_double2(omega[gr / np], -eta);
+      hp[r] = pset[gr % np];
+    } else {
+      hz[r] = make_double2(1.0, -eta);  // padding column: b = 0, done at once
+      hp[r] = -1;
+    }
+  }
+  GFCC_HIP(hipMemcpyAsync(gb.z, hz.data(), sizeof(double2) * nb, hipMemcpyHostToDevice, st));
+  GFCC_HIP(hipMemcpyAsync(gb.prow, hp.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(rhs_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.prow,
+                     ctx->op.Crows.as<double>(), gb.transpose ? 1 : 0, D, nb, gb.B);
+  GFCC_LAUNCH_CHECK();
+  std::vector<double> bnorm(nb), rn(nb);
+  gb.norms(gb.B, gb.nrm);
+  GFCC_HIP(hipMemcpyAsync(bnorm.data(), gb.nrm, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+  fill(ctx, reinterpret_cast<double*>(gb.X), D * nb * 2, 0.0);
+  std::vector<int> zeros(nb, 0);
+  GFCC_HIP(hipMemcpyAsync(gb.s.brk, zeros.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
+  GFCC_HIP(hipStreamSynchronize(st));
+
+  std::vector<int> its(nb, 0), act(nb), brk(nb, 0);
+  std::vector<double> thr(nb), inv0(nb), rel(nb, 0.0);
+  std::vector<double2> g0((size_t)nb * (m + 1));
+  bool first = true;
+  const bool mixed = gb.precision != GFCC_FP64;
+  const double inner_rel = 1e-4;  // relative tolerance of a reduced-precision cycle
+  for (;;) {
+    // ---- explicit FP64 residual R = B - M X (in W) and its norm
+    if (first) {
+      GFCC_HIP(hipMemcpyAsync(gb.W, gb.B, sizeof(double2) * D * nb, hipMemcpyDeviceToDevice, st));
+    } else {
+      gb.apply_M(gb.X, gb.U, true);
+      hipLaunchKernelGGL(residual_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.B, gb.U,
+                         D * nb, gb.W);
+      GFCC_LAUNCH_CHECK();
+    }
+    first = false;
+    gb.norms(gb.W, gb.nrm);
+    GFCC_HIP(hipMemcpyAsync(rn.data(), gb.nrm, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+    GFCC_HIP(hipStreamSynchronize(st));
+    int nact = 0;
+    for (int r = 0; r < nb; ++r) {
+      rel[r] = bnorm[r] > 0 ? rn[r] / bnorm[r] : 0.0;
+      bool done = (bnorm[r] == 0.0) || rel[r] <= tol || its[r] >= maxit || brk[r];
+      act[r] = done ? 0 : 1;
+      nact += act[r];
+      inv0[r] = act[r] ? 1.0 / rn[r] : 0.0;
+      const double t_abs = 0.5 * tol * bnorm[r];
+      thr[r] = mixed ? std::max(t_abs, inner_rel * rn[r]) : t_abs;
+      for (int i = 0; i <= m; ++i) g0[(size_t)r * (m + 1) + i] = make_double2(0.0, 0.0);
+      g0[(size_t)r * (m + 1)] = make_double2(act[r] ? rn[r] : 0.0, 0.0);
+    }
+    if (nact == 0) break;
+    // ---- cycle start: V0 = R / ||R||, g = (||R||, 0, ...)
+    GFCC_HIP(hipMemcpyAsync(gb.s.active, act.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
+    GFCC_HIP(hipMemcpyAsync(gb.used, act.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
+    GFCC_HIP(hipMemcpyAsync(gb.s.thresh, thr.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st));
+    GFCC_HIP(hipMemcpyAsync(gb.s.inv, inv0.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st));
+    GFCC_HIP(hipMemcpyAsync(gb.s.g, g0.data(), sizeof(double2) * g0.size(), hipMemcpyHostToDevice, st));
+    GFCC_HIP(hipMemcpyAsync(gb.s.kend, zeros.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
+    GFCC_HIP(hipMemcpyAsync(gb.s.its, its.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(scale_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.W, gb.s.inv, D, nb,
+                       gb.V);
+    GFCC_LAUNCH_CHECK();
+    for (int k = 0; k < m; ++k) {
+      double2* Vk = gb.V + (int64_t)k * D * nb;
+      hipLaunchKernelGGL(precond_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, Vk,
+                         ctx->op.diag.as<double>(), gb.z, D, nb, gb.U);
+      GFCC_LAUNCH_CHECK();
+      gb.apply_M(gb.U, gb.W, false);
+      // CGS2: two passes of classical Gram-Schmidt; Hessenberg column = sum of both
+      gb.dots(k + 1, gb.Hh);
+      hipLaunchKernelGGL(update_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.V, D * nb,
+                         k + 1, gb.Hh, D, nb, gb.W);
+      GFCC_LAUNCH_CHECK();
+      gb.dots(k + 1, gb.Hh2);
+      hipLaunchKernelGGL(update_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.V, D * nb,
+                         k + 1, gb.Hh2, D, nb, gb.W);
+      GFCC_LAUNCH_CHECK();
+      hipLaunchKernelGGL(cadd_kernel, dim3(blocks_for((int64_t)(k + 1) * nb, 256)), dim3(256), 0,
+                         st, gb.Hh, gb.Hh2, (int64_t)(k + 1) * nb);
+      GFCC_LAUNCH_CHECK();
+      gb.norms(gb.W, gb.nrm);
+      hipLaunchKernelGGL(arnoldi_finish_kernel, dim3(blocks_for(nb, 64)), dim3(64), 0, st, gb.Hh,
+                         gb.nrm, k, m, nb, maxit, gb.s);
+      GFCC_LAUNCH_CHECK();
+      hipLaunchKernelGGL(scale_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.W, gb.s.inv, D,
+                         nb, gb.V + (int64_t)(k + 1) * D * nb);
+      GFCC_LAUNCH_CHECK();
+      GFCC_HIP(hipMemcpyAsync(act.data(), gb.s.active, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+      GFCC_HIP(hipStreamSynchronize(st));
+      int any = 0;
+      for (int r = 0; r < nb; ++r) any |= act[r];
+      if (!any) break;
+    }
+    // ---- solution update x += P^{-1} V y
+    hipLaunchKernelGGL(ysolve_kernel, dim3(blocks_for(nb, 64)), dim3(64), 0, st, m, nb, gb.s,
+                       gb.used, gb.Y);
+    GFCC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(xupdate_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.V, D * nb, m,
+                       gb.Y, ctx->op.diag.as<double>(), gb.z, D, nb, gb.X);
+    GFCC_LAUNCH_CHECK();
+    GFCC_HIP(hipMemcpyAsync(its.data(), gb.s.its, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+    GFCC_HIP(hipMemcpyAsync(brk.data(), gb.s.brk, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
+    GFCC_HIP(hipStreamSynchronize(st));
+  }
+  for (int r = 0; r < nb; ++r) {
+    int gr = r0 + r;
+    if (gr >= nrhs) continue;
+    its_out[gr] = its[r];
+    res_out[gr] = rel[r];
+    brk_out[gr] = brk[r];
+  }
+}
+
+// Full driver shared by gfcc_solve and the reduced-order model: solves every (omega, p),
+// writes G (device, [nw][np][np]) and optionally X ([nw][np][D] device).
+gfcc_status solve_all(gfcc_ctx* ctx, int nw, const double* omega, int np, const int* p,
+                      double eta, double tol, int maxit, int restart, int block, int precision,
+                      int transpose, void* X_out, void* G_out, int* iters_out, double* resid_out) {
+  Operator& op = ctx->op;
+  const int64_t D = op.D;
+  const int nrhs = nw * np;
+  int nb = block > 0 ? block : std::min(nrhs, 128);
+  nb = std::max(1, std::min(nb, nrhs));
+  GFCC_REQUIRE(nb <= 2048, GFCC_EINVAL, "gfcc_solve: block too large");
+  GmresBlock gb;
+  gb.setup(ctx, nb, restart, precision, transpose != 0);
+  std::vector<int> its(nrhs, 0), brk(nrhs, 0);
+  std::vector<double> res(nrhs, 0.0);
+  // rows used for G: c_q rows (forward) or the 1h entries q (transpose)
+  DevBuf bq, bC, bG;
+  bq.alloc(sizeof(int) * np);
+  GFCC_HIP(hipMemcpyAsync(bq.p, p, sizeof(int) * np, hipMemcpyHostToDevice, ctx->stream));
+  if (!transpose) {
+    bC.alloc(sizeof(double) * (size_t)np * D);
+    hipLaunchKernelGGL(copy_rows_kernel, dim3(gridn((int64_t)np * D)), dim3(256), 0, ctx->stream,
+                       op.Crows.as<double>(), bq.as<int>(), np, D, bC.as<double>());
+    GFCC_LAUNCH_CHECK();
+  }
+  bG.alloc(sizeof(double2) * (size_t)np * nb);
+  for (int r0 = 0; r0 < nrhs; r0 += nb) {
+    solve_block(gb, omega, p, np, nrhs, r0, eta, tol, maxit, its, res, brk);
+    // G rows for this block
+    if (!transpose) {
+      gemm<double>(ctx, false, false, np, 2 * nb, (int)D, 1.0, bC.as<double>(), D,
+                   reinterpret_cast<const double*>(gb.X), 2 * nb, 0.0, bG.as<double>(), 2 * nb);
+    } else {
+      hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks_for((int64_t)np * nb, 256)), dim3(256),
+                         0, ctx->stream, gb.X, bq.as<int>(), np, nb, bG.as<double2>());
+      GFCC_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(scatter_G_kernel, dim3(blocks_for((int64_t)np * nb, 256)), dim3(256), 0,
+                       ctx->stream, bG.as<double2>(), np, nb, r0, nrhs, np, transpose,
+                       static_cast<double2*>(G_out));
+    GFCC_LAUNCH_CHECK();
+    if (X_out) {
+      int cnt = std::min(nb, nrhs - r0);
+      ctranspose(ctx, gb.X, D, cnt, nb, static_cast<double2*>(X_out) + (int64_t)r0 * D, D);
+    }
+  }
+  GFCC_HIP(hipStreamSynchronize(ctx->stream));
+  timers_collect(ctx);
+  bool noconv = false, anybrk = false;
+  for (int r = 0; r < nrhs; ++r) {
+    if (iters_out) iters_out[r] = its[r];
+    if (resid_out) resid_out[r] = res[r];
+    if (brk[r]) anybrk = true;
+    if (!(res[r] <= tol)) noconv = true;
+  }
+  if (anybrk) {
+    ctx->last_error = "gfcc_solve: singular shifted operator on a Krylov space";
+    return GFCC_EBREAKDOWN;
+  }
+  if (noconv) {
+    ctx->last_error = "gfcc_solve: some right-hand sides did not reach the tolerance";
+    return GFCC_ENOCONV;
+  }
+  return GFCC_OK;
+}
+
+namespace {
+
+// S[d] = sum_r weight_{w(r)} Im(Y[r][d] X[r][d])
+__global__ void grad_rows_kernel(const double2* __restrict__ X, const double2* __restrict__ Y,
+                                 const double* __restrict__ wt, int nw, int np, int64_t D,
+                                 double* __restrict__ S) {
+  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < D;
+       d += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      double aw = 0.0;
+      for (int k = 0; k < np; ++k) {
+        int64_t off = ((int64_t)w * np + k) * D + d;
+        double2 y = Y[off], x = X[off];
+        aw += y.x * x.y + y.y * x.x;
+      }
+      acc += wt[w] * aw;
+    }
+    S[d] = acc;
+  }
+}
+
+// grad[m] for occupied m: (1/pi) (S[m] + sum_{pairs with m} sum_a S[...]);
+// grad[o+a] for virtual a: -(1/pi) sum_pairs S[o + pr v + a]
+__global__ void grad_bins_kernel(const double* __restrict__ S, int o, int v,
+                                 double* __restrict__ grad) {
+  __shared__ double red[256];
+  const int orb = blockIdx.x;
+  const int64_t P = (int64_t)o * (o - 1) / 2;
+  double acc = 0.0;
+  if (orb < o) {
+    const int mm = orb;
+    const int64_t nterm = (int64_t)(o - 1) * v;
+    for (int64_t t = threadIdx.x; t < nterm; t += blockDim.x) {
+      int kk = (int)(t / v), a = (int)(t % v);
+      int k = kk < mm ? kk : kk + 1;
+      int64_t pr = k < mm ? pair_of(k, mm, o) : pair_of(mm, k, o);
+      acc += S[o + pr * v + a];
+    }
+    if (threadIdx.x == 0) acc += S[mm];
+  } else {
+    const int a = orb - o;
+    for (int64_t pr = threadIdx.x; pr < P; pr += blockDim.x) acc += S[o + pr * v + a];
+    acc = -acc;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad[orb] = red[0] / 3.14159265358979323846;
+}
+
+__global__ void spectral_kernel(const double2* __restrict__ G, int nw, int np, double* __restrict__ A) {
+  int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nw) return;
+  double s = 0.0;
+  for (int k = 0; k < np; ++k) s += G[((int64_t)w * np + k) * np + k].y;
+  A[w] = s / 3.14159265358979323846;
+}
+
+}  // namespace
+}  // namespace gfcc
+
+extern "C" {
+
+gfcc_status gfcc_solve(gfcc_ctx* ctx, int nw, const double* omega, int np, const int* p,
+                       double eta, double tol, int maxit, int restart, int block, int precision,
+                       int transpose, void* X_out, void* G_out, int* iters_out,
+                       double* resid_out) {
+  if (!ctx) return GFCC_EINVAL;
+  GFCC_API_BEGIN(ctx)
+  using namespace gfcc;
+  GFCC_HIP(hipSetDevice(ctx->device));
+  GFCC_REQUIRE(ctx->op.built, GFCC_ESTATE, "gfcc_solve: no operator built");
+  GFCC_REQUIRE(nw >= 0 && np >= 0, GFCC_EINVAL, "gfcc_solve: negative sizes");
+  if (nw == 0 || np == 0) return GFCC_OK;
+  GFCC_REQUIRE(omega && p && G_out, GFCC_EINVAL, "gfcc_solve: null pointer");
+  GFCC_REQUIRE((int64_t)nw * np < (1LL << 30), GFCC_EINVAL, "gfcc_solve: too many right-hand sides");
+  GFCC_REQUIRE(eta > 0.0 && std::isfinite(eta), GFCC_EINVAL, "gfcc_solve: eta must be > 0");
+  GFCC_REQUIRE(tol > 0.0 && tol < 1.0, GFCC_EINVAL, "gfcc_solve: tol must be in (0, 1)");
+  GFCC_REQUIRE(maxit >= 1, GFCC_EINVAL, "gfcc_solve: maxit must be >= 1");
+  GFCC_REQUIRE(restart >= 1 && restart <= 200, GFCC_EINVAL, "gfcc_solve: restart in [1, 200]");
+  GFCC_REQUIRE(precision == GFCC_FP64 || precision == GFCC_FP32 ||
+                   precision == GFCC_FP32_BF16_3BODY,
+               GFCC_EINVAL, "gfcc_solve: unknown precision");
+  GFCC_REQUIRE(precision == GFCC_FP64 || (ctx->op.keep & GFCC_KEEP_FP32), GFCC_ESTATE,
+               "gfcc_solve: reduced precision needs GFCC_KEEP_FP32 at build time");
+  GFCC_REQUIRE(!(transpose && precision != GFCC_FP64), GFCC_EINVAL,
+               "gfcc_solve: the transpose solve is FP64 only");
+  for (int w = 0; w < nw; ++w)
+    GFCC_REQUIRE(std::isfinite(omega[w]), GFCC_EINVAL, "gfcc_solve: non-finite omega");
+  std::vector<char> seen(ctx->op.o, 0);
+  for (int k = 0; k < np; ++k) {
+    GFCC_REQUIRE(p[k] >= 0 && p[k] < ctx->op.o, GFCC_EINVAL,
+                 "gfcc_solve: p must be occupied orbitals 0 <= p < o");
+    GFCC_REQUIRE(!seen[p[k]], GFCC_EINVAL, "gfcc_solve: repeated orbital in p");
+    seen[p[k]] = 1;
+  }
+  return solve_all(ctx, nw, omega, np, p, eta, tol, maxit, restart, block, precision, transpose,
+                   X_out, G_out, iters_out, resid_out);
+  GFCC_API_END(ctx)
+}
+
+gfcc_status gfcc_grad_eps(gfcc_ctx* ctx, int nw, const double* weight, int np, const void* X,
+                          const void* Y, double* grad_out) {
+  if (!ctx) return GFCC_EINVAL;
+  GFCC_API_BEGIN(ctx)
+  using namespace gfcc;
+  GFCC_REQUIRE(ctx->op.built, GFCC_ESTATE, "gfcc_grad_eps: no operator built");
+  GFCC_REQUIRE(nw >= 1 && np >= 1 && weight && X && Y && grad_out, GFCC_EINVAL,
+               "gfcc_grad_eps: bad arguments");
+  const int o = ctx->op.o, v = ctx->op.v;
+  const int64_t D = ctx->op.D;
+  DevBuf bw, bS, bg;
+  bw.alloc(sizeof(double) * nw);
+  bS.alloc(sizeof(double) * D);
+  bg.alloc(sizeof(double) * (o + v));
+  GFCC_HIP(hipMemcpyAsync(bw.p, weight, sizeof(double) * nw, hipMemcpyHostToDevice, ctx->stream));
+  hipLaunchKernelGGL(grad_rows_kernel, dim3(gridn(D)), dim3(256), 0, ctx->stream,
+                     static_cast<const double2*>(X), static_cast<const double2*>(Y), bw.as<double>(),
+                     nw, np, D, bS.as<double>());
+  GFCC_LAUNCH_CHECK();
+  hipLaunchKernelGGL(grad_bins_kernel, dim3(o + v), dim3(256), 0, ctx->stream, bS.as<double>(),
+                     o, v, bg.as<double>());
+  GFCC_LAUNCH_CHECK();
+  GFCC_HIP(hipMemcpyAsync(grad_out, bg.p, sizeof(double) * (o + v), hipMemcpyDeviceToHost,
+                          ctx->stream));
+  GFCC_HIP(hipStreamSynchronize(ctx->stream));
+  GFCC_API_END(ctx)
+}
+
+gfcc_status spectral_function(int nw, int np, const void* G, int is_device, double* A_out) {
+  if (nw < 0 || np < 0 || (nw > 0 && (!G || !A_out))) return GFCC_EINVAL;
+  if (nw == 0) return GFCC_OK;
+  if (!is_device) {
+    const double* g = static_cast<const double*>(G);
+    for (int w = 0; w < nw; ++w) {
+      double s = 0.0;
+      for (int k = 0; k < np; ++k) s += g[2 * (((int64_t)w * np + k) * np + k) + 1];
+      A_out[w] = s / 3.14159265358979323846;
+    }
+    return GFCC_OK;
+  }
+  double* dA = nullptr;
+  if (hipMalloc(&dA, sizeof(double) * nw) != hipSuccess) return GFCC_ENOMEM;
+  hipLaunchKernelGGL(gfcc::spectral_kernel, dim3((nw + 255) / 256), dim3(256), 0, nullptr,
+                     static_cast<const double2*>(G), nw, np, dA);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpy(A_out, dA, sizeof(double) * nw, hipMemcpyDeviceToHost);
+  (void)hipFree(dA);
+  return e == hipSuccess ? GFCC_OK : GFCC_EHIP;
+}
+
+}  // extern "C"

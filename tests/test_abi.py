@@ -1,0 +1,46 @@
+"""The C-ABI library loads and exports every symbol include/gfcc.h declares (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "gfcc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def test_symbols_exported():
+    from paper_1902_06016_amd import gfcc
+    declared = _declared()
+    assert len(declared) >= 16, declared
+    lib = ctypes.CDLL(gfcc.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(gfcc.SYMBOLS) == declared
+
+
+def test_host_only_entry_points():
+    from paper_1902_06016_amd import gfcc
+    assert gfcc.dim(10, 20) == 910
+    assert gfcc.dim(42, 186) == 160188
+    assert gfcc.dim(70, 260) == 627970
+    assert gfcc.lib.gfcc_dim(-1, 3) == -1
+    # spectral_function on a host array
+    G = np.zeros((3, 2, 2), dtype=np.complex128)
+    G[:, 0, 0] = 1j * np.pi
+    G[:, 1, 1] = 2j * np.pi
+    G[:, 0, 1] = 5j
+    assert np.allclose(gfcc.spectral_function(G), 3.0)
+    # bad arguments are rejected without touching a device
+    assert gfcc.lib.spectral_function(-1, 1, None, 0, None) == gfcc.GFCC_EINVAL
+    assert gfcc.lib.gfcc_solve(None, 1, None, 1, None, 0.1, 1e-8, 10, 10, 0, 0, 0, None, None,
+                               None, None) == gfcc.GFCC_EINVAL
+    assert gfcc.lib.mor_eval(None, 1, None, None, None) == gfcc.GFCC_EINVAL
+    assert gfcc.lib.gfcc_destroy(None) == gfcc.GFCC_OK

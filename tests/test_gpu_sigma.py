@@ -1,0 +1,74 @@
+"""GPU parity: operator build and sigma product through the C ABI vs the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import hbar as ohbar
+from oracle import sigma as osig
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(2, 1, 3), (3, 2, 4), (5, 7, 11), (10, 20, 0), (13, 37, 2), (17, 45, 9)]
+
+
+def _cases():
+    return [pytest.param(o, v, s, id=f"o{o}v{v}s{s}") for (o, v, s) in SHAPES]
+
+
+@pytest.mark.parametrize("o,v,seed", _cases())
+def test_hbar_blocks(gpu_ctx, o, v, seed):
+    print(f"[hbar_blocks o={o} v={v} seed={seed}]", flush=True)
+    prob = synth.make_problem(o, v, seed)
+    # stronger T1 than the default so every T1 term matters
+    prob.t1 = synth.normal(seed, 9, o * v, 0.1).reshape(o, v)
+    hb = ohbar.build_hbar_from_problem(prob)
+    gpu_ctx.build_from_problem(prob)
+    for name in ("Foo", "Fov", "Fvv", "Woooo", "Wooov", "Wovvo", "Wovoo"):
+        got = gpu_ctx.export(name).cpu().numpy()
+        ref = getattr(hb, name)
+        err = np.abs(got - ref).max()
+        assert err <= 1e-13 * max(1.0, np.abs(ref).max()), (name, err)
+    diag = gpu_ctx.export("diag").cpu().numpy()
+    assert np.abs(diag - osig.diagonal(hb)).max() <= 1e-12 * np.abs(diag).max()
+
+
+@pytest.mark.parametrize("o,v,seed", _cases())
+@pytest.mark.parametrize("nrhs", [1, 3, 70])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_sigma_fp64(gpu_ctx, o, v, seed, nrhs, transpose):
+    print(f"[sigma o={o} v={v} seed={seed} nrhs={nrhs} T={transpose}]", flush=True)
+    prob = synth.make_problem(o, v, seed)
+    prob.t1 = synth.normal(seed, 9, o * v, 0.1).reshape(o, v)
+    hb = ohbar.build_hbar_from_problem(prob)
+    gpu_ctx.build_from_problem(prob)
+    D = osig.dim(o, v)
+    rng = np.random.default_rng(seed + 100 * nrhs)
+    x = rng.standard_normal((nrhs, D)) + 1j * rng.standard_normal((nrhs, D))
+    y = gpu_ctx.sigma_apply(torch.from_numpy(x).cuda(), transpose=transpose).cpu().numpy()
+    ref = osig.sigma_t(hb, x) if transpose else osig.sigma(hb, x)
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    assert err < 1e-13, err
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 2e-6), (2, 2e-3)])
+def test_sigma_reduced_precision(gpu_ctx, prec, tol):
+    o, v, seed = 13, 37, 2
+    print(f"[sigma_mixed prec={prec}]", flush=True)
+    prob = synth.make_problem(o, v, seed)
+    hb = ohbar.build_hbar_from_problem(prob)
+    from paper_1902_06016_amd import gfcc
+    gpu_ctx.build_from_problem(prob, keep=gfcc.KEEP_FP32)
+    D = osig.dim(o, v)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((5, D)) + 1j * rng.standard_normal((5, D))
+    y = gpu_ctx.sigma_apply(torch.from_numpy(x).cuda(), precision=prec).cpu().numpy()
+    ref = osig.sigma(hb, x)
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    assert err < tol, err
+    if prec == 2:
+        # the bf16 error is confined to the three-body term
+        t9 = osig.sigma_parts(hb, x)["T9"]
+        rest = ref - t9
+        e9 = np.abs(y - rest - t9).max() / np.abs(t9).max()
+        assert e9 < 3e-2, e9

@@ -1,0 +1,98 @@
+"""GPU parity: shifted solves, G and A vs the oracle's dense LU."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import hbar as ohbar
+from oracle import sigma as osig
+from oracle import solve as osolve
+from paper_1902_06016_amd import gfcc
+
+pytestmark = pytest.mark.gpu
+
+
+def _dense_ref(prob, omegas, ps, eta, transpose=False):
+    hb = ohbar.build_hbar_from_problem(prob)
+    H = osolve.dense_hbar(hb)
+    o, v = prob.o, prob.v
+    B = np.stack([osig.b_vector(o, v, p) for p in ps], 1)
+    C = np.stack([osig.c_vector(o, v, prob.t1, prob.t2, prob.l1, prob.l2, q) for q in ps], 0)
+    X = osolve.dense_solve(H, omegas, B, eta)
+    G = osolve.green(C, X)
+    return hb, H, B, C, X, G
+
+
+@pytest.mark.parametrize("block", [0, 7, 640])
+def test_config0_fp64(gpu_ctx, block):
+    cfg = synth.CONFIGS[0]
+    print(f"[solve c0 block={block}]", flush=True)
+    prob = synth.make_problem(cfg["o"], cfg["v"], cfg["seed"])
+    om = synth.omega_grid(cfg["omega"])
+    ps = synth.valence_p(cfg["o"], cfg["np"])
+    _, _, _, _, Xr, Gr = _dense_ref(prob, om, ps, cfg["eta"])
+    gpu_ctx.build_from_problem(prob)
+    res = gpu_ctx.gfcc_solve(om, ps, cfg["eta"], tol=1e-12, restart=30, block=block, want_x=True)
+    G = res.G.cpu().numpy()
+    X = res.X.cpu().numpy()
+    assert res.resid.max() <= 1e-12
+    A = gfcc.spectral_function(res.G)
+    Ar = osolve.spectral(Gr)
+    assert np.abs(A - Ar).max() / np.abs(Ar).max() < 1e-10
+    assert np.abs(G - Gr).max() / np.abs(Gr).max() < 1e-10
+    assert np.abs(X - Xr).max() / np.abs(Xr).max() < 1e-9
+
+
+def test_near_poles_and_transpose(gpu_ctx):
+    """Frequencies across the lowest poles (harder systems) and the adjoint systems."""
+    o, v, seed = 6, 10, 4
+    prob = synth.make_problem(o, v, seed)
+    hb = ohbar.build_hbar_from_problem(prob)
+    H = osolve.dense_hbar(hb)
+    lam = np.sort(np.linalg.eigvals(H).real)
+    om = np.linspace(-lam[0] - 0.05, -lam[0] + 0.05, 9)
+    ps = np.arange(o)
+    eta = 0.005
+    _, _, B, C, Xr, Gr = _dense_ref(prob, om, ps, eta)
+    gpu_ctx.build_from_problem(prob)
+    fwd = gpu_ctx.gfcc_solve(om, ps, eta, tol=1e-12, restart=25, maxit=2000, want_x=True)
+    assert np.abs(fwd.G.cpu().numpy() - Gr).max() / np.abs(Gr).max() < 1e-9
+    adj = gpu_ctx.gfcc_solve(om, ps, eta, tol=1e-12, restart=25, maxit=2000, transpose=True,
+                             want_x=True)
+    Yr = np.stack([np.linalg.solve(osolve.shifted(H, w, eta).T, C.T.astype(complex)).T for w in om])
+    assert np.abs(adj.X.cpu().numpy() - Yr).max() / np.abs(Yr).max() < 1e-9
+    # G from the adjoint systems equals G from the forward ones
+    assert np.abs(adj.G.cpu().numpy() - Gr).max() / np.abs(Gr).max() < 1e-9
+
+
+def test_errors(gpu_ctx):
+    prob = synth.make_problem(4, 3, 1)
+    gpu_ctx.build_from_problem(prob)
+    with pytest.raises(gfcc.GfccError) as e:
+        gpu_ctx.gfcc_solve([-0.5], [4], 0.01)  # virtual p
+    assert e.value.status == gfcc.GFCC_EINVAL
+    with pytest.raises(gfcc.GfccError) as e:
+        gpu_ctx.gfcc_solve([-0.5], [1, 1], 0.01)  # repeated p
+    assert e.value.status == gfcc.GFCC_EINVAL
+    with pytest.raises(gfcc.GfccError) as e:
+        gpu_ctx.gfcc_solve([-0.5], [1], 0.0)  # eta = 0
+    assert e.value.status == gfcc.GFCC_EINVAL
+    r = gpu_ctx.gfcc_solve([-0.5, -0.4], [0, 1], 0.01, tol=1e-14, maxit=1, allow_noconv=True)
+    assert r.status == gfcc.GFCC_ENOCONV and r.iters.max() == 1
+    with pytest.raises(ValueError):
+        gpu_ctx.sigma_apply(torch.zeros((1, 5), dtype=torch.complex128, device="cuda"))
+    fresh = gfcc.Context(0)
+    with pytest.raises(gfcc.GfccError) as e:
+        fresh.D = gpu_ctx.D
+        fresh.sigma_apply(torch.zeros((1, gpu_ctx.D), dtype=torch.complex128, device="cuda"))
+    assert e.value.status == gfcc.GFCC_ESTATE
+    fresh.close()
+    # non-finite operator input
+    T = torch
+    bad = [T.from_numpy(np.ascontiguousarray(a)).cuda() for a in
+           (prob.eps, prob.t1, prob.t2, prob.l1, prob.l2, prob.block("oooo"), prob.block("ooov"),
+            prob.block("oovv"), prob.block("ovvo"), prob.block("ovvv"))]
+    bad[8][0, 0, 0, 0] = float("nan")
+    with pytest.raises(gfcc.GfccError) as e:
+        gpu_ctx.build_hbar_operands(4, 3, *bad)
+    assert e.value.status == gfcc.GFCC_EINVAL
