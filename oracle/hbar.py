@@ -16,7 +16,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-es = np.einsum
+def es(*args):
+    return np.einsum(*args, optimize=True)
 
 
 @dataclass

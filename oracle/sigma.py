@@ -20,7 +20,8 @@ from __future__ import annotations
 
 import numpy as np
 
-es = np.einsum
+def es(*args):
+    return np.einsum(*args, optimize=True)
 
 
 def dim(o: int, v: int) -> int:

@@ -12,8 +12,11 @@
 // Projection. Hhat = S^T H-bar_N S, bhat = S^T b_p, chat = c_q^T S.
 // Residual. With F = H-bar_N S - S Hhat (the part of H-bar_N S outside span S) and
 // ((omega - i eta) I + Hhat) xhat = bhat, the full-space residual is
-//   b - (omega - i eta) S xhat - H-bar_N S xhat = (I - S S^T) b - F xhat,
-// so ||r||^2 = ||b||^2 - ||bhat||^2 - 2 Re(f_p^T xhat) + xhat^H (F^T F) xhat, f_p = F^T b_p.
+//   b - (omega - i eta) S xhat - H-bar_N S xhat = (I - S S^T) b - F xhat.
+// With F = Q R (Q orthonormal, orthogonal to S) this splits into orthogonal pieces,
+//   ||r||^2 = ||(I - S S^T - Q Q^T) b||^2 + ||Q^T b - R xhat||^2,
+// a sum of squares: the first term is formed once from an explicit vector, the second is a
+// short vector per frequency, so neither cancels as the residual becomes small.
 // Evaluation. One workgroup per frequency: complex LU with partial pivoting of
 // (omega - i eta) I + Hhat, solves for every orbital, Ghat = chat^T xhat and the residual.
 #include <algorithm>
@@ -35,7 +38,9 @@ struct gfcc_mor {
   double eta = 0.0, solve_tol = 1e-10, defl_tol = 1e-10;
   int64_t D = 0;
   int m = 0, mcap = 0;
-  gfcc::DevBuf St, HSt, Ft, Hhat, Gff, bhat, fvec, chat, bperp2, prows;
+  gfcc::DevBuf St, HSt, Hhat, bhat, chat, prows;
+  gfcc::DevBuf Qt, Rm, beta, cnst;  // QR of F = H S - S Hhat, Q^T b_p, ||(I - SS^T - QQ^T) b_p||^2
+  int r = 0;                        // rank of F
   std::vector<double> omega_k;
   int solve_maxit = 2000, solve_restart = 30;
 };
@@ -94,12 +99,20 @@ __global__ void gather_cols_kernel(const double* __restrict__ Rows, int m, int64
   out[idx] = Rows[(int64_t)i * D + p[k]];
 }
 
-__global__ void bperp_kernel(const double* __restrict__ bhat, int m, int np, double* __restrict__ out) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= np) return;
-  double s = 0.0;
-  for (int i = 0; i < m; ++i) s += bhat[(int64_t)k * m + i] * bhat[(int64_t)k * m + i];
-  out[k] = 1.0 - s;
+// R0[k][d] = (d == p_k)
+__global__ void unit_rows_kernel(const int* __restrict__ p, int np, int64_t D, double* __restrict__ R0) {
+  const int64_t n = (int64_t)np * D;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int k = (int)(idx / D);
+    int64_t d = idx - (int64_t)k * D;
+    R0[idx] = (d == p[k]) ? 1.0 : 0.0;
+  }
+}
+
+__global__ void square_kernel(double* __restrict__ a, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = a[i] * a[i];
 }
 
 __device__ __forceinline__ double2 cm(double2 a, double2 b) {
@@ -115,8 +128,8 @@ __device__ __forceinline__ double2 cdv(double2 a, double2 b) {
 // One workgroup per frequency. Work space per frequency: A (m x m complex) and Xs (np x m).
 __global__ __launch_bounds__(256) void rom_solve_kernel(
     const double* __restrict__ Hhat, const double* __restrict__ bhat,
-    const double* __restrict__ chat, const double* __restrict__ Gff,
-    const double* __restrict__ fvec, const double* __restrict__ bperp2,
+    const double* __restrict__ chat, const double* __restrict__ Rm,
+    const double* __restrict__ beta, const double* __restrict__ cnst, int rk,
     const double* __restrict__ omega, double eta, int m, int np, int w0, int nw,
     double2* __restrict__ work, double2* __restrict__ G, double* __restrict__ resid) {
   const int wl = blockIdx.x;
@@ -237,21 +250,21 @@ __global__ __launch_bounds__(256) void rom_solve_kernel(
     }
     G[((int64_t)w * np + q) * np + pk] = acc;
   }
-  // residual: max_p sqrt(bperp2 - 2 Re(f_p . x) + x^H Gff x)
+  // residual: max_p sqrt(cnst_p + ||beta_p - R xhat_p||^2)
   if (t == 0) rmax = 0.0;
   __syncthreads();
   for (int pk = 0; pk < np; ++pk) {
     double acc = 0.0;
     const double2* x = Xs + (int64_t)pk * m;
-    for (int i = t; i < m; i += nt) {
-      double2 gx = make_double2(0.0, 0.0);
+    for (int i = t; i < rk; i += nt) {
+      double2 rx = make_double2(0.0, 0.0);
+      const double* Ri = Rm + (int64_t)i * m;
       for (int j = 0; j < m; ++j) {
-        double g = Gff[(int64_t)i * m + j];
-        gx.x += g * x[j].x;
-        gx.y += g * x[j].y;
+        rx.x += Ri[j] * x[j].x;
+        rx.y += Ri[j] * x[j].y;
       }
-      acc += x[i].x * gx.x + x[i].y * gx.y;  // Re(conj(x_i) gx)
-      acc -= 2.0 * fvec[(int64_t)pk * m + i] * x[i].x;
+      double dr = beta[(int64_t)pk * (rk > 0 ? rk : 1) + i] - rx.x, di = -rx.y;
+      acc += dr * dr + di * di;
     }
     red_v[t] = acc;
     __syncthreads();
@@ -259,17 +272,80 @@ __global__ __launch_bounds__(256) void rom_solve_kernel(
       if (t < s) red_v[t] += red_v[t + s];
       __syncthreads();
     }
-    if (t == 0) {
-      double r2 = bperp2[pk] + red_v[0];
-      double r = sqrt(r2 > 0.0 ? r2 : 0.0);
-      rmax = fmax(rmax, r);
-    }
+    if (t == 0) rmax = fmax(rmax, sqrt(cnst[pk] + red_v[0]));
     __syncthreads();
   }
   if (t == 0 && resid) resid[w] = rmax;
 }
 
 }  // namespace
+
+// Orthogonalise the rows W[0..n) ([n][D], overwritten) against the fixed orthonormal rows
+// B[0..nb) by two block passes of classical Gram-Schmidt, then one by one (two passes each,
+// every pass against B and against the rows accepted so far, which are written to Out).
+// Projecting each pass on B as well keeps accepted rows orthogonal to B even when a row's
+// remainder is many orders of magnitude below its original norm. Row j is accepted when its
+// norm after orthogonalisation exceeds thresh[j]. If coef is given ([ldc] per row j), it
+// receives the coefficients of row j along the accepted Out rows (the norm for its own row).
+// Returns the number of accepted rows.
+static int orth_rows(gfcc_ctx* ctx, int64_t D, const double* B, int nb, double* W, int n,
+                     double* Out, const std::vector<double>& thresh, std::vector<double>* coef,
+                     int ldc) {
+  hipStream_t st = ctx->stream;
+  DevBuf bhb;
+  if (nb > 0) {
+    DevBuf bh;
+    bh.alloc(sizeof(double) * (size_t)nb * n);
+    for (int pass = 0; pass < 2; ++pass) {
+      gemm<double>(ctx, false, true, nb, n, (int)D, 1.0, B, D, W, D, 0.0, bh.as<double>(), n);
+      gemm<double>(ctx, true, false, n, (int)D, nb, -1.0, bh.as<double>(), n, B, D, 1.0, W, D);
+    }
+    GFCC_HIP(hipStreamSynchronize(st));
+    bhb.alloc(sizeof(double) * (size_t)nb);
+  }
+  int acc = 0;
+  DevBuf bh, bn;
+  bh.alloc(sizeof(double) * (size_t)(n + 1));
+  bn.alloc(sizeof(double));
+  std::vector<double> h(n + 1), hsum(n + 1);
+  double nrm = 0.0;
+  if (coef) coef->assign((size_t)n * ldc, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double* wj = W + (int64_t)j * D;
+    std::fill(hsum.begin(), hsum.end(), 0.0);
+    for (int pass = 0; pass < 2; ++pass) {
+      if (nb > 0) {
+        gemm<double>(ctx, false, false, nb, 1, (int)D, 1.0, B, D, wj, 1, 0.0, bhb.as<double>(), 1);
+        gemm<double>(ctx, false, false, 1, (int)D, nb, -1.0, bhb.as<double>(), nb, B, D, 1.0, wj, D);
+      }
+      if (acc > 0) {
+        gemm<double>(ctx, false, false, acc, 1, (int)D, 1.0, Out, D, wj, 1, 0.0, bh.as<double>(), 1);
+        gemm<double>(ctx, false, false, 1, (int)D, acc, -1.0, bh.as<double>(), acc, Out, D, 1.0,
+                     wj, D);
+        if (coef) {
+          GFCC_HIP(hipMemcpyAsync(h.data(), bh.p, sizeof(double) * acc, hipMemcpyDeviceToHost, st));
+          GFCC_HIP(hipStreamSynchronize(st));
+          for (int i = 0; i < acc; ++i) hsum[i] += h[i];
+        }
+      }
+    }
+    hipLaunchKernelGGL(rownorm_kernel, dim3(1), dim3(256), 0, st, wj, D, bn.as<double>());
+    GFCC_LAUNCH_CHECK();
+    GFCC_HIP(hipMemcpyAsync(&nrm, bn.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    GFCC_HIP(hipStreamSynchronize(st));
+    if (coef)
+      for (int i = 0; i < acc; ++i) (*coef)[(size_t)j * ldc + i] = hsum[i];
+    if (nrm > 0.0 && nrm > thresh[j]) {
+      hipLaunchKernelGGL(scale_row_kernel, dim3(gridn(D)), dim3(256), 0, st, wj, D, 1.0 / nrm,
+                         Out + (int64_t)acc * D);
+      GFCC_LAUNCH_CHECK();
+      if (coef) (*coef)[(size_t)j * ldc + acc] = nrm;
+      ++acc;
+    }
+  }
+  GFCC_HIP(hipStreamSynchronize(st));
+  return acc;
+}
 
 // Append the real and imaginary parts of the solutions at omega_new to the basis.
 static void mor_extend(gfcc_mor* M, const std::vector<double>& omega_new) {
@@ -299,14 +375,6 @@ static void mor_extend(gfcc_mor* M, const std::vector<double>& omega_new) {
   GFCC_LAUNCH_CHECK();
   GFCC_HIP(hipStreamSynchronize(st));
   bX.release();
-  // original norms (rows of W^T)
-  transpose2d(ctx, W, D, nn, Wt);
-  DevBuf bn;
-  bn.alloc(sizeof(double) * nn);
-  hipLaunchKernelGGL(rownorm_kernel, dim3(nn), dim3(256), 0, st, Wt, D, bn.as<double>());
-  GFCC_LAUNCH_CHECK();
-  std::vector<double> n0(nn), n1(1);
-  GFCC_HIP(hipMemcpyAsync(n0.data(), bn.p, sizeof(double) * nn, hipMemcpyDeviceToHost, st));
   const int m_old = M->m;
   // capacity
   if (m_old + nn > M->mcap) {
@@ -326,44 +394,19 @@ static void mor_extend(gfcc_mor* M, const std::vector<double>& omega_new) {
     M->mcap = cap;
   }
   double* St = M->St.as<double>();
-  // two block passes against the existing basis
-  if (m_old > 0) {
-    DevBuf bh;
-    bh.alloc(sizeof(double) * (size_t)m_old * nn);
-    for (int pass = 0; pass < 2; ++pass) {
-      gemm<double>(ctx, false, false, m_old, nn, (int)D, 1.0, St, D, W, nn, 0.0, bh.as<double>(), nn);
-      gemm<double>(ctx, true, false, (int)D, nn, m_old, -1.0, St, D, bh.as<double>(), nn, 1.0, W, nn);
-    }
-    GFCC_HIP(hipStreamSynchronize(st));
-    transpose2d(ctx, W, D, nn, Wt);
-  }
+  transpose2d(ctx, W, D, nn, Wt);
+  std::vector<double> n0(nn);
+  DevBuf bn;
+  bn.alloc(sizeof(double) * nn);
+  hipLaunchKernelGGL(rownorm_kernel, dim3(nn), dim3(256), 0, st, Wt, D, bn.as<double>());
+  GFCC_LAUNCH_CHECK();
+  GFCC_HIP(hipMemcpyAsync(n0.data(), bn.p, sizeof(double) * nn, hipMemcpyDeviceToHost, st));
   GFCC_HIP(hipStreamSynchronize(st));
-  // one by one against this round's accepted columns
-  int m_cur = m_old;
-  DevBuf bh;
-  bh.alloc(sizeof(double) * (size_t)(nn + 1));
-  for (int j = 0; j < nn; ++j) {
-    double* wj = Wt + (int64_t)j * D;
-    const int acc = m_cur - m_old;
-    if (acc > 0) {
-      for (int pass = 0; pass < 2; ++pass) {
-        gemm<double>(ctx, false, false, acc, 1, (int)D, 1.0, St + (int64_t)m_old * D, D, wj, 1, 0.0,
-                     bh.as<double>(), 1);
-        gemm<double>(ctx, false, false, 1, (int)D, acc, -1.0, bh.as<double>(), acc,
-                     St + (int64_t)m_old * D, D, 1.0, wj, D);
-      }
-    }
-    hipLaunchKernelGGL(rownorm_kernel, dim3(1), dim3(256), 0, st, wj, D, bn.as<double>());
-    GFCC_LAUNCH_CHECK();
-    GFCC_HIP(hipMemcpyAsync(n1.data(), bn.p, sizeof(double), hipMemcpyDeviceToHost, st));
-    GFCC_HIP(hipStreamSynchronize(st));
-    if (n0[j] > 0.0 && n1[0] > M->defl_tol * n0[j]) {
-      hipLaunchKernelGGL(scale_row_kernel, dim3(gridn(D)), dim3(256), 0, st, wj, D, 1.0 / n1[0],
-                         St + (int64_t)m_cur * D);
-      GFCC_LAUNCH_CHECK();
-      ++m_cur;
-    }
-  }
+  std::vector<double> thresh(nn);
+  for (int j = 0; j < nn; ++j) thresh[j] = M->defl_tol * n0[j];
+  const int nacc_rows = orth_rows(ctx, D, St, m_old, Wt, nn, St + (int64_t)m_old * D, thresh,
+                                  nullptr, 0);
+  const int m_cur = m_old + nacc_rows;
   const int nacc = m_cur - m_old;
   if (nacc > 0) {
     // H-bar_N applied to the accepted columns (D-major block through sigma)
@@ -380,7 +423,7 @@ static void mor_extend(gfcc_mor* M, const std::vector<double>& omega_new) {
   GFCC_HIP(hipStreamSynchronize(st));
 }
 
-// Hhat, F, Gff, bhat, f, chat, ||b_perp||^2 for the current basis.
+// Hhat, bhat, chat and the residual factors (Q, R, Q^T b, constant term) for the current basis.
 static void mor_project(gfcc_mor* M) {
   gfcc_ctx* ctx = M->ctx;
   hipStream_t st = ctx->stream;
@@ -390,28 +433,63 @@ static void mor_project(gfcc_mor* M) {
   const double* St = M->St.as<double>();
   const double* HSt = M->HSt.as<double>();
   M->Hhat.alloc(sizeof(double) * (size_t)m * m);
-  M->Gff.alloc(sizeof(double) * (size_t)m * m);
-  M->Ft.alloc(sizeof(double) * (size_t)m * D);
   M->bhat.alloc(sizeof(double) * (size_t)np * m);
-  M->fvec.alloc(sizeof(double) * (size_t)np * m);
   M->chat.alloc(sizeof(double) * (size_t)np * m);
-  M->bperp2.alloc(sizeof(double) * (size_t)np);
   // Hhat[i][j] = S_i . (H S)_j
   gemm<double>(ctx, false, true, m, m, (int)D, 1.0, St, D, HSt, D, 0.0, M->Hhat.as<double>(), m);
-  // Ft = HSt - Hhat^T St
-  GFCC_HIP(hipMemcpyAsync(M->Ft.p, HSt, sizeof(double) * (size_t)m * D, hipMemcpyDeviceToDevice, st));
-  gemm<double>(ctx, true, false, m, (int)D, m, -1.0, M->Hhat.as<double>(), m, St, D, 1.0,
-               M->Ft.as<double>(), D);
-  gemm<double>(ctx, false, true, m, m, (int)D, 1.0, M->Ft.as<double>(), D, M->Ft.as<double>(), D,
-               0.0, M->Gff.as<double>(), m);
+  // F rows: Ft = HSt - Hhat^T St
+  DevBuf bF, bnrm;
+  bF.alloc(sizeof(double) * (size_t)m * D);
+  double* Ft = bF.as<double>();
+  GFCC_HIP(hipMemcpyAsync(Ft, HSt, sizeof(double) * (size_t)m * D, hipMemcpyDeviceToDevice, st));
+  gemm<double>(ctx, true, false, m, (int)D, m, -1.0, M->Hhat.as<double>(), m, St, D, 1.0, Ft, D);
+  // F = Q R: a row of F whose part outside span{S, earlier Q} is below
+  // max(1e-10 ||F_j||, 1e-13 ||(H S)_j||) is rounding-level and adds no direction (its R
+  // column has no diagonal entry)
+  bnrm.alloc(sizeof(double) * 2 * m);
+  hipLaunchKernelGGL(rownorm_kernel, dim3(m), dim3(256), 0, st, HSt, D, bnrm.as<double>());
+  GFCC_LAUNCH_CHECK();
+  hipLaunchKernelGGL(rownorm_kernel, dim3(m), dim3(256), 0, st, Ft, D, bnrm.as<double>() + m);
+  GFCC_LAUNCH_CHECK();
+  std::vector<double> hsn(2 * m), thresh(m);
+  GFCC_HIP(hipMemcpyAsync(hsn.data(), bnrm.p, sizeof(double) * 2 * m, hipMemcpyDeviceToHost, st));
+  GFCC_HIP(hipStreamSynchronize(st));
+  for (int j = 0; j < m; ++j) thresh[j] = std::max(1e-10 * hsn[m + j], 1e-13 * hsn[j]);
+  M->Qt.alloc(sizeof(double) * (size_t)m * D);
+  std::vector<double> coef;
+  const int r = orth_rows(ctx, D, St, m, Ft, m, M->Qt.as<double>(), thresh, &coef, m);
+  M->r = r;
+  // R[i][j] = coefficient of F_j along Q_i
+  std::vector<double> R((size_t)std::max(r, 1) * m, 0.0);
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < r; ++i) R[(size_t)i * m + j] = coef[(size_t)j * m + i];
+  M->Rm.alloc(sizeof(double) * R.size());
+  GFCC_HIP(hipMemcpyAsync(M->Rm.p, R.data(), sizeof(double) * R.size(), hipMemcpyHostToDevice, st));
+  // bhat[k][i] = S_i[p_k], beta[k][i] = Q_i[p_k]
   hipLaunchKernelGGL(gather_cols_kernel, dim3(blocks_for((int64_t)m * np, 256)), dim3(256), 0, st,
                      St, m, D, M->prows.as<int>(), np, M->bhat.as<double>());
   GFCC_LAUNCH_CHECK();
-  hipLaunchKernelGGL(gather_cols_kernel, dim3(blocks_for((int64_t)m * np, 256)), dim3(256), 0, st,
-                     M->Ft.as<double>(), m, D, M->prows.as<int>(), np, M->fvec.as<double>());
+  M->beta.alloc(sizeof(double) * (size_t)np * std::max(r, 1));
+  if (r > 0) {
+    hipLaunchKernelGGL(gather_cols_kernel, dim3(blocks_for((int64_t)r * np, 256)), dim3(256), 0,
+                       st, M->Qt.as<double>(), r, D, M->prows.as<int>(), np, M->beta.as<double>());
+    GFCC_LAUNCH_CHECK();
+  }
+  // constant term: || e_p - S bhat_p - Q beta_p ||^2, from the explicit vector
+  DevBuf bR0;
+  bR0.alloc(sizeof(double) * (size_t)np * D);
+  double* R0 = bR0.as<double>();
+  hipLaunchKernelGGL(unit_rows_kernel, dim3(gridn((int64_t)np * D)), dim3(256), 0, st,
+                     M->prows.as<int>(), np, D, R0);
   GFCC_LAUNCH_CHECK();
-  hipLaunchKernelGGL(bperp_kernel, dim3(1), dim3(256), 0, st, M->bhat.as<double>(), m, np,
-                     M->bperp2.as<double>());
+  gemm<double>(ctx, false, false, np, (int)D, m, -1.0, M->bhat.as<double>(), m, St, D, 1.0, R0, D);
+  if (r > 0)
+    gemm<double>(ctx, false, false, np, (int)D, r, -1.0, M->beta.as<double>(), r,
+                 M->Qt.as<double>(), D, 1.0, R0, D);
+  M->cnst.alloc(sizeof(double) * np);
+  hipLaunchKernelGGL(rownorm_kernel, dim3(np), dim3(256), 0, st, R0, D, M->cnst.as<double>());
+  GFCC_LAUNCH_CHECK();
+  hipLaunchKernelGGL(square_kernel, dim3(1), dim3(256), 0, st, M->cnst.as<double>(), np);
   GFCC_LAUNCH_CHECK();
   // chat[k][i] = c_{p_k} . S_i
   DevBuf bC;
@@ -440,8 +518,8 @@ static void mor_eval_impl(gfcc_mor* M, int nw, const double* omega, double2* G, 
   for (int w0 = 0; w0 < nw; w0 += chunk) {
     int cnt = std::min(chunk, nw - w0);
     hipLaunchKernelGGL(rom_solve_kernel, dim3(cnt), dim3(256), 0, st, M->Hhat.as<double>(),
-                       M->bhat.as<double>(), M->chat.as<double>(), M->Gff.as<double>(),
-                       M->fvec.as<double>(), M->bperp2.as<double>(), bom.as<double>(), M->eta, m,
+                       M->bhat.as<double>(), M->chat.as<double>(), M->Rm.as<double>(),
+                       M->beta.as<double>(), M->cnst.as<double>(), M->r, bom.as<double>(), M->eta, m,
                        np, w0, nw, bw.as<double2>(), G, bres.as<double>());
     GFCC_LAUNCH_CHECK();
   }

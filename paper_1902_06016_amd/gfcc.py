@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -111,6 +112,7 @@ class Context:
                     ctx=None)
         self.h = h
         self.o = self.v = self.D = None
+        self._models = weakref.WeakSet()
 
     def _check(self, st, ctx="self", allow=()):
         if st != GFCC_OK and st not in allow:
@@ -119,11 +121,18 @@ class Context:
         return st
 
     def close(self):
+        """Free the context; models built on it are freed first (they point into it)."""
         if getattr(self, "h", None) is not None and self.h.value:
+            for m in list(getattr(self, "_models", ())):
+                m.close()
             lib.gfcc_destroy(self.h)
             self.h = ctypes.c_void_p()
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def __enter__(self):
         return self
@@ -213,7 +222,9 @@ class Context:
         h = ctypes.c_void_p()
         self._check(lib.mor_build(self.h, len(om), om_p, len(pp), p_p, eta, solve_tol, defl_tol,
                                   ctypes.byref(h)))
-        return MorModel(self, h, len(pp))
+        model = MorModel(self, h, len(pp))
+        self._models.add(model)
+        return model
 
 
 class MorModel:
@@ -254,7 +265,11 @@ class MorModel:
             lib.mor_destroy(self.h)
             self.h = ctypes.c_void_p()
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def spectral_function(G) -> np.ndarray:

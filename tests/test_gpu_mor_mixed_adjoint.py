@@ -1,0 +1,126 @@
+"""GPU parity: reduced-order model, mixed-precision refinement and the adjoint gradient."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import adjoint as oadj
+from oracle import hbar as ohbar
+from oracle import mor as omor
+from oracle import sigma as osig
+from oracle import solve as osolve
+from paper_1902_06016_amd import gfcc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def model():
+    o, v = 6, 10
+    p = synth.make_problem(o, v, 31)
+    hb = ohbar.build_hbar_from_problem(p)
+    H = osolve.dense_hbar(hb)
+    lam = np.sort(np.linalg.eigvals(H).real)
+    ps = np.array([o - 2, o - 1])
+    B = np.stack([osig.b_vector(o, v, q) for q in ps], 1)
+    C = np.stack([osig.c_vector(o, v, p.t1, p.t2, p.l1, p.l2, q) for q in ps], 0)
+    return p, hb, H, lam, ps, B, C
+
+
+def test_mor_matches_oracle_model(gpu_ctx, model):
+    print("[mor_vs_oracle]", flush=True)
+    p, hb, H, lam, ps, B, C = model
+    eta = 0.01
+    wk = np.linspace(-lam[0] - 0.3, -lam[0] + 0.3, 3)
+    gpu_ctx.build_from_problem(p)
+    m = gpu_ctx.mor_build(wk, ps, eta, solve_tol=1e-13, defl_tol=1e-10)
+    rom = omor.ROM(hb, ps, eta, C, omor.dense_solver(H, B, eta))
+    rom.extend(wk, 1e-10)
+    order, oks = m.info()
+    assert order == rom.m and np.allclose(oks, wk)
+    grid = np.linspace(-lam[0] - 0.5, -lam[0] + 0.5, 41)
+    Gg, rg = m.eval(grid)
+    Go, ro = rom.eval(grid)
+    Gg = Gg.cpu().numpy()
+    assert np.abs(Gg - Go).max() < 1e-9 * np.abs(Go).max()
+    assert np.abs(rg - ro).max() < 1e-7
+    # interpolation at the sampled frequencies (Eq. model and the text after it)
+    Gk, rk = m.eval(wk)
+    Gfull = osolve.green(C, osolve.dense_solve(H, wk, B, eta))
+    assert np.abs(Gk.cpu().numpy() - Gfull).max() < 1e-10 * np.abs(Gfull).max()
+    assert rk.max() < 1e-9
+    m.close()
+
+
+def test_mor_refinement(gpu_ctx, model):
+    print("[mor_refine]", flush=True)
+    p, hb, H, lam, ps, B, C = model
+    eta = 0.01
+    lo, hi = -lam[0] - 0.4, -lam[0] + 0.2
+    gpu_ctx.build_from_problem(p)
+    m = gpu_ctx.mor_build(np.linspace(lo, hi, 3), ps, eta, solve_tol=1e-12)
+    grid = np.linspace(lo - 0.1, hi + 0.1, 161)
+    rounds, rmax = m.refine(grid, lo, hi, per_round=2, resid_tol=1e-6)
+    assert rmax <= 1e-6 and rounds >= 1
+    win = grid[(grid >= lo) & (grid <= hi)]
+    Gh, res = m.eval(win)
+    assert res.max() <= 1e-6
+    G = osolve.green(C, osolve.dense_solve(H, win, B, eta))
+    assert np.abs(Gh.cpu().numpy() - G).max() < 1e-4 * np.abs(G).max()
+    m.close()
+
+
+@pytest.mark.parametrize("prec", [gfcc.FP32, gfcc.FP32_BF16_3BODY])
+def test_mixed_precision_solve(gpu_ctx, prec):
+    print(f"[mixed prec={prec}]", flush=True)
+    cfg = synth.CONFIGS[0]
+    p = synth.make_problem(cfg["o"], cfg["v"], cfg["seed"])
+    hb = ohbar.build_hbar_from_problem(p)
+    H = osolve.dense_hbar(hb)
+    om = synth.omega_grid(cfg["omega"])
+    ps = synth.valence_p(cfg["o"], cfg["np"])
+    B = np.stack([osig.b_vector(p.o, p.v, q) for q in ps], 1)
+    C = np.stack([osig.c_vector(p.o, p.v, p.t1, p.t2, p.l1, p.l2, q) for q in ps], 0)
+    Ar = osolve.spectral(osolve.green(C, osolve.dense_solve(H, om, B, cfg["eta"])))
+    gpu_ctx.build_from_problem(p, keep=gfcc.KEEP_FP32)
+    res = gpu_ctx.gfcc_solve(om, ps, cfg["eta"], tol=1e-8, precision=prec)
+    assert res.resid.max() <= 1e-8
+    A = gfcc.spectral_function(res.G)
+    assert np.abs(A - Ar).max() / np.abs(Ar).max() < 1e-6
+
+
+def test_adjoint_gradient(gpu_ctx, model):
+    print("[adjoint]", flush=True)
+    p, hb, H, lam, ps, B, C = model
+    o, v = p.o, p.v
+    eta = 0.02
+    om = np.linspace(-lam[0] - 0.2, -lam[0] + 0.2, 9)
+    w = oadj.trapezoid_weights(om)
+    gref = oadj.gradient_dense(H, om, w, B, C, eta, o, v)
+    gpu_ctx.build_from_problem(p)
+    fwd = gpu_ctx.gfcc_solve(om, ps, eta, tol=1e-13, want_x=True)
+    adj = gpu_ctx.gfcc_solve(om, ps, eta, tol=1e-13, transpose=True, want_x=True)
+    g = gpu_ctx.gfcc_grad_eps(w, fwd.X, adj.X)
+    assert np.abs(g - gref).max() < 1e-9 * np.abs(gref).max()
+    # the same through torch.autograd
+    from paper_1902_06016_amd.autograd import SpectralWeight
+    dev = gpu_ctx.device
+    up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    inputs = dict(t1=up(p.t1), t2=up(p.t2), l1=up(p.l1), l2=up(p.l2), oooo=up(p.block("oooo")),
+                  ooov=up(p.block("ooov")), oovv=up(p.block("oovv")), ovvo=up(p.block("ovvo")),
+                  ovvv=up(p.block("ovvv")))
+    eps = up(p.eps).requires_grad_(True)
+    J = SpectralWeight.apply(eps, gpu_ctx, inputs, om, w, ps, eta, 1e-13)
+    J.backward()
+    assert abs(J.item() - oadj.objective_dense(H, om, w, B, C, eta)) < 1e-10 * abs(J.item())
+    assert np.abs(eps.grad.cpu().numpy() - gref).max() < 1e-9 * np.abs(gref).max()
+    # central finite differences through the GPU path
+    h = 1e-5
+    for r in (o - 1, o + 3):
+        Js = []
+        for s in (1, -1):
+            e2 = p.eps.copy()
+            e2[r] += s * h
+            Js.append(SpectralWeight.apply(up(e2), gpu_ctx, inputs, om, w, ps, eta, 1e-13).item())
+        fd = (Js[0] - Js[1]) / (2 * h)
+        assert abs(fd - gref[r]) < 1e-6 * max(1.0, abs(fd)), (r, fd, gref[r])
