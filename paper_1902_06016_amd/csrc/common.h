@@ -160,6 +160,11 @@ template <typename T>
 void gemm_ovvo(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, const T* X2,
                int64_t ldx, const int* pairlut, T* Z);
 
+// Specialised kernel for the same product (ovvo.hip); false if the shape is unsupported.
+template <typename T>
+bool ovvo_fast(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, const T* X2,
+               int64_t ldx, T* Z);
+
 // bf16 x bf16 -> fp32 GEMM (three-body term of the mixed-precision sigma).
 void gemm_bf16(gfcc_ctx* ctx, bool transA, int M, int N, int K, float alpha,
                const __hip_bfloat16* A, int64_t lda, const __hip_bfloat16* B, int64_t ldb,
