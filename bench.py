@@ -73,6 +73,117 @@ def cpu_baseline(prob, cfg, omega, ps, gpu_G, n_p_sample):
     }, float(np.max(errs))
 
 
+def form_mor(ctx, prob, cfg, gfcc):
+    """Reduced-order model on the same operator: sample 8 frequencies of the window, refine
+    by midpoints (8 per round) until the max residual on the grid is <= 1e-6, evaluate 4000
+    points on [-0.9, -0.1] Ha, compare with full solves at 200 check points."""
+    import torch
+    ps = np.arange(prob.o - cfg["np"], prob.o, dtype=np.int32)
+    lo, hi = cfg["sample_window"]
+    grid = np.linspace(*cfg["omega"])
+    check = np.linspace(*cfg["check"])
+    torch.cuda.synchronize()
+    t0 = time.time()
+    model = ctx.mor_build(np.linspace(lo, hi, cfg["per_round"]), ps, cfg["eta"], solve_tol=cfg["tol"])
+    rounds, rmax = model.refine(grid, lo, hi, per_round=cfg["per_round"], resid_tol=cfg["resid_tol"])
+    t1 = time.time()
+    G, res = model.eval(grid)
+    A = gfcc.spectral_function(G)
+    torch.cuda.synchronize()
+    t2 = time.time()
+    m, oks = model.info()
+    Gc, _ = model.eval(check)
+    Ac = gfcc.spectral_function(Gc)
+    full = ctx.gfcc_solve(check, ps, cfg["eta"], tol=1e-12, restart=30)
+    Af = gfcc.spectral_function(full.G)
+    inside = (check >= lo) & (check <= hi)
+    err = np.abs(Ac - Af) / np.abs(Af).max()
+    model.close()
+    return {
+        "points": len(grid), "points_per_s_end_to_end": len(grid) / (t2 - t0),
+        "points_per_s_eval_only": len(grid) / (t2 - t1), "build_refine_s": t1 - t0,
+        "eval_s": t2 - t1, "rounds": rounds, "order_m": m, "sampled_omegas": len(oks),
+        "full_solves": len(oks) * len(ps), "max_resid_window": float(rmax),
+        "max_resid_grid": float(res.max()),
+        "A_max_rel_err_interp": float(err[inside].max()),
+        "A_max_rel_err_extrap": float(err[~inside].max()) if (~inside).any() else None,
+        "check_points": len(check),
+    }
+
+
+def form_adjoint(ctx, cfg, gfcc, inputs):
+    """Gradient of the trapezoid-integrated A over [-0.6, -0.3] Ha (100 points) with respect to
+    all orbital energies: forward solves, transposed solves, device reduction."""
+    import torch
+    o = inputs[1].shape[0]
+    ps = np.arange(o - cfg["np"], o, dtype=np.int32)
+    om = np.linspace(*cfg["omega"])
+    w = np.zeros(len(om))
+    h = np.diff(om)
+    w[:-1] += 0.5 * h
+    w[1:] += 0.5 * h
+    torch.cuda.synchronize()
+    t0 = time.time()
+    fwd = ctx.gfcc_solve(om, ps, cfg["eta"], tol=cfg["tol"], want_x=True)
+    adj = ctx.gfcc_solve(om, ps, cfg["eta"], tol=cfg["tol"], transpose=True, want_x=True)
+    g = ctx.gfcc_grad_eps(w, fwd.X, adj.X)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    J = float(np.dot(w, gfcc.spectral_function(fwd.G)))
+    return {"points": len(om), "s": dt, "points_per_s": len(om) / dt, "J": J,
+            "grad_occ_norm": float(np.linalg.norm(g[:o])), "max_rel_resid_fwd": float(fwd.resid.max()),
+            "max_rel_resid_adj": float(adj.resid.max())}
+
+
+def form_mixed(cfg, gfcc, torch):
+    """Batched mixed precision at the adenine/cc-pVDZ shape: one launch of 32 omega x 16 p
+    right-hand sides, FP32 sigma with the three-body term on bf16 matrix cores, FP64
+    refinement to relative residual 1e-8; the same block in FP64 for the error and the rate."""
+    import synth
+    o, v = cfg["o"], cfg["v"]
+    t0 = time.time()
+    prob = synth.make_problem(o, v, cfg["seed"])
+    host = [prob.eps, prob.t1, prob.t2, prob.l1, prob.l2] + [
+        prob.block(k) for k in ("oooo", "ooov", "oovv", "ovvo", "ovvv")]
+    log(f"[bench] mixed: generated o={o} v={v} inputs in {time.time() - t0:.1f} s")
+    dev = torch.device("cuda", 0)
+    ctx = gfcc.Context(0)
+    inputs = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in host]
+    del host, prob
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ctx.build_hbar_operands(o, v, *inputs, keep=gfcc.KEEP_FP32)
+    torch.cuda.synchronize()
+    t_build = time.time() - t0
+    del inputs
+    torch.cuda.empty_cache()
+    om = np.linspace(*cfg["omega"])
+    ps = np.arange(o - cfg["np"], o, dtype=np.int32)
+    nrhs = len(om) * len(ps)
+    out = {"workload": f"o={o} v={v} (D={gfcc.dim(o, v)}), {len(om)} omega x {len(ps)} p = "
+                       f"{nrhs} right-hand sides in one block, eta={cfg['eta']}",
+           "build_s": t_build}
+    res = {}
+    for name, prec in (("fp32_bf16", gfcc.FP32_BF16_3BODY), ("fp64", gfcc.FP64)):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        r = ctx.gfcc_solve(om, ps, cfg["eta"], tol=cfg["tol"], restart=12, block=nrhs,
+                           precision=prec)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        res[name] = (r, dt)
+        out[name] = {"s": dt, "points_per_s": len(om) / dt,
+                     "iterations_mean": float(r.iters.mean()),
+                     "max_rel_resid_fp64": float(r.resid.max())}
+        log(f"[bench] mixed: {name} {dt:.2f} s")
+    Am = gfcc.spectral_function(res["fp32_bf16"][0].G)
+    Ad = gfcc.spectral_function(res["fp64"][0].G)
+    out["A_max_rel_err_vs_fp64"] = float(np.abs(Am - Ad).max() / np.abs(Ad).max())
+    out["speedup_vs_fp64"] = res["fp64"][1] / res["fp32_bf16"][1]
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,11 +194,13 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-p", type=int, default=2)
+    ap.add_argument("--forms", default="mor,adjoint,mixed",
+                    help="extra forms reported beside the plain path: mor, adjoint, mixed, none")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the (omega, p) right-hand "
                                    "sides would be sharded across GPUs with the operator "
-                                   "replicated (see DESIGN.md)", "n_gpus": args.gpus}))
+                                   "replicated", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
@@ -172,6 +285,11 @@ def main():
             "sigma_ms_total": sig_ms, "A_range": [float(A.min()), float(A.max())],
         },
     }
+    forms = [f for f in args.forms.split(",") if f and f != "none"]
+    if "mor" in forms:
+        out["mor"] = form_mor(ctx, prob, synth.CONFIGS[2], gfcc)
+    if "adjoint" in forms:
+        out["adjoint"] = form_adjoint(ctx, synth.CONFIGS[4], gfcc, inputs)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample) ...")
         G = res.G.cpu().numpy()
@@ -180,8 +298,12 @@ def main():
         out["solver"]["sampled_rel_err_G_vs_oracle"] = err
     else:
         out["cpu_baseline"] = None
-    print(json.dumps(out))
     ctx.close()
+    if "mixed" in forms:
+        del inputs
+        torch.cuda.empty_cache()
+        out["mixed"] = form_mixed(synth.CONFIGS[3], gfcc, torch)
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":

@@ -50,12 +50,12 @@ template <typename T> struct Params {
 };
 
 template <typename T, bool TA, int BMODE, bool SPLIT>
-__global__ __launch_bounds__(NT) void gemm_kernel(Params<T> p) {
+__global__ __launch_bounds__(NT, 2) void gemm_kernel(Params<T> p) {
   using M4 = Mfma<T>;
   using C4 = typename M4::C4;
   constexpr int PAD = M4::PAD;
-  __shared__ T As[BK][BM + PAD];
-  __shared__ T Bs[BK][BN + PAD];
+  __shared__ T As[2][BK][BM + PAD];
+  __shared__ T Bs[2][BK][BN + PAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -95,53 +95,62 @@ __global__ __launch_bounds__(NT) void gemm_kernel(Params<T> p) {
     }
   }
 
+  // Loads are unconditional (indices clamped into range); their values are only consumed when
+  // the slab is written to LDS after the MFMAs of the current slab, where out-of-range entries
+  // are zeroed (bits of amask/bmask) and gathered entries get their sign.
   T ra[8], rb[8];
-
+  unsigned amask = 0, bmask = 0, bneg = 0;
+  const int Mc = p.M - 1, Nc = p.N - 1;
   auto load_tile = [&](int k0) {
+    amask = bmask = bneg = 0;
+    const int kc = kend - 1;
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       int m, k;
       if (TA) { m = m0 + a_c0; k = k0 + a_r0 + 2 * r; }
       else    { k = k0 + a_c0; m = m0 + a_r0 + 16 * r; }
-      T val = T(0);
-      if (m < p.M && k < kend) val = TA ? A[(int64_t)k * p.lda + m] : A[(int64_t)m * p.lda + k];
-      ra[r] = val;
+      amask |= (m < p.M && k < kend) ? (1u << r) : 0u;
+      const int mm = m < Mc ? m : Mc, kk = k < kc ? k : kc;
+      ra[r] = TA ? A[(int64_t)kk * p.lda + mm] : A[(int64_t)mm * p.lda + kk];
     }
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      T val = T(0);
       if (BMODE == B_TRANS) {
-        int k = k0 + b_c0, n = n0 + b_r0 + 16 * r;
-        if (n < p.N && k < kend) val = B[(int64_t)n * p.ldb + k];
+        const int k = k0 + b_c0, n = n0 + b_r0 + 16 * r;
+        bmask |= (n < p.N && k < kend) ? (1u << r) : 0u;
+        const int nn = n < Nc ? n : Nc, kk = k < kc ? k : kc;
+        rb[r] = B[(int64_t)nn * p.ldb + kk];
       } else if (BMODE == B_ROW) {
-        int k = k0 + b_r0 + 2 * r, n = n0 + b_c0;
-        if (n < p.N && k < kend) val = B[(int64_t)k * p.ldb + n];
+        const int k = k0 + b_r0 + 2 * r, n = n0 + b_c0;
+        bmask |= (n < p.N && k < kend) ? (1u << r) : 0u;
+        const int nn = n < Nc ? n : Nc, kk = k < kc ? k : kc;
+        rb[r] = B[(int64_t)kk * p.ldb + nn];
       } else {
-        int k = k0 + b_r0 + 2 * r;
-        if (g_nok && k < kend) {
-          int m = k / p.v;
-          int e = k - m * p.v;
-          int s = p.lut[m * p.o + g_j];
-          if (s != 0) {
-            int64_t pr = (s > 0 ? s : -s) - 1;
-            T x = B[(pr * p.v + e) * p.ldb + g_c];
-            val = s > 0 ? x : -x;
-          }
-        }
+        const int k = k0 + b_r0 + 2 * r;
+        const int kk = k < kc ? k : kc;
+        const int m = kk / p.v;
+        const int e = kk - m * p.v;
+        const int s = p.lut[m * p.o + g_j];
+        const int64_t pr = (s > 0 ? s : (s < 0 ? -s : 1)) - 1;
+        bmask |= (g_nok && k < kend && s != 0) ? (1u << r) : 0u;
+        bneg |= (s < 0) ? (1u << r) : 0u;
+        rb[r] = B[(pr * p.v + e) * p.ldb + g_c];
       }
-      rb[r] = val;
     }
   };
-  auto store_tile = [&]() {
+  auto store_tile = [&](int buf) {
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      if (TA) As[a_r0 + 2 * r][a_c0] = ra[r];
-      else    As[a_c0][a_r0 + 16 * r] = ra[r];
+      const T x = ((amask >> r) & 1u) ? ra[r] : T(0);
+      if (TA) As[buf][a_r0 + 2 * r][a_c0] = x;
+      else    As[buf][a_c0][a_r0 + 16 * r] = x;
     }
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      if (BMODE == B_TRANS) Bs[b_c0][b_r0 + 16 * r] = rb[r];
-      else                  Bs[b_r0 + 2 * r][b_c0] = rb[r];
+      T x = ((bmask >> r) & 1u) ? rb[r] : T(0);
+      if (BMODE == B_OVVO) x = ((bneg >> r) & 1u) ? -x : x;
+      if (BMODE == B_TRANS) Bs[buf][b_c0][b_r0 + 16 * r] = x;
+      else                  Bs[buf][b_r0 + 2 * r][b_c0] = x;
     }
   };
 
@@ -153,9 +162,10 @@ __global__ __launch_bounds__(NT) void gemm_kernel(Params<T> p) {
 
   if (kbeg < kend) {
     load_tile(kbeg);
-    store_tile();
+    store_tile(0);
     __syncthreads();
     const int row_l = lane & 15, kq = lane >> 4;
+    int buf = 0;
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
       const bool more = k0 + BK < kend;
       if (more) load_tile(k0 + BK);
@@ -163,19 +173,17 @@ __global__ __launch_bounds__(NT) void gemm_kernel(Params<T> p) {
       for (int s = 0; s < BK / 4; ++s) {
         T af[4], bf[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) af[i] = As[s * 4 + kq][wm * 64 + i * 16 + row_l];
+        for (int i = 0; i < 4; ++i) af[i] = As[buf][s * 4 + kq][wm * 64 + i * 16 + row_l];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bf[j] = Bs[s * 4 + kq][wn * 64 + j * 16 + row_l];
+        for (int j = 0; j < 4; ++j) bf[j] = Bs[buf][s * 4 + kq][wn * 64 + j * 16 + row_l];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j) acc[i][j] = M4::op(af[i], bf[j], acc[i][j]);
       }
+      if (more) store_tile(buf ^ 1);
       __syncthreads();
-      if (more) {
-        store_tile();
-        __syncthreads();
-      }
+      buf ^= 1;
     }
   }
 
