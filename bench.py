@@ -194,6 +194,9 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-p", type=int, default=2)
+    ap.add_argument("--sigma-only", type=int, default=0,
+                    help="profiling driver: K sigma products of one block in the benchmark's "
+                         "launch configuration, then a 1 GiB device copy (counter calibration)")
     ap.add_argument("--forms", default="mor,adjoint,mixed",
                     help="extra forms reported beside the plain path: mor, adjoint, mixed, none")
     args = ap.parse_args()
@@ -222,6 +225,28 @@ def main():
     torch.cuda.synchronize()
     ctx = gfcc.Context(0)
     D = gfcc.dim(o, v)
+
+    if args.sigma_only:
+        ctx.build_hbar_operands(o, v, *inputs)
+        nrhs = min(args.block, len(omega) * len(ps))
+        g = torch.Generator(device=dev).manual_seed(0)
+        x = torch.randn((nrhs, D), dtype=torch.complex128, device=dev, generator=g)
+        ctx.timer(0, enable=True, reset=True)
+        for _ in range(args.sigma_only):
+            y = ctx.sigma_apply(x)
+        torch.cuda.synchronize()
+        ms, n = ctx.timer(0, enable=False, reset=True)
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        flops = 2.0 * (o * v) ** 2 * (o * 2 * nrhs)
+        print(json.dumps({"sigma_products": args.sigma_only, "nrhs": nrhs, "ovvo_launches": n,
+                          "ovvo_avg_ms": ms / max(n, 1),
+                          "ovvo_tflops": flops / (ms / max(n, 1) * 1e-3) / 1e12 if n else None,
+                          "copy_bytes": 2 * src.numel() * 8}))
+        ctx.close()
+        return
 
     def step():
         ctx.build_hbar_operands(o, v, *inputs)
@@ -274,7 +299,7 @@ def main():
             "block": nb, "restart": args.restart, "seed": cfg["seed"],
         },
         "roofline": {
-            "bound": "mfma", "kernel": "ovvo contraction (gemm_kernel<double, B_OVVO>)",
+            "bound": "mfma", "kernel": "ovvo contraction (ovvo_kernel<double>, column-block loader)",
             "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
             "avg_launch_ms": avg_ms, "launches": ovvo_n, "flops_per_launch": flops_launch,

@@ -130,6 +130,7 @@ struct gfcc_ctx {
   // scratch, grow-only
   gfcc::DevBuf ws_gemm;     // split-K partials
   gfcc::DevBuf ws_a, ws_b, ws_c, ws_d, ws_e;
+  gfcc::DevBuf zrow;        // zeros (read for structurally zero rows of the ovvo operand)
   gfcc::TimerSlot timers[2];
   std::vector<hipEvent_t> event_pool;
 };
@@ -160,10 +161,16 @@ template <typename T>
 void gemm_ovvo(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, const T* X2,
                int64_t ldx, const int* pairlut, T* Z);
 
-// Specialised kernel for the same product (ovvo.hip); false if the shape is unsupported.
+// Specialised kernels for the same product (ovvo.hip); false if the shape is unsupported.
+// W must be followed by ovvo_pad_bytes(o * v) bytes of zeros; zrow holds at least nc zeros
+// (null disables the column-block variant).
 template <typename T>
 bool ovvo_fast(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, const T* X2,
-               int64_t ldx, T* Z);
+               int64_t ldx, T* Z, const T* zrow);
+inline int64_t ovvo_pad_bytes(int64_t M) { return 512 * M; }
+
+// A device buffer of at least `bytes` zero bytes, owned by the context (grown on demand).
+const void* zero_row(gfcc_ctx* ctx, size_t bytes);
 
 // bf16 x bf16 -> fp32 GEMM (three-body term of the mixed-precision sigma).
 void gemm_bf16(gfcc_ctx* ctx, bool transA, int M, int N, int K, float alpha,

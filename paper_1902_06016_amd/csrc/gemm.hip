@@ -329,7 +329,8 @@ template void gemm<float>(gfcc_ctx*, bool, bool, int, int, int, float, const flo
 template <typename T>
 void gemm_ovvo(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, const T* X2,
                int64_t ldx, const int* pairlut, T* Z) {
-  if (ovvo_fast<T>(ctx, transW, o, v, nc, W, X2, ldx, Z)) return;
+  const T* zrow = static_cast<const T*>(zero_row(ctx, (size_t)nc * sizeof(T)));
+  if (ovvo_fast<T>(ctx, transW, o, v, nc, W, X2, ldx, Z, zrow)) return;
   const int OV = o * v;
   gemm_impl<T>(ctx, transW, B_OVVO, OV, o * nc, OV, T(1), W, OV, X2, ldx, T(0), Z,
                (int64_t)o * nc, 1, 0, 0, 0, pairlut, o, v, nc);

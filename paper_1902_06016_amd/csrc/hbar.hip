@@ -376,7 +376,10 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
     double* Vp = B(f.Vp, PV * V);
     hipLaunchKernelGGL(assemble_Vp_kernel, dim3(grid_for(PV * V)), dim3(256), 0, st, oovv, o, v, PV, Vp);
     GFCC_LAUNCH_CHECK();
-    double* Weff = B(f.Weff, OV * OV);
+    // Weff is followed by zero padding read by the ovvo kernels past the last k slab
+    const int64_t wpad = ovvo_pad_bytes(OV) / (int64_t)sizeof(double);
+    double* Weff = B(f.Weff, OV * OV + wpad);
+    fill(ctx, Weff + OV * OV, wpad, 0.0);
     hipLaunchKernelGGL(assemble_Weff_kernel, dim3(grid_for(OV * OV)), dim3(256), 0, st, Wovvo,
                        Foo, Fvv, o, v, Weff);
     GFCC_LAUNCH_CHECK();
@@ -406,7 +409,10 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
       cast_f64_f32(ctx, W4c, F(g.W4c, PV * (O + V)), PV * (O + V));
       cast_f64_f32(ctx, Woo, F(g.Woo, P * P), P * P);
       cast_f64_f32(ctx, Vp, F(g.Vp, PV * V), PV * V);
-      cast_f64_f32(ctx, Weff, F(g.Weff, OV * OV), OV * OV);
+      const int64_t wpadf = ovvo_pad_bytes(OV) / (int64_t)sizeof(float);
+      float* Wf = F(g.Weff, OV * OV + wpadf);
+      cast_f64_f32(ctx, Weff, Wf, OV * OV);
+      fill_f(ctx, Wf + OV * OV, wpadf, 0.0f);
       // bf16 three-body operands: Vp and -t2 packed as [(ij)a][d]
       op.Vp_bf16.alloc((size_t)PV * V * sizeof(__hip_bfloat16));
       cast_f64_bf16(ctx, Vp, op.Vp_bf16.as<__hip_bfloat16>(), PV * V);

@@ -1,6 +1,8 @@
 // Memory-bound helpers: strided permutation, fills, casts, transposes, finiteness check.
 #include "common.h"
 
+#include <algorithm>
+
 namespace gfcc {
 namespace {
 
@@ -127,6 +129,15 @@ void fill_f(gfcc_ctx* ctx, float* p, int64_t n, float val) {
   if (n == 0) return;
   hipLaunchKernelGGL(fill_kernel<float>, dim3(grid_for(n)), dim3(256), 0, ctx->stream, p, n, val);
   GFCC_LAUNCH_CHECK();
+}
+
+const void* zero_row(gfcc_ctx* ctx, size_t bytes) {
+  bytes = (std::max<size_t>(bytes, 256) + 7) / 8 * 8;
+  if (ctx->zrow.bytes < bytes) {
+    ws_ensure(ctx, ctx->zrow, bytes);
+    fill(ctx, ctx->zrow.as<double>(), (int64_t)(ctx->zrow.bytes / sizeof(double)), 0.0);
+  }
+  return ctx->zrow.p;
 }
 
 void cast_f64_f32(gfcc_ctx* ctx, const double* s, float* d, int64_t n) {

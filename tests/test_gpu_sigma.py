@@ -34,7 +34,8 @@ def test_hbar_blocks(gpu_ctx, o, v, seed):
 
 
 @pytest.mark.parametrize("o,v,seed", _cases())
-@pytest.mark.parametrize("nrhs", [1, 3, 70])
+# 64 right-hand sides = 128 real columns: the column-block variant of the ovvo kernel
+@pytest.mark.parametrize("nrhs", [1, 3, 64, 70])
 @pytest.mark.parametrize("transpose", [False, True])
 def test_sigma_fp64(gpu_ctx, o, v, seed, nrhs, transpose):
     print(f"[sigma o={o} v={v} seed={seed} nrhs={nrhs} T={transpose}]", flush=True)
@@ -52,16 +53,17 @@ def test_sigma_fp64(gpu_ctx, o, v, seed, nrhs, transpose):
 
 
 @pytest.mark.parametrize("prec,tol", [(1, 2e-6), (2, 2e-3)])
-def test_sigma_reduced_precision(gpu_ctx, prec, tol):
+@pytest.mark.parametrize("nrhs", [5, 64])
+def test_sigma_reduced_precision(gpu_ctx, prec, tol, nrhs):
     o, v, seed = 13, 37, 2
-    print(f"[sigma_mixed prec={prec}]", flush=True)
+    print(f"[sigma_mixed prec={prec} nrhs={nrhs}]", flush=True)
     prob = synth.make_problem(o, v, seed)
     hb = ohbar.build_hbar_from_problem(prob)
     from paper_1902_06016_amd import gfcc
     gpu_ctx.build_from_problem(prob, keep=gfcc.KEEP_FP32)
     D = osig.dim(o, v)
     rng = np.random.default_rng(1)
-    x = rng.standard_normal((5, D)) + 1j * rng.standard_normal((5, D))
+    x = rng.standard_normal((nrhs, D)) + 1j * rng.standard_normal((nrhs, D))
     y = gpu_ctx.sigma_apply(torch.from_numpy(x).cuda(), precision=prec).cpu().numpy()
     ref = osig.sigma(hb, x)
     err = np.abs(y - ref).max() / np.abs(ref).max()
