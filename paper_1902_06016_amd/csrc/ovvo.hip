@@ -8,11 +8,13 @@
 // Tile 128 x 128 x BK (one slab is 128 bytes of k: BK = 16 for FP64, 32 for FP32), 256 threads
 // as 2 x 2 wavefronts of 64 x 64 = 4 x 4 MFMA 16x16x4 blocks, two workgroups per CU.
 //
-// Pipeline. Global loads run two slabs ahead of the matrix work and LDS stores one slab ahead:
-// while slab s feeds the MFMAs from one LDS buffer, the registers loaded during slab s-1 are
-// written to the other buffer and the loads of slab s+2 are issued under the first k-steps.
-// Fragments are read one k-step ahead, and the single barrier per slab sits before the last
-// k-step, whose MFMAs cover the latency of the next slab's first fragment reads.
+// Pipeline. LDS is double-buffered and global loads run two slabs ahead of the matrix work:
+// during slab s, the registers loaded during slab s-1 are stored to the other LDS buffer and
+// each store is followed by the loads of slab s+2 into the registers it freed. Fragments are
+// read one k-step ahead, and the single barrier per slab sits before the last k-step, whose
+// MFMAs cover the next slab's first fragment reads and the address bookkeeping of the slab
+// after. The step is written as fenced slots of two MFMAs plus a small group of other work,
+// so that every wavefront keeps its matrix pipe fed on its own.
 //
 // LDS holds both tiles k-contiguous ([row][k]) with a 136-byte pitch, which keeps the
 // per-k-step fragment reads (lanes 0-15 on 16 rows) and the 8-byte stores free of bank
@@ -142,13 +144,17 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
     }
   }
 
-  // slab position being loaded: k0 = ms * v + es (scalar)
+  // ---- B row bookkeeping. prep() prepares the rows of the next slab to be loaded (position
+  // k0 = ms * v + es, scalar); its sign / liveness state moves to the "in registers" copy once
+  // that slab's loads are issued, and is used when the registers are stored to LDS.
   int ms = 0, es = 0;
-  T ra[ACH][VPC];
-  T rb[RB];
-  unsigned nbits = 0;                                      // column-block: row r negated
-  bool l0 = false, l1 = false, g0 = false, g1 = false;    // general: live / negated, m and m+1
-  unsigned cbits = 0;                                      // general: row r uses base m+1
+  typedef const T __attribute__((address_space(1)))* gptr;
+  uint64_t prow[RB];                                      // column-block: row addresses
+  unsigned pneg = 0, sneg = 0;                            // column-block: row r negated
+  int pz0 = 0, pz1 = 0;                                   // general: row bases, m and m+1
+  unsigned pcar = 0, scar = 0;                            // general: row r uses base m+1
+  bool pl0 = false, pl1 = false, pg0 = false, pg1 = false;  // general: live / negated
+  bool sl0 = false, sl1 = false, sg0 = false, sg1 = false;
   // element offset of X2[pair(m, j)][0][c], or 0 when the row is structurally zero (general)
   auto rowbase = [&](int m, bool& live, bool& neg) -> int {
     live = ncol && m < o && m != j;
@@ -156,109 +162,126 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
     const int lo = m < j ? m : j, hi = m < j ? j : m;
     return live ? pair_index(lo, hi, o) * v * ldx + c : 0;
   };
-
-  auto load = [&](int k0) {
-    // ---- A
-    if (BLOCKJ) {
+  // column-block: scalar bases of the first owned row in segments m and m+1 (the X2 row
+  // (pair(m, j), e) with stride ldx, or the zero row with stride 0); selects are written as
+  // masks so that the compiler keeps them in straight-line scalar code
+  uint64_t q0 = 0, q1 = 0, d0 = 0, d1 = 0;
+  int rc = 0, pb0 = 0, pb1 = 0;
+  auto cbase = [&](int m, int e, uint64_t& ptr, uint64_t& stride) {
+    const int lo = min(m, j), hi = max(m, j);
+    const int pr = lo * o - ((lo * (lo + 1)) >> 1) + hi - lo - 1;
+    const uint64_t live = 0ull - (uint64_t)((m < o) & (m != j));
+    const uint64_t a = reinterpret_cast<uint64_t>(X2) +
+                       (uint64_t)(((int64_t)pr * v + e) * ldx) * sizeof(T);
+    ptr = (a & live) | (reinterpret_cast<uint64_t>(p.zrow) & ~live);
+    stride = (uint64_t)ldx * sizeof(T) & live;
+  };
+  // in three parts (segment m, segment m+1, carry / sign / advance) so that they can be spread
+  // between MFMAs
+  auto prep_base = [&](int part) {
+    if (part == 0) {
+      if (BLOCKJ) cbase(ms, es + first, q0, d0);
+      else pb0 = rowbase(ms, pl0, pg0) + es * ldx;
+    } else if (part == 1) {
+      if (BLOCKJ) cbase(ms + 1, es + first - v, q1, d1);
+      else pb1 = rowbase(ms + 1, pl1, pg1) + (es - v) * ldx;
+    } else {
+      if (BLOCKJ) {
+        rc = v - es - first;   // owned rows r >= rc lie in segment m+1
+        constexpr unsigned full = (RB >= 32) ? ~0u : ((1u << RB) - 1u);
+        const unsigned hi = rc <= 0 ? full : (rc >= RB ? 0u : full & ~((1u << rc) - 1u));
+        pneg = (ms > j ? full & ~hi : 0u) | (ms + 1 > j ? hi : 0u);
+      } else {
+        pz0 = pl0 ? pb0 : 0;
+        pz1 = pl1 ? pb1 : 0;
+        pcar = 0;
 #pragma unroll
-      for (int r = 0; r < ACH; ++r) {
-        const V16 x = *reinterpret_cast<const V16*>(wa[r] + (TA ? (int64_t)k0 * M : k0));
-#pragma unroll
-        for (int u = 0; u < VPC; ++u) ra[r][u] = x[u];
+        for (int r = 0; r < RB; ++r) pcar |= (es + first + r >= v) ? 1u << r : 0u;
       }
+      const int cy = es + BK >= v;
+      es = es + BK - (cy ? v : 0);
+      ms += cy;
+    }
+  };
+  auto prep_row = [&](int r) {
+    if (BLOCKJ) {
+      const uint64_t mk = 0ull - (uint64_t)(r >= rc);
+      prow[r] = ((q1 + r * d1) & mk) | ((q0 + r * d0) & ~mk);
+    }
+  };
+  auto prep_all = [&]() {
+    prep_base(0);
+    prep_base(1);
+    prep_base(2);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) prep_row(r);
+  };
+  // the prepared state becomes the state of the slab held in registers
+  auto commit = [&]() {
+    sneg = pneg;
+    scar = pcar;
+    sl0 = pl0; sl1 = pl1; sg0 = pg0; sg1 = pg1;
+  };
+
+  T ra[ACH][VPC];
+  T rb[RB];
+  // ---- loads of one slab: ACH A chunks (ops 0 .. ACH-1), then B rows
+  auto load_a = [&](int r, int k0) {
+    if (BLOCKJ) {
+      const V16 x = *reinterpret_cast<const V16*>(wa[r] + (TA ? (int64_t)k0 * M : k0));
+#pragma unroll
+      for (int u = 0; u < VPC; ++u) ra[r][u] = x[u];
     } else if (!TA) {
       if (VEC) {
+        const int row = m0 + tid / CPR + (NT / CPR) * r, k = k0 + (tid % CPR) * VPC;
+        const int rr = row < M ? row : M - 1, kk = k < K ? k : K - VPC;
+        const V16 x = *reinterpret_cast<const V16*>(W + (int64_t)rr * K + kk);
 #pragma unroll
-        for (int r = 0; r < ACH; ++r) {
-          const int row = m0 + tid / CPR + (NT / CPR) * r, k = k0 + (tid % CPR) * VPC;
-          const int rr = row < M ? row : M - 1, kk = k < K ? k : K - VPC;
-          const V16 x = *reinterpret_cast<const V16*>(W + (int64_t)rr * K + kk);
-#pragma unroll
-          for (int u = 0; u < VPC; ++u) ra[r][u] = x[u];
-        }
+        for (int u = 0; u < VPC; ++u) ra[r][u] = x[u];
       } else {
 #pragma unroll
-        for (int r = 0; r < ACH; ++r)
-#pragma unroll
-          for (int u = 0; u < VPC; ++u) {
-            const int f = tid + NT * (r * VPC + u);
-            const int row = m0 + f / BK, k = k0 + f % BK;
-            const int rr = row < M ? row : M - 1, kk = k < K ? k : K - 1;
-            ra[r][u] = W[(int64_t)rr * K + kk];
-          }
+        for (int u = 0; u < VPC; ++u) {
+          const int f = tid + NT * (r * VPC + u);
+          const int row = m0 + f / BK, k = k0 + f % BK;
+          const int rr = row < M ? row : M - 1, kk = k < K ? k : K - 1;
+          ra[r][u] = W[(int64_t)rr * K + kk];
+        }
       }
     } else {
       // W stored [K][M]: chunks run along m
+      const int f = tid + NT * r;
+      const int k = k0 + f / (BM / VPC), mm = m0 + (f % (BM / VPC)) * VPC;
+      const int kk = k < K ? k : K - 1;
+      if (VEC) {
+        const int rr = mm < M ? mm : M - VPC;
+        const V16 x = *reinterpret_cast<const V16*>(W + (int64_t)kk * M + rr);
 #pragma unroll
-      for (int r = 0; r < ACH; ++r) {
-        const int f = tid + NT * r;
-        const int k = k0 + f / (BM / VPC), mm = m0 + (f % (BM / VPC)) * VPC;
-        const int kk = k < K ? k : K - 1;
-        if (VEC) {
-          const int rr = mm < M ? mm : M - VPC;
-          const V16 x = *reinterpret_cast<const V16*>(W + (int64_t)kk * M + rr);
+        for (int u = 0; u < VPC; ++u) ra[r][u] = x[u];
+      } else {
 #pragma unroll
-          for (int u = 0; u < VPC; ++u) ra[r][u] = x[u];
-        } else {
-#pragma unroll
-          for (int u = 0; u < VPC; ++u) {
-            const int rr = mm + u < M ? mm + u : M - 1;
-            ra[r][u] = W[(int64_t)kk * M + rr];
-          }
+        for (int u = 0; u < VPC; ++u) {
+          const int rr = mm + u < M ? mm + u : M - 1;
+          ra[r][u] = W[(int64_t)kk * M + rr];
         }
       }
     }
-    // ---- B: rows first + r of the slab; at most one carry into m
-    if (BLOCKJ) {
-      // Scalar row bases of the slab's first owned row in segments m and m+1: the X2 row
-      // (pair(m, j), e) with stride ldx, or the zero row with stride 0. Selects are written
-      // as masks so that the compiler keeps them in straight-line scalar code.
-      auto base = [&](int m, int e, uint64_t& ptr, uint64_t& stride) {
-        const int lo = min(m, j), hi = max(m, j);
-        const int pr = lo * o - ((lo * (lo + 1)) >> 1) + hi - lo - 1;
-        const uint64_t live = 0ull - (uint64_t)((m < o) & (m != j));
-        const uint64_t a = reinterpret_cast<uint64_t>(X2) +
-                           (uint64_t)(((int64_t)pr * v + e) * ldx) * sizeof(T);
-        ptr = (a & live) | (reinterpret_cast<uint64_t>(p.zrow) & ~live);
-        stride = (uint64_t)ldx * sizeof(T) & live;
-      };
-      uint64_t q0, q1, d0, d1;
-      base(ms, es + first, q0, d0);
-      base(ms + 1, es + first - v, q1, d1);
-      const int rc = v - es - first;   // owned rows r >= rc lie in segment m+1
-      constexpr unsigned full = (RB >= 32) ? ~0u : ((1u << RB) - 1u);
-      const unsigned hi = rc <= 0 ? full : (rc >= RB ? 0u : full & ~((1u << rc) - 1u));
-      nbits = (ms > j ? full & ~hi : 0u) | (ms + 1 > j ? hi : 0u);
-      typedef const T __attribute__((address_space(1)))* gptr;
-#pragma unroll
-      for (int r = 0; r < RB; ++r) {   // all scalar but the column c
-        const uint64_t mk = 0ull - (uint64_t)(r >= rc);
-        const uint64_t rowp = ((q1 + r * d1) & mk) | ((q0 + r * d0) & ~mk);
-        rb[r] = reinterpret_cast<gptr>(rowp)[c];
-      }
-    } else {
-      // per-lane row bases for m and m+1
-      const int b0 = rowbase(ms, l0, g0) + es * ldx;
-      const int b1 = rowbase(ms + 1, l1, g1) + (es - v) * ldx;
-      const int z0 = l0 ? b0 : 0, z1 = l1 ? b1 : 0;
-      cbits = 0;
-#pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        const bool carry = es + first + r >= v;   // scalar
-        cbits |= carry ? 1u << r : 0u;
-        rb[r] = X2[(carry ? z1 : z0) + (first + r) * ldx];
-      }
-    }
-    const int cy = es + BK >= v;
-    es = es + BK - (cy ? v : 0);
-    ms += cy;
   };
-
-  auto store = [&](auto BUFC) {
+  auto load_b = [&](int r) {
+    if (BLOCKJ) {
+      rb[r] = reinterpret_cast<gptr>(prow[r])[c];
+    } else {
+      const bool carry = (pcar >> r) & 1u;
+      rb[r] = X2[(carry ? pz1 : pz0) + (first + r) * ldx];
+    }
+  };
+  // ---- LDS stores of the slab in registers: ops 0 .. ACH-1 are A chunks, ops ACH .. ACH+3
+  // each hold RB/4 B rows
+  constexpr int BG = RB / 4;
+  auto store_op = [&](auto BUFC, int t) {
     constexpr int b = decltype(BUFC)::value;
-    if (!TA && (BLOCKJ || VEC)) {
-#pragma unroll
-      for (int r = 0; r < ACH; ++r) {
+    if (t < ACH) {
+      const int r = t;
+      if (!TA && (BLOCKJ || VEC)) {
         T* d = &As[b][tid / CPR + (NT / CPR) * r][(tid % CPR) * VPC];
 #pragma unroll
         for (int h = 0; h < VPC; h += VP8) {
@@ -267,39 +290,45 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
           for (int u = 0; u < VP8; ++u) y[u] = ra[r][h + u];
           *reinterpret_cast<V8*>(d + h) = y;
         }
-      }
-    } else if (!TA) {
-#pragma unroll
-      for (int r = 0; r < ACH; ++r)
+      } else if (!TA) {
 #pragma unroll
         for (int u = 0; u < VPC; ++u) {
           const int f = tid + NT * (r * VPC + u);
           As[b][f / BK][f % BK] = ra[r][u];
         }
-    } else {
-#pragma unroll
-      for (int r = 0; r < ACH; ++r) {
+      } else {
         const int f = tid + NT * r;
         const int k = f / (BM / VPC), mm = (f % (BM / VPC)) * VPC;
 #pragma unroll
         for (int u = 0; u < VPC; ++u) As[b][mm + u][k] = ra[r][u];
       }
-    }
+    } else {
+      const int g = t - ACH;
 #pragma unroll
-    for (int t = 0; t < RB; t += VP8) {
-      V8 y;
+      for (int h = 0; h < BG; h += VP8) {
+        V8 y;
 #pragma unroll
-      for (int u = 0; u < VP8; ++u) {
-        const int r = t + u;
-        if (BLOCKJ) {
-          y[u] = M4::flip(rb[r], (nbits >> r) & 1u);
-        } else {
-          const bool cr = (cbits >> r) & 1u;
-          const T x = (cr ? l1 : l0) ? rb[r] : T(0);
-          y[u] = (cr ? g1 : g0) ? -x : x;
+        for (int u = 0; u < VP8; ++u) {
+          const int r = g * BG + h + u;
+          if (BLOCKJ) {
+            y[u] = M4::flip(rb[r], (sneg >> r) & 1u);
+          } else {
+            const bool cr = (scar >> r) & 1u;
+            const T x = (cr ? sl1 : sl0) ? rb[r] : T(0);
+            y[u] = (cr ? sg1 : sg0) ? -x : x;
+          }
         }
+        *reinterpret_cast<V8*>(&Bs[b][bn][first + g * BG + h]) = y;
       }
-      *reinterpret_cast<V8*>(&Bs[b][bn][first + t]) = y;
+    }
+  };
+  // load op issued after store op t, into the registers that store freed
+  auto load_op = [&](int t, int k0) {
+    if (t < ACH) {
+      load_a(t, k0);
+    } else {
+#pragma unroll
+      for (int h = 0; h < BG; ++h) load_b((t - ACH) * BG + h);
     }
   };
 
@@ -311,42 +340,84 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
 
   const int row_l = lane & 15, kq = lane >> 4;
   T af[NS][4], bf[NS][4];   // fragments of the k-steps of a slab
-  auto frag = [&](auto BUFC, int s) {
+  auto frag_read = [&](auto BUFC, int s, int h) {
     constexpr int b = decltype(BUFC)::value;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) af[s][i] = As[b][wm * 64 + i * 16 + row_l][4 * s + kq];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) bf[s][q] = Bs[b][wn * 64 + q * 16 + row_l][4 * s + kq];
+    if (h < 4) af[s][h] = As[b][wm * 64 + h * 16 + row_l][4 * s + kq];
+    else bf[s][h - 4] = Bs[b][wn * 64 + (h - 4) * 16 + row_l][4 * s + kq];
   };
-  auto mfma = [&](int s) {
+  auto mfma2 = [&](int s, int t) {   // MFMAs 2t and 2t+1 of k-step s
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[i][q] = M4::op(af[s][i], bf[s][q], acc[i][q]);
+    for (int x = 2 * t; x < 2 * t + 2; ++x)
+      acc[x >> 2][x & 3] = M4::op(af[s][x >> 2], bf[s][x & 3], acc[x >> 2][x & 3]);
   };
-  // One slab from LDS buffer b (its first two fragments already in registers).
+  auto fence = []() { __builtin_amdgcn_sched_barrier(0); };
+
+  // One slab from LDS buffer b, its first two fragments already in registers. The step is
+  // laid out as 8 slots per k-step, each two MFMAs plus a small group of other work, fenced so
+  // that the compiler keeps the order:
+  //  k-step 0:        the LDS stores of the slab held in registers (next slab, other buffer),
+  //                   each followed by the loads of the slab after it into the freed registers;
+  //  k-steps 1..NS-2: fragment reads one k-step ahead;
+  //  barrier;
+  //  k-step NS-1:     the next slab's first two fragments and the row bookkeeping of the
+  //                   slab to be loaded in the next step.
   auto step = [&](auto BUFC, int kload) {
     constexpr int b = decltype(BUFC)::value;
-    store(IC<b ^ 1>{});
 #pragma unroll
-    for (int s = 0; s + 1 < NS; ++s) {
-      mfma(s);
-      if (s + 2 < NS) frag(IC<b>{}, s + 2);
-      if (s == 0) load(kload);
+    for (int t = 0; t < 8; ++t) {
+      mfma2(0, t);
+      store_op(IC<b ^ 1>{}, t);
+      load_op(t, kload);
+      fence();
     }
+    commit();
+#pragma unroll
+    for (int s = 1; s + 1 < NS; ++s)
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        mfma2(s, t);
+        if (t < 4) {
+          frag_read(IC<b>{}, s + 1, 2 * t);
+          frag_read(IC<b>{}, s + 1, 2 * t + 1);
+        }
+        fence();
+      }
+    fence();
     __syncthreads();
-    frag(IC<b ^ 1>{}, 0);
-    mfma(NS - 1);
-    frag(IC<b ^ 1>{}, 1);
+    fence();
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      mfma2(NS - 1, t);
+      frag_read(IC<b ^ 1>{}, t >> 2, 2 * (t & 3));
+      frag_read(IC<b ^ 1>{}, t >> 2, 2 * (t & 3) + 1);
+      if (t < 3) prep_base(t);
+      constexpr int RPS = (RB + 5) / 6;   // rows prepared per slot, slots 2..7
+#pragma unroll
+      for (int h = 0; h < RPS; ++h)
+        if (t >= 2 && (t - 2) * RPS + h < RB) prep_row((t - 2) * RPS + h);
+      fence();
+    }
   };
 
-  // prologue: slab 0 into LDS buffer 0 and its first fragments, slab 1 into registers
-  load(0);
-  store(IC<0>{});
-  load(BK);
+  // prologue: slab 0 into LDS buffer 0 and its first fragments, slab 1 into registers, the
+  // rows of slab 2 prepared
+  prep_all();
+  commit();
+#pragma unroll
+  for (int t = 0; t < ACH + 4; ++t) load_op(t, 0);
+#pragma unroll
+  for (int t = 0; t < ACH + 4; ++t) store_op(IC<0>{}, t);
+  prep_all();
+#pragma unroll
+  for (int t = 0; t < ACH + 4; ++t) load_op(t, BK);
+  commit();
+  prep_all();
   __syncthreads();
-  frag(IC<0>{}, 0);
-  frag(IC<0>{}, 1);
+#pragma unroll
+  for (int h = 0; h < 8; ++h) {
+    frag_read(IC<0>{}, 0, h);
+    frag_read(IC<0>{}, 1, h);
+  }
   // Every step stores and loads ahead. Past the last slab the B rows are structurally zero
   // and the A reads stay in range (clamped, or in the padding after W), and the stores go to
   // the buffer that is no longer read.
