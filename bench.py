@@ -35,6 +35,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(o, v, nb):
+    """HBM bytes per ovvo launch from the committed counter summary (FETCH_SIZE and WRITE_SIZE
+    scaled by the copy calibration), or None when the summary is for another workload or the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", "ovvo_o42v186_pmc.txt")
+    src = os.path.join(HERE, "paper_1902_06016_amd", "csrc", "ovvo.hip")
+    if (o, v, nb) != (42, 186, 320) or not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    rec, traffic = None, None
+    for line in open(path):
+        if line.startswith("ovvo.hip sha256:"):
+            rec = line.split(":", 1)[1].strip()
+        if line.startswith("traffic_bytes_per_launch:"):
+            traffic = float(line.split(":", 1)[1])
+    return traffic if rec == sha else None
+
+
 def cpu_baseline(prob, cfg, omega, ps, gpu_G, n_p_sample):
     """Oracle on a bounded sample: H-bar build once, then GMRES at one frequency for
     n_p_sample orbitals. Scaled to frequency points/s of the full workload."""
@@ -301,7 +320,7 @@ def main():
         "roofline": {
             "bound": "mfma", "kernel": "ovvo contraction (ovvo_kernel<double>, column-block loader)",
             "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(o, v, nb),
             "avg_launch_ms": avg_ms, "launches": ovvo_n, "flops_per_launch": flops_launch,
         },
         "solver": {
