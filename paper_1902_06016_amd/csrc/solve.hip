@@ -32,51 +32,38 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
 }
 
 constexpr int JG = 16;  // basis vectors per dot pass
+constexpr int CW = 64;  // right-hand sides per reduction block: one wavefront, one per lane
 
-// partial[blk][jj][r] = sum over this block's rows of conj(V_j[d][r]) * W[d][r], j = j0 + jj
-__global__ __launch_bounds__(256) void dots_kernel(const double2* __restrict__ V, int64_t vstride,
-                                                   int j0, int nj, const double2* __restrict__ W,
-                                                   int64_t D, int nb, double2* __restrict__ partial) {
-  __shared__ double2 red[256];
-  const int RB = nb < 256 ? nb : 256;
-  const int lanes = 256 / RB;
-  const int t = threadIdx.x;
-  const int rl = t % RB, rowlane = t / RB;
-  const int r = blockIdx.y * RB + rl;
-  const bool live = rowlane < lanes && r < nb;
+// partial[blk][jj][r] = sum over this block's rows of conj(V_j[d][r]) * W[d][r], j = j0 + jj.
+// Grid (nblk, ceil(nb / 64)), one wavefront per block; every lane owns one right-hand side
+// and walks the block's rows, so each row of V_j and W is one contiguous 1 KB read per wave.
+__global__ __launch_bounds__(CW) void dots_kernel(const double2* __restrict__ V, int64_t vstride,
+                                                  int j0, int nj, const double2* __restrict__ W,
+                                                  int64_t D, int nb, double2* __restrict__ partial) {
+  const int r = blockIdx.y * CW + threadIdx.x;
+  if (r >= nb) return;
   double2 acc[JG];
 #pragma unroll
   for (int jj = 0; jj < JG; ++jj) acc[jj] = make_double2(0.0, 0.0);
   const int64_t rows_per_blk = (D + gridDim.x - 1) / gridDim.x;
   const int64_t d0 = (int64_t)blockIdx.x * rows_per_blk;
   const int64_t d1 = min(D, d0 + rows_per_blk);
-  if (live) {
-    for (int64_t d = d0 + rowlane; d < d1; d += lanes) {
-      double2 w = W[d * nb + r];
+  const double2* __restrict__ Vj = V + (int64_t)j0 * vstride + r;
+#pragma unroll 2
+  for (int64_t d = d0; d < d1; ++d) {
+    const double2 w = W[d * nb + r];
 #pragma unroll
-      for (int jj = 0; jj < JG; ++jj) {
-        if (jj < nj) {
-          double2 p = cconjmul(V[(int64_t)(j0 + jj) * vstride + d * nb + r], w);
-          acc[jj].x += p.x;
-          acc[jj].y += p.y;
-        }
+    for (int jj = 0; jj < JG; ++jj) {
+      if (jj < nj) {
+        const double2 p = cconjmul(Vj[(int64_t)jj * vstride + d * nb], w);
+        acc[jj].x += p.x;
+        acc[jj].y += p.y;
       }
     }
   }
-  for (int jj = 0; jj < nj; ++jj) {
-    red[t] = live ? acc[jj] : make_double2(0.0, 0.0);
-    __syncthreads();
-    if (rowlane == 0 && r < nb) {
-      double2 s = red[t];
-      for (int q = 1; q < lanes; ++q) {
-        double2 x = red[t + q * RB];
-        s.x += x.x;
-        s.y += x.y;
-      }
-      partial[((int64_t)blockIdx.x * JG + jj) * nb + r] = s;
-    }
-    __syncthreads();
-  }
+#pragma unroll
+  for (int jj = 0; jj < JG; ++jj)
+    if (jj < nj) partial[((int64_t)blockIdx.x * JG + jj) * nb + r] = acc[jj];
 }
 
 // h[(j0+jj)][r] (+)= sum_blk partial[blk][jj][r]
@@ -112,32 +99,21 @@ __global__ void update_kernel(const double2* __restrict__ V, int64_t vstride, in
   }
 }
 
-// nrm partial: sum |W[d][r]|^2
-__global__ __launch_bounds__(256) void norm_kernel(const double2* __restrict__ W, int64_t D, int nb,
-                                                   double* __restrict__ partial) {
-  __shared__ double red[256];
-  const int RB = nb < 256 ? nb : 256;
-  const int lanes = 256 / RB;
-  const int t = threadIdx.x;
-  const int rl = t % RB, rowlane = t / RB;
-  const int r = blockIdx.y * RB + rl;
-  const bool live = rowlane < lanes && r < nb;
+// nrm partial: sum |W[d][r]|^2 (same grid as dots_kernel)
+__global__ __launch_bounds__(CW) void norm_kernel(const double2* __restrict__ W, int64_t D, int nb,
+                                                  double* __restrict__ partial) {
+  const int r = blockIdx.y * CW + threadIdx.x;
+  if (r >= nb) return;
   double acc = 0.0;
   const int64_t rows_per_blk = (D + gridDim.x - 1) / gridDim.x;
   const int64_t d0 = (int64_t)blockIdx.x * rows_per_blk;
   const int64_t d1 = min(D, d0 + rows_per_blk);
-  if (live)
-    for (int64_t d = d0 + rowlane; d < d1; d += lanes) {
-      double2 w = W[d * nb + r];
-      acc += w.x * w.x + w.y * w.y;
-    }
-  red[t] = live ? acc : 0.0;
-  __syncthreads();
-  if (rowlane == 0 && r < nb) {
-    double s = red[t];
-    for (int q = 1; q < lanes; ++q) s += red[t + q * RB];
-    partial[(int64_t)blockIdx.x * nb + r] = s;
+#pragma unroll 4
+  for (int64_t d = d0; d < d1; ++d) {
+    const double2 w = W[d * nb + r];
+    acc += w.x * w.x + w.y * w.y;
   }
+  partial[(int64_t)blockIdx.x * nb + r] = acc;
 }
 
 __global__ void norm_reduce(const double* __restrict__ partial, int nblk, int nb,
@@ -416,8 +392,7 @@ struct GmresBlock {
     transpose = tr;
     const int64_t vec = D * nb;
     nblk_rows = (int)std::min<int64_t>(1024, std::max<int64_t>(1, vec / 4096));
-    const int RB = nb < 256 ? nb : 256;
-    nbrows_y = (nb + RB - 1) / RB;
+    nbrows_y = (nb + CW - 1) / CW;
     int64_t bytes = 0;
     auto add = [&](int64_t n, int64_t sz) { bytes += ((n * sz + 255) / 256) * 256; };
     add(vec * (m + 1), 16);                                   // V
@@ -472,7 +447,7 @@ struct GmresBlock {
 
   // out[r] = ||Wv[:, r]||
   void norms(const double2* Wv, double* out) {
-    hipLaunchKernelGGL(norm_kernel, dim3(nblk_rows, nbrows_y), dim3(256), 0, st(), Wv, D, nb, part_n);
+    hipLaunchKernelGGL(norm_kernel, dim3(nblk_rows, nbrows_y), dim3(CW), 0, st(), Wv, D, nb, part_n);
     GFCC_LAUNCH_CHECK();
     hipLaunchKernelGGL(norm_reduce, dim3(blocks_for(nb, 256)), dim3(256), 0, st(), part_n,
                        nblk_rows, nb, out);
@@ -483,7 +458,7 @@ struct GmresBlock {
   void dots(int nj, double2* h) {
     for (int j0 = 0; j0 < nj; j0 += JG) {
       int cnt = std::min(JG, nj - j0);
-      hipLaunchKernelGGL(dots_kernel, dim3(nblk_rows, nbrows_y), dim3(256), 0, st(), V, D * nb,
+      hipLaunchKernelGGL(dots_kernel, dim3(nblk_rows, nbrows_y), dim3(CW), 0, st(), V, D * nb,
                          j0, cnt, W, D, nb, part_h);
       GFCC_LAUNCH_CHECK();
       hipLaunchKernelGGL(dots_reduce, dim3(blocks_for((int64_t)cnt * nb, 256)), dim3(256), 0,
@@ -592,6 +567,7 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
     hipLaunchKernelGGL(scale_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.W, gb.s.inv, D, nb,
                        gb.V);
     GFCC_LAUNCH_CHECK();
+    int ksteps = 0;  // Arnoldi steps taken in this cycle (basis vectors that y can weight)
     for (int k = 0; k < m; ++k) {
       double2* Vk = gb.V + (int64_t)k * D * nb;
       hipLaunchKernelGGL(precond_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, Vk,
@@ -617,17 +593,19 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
       hipLaunchKernelGGL(scale_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.W, gb.s.inv, D,
                          nb, gb.V + (int64_t)(k + 1) * D * nb);
       GFCC_LAUNCH_CHECK();
+      ksteps = k + 1;
       GFCC_HIP(hipMemcpyAsync(act.data(), gb.s.active, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
       GFCC_HIP(hipStreamSynchronize(st));
       int any = 0;
       for (int r = 0; r < nb; ++r) any |= act[r];
       if (!any) break;
     }
-    // ---- solution update x += P^{-1} V y
+    // ---- solution update x += P^{-1} V y (y is zero beyond each right-hand side's kend,
+    // and kend <= ksteps)
     hipLaunchKernelGGL(ysolve_kernel, dim3(blocks_for(nb, 64)), dim3(64), 0, st, m, nb, gb.s,
                        gb.used, gb.Y);
     GFCC_LAUNCH_CHECK();
-    hipLaunchKernelGGL(xupdate_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.V, D * nb, m,
+    hipLaunchKernelGGL(xupdate_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.V, D * nb, ksteps,
                        gb.Y, ctx->op.diag.as<double>(), gb.z, D, nb, gb.X);
     GFCC_LAUNCH_CHECK();
     GFCC_HIP(hipMemcpyAsync(its.data(), gb.s.its, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
