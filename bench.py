@@ -92,6 +92,92 @@ def cpu_baseline(prob, cfg, omega, ps, gpu_G, n_p_sample):
     }, float(np.max(errs))
 
 
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBPS = 8000.0
+
+
+def rows_report(o, v, D, nb, t_step, t_build, sig_ms_step, sig_calls_step, its, restart):
+    """Per-row measurements of the plain step against the roofline that bounds each row."""
+    ov = o * v
+    build_flops = 2.0 * ov ** 3             # dominant build contraction (W_mbej's T2 term)
+    sigma_flops = 1.0 * nb * sigma_flops_per_rhs(o, v)
+    t_sig = sig_ms_step * 1e-3
+    # GMRES vector work: everything in the step but the build and the sigma products; bytes as
+    # counted per iteration j and right-hand side: 16 D (2j+3) (one Gram-Schmidt pass over the
+    # basis plus the update), and as moved by this implementation: two passes fused into three
+    # sweeps plus the normalisation, 16 D (3j+13) for j < 16, 16 D (4j+18) beyond
+    algo = 0.0
+    moved = 0.0
+    for n in its.reshape(-1):
+        for it in range(int(n)):
+            j = it % restart
+            algo += 16.0 * D * (2 * j + 3)
+            moved += 16.0 * D * ((3 * j + 13) if j < 16 else (4 * j + 18))
+    t_vec = max(t_step - t_build - t_sig, 1e-9)
+    return {
+        "a1_build": {"s": t_build, "flops": build_flops, "tflops": build_flops / t_build / 1e12,
+                     "frac_fp64_mfma": build_flops / t_build / 1e12 / PEAK_FP64_TFLOPS},
+        "a2_sigma": {"ms_per_call": sig_ms_step / max(sig_calls_step, 1), "rhs_per_call": nb,
+                     "flops_per_call": sigma_flops,
+                     "tflops": sigma_flops * sig_calls_step / max(t_sig, 1e-9) / 1e12,
+                     "frac_fp64_mfma": sigma_flops * sig_calls_step / max(t_sig, 1e-9) / 1e12
+                     / PEAK_FP64_TFLOPS},
+        "a3_gmres_vectors": {"s_per_step": t_vec, "algorithmic_bytes": algo,
+                             "gbps_algorithmic": algo / t_vec / 1e9,
+                             "frac_hbm_algorithmic": algo / t_vec / 1e9 / PEAK_HBM_GBPS,
+                             "bytes_moved": moved, "gbps_moved": moved / t_vec / 1e9,
+                             "frac_hbm_moved": moved / t_vec / 1e9 / PEAK_HBM_GBPS},
+    }
+
+
+def sigma_flops_per_rhs(o, v):
+    """Flops of one complex sigma product: multiply-adds of the nine terms per real column,
+    times 2 real columns and 2 flops per multiply-add."""
+    P = o * (o - 1) // 2
+    ov = o * v
+    macs = (o * o                 # T1  F_ki r_k
+            + o * o * v           # T2  F_ld r_il^d
+            + o * P * v           # T3  W_klid r_kl^d
+            + P * v * o           # T4  W_kaij r_k
+            + 2 * P * v * o       # T5  P(ij) F_ki r_kj^a
+            + P * v * v           # T6  F_ae r_ij^e
+            + P * P * v           # T7  W_klij r_kl^a
+            + ov * ov * o         # T8  P(ij) W_maei r_mj^e (full expansion)
+            + 2 * P * v * v)      # T9  tau_d = <kl||cd> r_kl^c, then t_ij^ad tau_d
+    return 4.0 * macs
+
+
+def form_small(gfcc, torch):
+    """The small case (o=10, v=20, D=910): 64 omega x 10 p, tol 1e-10. Latency-bound."""
+    import synth
+    cfg = synth.CONFIGS[0]
+    o, v = cfg["o"], cfg["v"]
+    prob = synth.make_problem(o, v, cfg["seed"])
+    dev = torch.device("cuda", 0)
+    host = [prob.eps, prob.t1, prob.t2, prob.l1, prob.l2] + [
+        prob.block(k) for k in ("oooo", "ooov", "oovv", "ovvo", "ovvv")]
+    inputs = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in host]
+    ctx = gfcc.Context(0)
+    om = synth.omega_grid(cfg["omega"])
+    ps = synth.valence_p(o, cfg["np"])
+    nrhs = len(om) * len(ps)
+    best = None
+    for rep in range(3):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        ctx.build_hbar_operands(o, v, *inputs)
+        r = ctx.gfcc_solve(om, ps, cfg["eta"], tol=cfg["tol"], block=nrhs)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        best = dt if best is None else min(best, dt)
+    ctx.close()
+    return {"workload": f"o={o} v={v} (D={gfcc.dim(o, v)}), {len(om)} omega x {len(ps)} p "
+                        f"in one block, eta={cfg['eta']}, tol={cfg['tol']}, build included",
+            "s": best, "points_per_s": len(om) / best, "iterations_mean": float(r.iters.mean()),
+            "max_rel_resid": float(r.resid.max()),
+            "note": "launch/latency-bound: the operator is about 1 MB"}
+
+
 def form_mor(ctx, prob, cfg, gfcc):
     """Reduced-order model on the same operator: sample 8 frequencies of the window, refine
     by midpoints (8 per round) until the max residual on the grid is <= 1e-6, evaluate 4000
@@ -121,7 +207,9 @@ def form_mor(ctx, prob, cfg, gfcc):
     return {
         "points": len(grid), "points_per_s_end_to_end": len(grid) / (t2 - t0),
         "points_per_s_eval_only": len(grid) / (t2 - t1), "build_refine_s": t1 - t0,
-        "eval_s": t2 - t1, "rounds": rounds, "order_m": m, "sampled_omegas": len(oks),
+        "eval_s": t2 - t1,
+        "eval_gflops": len(grid) * (8.0 / 3.0) * m ** 3 / (t2 - t1) / 1e9,
+        "rounds": rounds, "order_m": m, "sampled_omegas": len(oks),
         "full_solves": len(oks) * len(ps), "max_resid_window": float(rmax),
         "max_resid_grid": float(res.max()),
         "A_max_rel_err_interp": float(err[inside].max()),
@@ -149,7 +237,19 @@ def form_adjoint(ctx, cfg, gfcc, inputs):
     torch.cuda.synchronize()
     dt = time.time() - t0
     J = float(np.dot(w, gfcc.spectral_function(fwd.G)))
+    # the transposed ovvo kernel in the benchmark's launch shape (320 right-hand sides)
+    ov = o * (inputs[0].shape[0] - o)
+    x = torch.randn((320, ctx.D), dtype=torch.complex128, device=fwd.X.device)
+    ctx.sigma_apply(x, transpose=True)
+    ctx.timer(0, enable=True, reset=True)
+    for _ in range(2):
+        ctx.sigma_apply(x, transpose=True)
+    torch.cuda.synchronize()
+    ms, n = ctx.timer(0, enable=False, reset=True)
+    tf = 2.0 * ov * ov * (o * 640) / (ms / n * 1e-3) / 1e12
+    del x
     return {"points": len(om), "s": dt, "points_per_s": len(om) / dt, "J": J,
+            "ovvo_transposed_tflops": tf, "ovvo_transposed_frac": tf / PEAK_FP64_TFLOPS,
             "grad_occ_norm": float(np.linalg.norm(g[:o])), "max_rel_resid_fwd": float(fwd.resid.max()),
             "max_rel_resid_adj": float(adj.resid.max())}
 
@@ -199,6 +299,21 @@ def form_mixed(cfg, gfcc, torch):
     Ad = gfcc.spectral_function(res["fp64"][0].G)
     out["A_max_rel_err_vs_fp64"] = float(np.abs(Am - Ad).max() / np.abs(Ad).max())
     out["speedup_vs_fp64"] = res["fp64"][1] / res["fp32_bf16"][1]
+    del res
+    # the ovvo kernel of this shape and block in both precisions
+    ov = o * v
+    x = torch.randn((nrhs, ctx.D), dtype=torch.complex128, device=dev)
+    for name, prec, peak in (("fp32", gfcc.FP32, PEAK_FP32_TFLOPS), ("fp64", gfcc.FP64, PEAK_FP64_TFLOPS)):
+        ctx.sigma_apply(x, precision=prec)
+        ctx.timer(0, enable=True, reset=True)
+        for _ in range(2):
+            ctx.sigma_apply(x, precision=prec)
+        torch.cuda.synchronize()
+        ms, n = ctx.timer(0, enable=False, reset=True)
+        tf = 2.0 * ov * ov * (o * 2 * nrhs) / (ms / n * 1e-3) / 1e12
+        out[f"ovvo_{name}_tflops"] = tf
+        out[f"ovvo_{name}_frac"] = tf / peak
+    del x
     ctx.close()
     return out
 
@@ -216,8 +331,9 @@ def main():
     ap.add_argument("--sigma-only", type=int, default=0,
                     help="profiling driver: K sigma products of one block in the benchmark's "
                          "launch configuration, then a 1 GiB device copy (counter calibration)")
-    ap.add_argument("--forms", default="mor,adjoint,mixed",
-                    help="extra forms reported beside the plain path: mor, adjoint, mixed, none")
+    ap.add_argument("--forms", default="mor,adjoint,mixed,small",
+                    help="extra forms reported beside the plain path: mor, adjoint, mixed, "
+                         "small, none")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the (omega, p) right-hand "
@@ -289,6 +405,12 @@ def main():
     ovvo_ms, ovvo_n = ctx.timer(0, enable=False, reset=True)
     sig_ms, sig_n = ctx.timer(1, enable=False, reset=True)
     its = res.iters
+    # operator build on its own (inside every step above)
+    torch.cuda.synchronize()
+    tb = time.time()
+    ctx.build_hbar_operands(o, v, *inputs)
+    torch.cuda.synchronize()
+    t_build = time.time() - tb
     points = args.steps * len(omega)
     value = points / dt
     # dominant kernel: ovvo contraction, algorithmic flops per launch = 2 (ov)^2 (o * 2 nb)
@@ -329,7 +451,11 @@ def main():
             "sigma_ms_total": sig_ms, "A_range": [float(A.min()), float(A.max())],
         },
     }
+    out["rows"] = rows_report(o, v, D, nb, dt / args.steps, t_build, sig_ms / args.steps,
+                              sig_n // args.steps, its, args.restart)
     forms = [f for f in args.forms.split(",") if f and f != "none"]
+    if "small" in forms:
+        out["small"] = form_small(gfcc, torch)
     if "mor" in forms:
         out["mor"] = form_mor(ctx, prob, synth.CONFIGS[2], gfcc)
     if "adjoint" in forms:

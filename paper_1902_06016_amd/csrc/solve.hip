@@ -66,19 +66,173 @@ __global__ __launch_bounds__(CW) void dots_kernel(const double2* __restrict__ V,
     if (jj < nj) partial[((int64_t)blockIdx.x * JG + jj) * nb + r] = acc[jj];
 }
 
-// h[(j0+jj)][r] (+)= sum_blk partial[blk][jj][r]
-__global__ void dots_reduce(const double2* __restrict__ partial, int nblk, int j0, int nj, int nb,
-                            double2* __restrict__ h) {
-  int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nj * nb) return;
-  int jj = idx / nb, r = idx % nb;
-  double2 s = make_double2(0.0, 0.0);
-  for (int b = 0; b < nblk; ++b) {
-    double2 x = partial[((int64_t)b * JG + jj) * nb + r];
-    s.x += x.x;
-    s.y += x.y;
+// ---- fused Arnoldi passes over NJ <= JG basis vectors (same grid and partial layout as
+// dots_kernel). NJ is a template parameter so that every load of a row is issued before the
+// arithmetic that consumes it.
+
+// W += z U (the shift of M(omega) after the sigma product), then the first Gram-Schmidt
+// pass's dots with V_0 .. V_{NJ-1}
+template <int NJ>
+__global__ __launch_bounds__(CW) void shift_dots_kernel(const double2* __restrict__ V,
+                                                        int64_t vstride,
+                                                        const double2* __restrict__ U,
+                                                        const double2* __restrict__ z,
+                                                        double2* __restrict__ W, int64_t D, int nb,
+                                                        double2* __restrict__ partial) {
+  const int r = blockIdx.y * CW + threadIdx.x;
+  if (r >= nb) return;
+  const double2 zz = z[r];
+  double2 acc[NJ];
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) acc[jj] = make_double2(0.0, 0.0);
+  const int64_t rows_per_blk = (D + gridDim.x - 1) / gridDim.x;
+  const int64_t d0 = (int64_t)blockIdx.x * rows_per_blk;
+  const int64_t d1 = min(D, d0 + rows_per_blk);
+  for (int64_t d = d0; d < d1; ++d) {
+    const int64_t idx = d * nb + r;
+    double2 vj[NJ];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) vj[jj] = V[(int64_t)jj * vstride + idx];
+    double2 w = W[idx];
+    const double2 p = cmul(zz, U[idx]);
+    w.x += p.x;
+    w.y += p.y;
+    W[idx] = w;
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+      const double2 q = cconjmul(vj[jj], w);
+      acc[jj].x += q.x;
+      acc[jj].y += q.y;
+    }
   }
-  h[(int64_t)(j0 + jj) * nb + r] = s;
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) partial[((int64_t)blockIdx.x * JG + jj) * nb + r] = acc[jj];
+}
+
+// W -= sum_j V_j h[j]; then, with the same V_j in registers, the dots of the next pass
+template <int NJ>
+__global__ __launch_bounds__(CW) void update_dots_kernel(const double2* __restrict__ V,
+                                                         int64_t vstride,
+                                                         const double2* __restrict__ h,
+                                                         double2* __restrict__ W, int64_t D,
+                                                         int nb, double2* __restrict__ partial) {
+  const int r = blockIdx.y * CW + threadIdx.x;
+  if (r >= nb) return;
+  double2 hr[NJ], acc[NJ];
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) {
+    hr[jj] = h[(int64_t)jj * nb + r];
+    acc[jj] = make_double2(0.0, 0.0);
+  }
+  const int64_t rows_per_blk = (D + gridDim.x - 1) / gridDim.x;
+  const int64_t d0 = (int64_t)blockIdx.x * rows_per_blk;
+  const int64_t d1 = min(D, d0 + rows_per_blk);
+  for (int64_t d = d0; d < d1; ++d) {
+    const int64_t idx = d * nb + r;
+    double2 vj[NJ];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) vj[jj] = V[(int64_t)jj * vstride + idx];
+    double2 w = W[idx];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+      const double2 p = cmul(vj[jj], hr[jj]);
+      w.x -= p.x;
+      w.y -= p.y;
+    }
+    W[idx] = w;
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+      const double2 q = cconjmul(vj[jj], w);
+      acc[jj].x += q.x;
+      acc[jj].y += q.y;
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) partial[((int64_t)blockIdx.x * JG + jj) * nb + r] = acc[jj];
+}
+
+// W -= sum_j V_j h[j]; partial |W|^2 (the norm_kernel layout)
+template <int NJ>
+__global__ __launch_bounds__(CW) void update_norm_kernel(const double2* __restrict__ V,
+                                                         int64_t vstride,
+                                                         const double2* __restrict__ h,
+                                                         double2* __restrict__ W, int64_t D,
+                                                         int nb, double* __restrict__ partial) {
+  const int r = blockIdx.y * CW + threadIdx.x;
+  if (r >= nb) return;
+  double2 hr[NJ];
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) hr[jj] = h[(int64_t)jj * nb + r];
+  double acc = 0.0;
+  const int64_t rows_per_blk = (D + gridDim.x - 1) / gridDim.x;
+  const int64_t d0 = (int64_t)blockIdx.x * rows_per_blk;
+  const int64_t d1 = min(D, d0 + rows_per_blk);
+  for (int64_t d = d0; d < d1; ++d) {
+    const int64_t idx = d * nb + r;
+    double2 vj[NJ];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) vj[jj] = V[(int64_t)jj * vstride + idx];
+    double2 w = W[idx];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+      const double2 p = cmul(vj[jj], hr[jj]);
+      w.x -= p.x;
+      w.y -= p.y;
+    }
+    W[idx] = w;
+    acc += w.x * w.x + w.y * w.y;
+  }
+  partial[(int64_t)blockIdx.x * nb + r] = acc;
+}
+
+// launch tables over NJ = 1 .. JG
+typedef void (*ShiftDotsFn)(const double2*, int64_t, const double2*, const double2*, double2*,
+                            int64_t, int, double2*);
+typedef void (*UpdateDotsFn)(const double2*, int64_t, const double2*, double2*, int64_t, int,
+                             double2*);
+typedef void (*UpdateNormFn)(const double2*, int64_t, const double2*, double2*, int64_t, int,
+                             double*);
+template <int... I> struct FusedTables {
+  static constexpr ShiftDotsFn shift_dots[] = {shift_dots_kernel<I + 1>...};
+  static constexpr UpdateDotsFn update_dots[] = {update_dots_kernel<I + 1>...};
+  static constexpr UpdateNormFn update_norm[] = {update_norm_kernel<I + 1>...};
+};
+using Fused = FusedTables<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15>;
+static_assert(JG == 16, "the launch tables cover NJ = 1 .. 16");
+
+// h[(j0+jj)][r] = sum_blk partial[blk][jj][r]. Grid (ceil(nb/64), nj), 256 threads: the lanes
+// are 64 consecutive right-hand sides (coalesced reads), wave w sums the blocks w, w+4, ...,
+// and the four wave sums are added in a fixed order.
+__global__ __launch_bounds__(256) void dots_reduce(const double2* __restrict__ partial, int nblk,
+                                                   int j0, int nj, int nb,
+                                                   double2* __restrict__ h) {
+  __shared__ double2 red[4][CW];
+  const int lane = threadIdx.x % CW, w = threadIdx.x / CW;
+  const int r = blockIdx.x * CW + lane, jj = blockIdx.y;
+  double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
+  if (r < nb && jj < nj) {
+    int b = w;
+    for (; b + 4 < nblk; b += 8) {
+      const double2 x = partial[((int64_t)b * JG + jj) * nb + r];
+      const double2 y = partial[((int64_t)(b + 4) * JG + jj) * nb + r];
+      s0.x += x.x; s0.y += x.y;
+      s1.x += y.x; s1.y += y.y;
+    }
+    for (; b < nblk; b += 4) {
+      const double2 x = partial[((int64_t)b * JG + jj) * nb + r];
+      s0.x += x.x; s0.y += x.y;
+    }
+  }
+  red[w][lane] = make_double2(s0.x + s1.x, s0.y + s1.y);
+  __syncthreads();
+  if (w == 0 && r < nb && jj < nj) {
+    double2 t = red[0][lane];
+    for (int q = 1; q < 4; ++q) {
+      t.x += red[q][lane].x;
+      t.y += red[q][lane].y;
+    }
+    h[(int64_t)(j0 + jj) * nb + r] = t;
+  }
 }
 
 // W[d][r] -= sum_{j<=k} V_j[d][r] * h[j][r]
@@ -116,13 +270,24 @@ __global__ __launch_bounds__(CW) void norm_kernel(const double2* __restrict__ W,
   partial[(int64_t)blockIdx.x * nb + r] = acc;
 }
 
-__global__ void norm_reduce(const double* __restrict__ partial, int nblk, int nb,
-                            double* __restrict__ out) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nb) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * nb + r];
-  out[r] = sqrt(s);
+// out[r] = sqrt(sum_blk partial[blk][r]); same scheme as dots_reduce, grid ceil(nb/64)
+__global__ __launch_bounds__(256) void norm_reduce(const double* __restrict__ partial, int nblk,
+                                                   int nb, double* __restrict__ out) {
+  __shared__ double red[4][CW];
+  const int lane = threadIdx.x % CW, w = threadIdx.x / CW;
+  const int r = blockIdx.x * CW + lane;
+  double s0 = 0.0, s1 = 0.0;
+  if (r < nb) {
+    int b = w;
+    for (; b + 4 < nblk; b += 8) {
+      s0 += partial[(int64_t)b * nb + r];
+      s1 += partial[(int64_t)(b + 4) * nb + r];
+    }
+    for (; b < nblk; b += 4) s0 += partial[(int64_t)b * nb + r];
+  }
+  red[w][lane] = s0 + s1;
+  __syncthreads();
+  if (w == 0 && r < nb) out[r] = sqrt(red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane]);
 }
 
 // U[d][r] = V[d][r] / (diag[d] + z[r])
@@ -181,6 +346,26 @@ __global__ void scale_kernel(const double2* __restrict__ W, const double* __rest
     double s = inv[r];
     double2 w = W[idx];
     V[idx] = make_double2(w.x * s, w.y * s);
+  }
+}
+
+// Vn[d][r] = W[d][r] inv[r] and U[d][r] = Vn[d][r] / (diag[d] + z[r]) (the next basis vector
+// and its preconditioned copy in one pass)
+__global__ void scale_precond_kernel(const double2* __restrict__ W, const double* __restrict__ inv,
+                                     const double* __restrict__ diag, const double2* __restrict__ z,
+                                     int64_t D, int nb, double2* __restrict__ Vn,
+                                     double2* __restrict__ U) {
+  const int64_t n = D * nb;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx % nb);
+    const int64_t d = idx / nb;
+    const double s = inv[r];
+    const double2 w = W[idx];
+    const double2 x = make_double2(w.x * s, w.y * s);
+    Vn[idx] = x;
+    const double2 zz = z[r];
+    U[idx] = cdiv(x, make_double2(diag[d] + zz.x, zz.y));
   }
 }
 
@@ -449,8 +634,8 @@ struct GmresBlock {
   void norms(const double2* Wv, double* out) {
     hipLaunchKernelGGL(norm_kernel, dim3(nblk_rows, nbrows_y), dim3(CW), 0, st(), Wv, D, nb, part_n);
     GFCC_LAUNCH_CHECK();
-    hipLaunchKernelGGL(norm_reduce, dim3(blocks_for(nb, 256)), dim3(256), 0, st(), part_n,
-                       nblk_rows, nb, out);
+    hipLaunchKernelGGL(norm_reduce, dim3(nbrows_y), dim3(256), 0, st(), part_n, nblk_rows, nb,
+                       out);
     GFCC_LAUNCH_CHECK();
   }
 
@@ -461,15 +646,16 @@ struct GmresBlock {
       hipLaunchKernelGGL(dots_kernel, dim3(nblk_rows, nbrows_y), dim3(CW), 0, st(), V, D * nb,
                          j0, cnt, W, D, nb, part_h);
       GFCC_LAUNCH_CHECK();
-      hipLaunchKernelGGL(dots_reduce, dim3(blocks_for((int64_t)cnt * nb, 256)), dim3(256), 0,
-                         st(), part_h, nblk_rows, j0, cnt, nb, h);
+      hipLaunchKernelGGL(dots_reduce, dim3(nbrows_y, cnt), dim3(256), 0, st(), part_h, nblk_rows,
+                         j0, cnt, nb, h);
       GFCC_LAUNCH_CHECK();
     }
   }
 
   // Wv = M(omega) Uv = sigma(Uv) + z Uv ; sigma in FP64 when fp64 is set, else in the
   // block's precision
-  void apply_M(const double2* Uv, double2* Wv, bool fp64) {
+  // With shift false, only the sigma product is formed (the caller adds z U itself).
+  void apply_M(const double2* Uv, double2* Wv, bool fp64, bool shift = true) {
     const int nc = 2 * nb;
     if (fp64 || precision == GFCC_FP64) {
       sigma_block_f64(ctx, nc, reinterpret_cast<const double*>(Uv), reinterpret_cast<double*>(Wv),
@@ -484,7 +670,20 @@ struct GmresBlock {
                          reinterpret_cast<double*>(Wv), n);
       GFCC_LAUNCH_CHECK();
     }
+    if (!shift) return;
     hipLaunchKernelGGL(shift_kernel, dim3(gridn(D * nb)), dim3(256), 0, st(), Wv, Uv, z, D, nb, Wv);
+    GFCC_LAUNCH_CHECK();
+  }
+
+  // h[j][r] = sum over blocks of the partial dots (nj <= JG)
+  void reduce_dots(int nj, double2* h) {
+    hipLaunchKernelGGL(dots_reduce, dim3(nbrows_y, nj), dim3(256), 0, st(), part_h, nblk_rows, 0,
+                       nj, nb, h);
+    GFCC_LAUNCH_CHECK();
+  }
+  void reduce_norms(double* out) {
+    hipLaunchKernelGGL(norm_reduce, dim3(nbrows_y), dim3(256), 0, st(), part_n, nblk_rows, nb,
+                       out);
     GFCC_LAUNCH_CHECK();
   }
 };
@@ -564,34 +763,52 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
     GFCC_HIP(hipMemcpyAsync(gb.s.g, g0.data(), sizeof(double2) * g0.size(), hipMemcpyHostToDevice, st));
     GFCC_HIP(hipMemcpyAsync(gb.s.kend, zeros.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
     GFCC_HIP(hipMemcpyAsync(gb.s.its, its.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(scale_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.W, gb.s.inv, D, nb,
-                       gb.V);
+    // V0 = R / ||R|| and its preconditioned copy U
+    hipLaunchKernelGGL(scale_precond_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.W, gb.s.inv,
+                       ctx->op.diag.as<double>(), gb.z, D, nb, gb.V, gb.U);
     GFCC_LAUNCH_CHECK();
     int ksteps = 0;  // Arnoldi steps taken in this cycle (basis vectors that y can weight)
+    const dim3 rgrid(gb.nblk_rows, gb.nbrows_y);
     for (int k = 0; k < m; ++k) {
-      double2* Vk = gb.V + (int64_t)k * D * nb;
-      hipLaunchKernelGGL(precond_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, Vk,
-                         ctx->op.diag.as<double>(), gb.z, D, nb, gb.U);
+      const int nj = k + 1;
+      if (nj <= JG) {
+        // W = sigma(U); the shift, both Gram-Schmidt passes (CGS2) and the norm in three
+        // fused sweeps over the basis; Hessenberg column = sum of both passes
+        gb.apply_M(gb.U, gb.W, false, false);
+        hipLaunchKernelGGL(Fused::shift_dots[nj - 1], rgrid, dim3(CW), 0, st, gb.V, D * nb, gb.U,
+                           gb.z, gb.W, D, nb, gb.part_h);
+        GFCC_LAUNCH_CHECK();
+        gb.reduce_dots(nj, gb.Hh);
+        hipLaunchKernelGGL(Fused::update_dots[nj - 1], rgrid, dim3(CW), 0, st, gb.V, D * nb,
+                           gb.Hh, gb.W, D, nb, gb.part_h);
+        GFCC_LAUNCH_CHECK();
+        gb.reduce_dots(nj, gb.Hh2);
+        hipLaunchKernelGGL(Fused::update_norm[nj - 1], rgrid, dim3(CW), 0, st, gb.V, D * nb,
+                           gb.Hh2, gb.W, D, nb, gb.part_n);
+        GFCC_LAUNCH_CHECK();
+        gb.reduce_norms(gb.nrm);
+      } else {
+        gb.apply_M(gb.U, gb.W, false);
+        gb.dots(nj, gb.Hh);
+        hipLaunchKernelGGL(update_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.V, D * nb,
+                           nj, gb.Hh, D, nb, gb.W);
+        GFCC_LAUNCH_CHECK();
+        gb.dots(nj, gb.Hh2);
+        hipLaunchKernelGGL(update_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.V, D * nb,
+                           nj, gb.Hh2, D, nb, gb.W);
+        GFCC_LAUNCH_CHECK();
+        gb.norms(gb.W, gb.nrm);
+      }
+      hipLaunchKernelGGL(cadd_kernel, dim3(blocks_for((int64_t)nj * nb, 256)), dim3(256), 0,
+                         st, gb.Hh, gb.Hh2, (int64_t)nj * nb);
       GFCC_LAUNCH_CHECK();
-      gb.apply_M(gb.U, gb.W, false);
-      // CGS2: two passes of classical Gram-Schmidt; Hessenberg column = sum of both
-      gb.dots(k + 1, gb.Hh);
-      hipLaunchKernelGGL(update_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.V, D * nb,
-                         k + 1, gb.Hh, D, nb, gb.W);
-      GFCC_LAUNCH_CHECK();
-      gb.dots(k + 1, gb.Hh2);
-      hipLaunchKernelGGL(update_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.V, D * nb,
-                         k + 1, gb.Hh2, D, nb, gb.W);
-      GFCC_LAUNCH_CHECK();
-      hipLaunchKernelGGL(cadd_kernel, dim3(blocks_for((int64_t)(k + 1) * nb, 256)), dim3(256), 0,
-                         st, gb.Hh, gb.Hh2, (int64_t)(k + 1) * nb);
-      GFCC_LAUNCH_CHECK();
-      gb.norms(gb.W, gb.nrm);
       hipLaunchKernelGGL(arnoldi_finish_kernel, dim3(blocks_for(nb, 64)), dim3(64), 0, st, gb.Hh,
                          gb.nrm, k, m, nb, maxit, gb.s);
       GFCC_LAUNCH_CHECK();
-      hipLaunchKernelGGL(scale_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.W, gb.s.inv, D,
-                         nb, gb.V + (int64_t)(k + 1) * D * nb);
+      // V_{k+1} and the preconditioned input of the next step
+      hipLaunchKernelGGL(scale_precond_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.W,
+                         gb.s.inv, ctx->op.diag.as<double>(), gb.z, D, nb,
+                         gb.V + (int64_t)(k + 1) * D * nb, gb.U);
       GFCC_LAUNCH_CHECK();
       ksteps = k + 1;
       GFCC_HIP(hipMemcpyAsync(act.data(), gb.s.active, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
@@ -647,25 +864,34 @@ gfcc_status solve_all(gfcc_ctx* ctx, int nw, const double* omega, int np, const 
     GFCC_LAUNCH_CHECK();
   }
   bG.alloc(sizeof(double2) * (size_t)np * nb);
-  for (int r0 = 0; r0 < nrhs; r0 += nb) {
+  for (int r0 = 0; r0 < nrhs;) {
+    // the last block is only as wide as the right-hand sides left, rounded up to a multiple
+    // of 64 (which keeps the column-block ovvo kernel); padding columns have b = 0
+    const int left = nrhs - r0;
+    if (left < gb.nb) {
+      const int nbl = std::min(gb.nb, (left + 63) / 64 * 64);
+      if (nbl != gb.nb) gb.setup(ctx, nbl, restart, precision, transpose != 0);
+    }
+    const int nbb = gb.nb;
     solve_block(gb, omega, p, np, nrhs, r0, eta, tol, maxit, its, res, brk);
     // G rows for this block
     if (!transpose) {
-      gemm<double>(ctx, false, false, np, 2 * nb, (int)D, 1.0, bC.as<double>(), D,
-                   reinterpret_cast<const double*>(gb.X), 2 * nb, 0.0, bG.as<double>(), 2 * nb);
+      gemm<double>(ctx, false, false, np, 2 * nbb, (int)D, 1.0, bC.as<double>(), D,
+                   reinterpret_cast<const double*>(gb.X), 2 * nbb, 0.0, bG.as<double>(), 2 * nbb);
     } else {
-      hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks_for((int64_t)np * nb, 256)), dim3(256),
-                         0, ctx->stream, gb.X, bq.as<int>(), np, nb, bG.as<double2>());
+      hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks_for((int64_t)np * nbb, 256)), dim3(256),
+                         0, ctx->stream, gb.X, bq.as<int>(), np, nbb, bG.as<double2>());
       GFCC_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(scatter_G_kernel, dim3(blocks_for((int64_t)np * nb, 256)), dim3(256), 0,
-                       ctx->stream, bG.as<double2>(), np, nb, r0, nrhs, np, transpose,
+    hipLaunchKernelGGL(scatter_G_kernel, dim3(blocks_for((int64_t)np * nbb, 256)), dim3(256), 0,
+                       ctx->stream, bG.as<double2>(), np, nbb, r0, nrhs, np, transpose,
                        static_cast<double2*>(G_out));
     GFCC_LAUNCH_CHECK();
     if (X_out) {
-      int cnt = std::min(nb, nrhs - r0);
-      ctranspose(ctx, gb.X, D, cnt, nb, static_cast<double2*>(X_out) + (int64_t)r0 * D, D);
+      int cnt = std::min(nbb, nrhs - r0);
+      ctranspose(ctx, gb.X, D, cnt, nbb, static_cast<double2*>(X_out) + (int64_t)r0 * D, D);
     }
+    r0 += nbb;
   }
   GFCC_HIP(hipStreamSynchronize(ctx->stream));
   timers_collect(ctx);
