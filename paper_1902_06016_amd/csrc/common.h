@@ -169,6 +169,12 @@ bool ovvo_fast(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, con
                int64_t ldx, T* Z, const T* zrow);
 inline int64_t ovvo_pad_bytes(int64_t M) { return 512 * M; }
 
+// C[M][N] = alpha op(A) B + beta C, B row-major [K][ldb], on the pipelined kernel of ovvo.hip;
+// false when the product has too few 128 x 128 tiles to fill the GPU.
+template <typename T>
+bool gemm_pipe(gfcc_ctx* ctx, bool transA, int M, int N, int K, T alpha, const T* A, int64_t lda,
+               const T* B, int64_t ldb, T beta, T* C, int64_t ldc);
+
 // A device buffer of at least `bytes` zero bytes, owned by the context (grown on demand).
 const void* zero_row(gfcc_ctx* ctx, size_t bytes);
 

@@ -315,6 +315,10 @@ template <typename T>
 void gemm(gfcc_ctx* ctx, bool transA, bool transB, int M, int N, int K, T alpha, const T* A,
           int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc, int batch,
           int64_t sA, int64_t sB, int64_t sC) {
+  // large single products with a row-major B go to the pipelined kernel
+  if (!transB && batch == 1 &&
+      gemm_pipe<T>(ctx, transA, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc))
+    return;
   gemm_impl<T>(ctx, transA, transB ? B_TRANS : B_ROW, M, N, K, alpha, A, lda, B, ldb, beta, C,
                ldc, batch, sA, sB, sC, nullptr, 0, 1, 1);
 }

@@ -16,6 +16,9 @@
 // after. The step is written as fenced slots of two MFMAs plus a small group of other work,
 // so that every wavefront keeps its matrix pipe fed on its own.
 //
+// The same kernel also runs plain products C = alpha op(A) B + beta C with a row-major B
+// (gemm_pipe): the B rows are then addressed like the column-block loader's, without sign.
+//
 // LDS holds both tiles k-contiguous ([row][k]) with a 136-byte pitch, which keeps the
 // per-k-step fragment reads (lanes 0-15 on 16 rows) and the 8-byte stores free of bank
 // conflicts.
@@ -60,13 +63,16 @@ template <> struct MF<float> {
 };
 
 template <typename T> struct OvvoArgs {
-  const T* W;        // [M][K] (or [K][M] when transposed), followed by zero padding
-  const T* X2;       // packed 2h1p block [(pair, e)][ldx]
-  const T* zrow;     // >= nc zeros (column-block loader)
-  T* Z;              // [M][N]
-  int o, v, nc;      // N = o * nc
+  const T* W;        // A: [M][lda] (or [K][lda] when transposed); the ovvo Weff is followed by
+                     // zero padding
+  const T* X2;       // ovvo: packed 2h1p block [(pair, e)][ldx]; dense: B [K][ldb]
+  const T* zrow;     // zeros: >= nc (column-block loader) or >= N (dense loader)
+  T* Z;              // C [M][ldc]
+  int o, v, nc;      // ovvo: N = o * nc
   int M, N, K;
-  int ldx;
+  int ldx;           // ovvo: row stride of X2
+  int64_t lda, ldb, ldc;
+  T alpha, beta;     // C = alpha A B + beta C (beta == 0 never reads C)
   int mtiles, ntiles, nslabs;
 };
 
@@ -76,10 +82,17 @@ __device__ __forceinline__ int pair_index(int i, int j, int o) {  // i < j
 
 template <int N> struct IC { static constexpr int value = N; };
 
-// TA: W is stored transposed ([K][M]). BLOCKJ: column-block loader (nc % 128 == 0, W padded,
-// 16-byte aligned rows). VEC: 16-byte A loads (general loader only).
-template <typename T, bool TA, bool BLOCKJ, bool VEC>
+// B operand loaders
+enum { B_GATHER = 0, B_COLBLOCK = 1, B_DENSE = 2 };
+
+// TA: A is stored transposed ([K][lda]). MODE: B_GATHER (ovvo, general), B_COLBLOCK (ovvo,
+// nc % 128 == 0, W padded, 16-byte aligned rows) or B_DENSE (plain row-major B). VEC: 16-byte
+// A loads.
+template <typename T, bool TA, int MODE, bool VEC>
 __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
+  constexpr bool BLOCKJ = MODE == B_COLBLOCK;
+  constexpr bool DENSE = MODE == B_DENSE;
+  constexpr bool SCALARB = MODE != B_GATHER;   // scalar B row addresses
   using M4 = MF<T>;
   using C4 = typename M4::C4;
   constexpr int BK = 128 / (int)sizeof(T);      // k per slab
@@ -115,6 +128,7 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
   const T* __restrict__ W = p.W;
   const T* __restrict__ X2 = p.X2;
   const int K = p.K, M = p.M, v = p.v, o = p.o, ldx = p.ldx;
+  const int64_t lda = p.lda;
 
   // ---- B ownership: column bn, rows kh * RB + r of every slab (kh is wave-uniform)
   const int bn = tid % BN;
@@ -122,9 +136,10 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
   const int first = kh * RB;
   const int n = n0 + bn;
   const bool ncol = BLOCKJ || n < p.N;
-  const int jt = n0 / p.nc;                                  // column-block: the tile's j
-  const int j = BLOCKJ ? jt : (ncol ? n / p.nc : 0);
-  const int c = ncol ? n - j * p.nc : 0;
+  const int jt = DENSE ? 0 : n0 / p.nc;                      // column-block: the tile's j
+  const int j = (BLOCKJ || DENSE) ? jt : (ncol ? n / p.nc : 0);
+  // column read by this lane: of X2 (ovvo) or of B and the zero row (dense)
+  const int c = DENSE ? (ncol ? n : 0) : (ncol ? n - j * p.nc : 0);
 
   // ---- A ownership. Column-block loader: per-lane base pointers advanced by the slab offset;
   // reads past k = K land in the next row or in the zero padding after W, against B rows
@@ -135,19 +150,20 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
     for (int r = 0; r < ACH; ++r) {
       if (!TA) {
         const int row = min(m0 + tid / CPR + (NT / CPR) * r, M - 1);
-        wa[r] = W + (int64_t)row * K + (tid % CPR) * VPC;
+        wa[r] = W + (int64_t)row * lda + (tid % CPR) * VPC;
       } else {
         const int f = tid + NT * r;
         const int mm = min(m0 + (f % (BM / VPC)) * VPC, M - VPC);
-        wa[r] = W + (int64_t)(f / (BM / VPC)) * M + mm;
+        wa[r] = W + (int64_t)(f / (BM / VPC)) * lda + mm;
       }
     }
   }
 
   // ---- B row bookkeeping. prep() prepares the rows of the next slab to be loaded (position
-  // k0 = ms * v + es, scalar); its sign / liveness state moves to the "in registers" copy once
-  // that slab's loads are issued, and is used when the registers are stored to LDS.
-  int ms = 0, es = 0;
+  // k0 = ms * v + es for the ovvo operand, kp for a dense B, scalar); its sign / liveness
+  // state moves to the "in registers" copy once that slab's loads are issued, and is used when
+  // the registers are stored to LDS.
+  int ms = 0, es = 0, kp = 0;
   typedef const T __attribute__((address_space(1)))* gptr;
   uint64_t prow[RB];                                      // column-block: row addresses
   unsigned pneg = 0, sneg = 0;                            // column-block: row r negated
@@ -179,6 +195,21 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
   // in three parts (segment m, segment m+1, carry / sign / advance) so that they can be spread
   // between MFMAs
   auto prep_base = [&](int part) {
+    if (DENSE) {
+      // rows kp + first + r of B while below K, the zero row beyond
+      if (part == 0) {
+        q0 = reinterpret_cast<uint64_t>(X2) + (uint64_t)((int64_t)(kp + first) * p.ldb) * sizeof(T);
+        d0 = (uint64_t)p.ldb * sizeof(T);
+      } else if (part == 1) {
+        q1 = reinterpret_cast<uint64_t>(p.zrow);
+        d1 = 0;
+      } else {
+        rc = K - kp - first;
+        pneg = 0;
+        kp += BK;
+      }
+      return;
+    }
     if (part == 0) {
       if (BLOCKJ) cbase(ms, es + first, q0, d0);
       else pb0 = rowbase(ms, pl0, pg0) + es * ldx;
@@ -204,7 +235,7 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
     }
   };
   auto prep_row = [&](int r) {
-    if (BLOCKJ) {
+    if (SCALARB) {
       const uint64_t mk = 0ull - (uint64_t)(r >= rc);
       prow[r] = ((q1 + r * d1) & mk) | ((q0 + r * d0) & ~mk);
     }
@@ -228,14 +259,14 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
   // ---- loads of one slab: ACH A chunks (ops 0 .. ACH-1), then B rows
   auto load_a = [&](int r, int k0) {
     if (BLOCKJ) {
-      const V16 x = *reinterpret_cast<const V16*>(wa[r] + (TA ? (int64_t)k0 * M : k0));
+      const V16 x = *reinterpret_cast<const V16*>(wa[r] + (TA ? (int64_t)k0 * lda : k0));
 #pragma unroll
       for (int u = 0; u < VPC; ++u) ra[r][u] = x[u];
     } else if (!TA) {
       if (VEC) {
         const int row = m0 + tid / CPR + (NT / CPR) * r, k = k0 + (tid % CPR) * VPC;
         const int rr = row < M ? row : M - 1, kk = k < K ? k : K - VPC;
-        const V16 x = *reinterpret_cast<const V16*>(W + (int64_t)rr * K + kk);
+        const V16 x = *reinterpret_cast<const V16*>(W + (int64_t)rr * lda + kk);
 #pragma unroll
         for (int u = 0; u < VPC; ++u) ra[r][u] = x[u];
       } else {
@@ -244,7 +275,7 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
           const int f = tid + NT * (r * VPC + u);
           const int row = m0 + f / BK, k = k0 + f % BK;
           const int rr = row < M ? row : M - 1, kk = k < K ? k : K - 1;
-          ra[r][u] = W[(int64_t)rr * K + kk];
+          ra[r][u] = W[(int64_t)rr * lda + kk];
         }
       }
     } else {
@@ -254,20 +285,20 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
       const int kk = k < K ? k : K - 1;
       if (VEC) {
         const int rr = mm < M ? mm : M - VPC;
-        const V16 x = *reinterpret_cast<const V16*>(W + (int64_t)kk * M + rr);
+        const V16 x = *reinterpret_cast<const V16*>(W + (int64_t)kk * lda + rr);
 #pragma unroll
         for (int u = 0; u < VPC; ++u) ra[r][u] = x[u];
       } else {
 #pragma unroll
         for (int u = 0; u < VPC; ++u) {
           const int rr = mm + u < M ? mm + u : M - 1;
-          ra[r][u] = W[(int64_t)kk * M + rr];
+          ra[r][u] = W[(int64_t)kk * lda + rr];
         }
       }
     }
   };
   auto load_b = [&](int r) {
-    if (BLOCKJ) {
+    if (SCALARB) {
       rb[r] = reinterpret_cast<gptr>(prow[r])[c];
     } else {
       const bool carry = (pcar >> r) & 1u;
@@ -310,7 +341,9 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
 #pragma unroll
         for (int u = 0; u < VP8; ++u) {
           const int r = g * BG + h + u;
-          if (BLOCKJ) {
+          if (DENSE) {
+            y[u] = rb[r];
+          } else if (BLOCKJ) {
             y[u] = M4::flip(rb[r], (sneg >> r) & 1u);
           } else {
             const bool cr = (scar >> r) & 1u;
@@ -437,7 +470,10 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int mrow = m0 + wm * 64 + i * 16 + M4::row(lane, e);
-        if (mrow < M) p.Z[(int64_t)mrow * p.N + nn] = acc[i][q][e];
+        if (mrow >= M) continue;
+        T* cp = p.Z + (int64_t)mrow * p.ldc + nn;
+        if (DENSE) *cp = p.alpha * acc[i][q][e] + (p.beta != T(0) ? p.beta * *cp : T(0));
+        else *cp = acc[i][q][e];
       }
     }
 }
@@ -445,7 +481,7 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
 }  // namespace
 
 // Returns false when the shape is outside what the kernels support (the caller then uses the
-// generic gather path). W must be followed by ovvo_pad(M) zero elements; zrow holds at least
+// generic gather path). W must be followed by ovvo_pad_bytes(M) zero bytes; zrow holds at least
 // nc zeros (or is null, which disables the column-block loader).
 template <typename T>
 bool ovvo_fast(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, const T* X2,
@@ -457,6 +493,9 @@ bool ovvo_fast(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, con
   p.W = W; p.X2 = X2; p.Z = Z; p.zrow = zrow;
   p.o = o; p.v = v; p.nc = nc;
   p.M = o * v; p.K = o * v; p.N = o * nc;
+  p.lda = transW ? p.M : p.K;
+  p.ldb = 0; p.ldc = p.N;
+  p.alpha = T(1); p.beta = T(0);
   p.mtiles = (p.M + BM - 1) / BM;
   p.ntiles = (p.N + BN - 1) / BN;
   p.nslabs = (p.K + BK - 1) / BK;
@@ -471,13 +510,52 @@ bool ovvo_fast(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, con
   dim3 grid((unsigned)((tiles + 7) / 8 * 8));
   hipStream_t st = ctx->stream;
   if (transW) {
-    if (blockj) hipLaunchKernelGGL((ovvo_kernel<T, true, true, true>), grid, dim3(NT), 0, st, p);
-    else if (vec) hipLaunchKernelGGL((ovvo_kernel<T, true, false, true>), grid, dim3(NT), 0, st, p);
-    else hipLaunchKernelGGL((ovvo_kernel<T, true, false, false>), grid, dim3(NT), 0, st, p);
+    if (blockj) hipLaunchKernelGGL((ovvo_kernel<T, true, B_COLBLOCK, true>), grid, dim3(NT), 0, st, p);
+    else if (vec) hipLaunchKernelGGL((ovvo_kernel<T, true, B_GATHER, true>), grid, dim3(NT), 0, st, p);
+    else hipLaunchKernelGGL((ovvo_kernel<T, true, B_GATHER, false>), grid, dim3(NT), 0, st, p);
   } else {
-    if (blockj) hipLaunchKernelGGL((ovvo_kernel<T, false, true, true>), grid, dim3(NT), 0, st, p);
-    else if (vec) hipLaunchKernelGGL((ovvo_kernel<T, false, false, true>), grid, dim3(NT), 0, st, p);
-    else hipLaunchKernelGGL((ovvo_kernel<T, false, false, false>), grid, dim3(NT), 0, st, p);
+    if (blockj) hipLaunchKernelGGL((ovvo_kernel<T, false, B_COLBLOCK, true>), grid, dim3(NT), 0, st, p);
+    else if (vec) hipLaunchKernelGGL((ovvo_kernel<T, false, B_GATHER, true>), grid, dim3(NT), 0, st, p);
+    else hipLaunchKernelGGL((ovvo_kernel<T, false, B_GATHER, false>), grid, dim3(NT), 0, st, p);
+  }
+  GFCC_LAUNCH_CHECK();
+  return true;
+}
+
+// C[M][N] = alpha op(A) B + beta C with B row-major [K][ldb], on the same pipelined kernel.
+// op(A) = A ([M][lda]) or A^T (A stored [K][lda]). Returns false when the product is too small
+// to fill the GPU with 128 x 128 tiles (the caller then uses the split-K kernel).
+template <typename T>
+bool gemm_pipe(gfcc_ctx* ctx, bool transA, int M, int N, int K, T alpha, const T* A, int64_t lda,
+               const T* B, int64_t ldb, T beta, T* C, int64_t ldc) {
+  constexpr int BK = 128 / (int)sizeof(T);
+  constexpr int VPC = 16 / (int)sizeof(T);
+  if (M < 1 || N < 1 || K < 1) return false;
+  OvvoArgs<T> p{};
+  p.M = M; p.N = N; p.K = K;
+  p.mtiles = (M + BM - 1) / BM;
+  p.ntiles = (N + BN - 1) / BN;
+  p.nslabs = (K + BK - 1) / BK;
+  const int64_t tiles = (int64_t)p.mtiles * p.ntiles;
+  if (tiles < 256 || tiles >= (1LL << 31) - 8) return false;
+  p.W = A; p.lda = lda;
+  p.X2 = B; p.ldb = ldb;
+  p.Z = C; p.ldc = ldc;
+  p.alpha = alpha; p.beta = beta;
+  p.nc = 1; p.o = 1; p.v = 1; p.ldx = 0;
+  p.zrow = static_cast<const T*>(zero_row(ctx, (size_t)N * sizeof(T)));
+  // 16-byte A chunks need aligned rows and a chunked dimension that is a multiple of the chunk
+  // (the clamp of the last chunk then stays inside the row)
+  const bool vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (lda % VPC == 0) &&
+                   ((transA ? M : K) % VPC == 0);
+  dim3 grid((unsigned)((tiles + 7) / 8 * 8));
+  hipStream_t st = ctx->stream;
+  if (transA) {
+    if (vec) hipLaunchKernelGGL((ovvo_kernel<T, true, B_DENSE, true>), grid, dim3(NT), 0, st, p);
+    else hipLaunchKernelGGL((ovvo_kernel<T, true, B_DENSE, false>), grid, dim3(NT), 0, st, p);
+  } else {
+    if (vec) hipLaunchKernelGGL((ovvo_kernel<T, false, B_DENSE, true>), grid, dim3(NT), 0, st, p);
+    else hipLaunchKernelGGL((ovvo_kernel<T, false, B_DENSE, false>), grid, dim3(NT), 0, st, p);
   }
   GFCC_LAUNCH_CHECK();
   return true;
@@ -487,5 +565,9 @@ template bool ovvo_fast<double>(gfcc_ctx*, bool, int, int, int, const double*, c
                                 int64_t, double*, const double*);
 template bool ovvo_fast<float>(gfcc_ctx*, bool, int, int, int, const float*, const float*,
                                int64_t, float*, const float*);
+template bool gemm_pipe<double>(gfcc_ctx*, bool, int, int, int, double, const double*, int64_t,
+                                const double*, int64_t, double, double*, int64_t);
+template bool gemm_pipe<float>(gfcc_ctx*, bool, int, int, int, float, const float*, int64_t,
+                               const float*, int64_t, float, float*, int64_t);
 
 }  // namespace gfcc
