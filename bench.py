@@ -99,7 +99,11 @@ PEAK_HBM_GBPS = 8000.0
 def rows_report(o, v, D, nb, t_step, t_build, sig_ms_step, sig_calls_step, its, restart):
     """Per-row measurements of the plain step against the roofline that bounds each row."""
     ov = o * v
-    build_flops = 2.0 * ov ** 3             # dominant build contraction (W_mbej's T2 term)
+    o2, v2 = o * o, v * v
+    # the four dominant build contractions: the T2 term of W_mbej (ov)^3, the tau term of W_mbij
+    # ov o^2 v^2, the tau term of W_mnij o^4 v^2 and the T2 x W_mbej product of the 2h1p rows
+    # of c, o^2 (ov)^2 (each times 2 flops)
+    build_flops = 2.0 * (ov ** 3 + ov * o2 * v2 + o2 * o2 * v2 + o2 * ov * ov)
     sigma_flops = 1.0 * nb * sigma_flops_per_rhs(o, v)
     t_sig = sig_ms_step * 1e-3
     # GMRES vector work: everything in the step but the build and the sigma products; bytes as
