@@ -222,6 +222,79 @@ def form_mor(ctx, prob, cfg, gfcc):
     }
 
 
+def form_guess(ctx, cfg, gfcc):
+    """Initial guesses from a reduced model (a by-product the paper names for the model of
+    Eq. model): a model from the two ends of the window, lifted to full space at every
+    frequency of the grid, starts the full solves; compared with the same solves from zero."""
+    import torch
+    o = ctx.o
+    ps = synth_valence(o, cfg["np"])
+    om = np.linspace(*cfg["omega"])
+    lo, hi = cfg["omega"][0], cfg["omega"][1]
+    torch.cuda.synchronize()
+    t0 = time.time()
+    model = ctx.mor_build(np.array([lo, hi]), ps, cfg["eta"], solve_tol=cfg["tol"])
+    x0 = model.lift(om)
+    _, res_model = model.eval(om)
+    torch.cuda.synchronize()
+    t_model = time.time() - t0
+    out = {"points": len(om), "model_order": model.info()[0], "model_s": t_model,
+           "model_max_resid": float(res_model.max())}
+    model.close()
+    runs = {}
+    for name, guess in (("zero", None), ("model", x0)):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        r = ctx.gfcc_solve(om, ps, cfg["eta"], tol=cfg["tol"], restart=30, block=320, x0=guess)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        runs[name] = r
+        out[name] = {"s": dt, "iterations_mean": float(r.iters.mean()),
+                     "iterations_max": int(r.iters.max()), "max_rel_resid": float(r.resid.max())}
+    del x0
+    A0 = gfcc.spectral_function(runs["zero"].G)
+    A1 = gfcc.spectral_function(runs["model"].G)
+    out["A_max_rel_diff"] = float(np.abs(A1 - A0).max() / np.abs(A0).max())
+    out["speedup_solve"] = out["zero"]["s"] / out["model"]["s"]
+    out["speedup_with_model"] = out["zero"]["s"] / (out["model"]["s"] + t_model)
+    out["small"] = guess_small(gfcc, torch)
+    return out
+
+
+def guess_small(gfcc, torch):
+    """The same comparison on the small case, whose window lies next to the first pole, with
+    models from 2 and 4 frequencies of the window."""
+    import synth
+    cfg = synth.CONFIGS[0]
+    o, v = cfg["o"], cfg["v"]
+    prob = synth.make_problem(o, v, cfg["seed"])
+    ctx = gfcc.Context(0)
+    ctx.build_from_problem(prob)
+    om = synth.omega_grid(cfg["omega"])
+    ps = synth.valence_p(o, cfg["np"])
+    lo, hi = cfg["omega"][0], cfg["omega"][1]
+    out = {"workload": f"o={o} v={v}, {len(om)} omega x {len(ps)} p, tol={cfg['tol']}"}
+    base = ctx.gfcc_solve(om, ps, cfg["eta"], tol=cfg["tol"], restart=50)
+    out["zero"] = {"iterations_mean": float(base.iters.mean()), "iterations_max": int(base.iters.max())}
+    for nk in (2, 4):
+        model = ctx.mor_build(np.linspace(lo, hi, nk), ps, cfg["eta"], solve_tol=cfg["tol"])
+        x0 = model.lift(om)
+        _, rm = model.eval(om)
+        r = ctx.gfcc_solve(om, ps, cfg["eta"], tol=cfg["tol"], restart=50, x0=x0)
+        out[f"model_{nk}"] = {"order": model.info()[0], "model_max_resid": float(rm.max()),
+                              "iterations_mean": float(r.iters.mean()),
+                              "iterations_max": int(r.iters.max()),
+                              "max_rel_resid": float(r.resid.max())}
+        model.close()
+    ctx.close()
+    return out
+
+
+def synth_valence(o, n):
+    import synth
+    return synth.valence_p(o, n)
+
+
 def form_adjoint(ctx, cfg, gfcc, inputs):
     """Gradient of the trapezoid-integrated A over [-0.6, -0.3] Ha (100 points) with respect to
     all orbital energies: forward solves, transposed solves, device reduction."""
@@ -335,9 +408,9 @@ def main():
     ap.add_argument("--sigma-only", type=int, default=0,
                     help="profiling driver: K sigma products of one block in the benchmark's "
                          "launch configuration, then a 1 GiB device copy (counter calibration)")
-    ap.add_argument("--forms", default="mor,adjoint,mixed,small",
-                    help="extra forms reported beside the plain path: mor, adjoint, mixed, "
-                         "small, none")
+    ap.add_argument("--forms", default="mor,guess,adjoint,mixed,small",
+                    help="extra forms reported beside the plain path: mor, guess, adjoint, "
+                         "mixed, small, none")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the (omega, p) right-hand "
@@ -462,6 +535,8 @@ def main():
         out["small"] = form_small(gfcc, torch)
     if "mor" in forms:
         out["mor"] = form_mor(ctx, prob, synth.CONFIGS[2], gfcc)
+    if "guess" in forms:
+        out["guess"] = form_guess(ctx, cfg, gfcc)
     if "adjoint" in forms:
         out["adjoint"] = form_adjoint(ctx, synth.CONFIGS[4], gfcc, inputs)
     if not args.no_cpu_baseline:

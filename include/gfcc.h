@@ -134,6 +134,20 @@ gfcc_status gfcc_solve(gfcc_ctx* ctx, int nw, const double* omega, int np, const
                        int* iters_out, double* resid_out);
 
 /*
+ * gfcc_solve_x0 -- gfcc_solve started from the initial guesses X0 (complex128 [nw][np][D],
+ * device, the layout of X_out; for transpose = 1 the guesses of the adjoint solutions). The
+ * first restart cycle begins with the explicit FP64 residual b - M X0, so a guess that already
+ * meets tol costs one sigma product and no iteration. X0 may come from mor_lift (the reduced
+ * model's approximate solutions, the initial guesses the paper names as a by-product of the
+ * model described with Eq. model). X0 must not overlap X_out. Other arguments, outputs and
+ * status codes as gfcc_solve.
+ */
+gfcc_status gfcc_solve_x0(gfcc_ctx* ctx, int nw, const double* omega, int np, const int* p,
+                          double eta, double tol, int maxit, int restart, int block,
+                          int precision, int transpose, const void* X0, void* X_out,
+                          void* G_out, int* iters_out, double* resid_out);
+
+/*
  * gfcc_grad_eps -- adjoint gradient of J = sum_w weight_w A(omega_w) with respect to the
  * orbital energies eps (amplitudes held fixed):
  *   dJ/deps_r = (1/pi) sum_w weight_w sum_k Im( - Y_k^T D_r X_k ),
@@ -173,6 +187,14 @@ gfcc_status mor_refine(gfcc_mor* model, int nw, const double* grid, double wmin,
  */
 gfcc_status mor_eval(gfcc_mor* model, int nw, const double* omega, void* G_out,
                      double* resid_out);
+
+/*
+ * mor_lift -- the reduced model's full-space approximate solutions X_out[w][k] = S xhat_{p_k}
+ * (omega_w) for omega [nw] (host), the p set of the model: complex128 [nw][np][D] (device).
+ * At a sampled frequency this is the full solution (up to the solve tolerance); elsewhere its
+ * relative residual is the one mor_eval reports. Used as initial guesses by gfcc_solve_x0.
+ */
+gfcc_status mor_lift(gfcc_mor* model, int nw, const double* omega, void* X_out);
 
 /* Model facts: order m (columns of S), sampled frequencies (host array of cap entries). */
 gfcc_status mor_info(const gfcc_mor* model, int* m_out, int* nk_out, double* omega_k_out,

@@ -91,6 +91,19 @@ class ROM:
         return G, res
 
 
+def lift(rom: ROM, omegas) -> np.ndarray:
+    """Full-space approximate solutions S xhat_p(omega) [nw, np, D] of the reduced model: the
+    initial guesses for full solves that the reduced model provides (the model's by-product
+    described with Eq. model)."""
+    Hhat, bhat, _ = rom.projected()
+    X = np.empty((len(omegas), len(rom.ps), rom.D), dtype=complex)
+    for w, om in enumerate(omegas):
+        z = om - 1j * rom.eta
+        xh = sla.solve(Hhat + z * np.eye(rom.m), bhat.astype(complex))   # [m, np]
+        X[w] = (rom.S @ xh).T
+    return X
+
+
 def refine(rom: ROM, grid, wmin, wmax, per_round, resid_tol, max_order, max_rounds, defl_tol):
     """Midpoint refinement; returns (rounds, final max residual on the window's grid)."""
     g = np.sort(np.asarray([w for w in grid if wmin <= w <= wmax]))

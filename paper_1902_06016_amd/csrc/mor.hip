@@ -28,7 +28,8 @@
 namespace gfcc {
 gfcc_status solve_all(gfcc_ctx* ctx, int nw, const double* omega, int np, const int* p,
                       double eta, double tol, int maxit, int restart, int block, int precision,
-                      int transpose, void* X_out, void* G_out, int* iters_out, double* resid_out);
+                      int transpose, void* X_out, void* G_out, int* iters_out, double* resid_out,
+                      const void* X0);
 }
 
 struct gfcc_mor {
@@ -278,6 +279,41 @@ __global__ __launch_bounds__(256) void rom_solve_kernel(
   if (t == 0 && resid) resid[w] = rmax;
 }
 
+// X[(w0 + wl) np + q][d] = sum_i xhat_wl,q[i] St[i][d] for the cnt frequencies of a chunk,
+// xhat read from rom_solve_kernel's work buffer (the m solution entries follow the m x m
+// factor of each frequency). Grid (ceil(D / 256), ceil(cnt np / LR)); LR rows per thread.
+constexpr int LR = 8;
+__global__ __launch_bounds__(256) void lift_kernel(const double* __restrict__ St, int64_t D, int m,
+                                                   int np, const double2* __restrict__ work,
+                                                   int64_t per, int cnt, int w0,
+                                                   double2* __restrict__ X) {
+  const int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (d >= D) return;
+  const int rows = cnt * np;
+  const int row0 = blockIdx.y * LR;
+  double2 acc[LR];
+#pragma unroll
+  for (int r = 0; r < LR; ++r) acc[r] = make_double2(0.0, 0.0);
+  for (int i = 0; i < m; ++i) {
+    const double s = St[(int64_t)i * D + d];
+#pragma unroll
+    for (int r = 0; r < LR; ++r) {
+      const int row = row0 + r;
+      if (row < rows) {
+        const int wl = row / np, q = row - wl * np;
+        const double2 xh = work[(int64_t)wl * per + (int64_t)m * m + (int64_t)q * m + i];
+        acc[r].x += xh.x * s;
+        acc[r].y += xh.y * s;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < LR; ++r) {
+    const int row = row0 + r;
+    if (row < rows) X[((int64_t)w0 * np + row) * D + d] = acc[r];
+  }
+}
+
 }  // namespace
 
 // Orthogonalise the rows W[0..n) ([n][D], overwritten) against the fixed orthonormal rows
@@ -362,7 +398,7 @@ static void mor_extend(gfcc_mor* M, const std::vector<double>& omega_new) {
   std::vector<double> res(nr);
   gfcc_status s = solve_all(ctx, nk, omega_new.data(), np, M->p.data(), M->eta, M->solve_tol,
                             M->solve_maxit, M->solve_restart, 0, GFCC_FP64, 0, bX.p, bG.p,
-                            its.data(), res.data());
+                            its.data(), res.data(), nullptr);
   GFCC_REQUIRE(s == GFCC_OK, s, "mor: full solve failed: " + ctx->last_error);
   // new columns, D-major [D][nn]
   DevBuf bW, bWt;
@@ -528,6 +564,36 @@ static void mor_eval_impl(gfcc_mor* M, int nw, const double* omega, double2* G, 
   GFCC_HIP(hipStreamSynchronize(st));
 }
 
+static void mor_lift_impl(gfcc_mor* M, int nw, const double* omega, double2* X) {
+  gfcc_ctx* ctx = M->ctx;
+  hipStream_t st = ctx->stream;
+  const int m = M->m, np = M->np;
+  const int64_t D = M->D;
+  const int64_t per = (int64_t)m * m + (int64_t)np * m;
+  int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nw, (int64_t)(1ULL << 31) / (per * 16)));
+  chunk = std::min(chunk, 2048);
+  DevBuf bw, bom, bres, bG;
+  bw.alloc(sizeof(double2) * (size_t)per * chunk);
+  bom.alloc(sizeof(double) * nw);
+  bres.alloc(sizeof(double) * nw);
+  bG.alloc(sizeof(double2) * (size_t)nw * np * np);
+  GFCC_HIP(hipMemcpyAsync(bom.p, omega, sizeof(double) * nw, hipMemcpyHostToDevice, st));
+  for (int w0 = 0; w0 < nw; w0 += chunk) {
+    const int cnt = std::min(chunk, nw - w0);
+    hipLaunchKernelGGL(rom_solve_kernel, dim3(cnt), dim3(256), 0, st, M->Hhat.as<double>(),
+                       M->bhat.as<double>(), M->chat.as<double>(), M->Rm.as<double>(),
+                       M->beta.as<double>(), M->cnst.as<double>(), M->r, bom.as<double>(), M->eta, m,
+                       np, w0, nw, bw.as<double2>(), bG.as<double2>(), bres.as<double>());
+    GFCC_LAUNCH_CHECK();
+    const int64_t gy = ((int64_t)cnt * np + LR - 1) / LR;
+    GFCC_REQUIRE(gy < 65536, GFCC_EINVAL, "mor_lift: too many frequencies x orbitals per chunk");
+    hipLaunchKernelGGL(lift_kernel, dim3((unsigned)((D + 255) / 256), (unsigned)gy), dim3(256), 0,
+                       st, M->St.as<double>(), D, m, np, bw.as<double2>(), per, cnt, w0, X);
+    GFCC_LAUNCH_CHECK();
+  }
+  GFCC_HIP(hipStreamSynchronize(st));
+}
+
 }  // namespace gfcc
 
 extern "C" {
@@ -641,6 +707,20 @@ gfcc_status mor_eval(gfcc_mor* M, int nw, const double* omega, void* G_out, doub
   for (int i = 0; i < nw; ++i)
     GFCC_REQUIRE(std::isfinite(omega[i]), GFCC_EINVAL, "mor_eval: non-finite omega");
   mor_eval_impl(M, nw, omega, static_cast<double2*>(G_out), resid_out);
+  GFCC_API_END(ctx)
+}
+
+gfcc_status mor_lift(gfcc_mor* M, int nw, const double* omega, void* X_out) {
+  if (!M) return GFCC_EINVAL;
+  gfcc_ctx* ctx = M->ctx;
+  GFCC_API_BEGIN(ctx)
+  using namespace gfcc;
+  GFCC_REQUIRE(nw >= 0 && (nw == 0 || (omega && X_out)), GFCC_EINVAL, "mor_lift: bad arguments");
+  if (nw == 0) return GFCC_OK;
+  GFCC_REQUIRE(M->m > 0, GFCC_ESTATE, "mor_lift: empty model");
+  for (int i = 0; i < nw; ++i)
+    GFCC_REQUIRE(std::isfinite(omega[i]), GFCC_EINVAL, "mor_lift: non-finite omega");
+  mor_lift_impl(M, nw, omega, static_cast<double2*>(X_out));
   GFCC_API_END(ctx)
 }
 

@@ -690,9 +690,12 @@ struct GmresBlock {
 
 // Solve the systems of right-hand sides [r0, r0+nb) (global index r = w*np + k). On return
 // gb.X holds the solutions (D-major block).
+// X0: optional initial guesses [nrhs][D] (device); the first cycle then starts from the
+// explicit residual b - M X0.
 static void solve_block(GmresBlock& gb, const double* omega, const int* pset, int np, int nrhs,
                         int r0, double eta, double tol, int maxit, std::vector<int>& its_out,
-                        std::vector<double>& res_out, std::vector<int>& brk_out) {
+                        std::vector<double>& res_out, std::vector<int>& brk_out,
+                        const double2* X0) {
   gfcc_ctx* ctx = gb.ctx;
   const int nb = gb.nb, m = gb.m;
   const int64_t D = gb.D;
@@ -718,6 +721,10 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
   gb.norms(gb.B, gb.nrm);
   GFCC_HIP(hipMemcpyAsync(bnorm.data(), gb.nrm, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
   fill(ctx, reinterpret_cast<double*>(gb.X), D * nb * 2, 0.0);
+  if (X0) {
+    const int cnt = std::min(nb, nrhs - r0);
+    ctranspose(ctx, X0 + (int64_t)r0 * D, cnt, D, D, gb.X, nb);
+  }
   std::vector<int> zeros(nb, 0);
   GFCC_HIP(hipMemcpyAsync(gb.s.brk, zeros.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
   GFCC_HIP(hipStreamSynchronize(st));
@@ -725,7 +732,7 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
   std::vector<int> its(nb, 0), act(nb), brk(nb, 0);
   std::vector<double> thr(nb), inv0(nb), rel(nb, 0.0);
   std::vector<double2> g0((size_t)nb * (m + 1));
-  bool first = true;
+  bool first = X0 == nullptr;
   const bool mixed = gb.precision != GFCC_FP64;
   const double inner_rel = 1e-4;  // relative tolerance of a reduced-precision cycle
   for (;;) {
@@ -842,7 +849,8 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
 // writes G (device, [nw][np][np]) and optionally X ([nw][np][D] device).
 gfcc_status solve_all(gfcc_ctx* ctx, int nw, const double* omega, int np, const int* p,
                       double eta, double tol, int maxit, int restart, int block, int precision,
-                      int transpose, void* X_out, void* G_out, int* iters_out, double* resid_out) {
+                      int transpose, void* X_out, void* G_out, int* iters_out, double* resid_out,
+                      const void* X0) {
   Operator& op = ctx->op;
   const int64_t D = op.D;
   const int nrhs = nw * np;
@@ -873,7 +881,8 @@ gfcc_status solve_all(gfcc_ctx* ctx, int nw, const double* omega, int np, const 
       if (nbl != gb.nb) gb.setup(ctx, nbl, restart, precision, transpose != 0);
     }
     const int nbb = gb.nb;
-    solve_block(gb, omega, p, np, nrhs, r0, eta, tol, maxit, its, res, brk);
+    solve_block(gb, omega, p, np, nrhs, r0, eta, tol, maxit, its, res, brk,
+                static_cast<const double2*>(X0));
     // G rows for this block
     if (!transpose) {
       gemm<double>(ctx, false, false, np, 2 * nbb, (int)D, 1.0, bC.as<double>(), D,
@@ -980,17 +989,16 @@ __global__ void spectral_kernel(const double2* __restrict__ G, int nw, int np, d
 
 extern "C" {
 
-gfcc_status gfcc_solve(gfcc_ctx* ctx, int nw, const double* omega, int np, const int* p,
-                       double eta, double tol, int maxit, int restart, int block, int precision,
-                       int transpose, void* X_out, void* G_out, int* iters_out,
-                       double* resid_out) {
-  if (!ctx) return GFCC_EINVAL;
-  GFCC_API_BEGIN(ctx)
-  using namespace gfcc;
-  GFCC_HIP(hipSetDevice(ctx->device));
+}  // extern "C"
+
+namespace gfcc {
+// argument checks shared by gfcc_solve and gfcc_solve_x0 (throws Error)
+static void check_solve_args(gfcc_ctx* ctx, int nw, const double* omega, int np, const int* p,
+                             double eta, double tol, int maxit, int restart, int precision,
+                             int transpose, const void* G_out) {
   GFCC_REQUIRE(ctx->op.built, GFCC_ESTATE, "gfcc_solve: no operator built");
   GFCC_REQUIRE(nw >= 0 && np >= 0, GFCC_EINVAL, "gfcc_solve: negative sizes");
-  if (nw == 0 || np == 0) return GFCC_OK;
+  if (nw == 0 || np == 0) return;
   GFCC_REQUIRE(omega && p && G_out, GFCC_EINVAL, "gfcc_solve: null pointer");
   GFCC_REQUIRE((int64_t)nw * np < (1LL << 30), GFCC_EINVAL, "gfcc_solve: too many right-hand sides");
   GFCC_REQUIRE(eta > 0.0 && std::isfinite(eta), GFCC_EINVAL, "gfcc_solve: eta must be > 0");
@@ -1013,8 +1021,46 @@ gfcc_status gfcc_solve(gfcc_ctx* ctx, int nw, const double* omega, int np, const
     GFCC_REQUIRE(!seen[p[k]], GFCC_EINVAL, "gfcc_solve: repeated orbital in p");
     seen[p[k]] = 1;
   }
+}
+}  // namespace gfcc
+
+extern "C" {
+
+gfcc_status gfcc_solve(gfcc_ctx* ctx, int nw, const double* omega, int np, const int* p,
+                       double eta, double tol, int maxit, int restart, int block, int precision,
+                       int transpose, void* X_out, void* G_out, int* iters_out,
+                       double* resid_out) {
+  if (!ctx) return GFCC_EINVAL;
+  GFCC_API_BEGIN(ctx)
+  using namespace gfcc;
+  GFCC_HIP(hipSetDevice(ctx->device));
+  check_solve_args(ctx, nw, omega, np, p, eta, tol, maxit, restart, precision, transpose, G_out);
+  if (nw == 0 || np == 0) return GFCC_OK;
   return solve_all(ctx, nw, omega, np, p, eta, tol, maxit, restart, block, precision, transpose,
-                   X_out, G_out, iters_out, resid_out);
+                   X_out, G_out, iters_out, resid_out, nullptr);
+  GFCC_API_END(ctx)
+}
+
+gfcc_status gfcc_solve_x0(gfcc_ctx* ctx, int nw, const double* omega, int np, const int* p,
+                          double eta, double tol, int maxit, int restart, int block,
+                          int precision, int transpose, const void* X0, void* X_out,
+                          void* G_out, int* iters_out, double* resid_out) {
+  if (!ctx) return GFCC_EINVAL;
+  GFCC_API_BEGIN(ctx)
+  using namespace gfcc;
+  GFCC_HIP(hipSetDevice(ctx->device));
+  check_solve_args(ctx, nw, omega, np, p, eta, tol, maxit, restart, precision, transpose, G_out);
+  if (nw == 0 || np == 0) return GFCC_OK;
+  GFCC_REQUIRE(X0 != nullptr, GFCC_EINVAL, "gfcc_solve_x0: null X0");
+  if (X_out) {
+    const size_t bytes = sizeof(double2) * (size_t)nw * np * (size_t)ctx->op.D;
+    const char* a = static_cast<const char*>(X0);
+    const char* b = static_cast<const char*>(X_out);
+    GFCC_REQUIRE(a + bytes <= b || b + bytes <= a, GFCC_EINVAL,
+                 "gfcc_solve_x0: X0 and X_out overlap");
+  }
+  return solve_all(ctx, nw, omega, np, p, eta, tol, maxit, restart, block, precision, transpose,
+                   X_out, G_out, iters_out, resid_out, X0);
   GFCC_API_END(ctx)
 }
 

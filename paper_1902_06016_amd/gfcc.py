@@ -47,10 +47,13 @@ def _load():
         "sigma_apply": (i32, [vp, i32, vp, vp, i32, i32]),
         "gfcc_solve": (i32, [vp, i32, vp, i32, vp, dbl, dbl, i32, i32, i32, i32, i32, vp, vp, vp,
                              vp]),
+        "gfcc_solve_x0": (i32, [vp, i32, vp, i32, vp, dbl, dbl, i32, i32, i32, i32, i32, vp, vp,
+                                vp, vp, vp]),
         "gfcc_grad_eps": (i32, [vp, i32, vp, i32, vp, vp, vp]),
         "mor_build": (i32, [vp, i32, vp, i32, vp, dbl, dbl, dbl, P(vp)]),
         "mor_refine": (i32, [vp, i32, vp, dbl, dbl, i32, dbl, i32, i32, vp, vp]),
         "mor_eval": (i32, [vp, i32, vp, vp, vp]),
+        "mor_lift": (i32, [vp, i32, vp, vp]),
         "mor_info": (i32, [vp, vp, vp, vp, i32]),
         "mor_destroy": (i32, [vp]),
         "spectral_function": (i32, [i32, i32, vp, i32, vp]),
@@ -66,8 +69,9 @@ def _load():
 
 lib = _load()
 SYMBOLS = ("gfcc_dim", "gfcc_create", "gfcc_destroy", "gfcc_last_error", "build_hbar_operands",
-           "sigma_apply", "gfcc_solve", "gfcc_grad_eps", "mor_build", "mor_refine", "mor_eval",
-           "mor_info", "mor_destroy", "spectral_function", "gfcc_export", "gfcc_timer")
+           "sigma_apply", "gfcc_solve", "gfcc_solve_x0", "gfcc_grad_eps", "mor_build",
+           "mor_refine", "mor_eval", "mor_lift", "mor_info", "mor_destroy", "spectral_function",
+           "gfcc_export", "gfcc_timer")
 
 
 def dim(o: int, v: int) -> int:
@@ -185,7 +189,8 @@ class Context:
 
     # ------------------------------------------------------------------ solve
     def gfcc_solve(self, omega, p, eta, tol=1e-10, maxit=500, restart=30, block=0,
-                   precision=FP64, transpose=False, want_x=False, allow_noconv=False):
+                   precision=FP64, transpose=False, want_x=False, allow_noconv=False, x0=None):
+        """x0: optional initial guesses, complex128 [nw][np][D] device tensor (gfcc_solve_x0)."""
         om, om_p = _f64arr(omega)
         pp, p_p = _i32arr(p)
         nw, np_ = len(om), len(pp)
@@ -194,9 +199,17 @@ class Context:
         X = T.empty((nw, np_, self.D), dtype=T.complex128, device=self.device) if want_x else None
         its = np.zeros(nw * np_, dtype=np.int32)
         res = np.zeros(nw * np_, dtype=np.float64)
-        st = lib.gfcc_solve(self.h, nw, om_p, np_, p_p, eta, tol, maxit, restart, block, precision,
-                            int(transpose), _ptr(X) if X is not None else None, _ptr(G),
-                            its.ctypes.data_as(ctypes.c_void_p), res.ctypes.data_as(ctypes.c_void_p))
+        xp = _ptr(X) if X is not None else None
+        ip, rp = its.ctypes.data_as(ctypes.c_void_p), res.ctypes.data_as(ctypes.c_void_p)
+        if x0 is None:
+            st = lib.gfcc_solve(self.h, nw, om_p, np_, p_p, eta, tol, maxit, restart, block,
+                                precision, int(transpose), xp, _ptr(G), ip, rp)
+        else:
+            x0 = x0.contiguous()
+            if x0.dtype != T.complex128 or tuple(x0.shape) != (nw, np_, self.D):
+                raise ValueError("x0 must be complex128 [nw][np][D]")
+            st = lib.gfcc_solve_x0(self.h, nw, om_p, np_, p_p, eta, tol, maxit, restart, block,
+                                   precision, int(transpose), _ptr(x0), xp, _ptr(G), ip, rp)
         self._check(st, allow=(GFCC_ENOCONV,) if allow_noconv else ())
         return SolveResult(G=G, X=X, iters=its.reshape(nw, np_), resid=res.reshape(nw, np_), status=st)
 
@@ -251,6 +264,14 @@ class MorModel:
                           res.ctypes.data_as(ctypes.c_void_p) if want_resid else None)
         self.ctx._check(st)
         return G, res
+
+    def lift(self, omega):
+        """Full-space approximate solutions S xhat_p(omega): complex128 [nw][np][D] (device)."""
+        om, om_p = _f64arr(omega)
+        T = self.ctx.torch
+        X = T.empty((len(om), self.np, self.ctx.D), dtype=T.complex128, device=self.ctx.device)
+        self.ctx._check(lib.mor_lift(self.h, len(om), om_p, _ptr(X)))
+        return X
 
     def info(self, cap=4096):
         m = ctypes.c_int()

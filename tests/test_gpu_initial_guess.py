@@ -1,0 +1,107 @@
+"""GPU parity: the reduced model's full-space solutions (mor_lift) and solves started from an
+initial guess (gfcc_solve_x0)."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import hbar as ohbar
+from oracle import mor as omor
+from oracle import sigma as osig
+from oracle import solve as osolve
+from paper_1902_06016_amd import gfcc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def model():
+    o, v = 6, 10
+    p = synth.make_problem(o, v, 31)
+    hb = ohbar.build_hbar_from_problem(p)
+    H = osolve.dense_hbar(hb)
+    lam = np.sort(np.linalg.eigvals(H).real)
+    ps = np.array([o - 2, o - 1])
+    B = np.stack([osig.b_vector(o, v, q) for q in ps], 1)
+    C = np.stack([osig.c_vector(o, v, p.t1, p.t2, p.l1, p.l2, q) for q in ps], 0)
+    return p, hb, H, lam, ps, B, C
+
+
+def test_mor_lift_matches_oracle(gpu_ctx, model):
+    print("[mor_lift]", flush=True)
+    p, hb, H, lam, ps, B, C = model
+    eta = 0.01
+    wk = np.linspace(-lam[0] - 0.3, -lam[0] + 0.3, 3)
+    gpu_ctx.build_from_problem(p)
+    m = gpu_ctx.mor_build(wk, ps, eta, solve_tol=1e-13, defl_tol=1e-10)
+    rom = omor.ROM(hb, ps, eta, C, omor.dense_solver(H, B, eta))
+    rom.extend(wk, 1e-10)
+    grid = np.concatenate([wk, np.linspace(-lam[0] - 0.5, -lam[0] + 0.5, 21)])
+    Xg = m.lift(grid).cpu().numpy()
+    Xo = omor.lift(rom, grid)
+    assert Xg.shape == Xo.shape
+    assert np.abs(Xg - Xo).max() < 1e-9 * np.abs(Xo).max()
+    # at the sampled frequencies the lift is the full solution
+    Xd = osolve.dense_solve(H, wk, B, eta)
+    assert np.abs(Xg[:3] - Xd).max() < 1e-10 * np.abs(Xd).max()
+    # its Green's function is the model's
+    Gh, _ = m.eval(grid)
+    G_lift = np.einsum("qd,wkd->wqk", C, Xg)
+    assert np.abs(G_lift - Gh.cpu().numpy()).max() < 1e-10 * np.abs(G_lift).max()
+    m.close()
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_solve_from_exact_guess_takes_no_iteration(gpu_ctx, model, transpose):
+    print(f"[x0 exact T={transpose}]", flush=True)
+    p, hb, H, lam, ps, B, C = model
+    eta = 0.01
+    om = np.linspace(-lam[0] - 0.2, -lam[0] + 0.2, 5)
+    gpu_ctx.build_from_problem(p)
+    ref = gpu_ctx.gfcc_solve(om, ps, eta, tol=1e-12, want_x=True, transpose=transpose)
+    res = gpu_ctx.gfcc_solve(om, ps, eta, tol=1e-10, want_x=True, transpose=transpose, x0=ref.X)
+    assert res.iters.max() == 0
+    assert res.resid.max() <= 1e-10
+    assert torch.equal(res.X, ref.X)
+
+
+def test_solve_from_reduced_model_guess(gpu_ctx, model):
+    print("[x0 from the reduced model]", flush=True)
+    p, hb, H, lam, ps, B, C = model
+    eta = 0.01
+    lo, hi = -lam[0] - 0.4, -lam[0] + 0.4
+    om = np.linspace(lo, hi, 33)
+    gpu_ctx.build_from_problem(p)
+    m = gpu_ctx.mor_build(np.array([lo, hi]), ps, eta, solve_tol=1e-12)
+    x0 = m.lift(om)
+    plain = gpu_ctx.gfcc_solve(om, ps, eta, tol=1e-10, want_x=True)
+    guess = gpu_ctx.gfcc_solve(om, ps, eta, tol=1e-10, want_x=True, x0=x0)
+    Xd = osolve.dense_solve(H, om, B, eta)
+    for r in (plain, guess):
+        assert r.resid.max() <= 1e-10
+        assert np.abs(r.X.cpu().numpy() - Xd).max() < 1e-8 * np.abs(Xd).max()
+    assert (guess.iters <= plain.iters).all()
+    assert guess.iters.sum() < plain.iters.sum()
+    # a block size that is not a multiple of 64 and a last block narrower than the rest
+    g2 = gpu_ctx.gfcc_solve(om, ps, eta, tol=1e-10, x0=x0, block=20)
+    assert np.abs(g2.G.cpu().numpy() - guess.G.cpu().numpy()).max() < 1e-8 * np.abs(Xd).max()
+    m.close()
+
+
+def test_solve_x0_errors(gpu_ctx, model):
+    p, hb, H, lam, ps, B, C = model
+    gpu_ctx.build_from_problem(p)
+    om = np.array([-lam[0] - 0.1], dtype=np.float64)
+    pp = np.ascontiguousarray(ps, dtype=np.int32)
+    D = gpu_ctx.D
+    X = torch.zeros((1, len(ps), D), dtype=torch.complex128, device=gpu_ctx.device)
+    G = torch.zeros((1, len(ps), len(ps)), dtype=torch.complex128, device=gpu_ctx.device)
+    args = lambda x0, xo: (gpu_ctx.h, 1, om.ctypes.data_as(ctypes.c_void_p), len(ps),
+                           pp.ctypes.data_as(ctypes.c_void_p), 0.01, 1e-10, 100, 30, 0, gfcc.FP64,
+                           0, x0, xo, ctypes.c_void_p(G.data_ptr()), None, None)
+    assert gfcc.lib.gfcc_solve_x0(*args(None, None)) == gfcc.GFCC_EINVAL
+    xp = ctypes.c_void_p(X.data_ptr())
+    assert gfcc.lib.gfcc_solve_x0(*args(xp, xp)) == gfcc.GFCC_EINVAL
+    assert gfcc.lib.mor_lift(None, 1, om.ctypes.data_as(ctypes.c_void_p), xp) == gfcc.GFCC_EINVAL

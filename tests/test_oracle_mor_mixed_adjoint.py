@@ -85,6 +85,49 @@ def test_refinement_reaches_threshold(model):
     assert np.abs(Gh - G).max() < 1e-4 * np.abs(G).max()
 
 
+def test_lift_interpolates_and_carries_the_model_residual(model):
+    """S xhat(omega) equals the full solution at sampled frequencies; between them its true
+    residual (formed with the dense H-bar) equals the model's residual estimate, and c^T of it
+    is the model's Green's function."""
+    p, hb, H, lam, ps, B, C = model
+    eta = 0.01
+    wk = np.linspace(-lam[0] - 0.3, -lam[0] + 0.3, 3)
+    rom = omor.ROM(hb, ps, eta, C, omor.dense_solver(H, B, eta))
+    rom.extend(wk, 1e-12)
+    Xk = omor.lift(rom, wk)
+    Xd = osolve.dense_solve(H, wk, B, eta)
+    assert np.abs(Xk - Xd).max() < 1e-10 * np.abs(Xd).max()
+    mid = 0.5 * (wk[:-1] + wk[1:])
+    Xm = omor.lift(rom, mid)
+    Gh, res = rom.eval(mid)
+    for w, om in enumerate(mid):
+        R = B - osolve.shifted(H, om, eta) @ Xm[w].T
+        true = np.max(np.linalg.norm(R, axis=0) / np.linalg.norm(B, axis=0))
+        assert abs(true - res[w]) <= 1e-6 * res[w] + 1e-14
+        assert np.abs(C @ Xm[w].T - Gh[w]).max() < 1e-10 * np.abs(Gh[w]).max()
+    assert res.max() > 1e-8          # a real approximation between samples
+
+
+def test_gmres_initial_guess(model):
+    """An exact x0 needs no iteration; a reduced-model x0 converges to the same solution in no
+    more iterations than x0 = 0."""
+    p, hb, H, lam, ps, B, C = model
+    eta = 0.01
+    op = osolve.Operator(hb)
+    om = -lam[0] + 0.05
+    xd = osolve.dense_solve(H, [om], B, eta)[0, 0]
+    x, it, rel = osolve.gmres(op, B[:, 0], om, eta, tol=1e-10, x0=xd)
+    assert it == 0 and np.abs(x - xd).max() == 0.0
+    rom = omor.ROM(hb, ps, eta, C, omor.dense_solver(H, B, eta))
+    rom.extend([om - 0.2, om + 0.2], 1e-12)
+    x0 = omor.lift(rom, [om])[0, 0]
+    x1, it1, rel1 = osolve.gmres(op, B[:, 0], om, eta, tol=1e-10, x0=x0)
+    x2, it2, rel2 = osolve.gmres(op, B[:, 0], om, eta, tol=1e-10)
+    assert rel1 <= 1e-10 and rel2 <= 1e-10
+    assert it1 < it2
+    assert np.abs(x1 - xd).max() < 1e-8 * np.abs(xd).max()
+
+
 def test_bf16_rounding():
     x = np.array([1.0, 1.00390625, 1.005859375, -3.0e-8, 65504.0], dtype=np.float32)
     r = omix.bf16_round(x)
