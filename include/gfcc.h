@@ -169,6 +169,18 @@ gfcc_status mor_build(gfcc_ctx* ctx, int nk, const double* omega_k, int np, cons
                       double eta, double solve_tol, double defl_tol, gfcc_mor** model);
 
 /*
+ * mor_build_diag -- one reduced-order model per diagonal Green's function curve (the variant
+ * the paper proposes in its outlook: separate models for every G_pp, whose sum gives A): the
+ * full solves at omega_k [nk] (host) for all orbitals p [np] (host) run once, then model k is
+ * built from the solutions of p[k] alone (basis from Re and Im X_{p[k]}(omega_k), as
+ * mor_build with the single orbital p[k]). models [np] (host array) receives the np models;
+ * on failure none is returned. Each model is refined, evaluated, lifted and destroyed like
+ * one from mor_build; its G is the 1 x 1 block G_{p[k] p[k]}.
+ */
+gfcc_status mor_build_diag(gfcc_ctx* ctx, int nk, const double* omega_k, int np, const int* p,
+                           double eta, double solve_tol, double defl_tol, gfcc_mor** models);
+
+/*
  * mor_refine -- adaptive refinement (the strategy described after Eq. model): evaluate the
  * relative full-space residual of the reduced solutions on grid [nw] (host) restricted to
  * [wmin, wmax]; while its maximum exceeds resid_tol, add up to per_round midpoints of the

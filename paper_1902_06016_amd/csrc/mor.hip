@@ -383,34 +383,22 @@ static int orth_rows(gfcc_ctx* ctx, int64_t D, const double* B, int nb, double* 
   return acc;
 }
 
-// Append the real and imaginary parts of the solutions at omega_new to the basis.
-static void mor_extend(gfcc_mor* M, const std::vector<double>& omega_new) {
+// Append the real and imaginary parts of nr full solutions X [nr][D] (device, complex; the
+// solutions at omega_new for the model's orbitals) to the basis.
+static void mor_add(gfcc_mor* M, const double2* X, int nr, const std::vector<double>& omega_new) {
   gfcc_ctx* ctx = M->ctx;
   hipStream_t st = ctx->stream;
   const int64_t D = M->D;
-  const int np = M->np, nk = (int)omega_new.size();
-  const int nr = nk * np, nn = 2 * nr;
-  // full solves
-  DevBuf bX, bG;
-  bX.alloc(sizeof(double2) * (size_t)nr * D);
-  bG.alloc(sizeof(double2) * (size_t)nr * np);
-  std::vector<int> its(nr);
-  std::vector<double> res(nr);
-  gfcc_status s = solve_all(ctx, nk, omega_new.data(), np, M->p.data(), M->eta, M->solve_tol,
-                            M->solve_maxit, M->solve_restart, 0, GFCC_FP64, 0, bX.p, bG.p,
-                            its.data(), res.data(), nullptr);
-  GFCC_REQUIRE(s == GFCC_OK, s, "mor: full solve failed: " + ctx->last_error);
+  const int nn = 2 * nr;
   // new columns, D-major [D][nn]
   DevBuf bW, bWt;
   bW.alloc(sizeof(double) * (size_t)D * nn);
   bWt.alloc(sizeof(double) * (size_t)D * nn);
   double* W = bW.as<double>();
   double* Wt = bWt.as<double>();
-  hipLaunchKernelGGL(split_reim_kernel, dim3(gridn(D * nr)), dim3(256), 0, st,
-                     bX.as<double2>(), nr, D, W);
+  hipLaunchKernelGGL(split_reim_kernel, dim3(gridn(D * nr)), dim3(256), 0, st, X, nr, D, W);
   GFCC_LAUNCH_CHECK();
   GFCC_HIP(hipStreamSynchronize(st));
-  bX.release();
   const int m_old = M->m;
   // capacity
   if (m_old + nn > M->mcap) {
@@ -457,6 +445,24 @@ static void mor_extend(gfcc_mor* M, const std::vector<double>& omega_new) {
   M->m = m_cur;
   for (double w : omega_new) M->omega_k.push_back(w);
   GFCC_HIP(hipStreamSynchronize(st));
+}
+
+// Full solves at omega_new for the model's orbitals, appended to the basis.
+static void mor_extend(gfcc_mor* M, const std::vector<double>& omega_new) {
+  gfcc_ctx* ctx = M->ctx;
+  const int64_t D = M->D;
+  const int np = M->np, nk = (int)omega_new.size();
+  const int nr = nk * np;
+  DevBuf bX, bG;
+  bX.alloc(sizeof(double2) * (size_t)nr * D);
+  bG.alloc(sizeof(double2) * (size_t)nr * np);
+  std::vector<int> its(nr);
+  std::vector<double> res(nr);
+  gfcc_status s = solve_all(ctx, nk, omega_new.data(), np, M->p.data(), M->eta, M->solve_tol,
+                            M->solve_maxit, M->solve_restart, 0, GFCC_FP64, 0, bX.p, bG.p,
+                            its.data(), res.data(), nullptr);
+  GFCC_REQUIRE(s == GFCC_OK, s, "mor: full solve failed: " + ctx->last_error);
+  mor_add(M, bX.as<double2>(), nr, omega_new);
 }
 
 // Hhat, bhat, chat and the residual factors (Q, R, Q^T b, constant term) for the current basis.
@@ -635,6 +641,68 @@ gfcc_status mor_build(gfcc_ctx* ctx, int nk, const double* omega_k, int np, cons
     throw;
   }
   *model = M;
+  GFCC_API_END(ctx)
+}
+
+gfcc_status mor_build_diag(gfcc_ctx* ctx, int nk, const double* omega_k, int np, const int* p,
+                           double eta, double solve_tol, double defl_tol, gfcc_mor** models) {
+  if (!ctx || !models) return GFCC_EINVAL;
+  for (int k = 0; k < np; ++k) models[k] = nullptr;
+  std::vector<gfcc_mor*> made;
+  GFCC_API_BEGIN(ctx)
+  using namespace gfcc;
+  GFCC_REQUIRE(ctx->op.built, GFCC_ESTATE, "mor_build_diag: no operator built");
+  GFCC_REQUIRE(nk >= 1 && np >= 1 && omega_k && p, GFCC_EINVAL, "mor_build_diag: bad arguments");
+  GFCC_REQUIRE(eta > 0.0 && solve_tol > 0.0 && defl_tol >= 0.0, GFCC_EINVAL,
+               "mor_build_diag: bad tolerances");
+  std::vector<char> seen(ctx->op.o, 0);
+  for (int k = 0; k < np; ++k) {
+    GFCC_REQUIRE(p[k] >= 0 && p[k] < ctx->op.o && !seen[p[k]], GFCC_EINVAL,
+                 "mor_build_diag: p must be distinct occupied orbitals");
+    seen[p[k]] = 1;
+  }
+  for (int k = 0; k < nk; ++k)
+    GFCC_REQUIRE(std::isfinite(omega_k[k]), GFCC_EINVAL, "mor_build_diag: non-finite omega");
+  const int64_t D = ctx->op.D;
+  hipStream_t st = ctx->stream;
+  const std::vector<double> om(omega_k, omega_k + nk);
+  try {
+    // one set of full solves for every (omega_k, p) ...
+    DevBuf bX, bG, bXk;
+    bX.alloc(sizeof(double2) * (size_t)nk * np * D);
+    bG.alloc(sizeof(double2) * (size_t)nk * np * np);
+    bXk.alloc(sizeof(double2) * (size_t)nk * D);
+    std::vector<int> its((size_t)nk * np);
+    std::vector<double> res((size_t)nk * np);
+    gfcc_status s = solve_all(ctx, nk, omega_k, np, p, eta, solve_tol, 2000, 30, 0, GFCC_FP64, 0,
+                              bX.p, bG.p, its.data(), res.data(), nullptr);
+    GFCC_REQUIRE(s == GFCC_OK, s, "mor_build_diag: full solve failed: " + ctx->last_error);
+    // ... then one model per orbital from its own solutions
+    for (int k = 0; k < np; ++k) {
+      auto* M = new gfcc_mor();
+      made.push_back(M);
+      M->ctx = ctx;
+      M->np = 1;
+      M->p.assign(1, p[k]);
+      M->eta = eta;
+      M->solve_tol = solve_tol;
+      M->defl_tol = defl_tol;
+      M->D = D;
+      M->prows.alloc(sizeof(int));
+      GFCC_HIP(hipMemcpy(M->prows.p, p + k, sizeof(int), hipMemcpyHostToDevice));
+      for (int w = 0; w < nk; ++w)
+        GFCC_HIP(hipMemcpyAsync(bXk.as<double2>() + (int64_t)w * D,
+                                bX.as<double2>() + ((int64_t)w * np + k) * D,
+                                sizeof(double2) * D, hipMemcpyDeviceToDevice, st));
+      mor_add(M, bXk.as<double2>(), nk, om);
+      GFCC_REQUIRE(M->m > 0, GFCC_EINVAL, "mor_build_diag: all basis columns deflated");
+      mor_project(M);
+    }
+  } catch (...) {
+    for (gfcc_mor* M : made) delete M;
+    throw;
+  }
+  for (int k = 0; k < np; ++k) models[k] = made[k];
   GFCC_API_END(ctx)
 }
 

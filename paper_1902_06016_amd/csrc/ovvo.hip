@@ -524,13 +524,14 @@ bool ovvo_fast(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, con
 
 // C[M][N] = alpha op(A) B + beta C with B row-major [K][ldb], on the same pipelined kernel.
 // op(A) = A ([M][lda]) or A^T (A stored [K][lda]). Returns false when the product is too small
-// to fill the GPU with 128 x 128 tiles (the caller then uses the split-K kernel).
+// or too thin to fill the GPU with 128 x 128 tiles (the caller then uses the split-K kernel).
 template <typename T>
 bool gemm_pipe(gfcc_ctx* ctx, bool transA, int M, int N, int K, T alpha, const T* A, int64_t lda,
                const T* B, int64_t ldb, T beta, T* C, int64_t ldc) {
   constexpr int BK = 128 / (int)sizeof(T);
   constexpr int VPC = 16 / (int)sizeof(T);
-  if (M < 1 || N < 1 || K < 1) return false;
+  // thin products (vectors, a few rows or columns) would waste most of a 128 x 128 tile
+  if (M < 64 || N < 64 || K < 1) return false;
   OvvoArgs<T> p{};
   p.M = M; p.N = N; p.K = K;
   p.mtiles = (M + BM - 1) / BM;

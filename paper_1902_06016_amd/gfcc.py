@@ -51,6 +51,7 @@ def _load():
                                 vp, vp, vp]),
         "gfcc_grad_eps": (i32, [vp, i32, vp, i32, vp, vp, vp]),
         "mor_build": (i32, [vp, i32, vp, i32, vp, dbl, dbl, dbl, P(vp)]),
+        "mor_build_diag": (i32, [vp, i32, vp, i32, vp, dbl, dbl, dbl, vp]),
         "mor_refine": (i32, [vp, i32, vp, dbl, dbl, i32, dbl, i32, i32, vp, vp]),
         "mor_eval": (i32, [vp, i32, vp, vp, vp]),
         "mor_lift": (i32, [vp, i32, vp, vp]),
@@ -70,8 +71,8 @@ def _load():
 lib = _load()
 SYMBOLS = ("gfcc_dim", "gfcc_create", "gfcc_destroy", "gfcc_last_error", "build_hbar_operands",
            "sigma_apply", "gfcc_solve", "gfcc_solve_x0", "gfcc_grad_eps", "mor_build",
-           "mor_refine", "mor_eval", "mor_lift", "mor_info", "mor_destroy", "spectral_function",
-           "gfcc_export", "gfcc_timer")
+           "mor_build_diag", "mor_refine", "mor_eval", "mor_lift", "mor_info", "mor_destroy",
+           "spectral_function", "gfcc_export", "gfcc_timer")
 
 
 def dim(o: int, v: int) -> int:
@@ -238,6 +239,21 @@ class Context:
         model = MorModel(self, h, len(pp))
         self._models.add(model)
         return model
+
+    def mor_build_diag(self, omega_k, p, eta, solve_tol=1e-10, defl_tol=1e-10):
+        """One reduced model per orbital of p (each for its diagonal G_pp), sharing the full
+        solves; returns the list of models in the order of p."""
+        om, om_p = _f64arr(omega_k)
+        pp, p_p = _i32arr(p)
+        hs = (ctypes.c_void_p * len(pp))()
+        self._check(lib.mor_build_diag(self.h, len(om), om_p, len(pp), p_p, eta, solve_tol,
+                                       defl_tol, ctypes.cast(hs, ctypes.c_void_p)))
+        models = []
+        for h in hs:
+            model = MorModel(self, ctypes.c_void_p(h), 1)
+            self._models.add(model)
+            models.append(model)
+        return models
 
 
 class MorModel:

@@ -105,3 +105,36 @@ def test_solve_x0_errors(gpu_ctx, model):
     xp = ctypes.c_void_p(X.data_ptr())
     assert gfcc.lib.gfcc_solve_x0(*args(xp, xp)) == gfcc.GFCC_EINVAL
     assert gfcc.lib.mor_lift(None, 1, om.ctypes.data_as(ctypes.c_void_p), xp) == gfcc.GFCC_EINVAL
+
+
+def test_per_diagonal_models_match_oracle(gpu_ctx, model):
+    """mor_build_diag: one model per G_pp; each matches the oracle's single-orbital model and a
+    separate one-orbital mor_build, and their curves sum to the spectral function at the
+    sampled frequencies."""
+    print("[mor_build_diag]", flush=True)
+    p, hb, H, lam, ps, B, C = model
+    eta = 0.01
+    wk = np.linspace(-lam[0] - 0.3, -lam[0] + 0.3, 4)
+    grid = np.linspace(-lam[0] - 0.5, -lam[0] + 0.5, 41)
+    gpu_ctx.build_from_problem(p)
+    models = gpu_ctx.mor_build_diag(wk, ps, eta, solve_tol=1e-13, defl_tol=1e-10)
+    assert len(models) == len(ps)
+    Ak = osolve.spectral(osolve.green(C, osolve.dense_solve(H, wk, B, eta)))
+    A_k = np.zeros(len(wk))
+    for k, q in enumerate(ps):
+        rom = omor.ROM(hb, [q], eta, C[k:k + 1], omor.dense_solver(H, B[:, k:k + 1], eta))
+        rom.extend(wk, 1e-10)
+        m_gpu, oks = models[k].info()
+        assert m_gpu == rom.m and np.allclose(oks, wk)
+        Gg, rg = models[k].eval(grid)
+        Go, ro = rom.eval(grid)
+        assert Gg.shape == (len(grid), 1, 1)
+        assert np.abs(Gg.cpu().numpy() - Go).max() < 1e-9 * np.abs(Go).max()
+        assert np.abs(rg - ro).max() < 1e-7
+        single = gpu_ctx.mor_build(wk, [q], eta, solve_tol=1e-13, defl_tol=1e-10)
+        Gs, _ = single.eval(grid)
+        assert np.abs(Gs.cpu().numpy() - Gg.cpu().numpy()).max() < 1e-10 * np.abs(Go).max()
+        single.close()
+        A_k += gfcc.spectral_function(models[k].eval(wk)[0])
+        models[k].close()
+    assert np.abs(A_k - Ak).max() < 1e-10 * np.abs(Ak).max()

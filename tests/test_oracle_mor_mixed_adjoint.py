@@ -108,6 +108,29 @@ def test_lift_interpolates_and_carries_the_model_residual(model):
     assert res.max() > 1e-8          # a real approximation between samples
 
 
+def test_per_diagonal_models_sum_to_the_spectral_function(model):
+    """One model per diagonal curve G_pp (basis from X_p alone): at the sampled frequencies
+    every curve, and so their sum A, is the full one; between them the sum approximates A."""
+    p, hb, H, lam, ps, B, C = model
+    eta = 0.01
+    wk = np.linspace(-lam[0] - 0.3, -lam[0] + 0.3, 4)
+    grid = np.linspace(wk[0], wk[-1], 25)
+    Afull = osolve.spectral(osolve.green(C, osolve.dense_solve(H, grid, B, eta)))
+    Ak = osolve.spectral(osolve.green(C, osolve.dense_solve(H, wk, B, eta)))
+    curves_k, curves = [], []
+    for k, q in enumerate(ps):
+        rom = omor.ROM(hb, [q], eta, C[k:k + 1], omor.dense_solver(H, B[:, k:k + 1], eta))
+        rom.extend(wk, 1e-12)
+        assert rom.m <= 2 * len(wk)
+        curves_k.append(rom.eval(wk)[0][:, 0, 0])
+        curves.append(rom.eval(grid)[0][:, 0, 0])
+    A_k = np.sum(np.imag(curves_k), 0) / np.pi
+    A = np.sum(np.imag(curves), 0) / np.pi
+    assert np.abs(A_k - Ak).max() < 1e-10 * np.abs(Ak).max()
+    err = np.abs(A - Afull).max() / np.abs(Afull).max()
+    assert 0 < err < 1e-1
+
+
 def test_gmres_initial_guess(model):
     """An exact x0 needs no iteration; a reduced-model x0 converges to the same solution in no
     more iterations than x0 = 0."""
