@@ -4,6 +4,7 @@ Plain, slow, obviously-correct NumPy/SciPy implementations written from the pape
 * ``fock``   brute-force Fock-space construction (tiny models) -- the trust anchor;
 * ``hbar``   closed-form H-bar blocks; ``sigma`` the IP sigma product, its transpose, b, c;
 * ``solve``  dense and GMRES shifted solves, G and A (Eqs. xplin, gfcclineqn, gfxn2);
+* ``diis``   the complex DIIS solver of the convergence study (Fig. 3);
 * ``mor``    the reduced-order model and its adaptive refinement (Eq. model);
 * ``mixed``  FP64 iterative refinement around reduced-precision GMRES;
 * ``adjoint`` gradient of windowed spectral weight with respect to orbital energies.
