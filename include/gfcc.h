@@ -148,6 +148,29 @@ gfcc_status gfcc_solve_x0(gfcc_ctx* ctx, int nw, const double* omega, int np, co
                           void* G_out, int* iters_out, double* resid_out);
 
 /*
+ * gfcc_solve_diis -- Eq. xplin at every (omega_w, p_k) by complex DIIS, the linear solver of the
+ * paper's convergence study (Results, Fig. 3, which keeps 10 micro-iteration iterates), in
+ * FP64. A micro-iteration is one Jacobi step x <- x + e, e = P^{-1} (b - M x), P = diag(M),
+ * M = (omega - i eta) I + Hbar_N (or Hbar_N^T for transpose = 1); after ndiis steps the kept
+ * iterates are combined with the complex coefficients that minimise ||sum_k c_k e_k|| under
+ * sum_k c_k = 1, and the subspace starts afresh. Each micro-iteration costs one sigma product.
+ * The stopping test is the true relative residual, formed before every micro-iteration; a
+ * right-hand side stops at tol, at maxit micro-iterations or at a non-finite residual.
+ * ndiis: iterates per extrapolation, 1..16 (1 is the plain Jacobi iteration).
+ * X0: initial guesses complex128 [nw][np][D] (device, e.g. from mor_lift) or NULL (zero);
+ *   must not overlap X_out.
+ * hist_out: host [nw*np][maxit+1] or NULL: relative residual of every evaluated iterate of each
+ *   right-hand side (entry 0: the initial guess), -1 after the last one -- the convergence
+ *   profile of Fig. 3.
+ * iters_out receives micro-iterations. Other arguments, outputs and status codes as
+ * gfcc_solve (ENOCONV if some right-hand side did not reach tol).
+ */
+gfcc_status gfcc_solve_diis(gfcc_ctx* ctx, int nw, const double* omega, int np, const int* p,
+                            double eta, double tol, int maxit, int ndiis, int block,
+                            int transpose, const void* X0, void* X_out, void* G_out,
+                            int* iters_out, double* resid_out, double* hist_out);
+
+/*
  * gfcc_grad_eps -- adjoint gradient of J = sum_w weight_w A(omega_w) with respect to the
  * orbital energies eps (amplitudes held fixed):
  *   dJ/deps_r = (1/pi) sum_w weight_w sum_k Im( - Y_k^T D_r X_k ),

@@ -206,6 +206,34 @@ int64_t count_nonfinite(gfcc_ctx* ctx, const double* p, int64_t n);
 void sigma_block_f64(gfcc_ctx* ctx, int nc, const double* X, double* Y, bool transpose);
 void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, bool bf16_3body);
 
+// -------------------------------------------------------------------- shifted solves
+// Every (omega, p) of the grid, solved in blocks of right-hand sides (solve.hip). G_out is
+// device [nw][np][np], X_out null or device [nw][np][D], X0 null or device initial guesses
+// [nw][np][D]. ndiis > 0 selects the periodic complex DIIS of diis.hip with that many iterates
+// per extrapolation (FP64; restart and precision unused) and hist its residual histories
+// (null or host [nw * np][maxit + 1]).
+gfcc_status solve_all(gfcc_ctx* ctx, int nw, const double* omega, int np, const int* p,
+                      double eta, double tol, int maxit, int restart, int block, int precision,
+                      int transpose, void* X_out, void* G_out, int* iters_out, double* resid_out,
+                      const void* X0, int ndiis = 0, double* hist = nullptr);
+
+// Right-hand-side block B[D][nb] (complex128): forward b = e_p, transpose b = c_p; a column
+// with prow[r] = -1 is zero. prow is a device array.
+void solve_rhs(gfcc_ctx* ctx, const int* prow, bool transpose, int64_t D, int nb, void* B);
+
+// DIIS workspace, grown on demand and reused across blocks.
+struct DiisWork {
+  DevBuf mem;
+};
+// Solves the right-hand sides [r0, r0 + nb) (global index w * np + k; indices >= nrhs are
+// padding) by periodic DIIS with m iterates per extrapolation. Returns the device block of
+// solutions [D][nb] (inside w.mem). its and res are host arrays over all right-hand sides;
+// hist is null or host [nrhs][maxit + 1]; X0 is null or device [nrhs][D].
+const void* diis_block(gfcc_ctx* ctx, DiisWork& w, int nb, int m, const double* omega,
+                       const int* pset, int np, int nrhs, int r0, double eta, double tol,
+                       int maxit, bool transpose, int* its, double* res, double* hist,
+                       const void* X0);
+
 // event-timed launch helpers
 void timer_begin(gfcc_ctx* ctx, int which, hipEvent_t* ev);
 void timer_end(gfcc_ctx* ctx, int which, hipEvent_t ev0);

@@ -25,13 +25,6 @@
 
 #include "common.h"
 
-namespace gfcc {
-gfcc_status solve_all(gfcc_ctx* ctx, int nw, const double* omega, int np, const int* p,
-                      double eta, double tol, int maxit, int restart, int block, int precision,
-                      int transpose, void* X_out, void* G_out, int* iters_out, double* resid_out,
-                      const void* X0);
-}
-
 struct gfcc_mor {
   gfcc_ctx* ctx = nullptr;
   int np = 0;

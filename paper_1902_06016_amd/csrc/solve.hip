@@ -13,26 +13,11 @@
 #include <algorithm>
 #include <cmath>
 
-#include "common.h"
+#include "blockvec.h"
 
 namespace gfcc {
 namespace {
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cconjmul(double2 a, double2 b) {  // conj(a) * b
-  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
-}
-__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
-  double s = fabs(b.x) + fabs(b.y);
-  double ar = a.x / s, ai = a.y / s, br = b.x / s, bi = b.y / s;
-  double d = br * br + bi * bi;
-  return make_double2((ar * br + ai * bi) / d, (ai * br - ar * bi) / d);
-}
-
-constexpr int JG = 16;  // basis vectors per dot pass
-constexpr int CW = 64;  // right-hand sides per reduction block: one wavefront, one per lane
 
 // partial[blk][jj][r] = sum over this block's rows of conj(V_j[d][r]) * W[d][r], j = j0 + jj.
 // Grid (nblk, ceil(nb / 64)), one wavefront per block; every lane owns one right-hand side
@@ -200,40 +185,6 @@ template <int... I> struct FusedTables {
 using Fused = FusedTables<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15>;
 static_assert(JG == 16, "the launch tables cover NJ = 1 .. 16");
 
-// h[(j0+jj)][r] = sum_blk partial[blk][jj][r]. Grid (ceil(nb/64), nj), 256 threads: the lanes
-// are 64 consecutive right-hand sides (coalesced reads), wave w sums the blocks w, w+4, ...,
-// and the four wave sums are added in a fixed order.
-__global__ __launch_bounds__(256) void dots_reduce(const double2* __restrict__ partial, int nblk,
-                                                   int j0, int nj, int nb,
-                                                   double2* __restrict__ h) {
-  __shared__ double2 red[4][CW];
-  const int lane = threadIdx.x % CW, w = threadIdx.x / CW;
-  const int r = blockIdx.x * CW + lane, jj = blockIdx.y;
-  double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
-  if (r < nb && jj < nj) {
-    int b = w;
-    for (; b + 4 < nblk; b += 8) {
-      const double2 x = partial[((int64_t)b * JG + jj) * nb + r];
-      const double2 y = partial[((int64_t)(b + 4) * JG + jj) * nb + r];
-      s0.x += x.x; s0.y += x.y;
-      s1.x += y.x; s1.y += y.y;
-    }
-    for (; b < nblk; b += 4) {
-      const double2 x = partial[((int64_t)b * JG + jj) * nb + r];
-      s0.x += x.x; s0.y += x.y;
-    }
-  }
-  red[w][lane] = make_double2(s0.x + s1.x, s0.y + s1.y);
-  __syncthreads();
-  if (w == 0 && r < nb && jj < nj) {
-    double2 t = red[0][lane];
-    for (int q = 1; q < 4; ++q) {
-      t.x += red[q][lane].x;
-      t.y += red[q][lane].y;
-    }
-    h[(int64_t)(j0 + jj) * nb + r] = t;
-  }
-}
 
 // W[d][r] -= sum_{j<=k} V_j[d][r] * h[j][r]
 __global__ void update_kernel(const double2* __restrict__ V, int64_t vstride, int nj,
@@ -270,25 +221,6 @@ __global__ __launch_bounds__(CW) void norm_kernel(const double2* __restrict__ W,
   partial[(int64_t)blockIdx.x * nb + r] = acc;
 }
 
-// out[r] = sqrt(sum_blk partial[blk][r]); same scheme as dots_reduce, grid ceil(nb/64)
-__global__ __launch_bounds__(256) void norm_reduce(const double* __restrict__ partial, int nblk,
-                                                   int nb, double* __restrict__ out) {
-  __shared__ double red[4][CW];
-  const int lane = threadIdx.x % CW, w = threadIdx.x / CW;
-  const int r = blockIdx.x * CW + lane;
-  double s0 = 0.0, s1 = 0.0;
-  if (r < nb) {
-    int b = w;
-    for (; b + 4 < nblk; b += 8) {
-      s0 += partial[(int64_t)b * nb + r];
-      s1 += partial[(int64_t)(b + 4) * nb + r];
-    }
-    for (; b < nblk; b += 4) s0 += partial[(int64_t)b * nb + r];
-  }
-  red[w][lane] = s0 + s1;
-  __syncthreads();
-  if (w == 0 && r < nb) out[r] = sqrt(red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane]);
-}
 
 // U[d][r] = V[d][r] / (diag[d] + z[r])
 __global__ void precond_kernel(const double2* __restrict__ V, const double* __restrict__ diag,
@@ -537,17 +469,6 @@ __global__ void f32_to_f64_kernel(const float* __restrict__ s, double* __restric
     d[i] = (double)s[i];
 }
 
-inline unsigned gridn(int64_t n) {
-  int64_t b = (n + 255) / 256;
-  if (b > 16384) b = 16384;
-  return (unsigned)(b < 1 ? 1 : b);
-}
-
-template <typename T> T* carve(char*& cur, int64_t n) {
-  T* p = reinterpret_cast<T*>(cur);
-  cur += ((n * (int64_t)sizeof(T) + 255) / 256) * 256;
-  return p;
-}
 
 }  // namespace
 
@@ -714,9 +635,7 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
   }
   GFCC_HIP(hipMemcpyAsync(gb.z, hz.data(), sizeof(double2) * nb, hipMemcpyHostToDevice, st));
   GFCC_HIP(hipMemcpyAsync(gb.prow, hp.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(rhs_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.prow,
-                     ctx->op.Crows.as<double>(), gb.transpose ? 1 : 0, D, nb, gb.B);
-  GFCC_LAUNCH_CHECK();
+  solve_rhs(ctx, gb.prow, gb.transpose, D, nb, gb.B);
   std::vector<double> bnorm(nb), rn(nb);
   gb.norms(gb.B, gb.nrm);
   GFCC_HIP(hipMemcpyAsync(bnorm.data(), gb.nrm, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
@@ -847,18 +766,27 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
 
 // Full driver shared by gfcc_solve and the reduced-order model: solves every (omega, p),
 // writes G (device, [nw][np][np]) and optionally X ([nw][np][D] device).
+void solve_rhs(gfcc_ctx* ctx, const int* prow, bool transpose, int64_t D, int nb, void* B) {
+  hipLaunchKernelGGL(rhs_kernel, dim3(gridn(D * nb)), dim3(256), 0, ctx->stream, prow,
+                     ctx->op.Crows.as<double>(), transpose ? 1 : 0, D, nb,
+                     static_cast<double2*>(B));
+  GFCC_LAUNCH_CHECK();
+}
+
 gfcc_status solve_all(gfcc_ctx* ctx, int nw, const double* omega, int np, const int* p,
                       double eta, double tol, int maxit, int restart, int block, int precision,
                       int transpose, void* X_out, void* G_out, int* iters_out, double* resid_out,
-                      const void* X0) {
+                      const void* X0, int ndiis, double* hist) {
   Operator& op = ctx->op;
   const int64_t D = op.D;
   const int nrhs = nw * np;
   int nb = block > 0 ? block : std::min(nrhs, 128);
   nb = std::max(1, std::min(nb, nrhs));
   GFCC_REQUIRE(nb <= 2048, GFCC_EINVAL, "gfcc_solve: block too large");
+  const bool diis = ndiis > 0;
   GmresBlock gb;
-  gb.setup(ctx, nb, restart, precision, transpose != 0);
+  DiisWork dw;
+  if (!diis) gb.setup(ctx, nb, restart, precision, transpose != 0);
   std::vector<int> its(nrhs, 0), brk(nrhs, 0);
   std::vector<double> res(nrhs, 0.0);
   // rows used for G: c_q rows (forward) or the 1h entries q (transpose)
@@ -876,20 +804,31 @@ gfcc_status solve_all(gfcc_ctx* ctx, int nw, const double* omega, int np, const 
     // the last block is only as wide as the right-hand sides left, rounded up to a multiple
     // of 64 (which keeps the column-block ovvo kernel); padding columns have b = 0
     const int left = nrhs - r0;
-    if (left < gb.nb) {
-      const int nbl = std::min(gb.nb, (left + 63) / 64 * 64);
-      if (nbl != gb.nb) gb.setup(ctx, nbl, restart, precision, transpose != 0);
+    if (left < nb) {
+      const int nbl = std::min(nb, (left + 63) / 64 * 64);
+      if (nbl != nb) {
+        nb = nbl;
+        if (!diis) gb.setup(ctx, nb, restart, precision, transpose != 0);
+      }
     }
-    const int nbb = gb.nb;
-    solve_block(gb, omega, p, np, nrhs, r0, eta, tol, maxit, its, res, brk,
-                static_cast<const double2*>(X0));
+    const int nbb = nb;
+    const double2* Xb;
+    if (diis) {
+      Xb = static_cast<const double2*>(diis_block(ctx, dw, nbb, ndiis, omega, p, np, nrhs, r0,
+                                                  eta, tol, maxit, transpose != 0, its.data(),
+                                                  res.data(), hist, X0));
+    } else {
+      solve_block(gb, omega, p, np, nrhs, r0, eta, tol, maxit, its, res, brk,
+                  static_cast<const double2*>(X0));
+      Xb = gb.X;
+    }
     // G rows for this block
     if (!transpose) {
       gemm<double>(ctx, false, false, np, 2 * nbb, (int)D, 1.0, bC.as<double>(), D,
-                   reinterpret_cast<const double*>(gb.X), 2 * nbb, 0.0, bG.as<double>(), 2 * nbb);
+                   reinterpret_cast<const double*>(Xb), 2 * nbb, 0.0, bG.as<double>(), 2 * nbb);
     } else {
       hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks_for((int64_t)np * nbb, 256)), dim3(256),
-                         0, ctx->stream, gb.X, bq.as<int>(), np, nbb, bG.as<double2>());
+                         0, ctx->stream, Xb, bq.as<int>(), np, nbb, bG.as<double2>());
       GFCC_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(scatter_G_kernel, dim3(blocks_for((int64_t)np * nbb, 256)), dim3(256), 0,
@@ -898,7 +837,7 @@ gfcc_status solve_all(gfcc_ctx* ctx, int nw, const double* omega, int np, const 
     GFCC_LAUNCH_CHECK();
     if (X_out) {
       int cnt = std::min(nbb, nrhs - r0);
-      ctranspose(ctx, gb.X, D, cnt, nbb, static_cast<double2*>(X_out) + (int64_t)r0 * D, D);
+      ctranspose(ctx, Xb, D, cnt, nbb, static_cast<double2*>(X_out) + (int64_t)r0 * D, D);
     }
     r0 += nbb;
   }
@@ -1061,6 +1000,30 @@ gfcc_status gfcc_solve_x0(gfcc_ctx* ctx, int nw, const double* omega, int np, co
   }
   return solve_all(ctx, nw, omega, np, p, eta, tol, maxit, restart, block, precision, transpose,
                    X_out, G_out, iters_out, resid_out, X0);
+  GFCC_API_END(ctx)
+}
+
+gfcc_status gfcc_solve_diis(gfcc_ctx* ctx, int nw, const double* omega, int np, const int* p,
+                            double eta, double tol, int maxit, int ndiis, int block,
+                            int transpose, const void* X0, void* X_out, void* G_out,
+                            int* iters_out, double* resid_out, double* hist_out) {
+  if (!ctx) return GFCC_EINVAL;
+  GFCC_API_BEGIN(ctx)
+  using namespace gfcc;
+  GFCC_HIP(hipSetDevice(ctx->device));
+  check_solve_args(ctx, nw, omega, np, p, eta, tol, maxit, 1, GFCC_FP64, transpose, G_out);
+  if (nw == 0 || np == 0) return GFCC_OK;
+  GFCC_REQUIRE(ndiis >= 1 && ndiis <= 16, GFCC_EINVAL,
+               "gfcc_solve_diis: ndiis must be in [1, 16]");
+  if (X0 && X_out) {
+    const size_t bytes = sizeof(double2) * (size_t)nw * np * (size_t)ctx->op.D;
+    const char* a = static_cast<const char*>(X0);
+    const char* b = static_cast<const char*>(X_out);
+    GFCC_REQUIRE(a + bytes <= b || b + bytes <= a, GFCC_EINVAL,
+                 "gfcc_solve_diis: X0 and X_out overlap");
+  }
+  return solve_all(ctx, nw, omega, np, p, eta, tol, maxit, 1, block, GFCC_FP64, transpose, X_out,
+                   G_out, iters_out, resid_out, X0, ndiis, hist_out);
   GFCC_API_END(ctx)
 }
 

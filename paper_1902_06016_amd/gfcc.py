@@ -49,6 +49,8 @@ def _load():
                              vp]),
         "gfcc_solve_x0": (i32, [vp, i32, vp, i32, vp, dbl, dbl, i32, i32, i32, i32, i32, vp, vp,
                                 vp, vp, vp]),
+        "gfcc_solve_diis": (i32, [vp, i32, vp, i32, vp, dbl, dbl, i32, i32, i32, i32, vp, vp,
+                                  vp, vp, vp, vp]),
         "gfcc_grad_eps": (i32, [vp, i32, vp, i32, vp, vp, vp]),
         "mor_build": (i32, [vp, i32, vp, i32, vp, dbl, dbl, dbl, P(vp)]),
         "mor_build_diag": (i32, [vp, i32, vp, i32, vp, dbl, dbl, dbl, vp]),
@@ -70,7 +72,8 @@ def _load():
 
 lib = _load()
 SYMBOLS = ("gfcc_dim", "gfcc_create", "gfcc_destroy", "gfcc_last_error", "build_hbar_operands",
-           "sigma_apply", "gfcc_solve", "gfcc_solve_x0", "gfcc_grad_eps", "mor_build",
+           "sigma_apply", "gfcc_solve", "gfcc_solve_x0", "gfcc_solve_diis", "gfcc_grad_eps",
+           "mor_build",
            "mor_build_diag", "mor_refine", "mor_eval", "mor_lift", "mor_info", "mor_destroy",
            "spectral_function", "gfcc_export", "gfcc_timer")
 
@@ -100,6 +103,7 @@ class SolveResult:
     iters: np.ndarray    # [nw, np]
     resid: np.ndarray    # [nw, np]
     status: int
+    hist: np.ndarray | None = None   # DIIS: [nw, np, maxit + 1] residual histories, -1 padded
 
 
 class Context:
@@ -213,6 +217,33 @@ class Context:
                                    precision, int(transpose), _ptr(x0), xp, _ptr(G), ip, rp)
         self._check(st, allow=(GFCC_ENOCONV,) if allow_noconv else ())
         return SolveResult(G=G, X=X, iters=its.reshape(nw, np_), resid=res.reshape(nw, np_), status=st)
+
+    def gfcc_solve_diis(self, omega, p, eta, tol=1e-10, maxit=500, ndiis=10, block=0,
+                        transpose=False, want_x=False, allow_noconv=False, x0=None,
+                        want_hist=False):
+        """Complex DIIS solves (gfcc_solve_diis); x0 as in gfcc_solve."""
+        om, om_p = _f64arr(omega)
+        pp, p_p = _i32arr(p)
+        nw, np_ = len(om), len(pp)
+        T = self.torch
+        G = T.empty((nw, np_, np_), dtype=T.complex128, device=self.device)
+        X = T.empty((nw, np_, self.D), dtype=T.complex128, device=self.device) if want_x else None
+        its = np.zeros(nw * np_, dtype=np.int32)
+        res = np.zeros(nw * np_, dtype=np.float64)
+        hist = np.zeros((nw, np_, maxit + 1), dtype=np.float64) if want_hist else None
+        if x0 is not None:
+            x0 = x0.contiguous()
+            if x0.dtype != T.complex128 or tuple(x0.shape) != (nw, np_, self.D):
+                raise ValueError("x0 must be complex128 [nw][np][D]")
+        st = lib.gfcc_solve_diis(self.h, nw, om_p, np_, p_p, eta, tol, maxit, ndiis, block,
+                                 int(transpose), _ptr(x0) if x0 is not None else None,
+                                 _ptr(X) if X is not None else None, _ptr(G),
+                                 its.ctypes.data_as(ctypes.c_void_p),
+                                 res.ctypes.data_as(ctypes.c_void_p),
+                                 hist.ctypes.data_as(ctypes.c_void_p) if hist is not None else None)
+        self._check(st, allow=(GFCC_ENOCONV,) if allow_noconv else ())
+        return SolveResult(G=G, X=X, iters=its.reshape(nw, np_), resid=res.reshape(nw, np_),
+                           status=st, hist=hist)
 
     def gfcc_grad_eps(self, weight, X, Y):
         w, w_p = _f64arr(weight)

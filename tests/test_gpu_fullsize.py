@@ -54,6 +54,29 @@ def test_c1_sampled_parity_with_oracle(gpu_ctx, c1):
     assert np.abs(A1 - A2).max() / np.abs(A2).max() < 1e-9
 
 
+def test_c1_diis_matches_gmres(gpu_ctx, c1):
+    """The complex DIIS solver at the full operator size: four frequencies of the benchmark grid
+    (both ends and two inside) for all eight valence orbitals, against GMRES at tol 1e-12."""
+    print("[c1 diis]", flush=True)
+    om_all = synth.omega_grid(CFG1["omega"])
+    om = om_all[[0, 67, 133, len(om_all) - 1]]
+    ps = synth.valence_p(c1.o, CFG1["np"])
+    ref = gpu_ctx.gfcc_solve(om, ps, CFG1["eta"], tol=1e-12, restart=30)
+    res = gpu_ctx.gfcc_solve_diis(om, ps, CFG1["eta"], tol=1e-10, maxit=400, ndiis=10,
+                                  want_hist=True)
+    print(f"  DIIS micro-iterations {res.iters.min()}..{res.iters.max()}, "
+          f"GMRES {ref.iters.min()}..{ref.iters.max()}", flush=True)
+    assert res.resid.max() <= 1e-10
+    G, Gr = res.G.cpu().numpy(), ref.G.cpu().numpy()
+    assert np.abs(G - Gr).max() <= 1e-8 * np.abs(Gr).max()
+    # the recorded profile ends at the reported residual
+    for w in range(len(om)):
+        for k in range(len(ps)):
+            h = res.hist[w, k]
+            assert h[res.iters[w, k]] == res.resid[w, k]
+            assert h[0] == 1.0 and (h[res.iters[w, k] + 1:] == -1.0).all()
+
+
 def test_c2_mor_workflow(gpu_ctx, c1):
     print("[c2 mor]", flush=True)
     cfg = synth.CONFIGS[2]
