@@ -311,6 +311,81 @@ def guess_small(gfcc, torch):
     return out
 
 
+def form_diis(ctx, cfg, gfcc, gmres_A):
+    """The complex DIIS solver (periodic, 10 iterates: the solver of the paper's convergence
+    study) on the benchmark grid beside GMRES, and a synthetic analog of Fig. 3."""
+    import torch
+    import synth
+    ps = synth.valence_p(ctx.o, cfg["np"])
+    om = synth.omega_grid(cfg["omega"])
+    out = {"ndiis": 10}
+    for name in ("gmres", "diis"):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        if name == "gmres":
+            r = ctx.gfcc_solve(om, ps, cfg["eta"], tol=cfg["tol"], restart=30, block=320)
+        else:
+            r = ctx.gfcc_solve_diis(om, ps, cfg["eta"], tol=cfg["tol"], maxit=400, ndiis=10,
+                                    block=320)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        out[name] = {"solve_s": dt, "points_per_s": len(om) / dt,
+                     "iterations_mean": float(r.iters.mean()),
+                     "iterations_max": int(r.iters.max()),
+                     "max_rel_resid": float(r.resid.max())}
+        if name == "diis":
+            A = gfcc.spectral_function(r.G)
+            out[name]["A_max_rel_diff_vs_gmres"] = float(np.abs(A - gmres_A).max()
+                                                         / np.abs(gmres_A).max())
+    out["fig3_analog"] = diis_fig3(gfcc, torch)
+    return out
+
+
+def diis_fig3(gfcc, torch):
+    """Synthetic analog of Fig. 3 on the small case: two inner-valence frequencies among the
+    satellite poles below the window, DIIS from a zero guess and from the extrapolation of an
+    eight-frequency reduced model built on a narrower window above them; 80 micro-iterations
+    at most. Residual profiles are the worst over the orbitals p."""
+    import synth
+    cfg = synth.CONFIGS[0]
+    o, v = cfg["o"], cfg["v"]
+    prob = synth.make_problem(o, v, cfg["seed"])
+    ctx = gfcc.Context(0)
+    ctx.build_from_problem(prob)
+    ps = synth.valence_p(o, cfg["np"])
+    targets = np.array([-1.55, -1.35])
+    window = (-1.25, -0.85)
+    model = ctx.mor_build(np.linspace(*window, 8), ps, cfg["eta"], solve_tol=1e-12)
+    x0 = model.lift(targets)
+    out = {"workload": f"o={o} v={v}, omega={targets.tolist()} Ha x {len(ps)} p, "
+                       f"eta={cfg['eta']}, tol={cfg['tol']}",
+           "model": {"window": list(window), "sampled": 8, "order": model.info()[0]}}
+    model.close()
+    maxit = 80
+    marks = (0, 1, 5, 10, 20, 40, 80)
+    for name, guess in (("zero", None), ("model", x0)):
+        r = ctx.gfcc_solve_diis(targets, ps, cfg["eta"], tol=cfg["tol"], maxit=maxit, ndiis=10,
+                                x0=guess, want_hist=True, allow_noconv=True)
+        h = r.hist.copy()
+        for w in range(h.shape[0]):          # carry the last residual past convergence
+            for k in range(h.shape[1]):
+                n = r.iters[w, k]
+                h[w, k, n + 1:] = h[w, k, n]
+        worst = h.max(axis=1)                # [omega, iteration]
+        runs = {}
+        for w, om in enumerate(targets):
+            below = np.nonzero(worst[w] < 1e-5)[0]
+            runs[f"{om:+.2f}"] = {
+                "worst_resid_at": {str(i): float(worst[w, i]) for i in marks},
+                "iterations_to_1e-5": int(below[0]) if len(below) else None,
+                "converged": int((r.resid[w] <= cfg["tol"]).sum()), "of": len(ps)}
+        out[name] = runs
+    g = ctx.gfcc_solve(targets, ps, cfg["eta"], tol=cfg["tol"], restart=50)
+    out["gmres_from_zero_iterations_max"] = int(g.iters.max())
+    ctx.close()
+    return out
+
+
 def synth_valence(o, n):
     import synth
     return synth.valence_p(o, n)
@@ -429,9 +504,9 @@ def main():
     ap.add_argument("--sigma-only", type=int, default=0,
                     help="profiling driver: K sigma products of one block in the benchmark's "
                          "launch configuration, then a 1 GiB device copy (counter calibration)")
-    ap.add_argument("--forms", default="mor,guess,adjoint,mixed,small",
-                    help="extra forms reported beside the plain path: mor, guess, adjoint, "
-                         "mixed, small, none")
+    ap.add_argument("--forms", default="mor,guess,diis,adjoint,mixed,small",
+                    help="extra forms reported beside the plain path: mor, guess, diis, "
+                         "adjoint, mixed, small, none")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the (omega, p) right-hand "
@@ -558,6 +633,8 @@ def main():
         out["mor"] = form_mor(ctx, prob, synth.CONFIGS[2], gfcc)
     if "guess" in forms:
         out["guess"] = form_guess(ctx, cfg, gfcc)
+    if "diis" in forms:
+        out["diis"] = form_diis(ctx, cfg, gfcc, A)
     if "adjoint" in forms:
         out["adjoint"] = form_adjoint(ctx, synth.CONFIGS[4], gfcc, inputs)
     if not args.no_cpu_baseline:
