@@ -83,6 +83,26 @@ def build_hbar(o, v, eps, t1, t2, oooo, ooov, oovv, ovvo, ovvv) -> HBar:
                 Wovoo=Wovoo, oovv=oovv, t2=t2)
 
 
+def first_order_amplitudes(o, v, eps, oovv):
+    """T and Lambda replaced by their first-order perturbative terms (the variant of the
+    Conclusions, after Nooijen and Snijders), with the Moller-Plesset partitioning
+    H0 = sum_p eps_p a+_p a_p of a diagonal Fock matrix: t1 = 0 (the singles coupling f_ia
+    vanishes), t2_ij^ab = <ij||ab> / (e_i + e_j - e_a - e_b), and Lambda = T^dagger at this
+    order (l1 = 0, l2 = t2 for real integrals). Returns (t1, t2, l1, l2)."""
+    eo, ev = eps[:o], eps[o:]
+    den = (eo[:, None, None, None] + eo[None, :, None, None]
+           - ev[None, None, :, None] - ev[None, None, None, :])
+    t2 = oovv / den
+    z = np.zeros((o, v))
+    return z, t2, z.copy(), t2.copy()
+
+
+def build_hbar_first_order(prob) -> HBar:
+    t1, t2, _, _ = first_order_amplitudes(prob.o, prob.v, prob.eps, prob.block("oovv"))
+    return build_hbar(prob.o, prob.v, prob.eps, t1, t2, prob.block("oooo"), prob.block("ooov"),
+                      prob.block("oovv"), prob.block("ovvo"), prob.block("ovvv"))
+
+
 def build_hbar_from_problem(prob) -> HBar:
     return build_hbar(prob.o, prob.v, prob.eps, prob.t1, prob.t2, prob.block("oooo"),
                       prob.block("ooov"), prob.block("oovv"), prob.block("ovvo"),
