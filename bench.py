@@ -386,6 +386,70 @@ def diis_fig3(gfcc, torch):
     return out
 
 
+def form_pert(cfg, gfcc, inputs, A_full, t_build_full):
+    """First-order perturbative T and Lambda (the variant of the Conclusions, which skips the
+    CC ground state): the operator from t1 = l1 = 0 and first-order doubles formed on the
+    device, solved on the benchmark grid beside the full amplitudes."""
+    import torch
+    import synth
+    o, v = cfg["o"], cfg["v"]
+    om = synth.omega_grid(cfg["omega"])
+    ps = synth.valence_p(o, cfg["np"])
+    eps, oooo, ooov, oovv, ovvo, ovvv = [inputs[i] for i in (0, 5, 6, 7, 8, 9)]
+    ctx = gfcc.Context(0)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ctx.build_hbar_first_order(o, v, eps, oooo, ooov, oovv, ovvo, ovvv)
+    torch.cuda.synchronize()
+    t_build = time.time() - t0
+    t0 = time.time()
+    r = ctx.gfcc_solve(om, ps, cfg["eta"], tol=cfg["tol"], restart=30, block=320)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    A = gfcc.spectral_function(r.G)
+    ctx.close()
+    out = {"build_s": t_build, "build_s_full_amplitudes": t_build_full, "solve_s": dt,
+           "points_per_s": len(om) / (t_build + dt), "iterations_mean": float(r.iters.mean()),
+           "A_max_rel_diff_vs_full_amplitudes": float(np.abs(A - A_full).max()
+                                                      / np.abs(A_full).max())}
+    out["small"] = pert_small(gfcc, torch)
+    return out
+
+
+def pert_small(gfcc, torch):
+    """Peak positions of A over a window that holds the poles (small case, [-1.6, -0.3] Ha,
+    1301 points): full amplitudes against first-order ones."""
+    import synth
+    cfg = synth.CONFIGS[0]
+    o, v = cfg["o"], cfg["v"]
+    prob = synth.make_problem(o, v, cfg["seed"])
+    om = np.linspace(-1.6, -0.3, 1301)
+    ps = synth.valence_p(o, cfg["np"])
+    ctx = gfcc.Context(0)
+    curves = {}
+    for name in ("full", "first_order"):
+        if name == "full":
+            ctx.build_from_problem(prob)
+        else:
+            ctx.build_first_order_from_problem(prob)
+        r = ctx.gfcc_solve(om, ps, cfg["eta"], tol=cfg["tol"], restart=50)
+        curves[name] = gfcc.spectral_function(r.G)
+    ctx.close()
+
+    def peaks(A):
+        i = np.nonzero((A[1:-1] > A[:-2]) & (A[1:-1] >= A[2:]) & (A[1:-1] > 0.01 * A.max()))[0]
+        return om[i + 1]
+
+    pf, pp = peaks(curves["full"]), peaks(curves["first_order"])
+    shift = [float(np.abs(pp - w).min()) for w in pf] if len(pp) else []
+    return {"window": [-1.6, -0.3], "points": len(om), "eta": cfg["eta"],
+            "peaks_full": len(pf), "peaks_first_order": len(pp),
+            "max_peak_shift_Ha": max(shift) if shift else None,
+            "max_peak_shift_eV": max(shift) * 27.211386 if shift else None,
+            "A_max_rel_diff": float(np.abs(curves["first_order"] - curves["full"]).max()
+                                    / np.abs(curves["full"]).max())}
+
+
 def synth_valence(o, n):
     import synth
     return synth.valence_p(o, n)
@@ -504,8 +568,8 @@ def main():
     ap.add_argument("--sigma-only", type=int, default=0,
                     help="profiling driver: K sigma products of one block in the benchmark's "
                          "launch configuration, then a 1 GiB device copy (counter calibration)")
-    ap.add_argument("--forms", default="mor,guess,diis,adjoint,mixed,small",
-                    help="extra forms reported beside the plain path: mor, guess, diis, "
+    ap.add_argument("--forms", default="mor,guess,diis,pert,adjoint,mixed,small",
+                    help="extra forms reported beside the plain path: mor, guess, diis, pert, "
                          "adjoint, mixed, small, none")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -635,6 +699,8 @@ def main():
         out["guess"] = form_guess(ctx, cfg, gfcc)
     if "diis" in forms:
         out["diis"] = form_diis(ctx, cfg, gfcc, A)
+    if "pert" in forms:
+        out["pert"] = form_pert(cfg, gfcc, inputs, A, t_build)
     if "adjoint" in forms:
         out["adjoint"] = form_adjoint(ctx, synth.CONFIGS[4], gfcc, inputs)
     if not args.no_cpu_baseline:

@@ -97,6 +97,20 @@ gfcc_status build_hbar_operands(gfcc_ctx* ctx, int o, int v, const double* eps,
                                 int precision_mask);
 
 /*
+ * build_hbar_first_order -- build_hbar_operands with T and Lambda replaced by their
+ * first-order perturbative terms (the variant of the Conclusions, after Nooijen and Snijders,
+ * which skips the CC ground state): t1 = l1 = 0 and
+ * t2[i][j][a][b] = l2[i][j][a][b] = oovv[i][j][a][b] / (eps_i + eps_j - eps_a - eps_b), formed
+ * on the device from the Moller-Plesset partitioning of the diagonal Fock matrix diag(eps).
+ * Arguments as build_hbar_operands (no amplitudes). The amplitudes are temporary (o^2 v^2
+ * doubles during the call). Errors: as build_hbar_operands, and EINVAL unless every occupied
+ * energy lies below every virtual one (no vanishing denominator).
+ */
+gfcc_status build_hbar_first_order(gfcc_ctx* ctx, int o, int v, const double* eps,
+                                   const double* oooo, const double* ooov, const double* oovv,
+                                   const double* ovvo, const double* ovvv, int precision_mask);
+
+/*
  * sigma_apply -- y = Hbar_N x (transpose = 0) or y = Hbar_N^T x (transpose = 1) for nrhs
  * complex vectors: x, y are complex128 [nrhs][D] (device). This is the connected part of
  * Hbar_N acting on X_p (Eq. xplin), the product every Krylov iteration needs.

@@ -1,4 +1,7 @@
 // Context lifetime, operator build entry point, inspection and event timers.
+#include <algorithm>
+#include <initializer_list>
+
 #include "common.h"
 
 namespace gfcc {
@@ -7,6 +10,29 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
                     const double* t2, const double* l1, const double* l2, const double* oooo,
                     const double* ooov, const double* oovv, const double* ovvo,
                     const double* ovvv, int keep);
+void first_order_t2(gfcc_ctx* ctx, int o, int v, const double* eps, const double* oovv,
+                    double* t2);
+
+struct NamedArray {
+  const double* p;
+  int64_t n;
+  const char* name;
+};
+
+// Shared argument checks of the operator builds (throws Error).
+static void check_build_args(gfcc_ctx* ctx, const char* fn, int o, int v, int precision_mask,
+                             std::initializer_list<NamedArray> arrs) {
+  GFCC_REQUIRE(o >= 2 && v >= 1, GFCC_EINVAL, std::string(fn) + ": need o >= 2 and v >= 1");
+  GFCC_REQUIRE((int64_t)o * v <= (1 << 20) && o <= 4096, GFCC_EINVAL,
+               std::string(fn) + ": o*v too large");
+  for (auto& a : arrs)
+    GFCC_REQUIRE(a.p != nullptr, GFCC_EINVAL, std::string(fn) + ": null pointer");
+  GFCC_REQUIRE((precision_mask & ~(GFCC_KEEP_FP64 | GFCC_KEEP_FP32 | GFCC_KEEP_TRANSPOSE)) == 0,
+               GFCC_EINVAL, std::string(fn) + ": unknown precision_mask bits");
+  for (auto& a : arrs)
+    GFCC_REQUIRE(count_nonfinite(ctx, a.p, a.n) == 0, GFCC_EINVAL,
+                 std::string(fn) + ": non-finite entries in " + a.name);
+}
 
 static hipEvent_t event_get(gfcc_ctx* ctx) {
   if (!ctx->event_pool.empty()) {
@@ -101,23 +127,46 @@ gfcc_status build_hbar_operands(gfcc_ctx* ctx, int o, int v, const double* eps,
   GFCC_API_BEGIN(ctx)
   using namespace gfcc;
   GFCC_HIP(hipSetDevice(ctx->device));
-  GFCC_REQUIRE(o >= 2 && v >= 1, GFCC_EINVAL, "build_hbar_operands: need o >= 2 and v >= 1");
-  GFCC_REQUIRE((int64_t)o * v <= (1 << 20) && o <= 4096, GFCC_EINVAL,
-               "build_hbar_operands: o*v too large");
-  GFCC_REQUIRE(eps && t1 && t2 && l1 && l2 && oooo && ooov && oovv && ovvo && ovvv, GFCC_EINVAL,
-               "build_hbar_operands: null pointer");
-  GFCC_REQUIRE((precision_mask & ~(GFCC_KEEP_FP64 | GFCC_KEEP_FP32 | GFCC_KEEP_TRANSPOSE)) == 0,
-               GFCC_EINVAL, "build_hbar_operands: unknown precision_mask bits");
   const int64_t O = o, V = v;
-  struct { const double* p; int64_t n; const char* name; } arrs[] = {
-      {eps, O + V, "eps"}, {t1, O * V, "t1"}, {t2, O * O * V * V, "t2"}, {l1, O * V, "l1"},
-      {l2, O * O * V * V, "l2"}, {oooo, O * O * O * O, "oooo"}, {ooov, O * O * O * V, "ooov"},
-      {oovv, O * O * V * V, "oovv"}, {ovvo, O * V * V * O, "ovvo"}, {ovvv, O * V * V * V, "ovvv"}};
-  for (auto& a : arrs)
-    GFCC_REQUIRE(count_nonfinite(ctx, a.p, a.n) == 0, GFCC_EINVAL,
-                 std::string("build_hbar_operands: non-finite entries in ") + a.name);
+  check_build_args(ctx, "build_hbar_operands", o, v, precision_mask,
+                   {{eps, O + V, "eps"}, {t1, O * V, "t1"}, {t2, O * O * V * V, "t2"},
+                    {l1, O * V, "l1"}, {l2, O * O * V * V, "l2"}, {oooo, O * O * O * O, "oooo"},
+                    {ooov, O * O * O * V, "ooov"}, {oovv, O * O * V * V, "oovv"},
+                    {ovvo, O * V * V * O, "ovvo"}, {ovvv, O * V * V * V, "ovvv"}});
   build_operator(ctx, o, v, eps, t1, t2, l1, l2, oooo, ooov, oovv, ovvo, ovvv,
                  precision_mask | GFCC_KEEP_FP64);
+  GFCC_API_END(ctx)
+}
+
+gfcc_status build_hbar_first_order(gfcc_ctx* ctx, int o, int v, const double* eps,
+                                   const double* oooo, const double* ooov, const double* oovv,
+                                   const double* ovvo, const double* ovvv, int precision_mask) {
+  if (!ctx) return GFCC_EINVAL;
+  GFCC_API_BEGIN(ctx)
+  using namespace gfcc;
+  GFCC_HIP(hipSetDevice(ctx->device));
+  const int64_t O = o, V = v;
+  check_build_args(ctx, "build_hbar_first_order", o, v, precision_mask,
+                   {{eps, O + V, "eps"}, {oooo, O * O * O * O, "oooo"},
+                    {ooov, O * O * O * V, "ooov"}, {oovv, O * O * V * V, "oovv"},
+                    {ovvo, O * V * V * O, "ovvo"}, {ovvv, O * V * V * V, "ovvv"}});
+  std::vector<double> he(O + V);
+  GFCC_HIP(hipMemcpyAsync(he.data(), eps, sizeof(double) * (O + V), hipMemcpyDeviceToHost,
+                          ctx->stream));
+  GFCC_HIP(hipStreamSynchronize(ctx->stream));
+  double homo = he[0], lumo = he[O];
+  for (int64_t i = 1; i < O; ++i) homo = std::max(homo, he[i]);
+  for (int64_t a = O + 1; a < O + V; ++a) lumo = std::min(lumo, he[a]);
+  GFCC_REQUIRE(homo < lumo, GFCC_EINVAL,
+               "build_hbar_first_order: every occupied energy must lie below every virtual one");
+  DevBuf bt2, bz;
+  bt2.alloc(sizeof(double) * (size_t)(O * O * V * V));
+  bz.alloc(sizeof(double) * (size_t)(O * V));
+  fill(ctx, bz.as<double>(), O * V, 0.0);
+  first_order_t2(ctx, o, v, eps, oovv, bt2.as<double>());
+  build_operator(ctx, o, v, eps, bz.as<double>(), bt2.as<double>(), bz.as<double>(),
+                 bt2.as<double>(), oooo, ooov, oovv, ovvo, ovvv, precision_mask | GFCC_KEEP_FP64);
+  GFCC_HIP(hipStreamSynchronize(ctx->stream));  // the amplitudes are freed on return
   GFCC_API_END(ctx)
 }
 

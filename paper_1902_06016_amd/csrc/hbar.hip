@@ -218,6 +218,23 @@ inline unsigned grid_for(int64_t n) {
   return (unsigned)(b < 1 ? 1 : b);
 }
 
+// First-order doubles: t2[i][j][a][b] = oovv[i][j][a][b] / (eps_i + eps_j - eps_a - eps_b)
+// (virtual energies at eps[o + a]); the denominator is summed in that order.
+__global__ void first_order_t2_kernel(const double* __restrict__ eps,
+                                      const double* __restrict__ oovv, int o, int v,
+                                      double* __restrict__ t2) {
+  const int64_t n = (int64_t)o * o * v * v;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(idx % v);
+    const int a = (int)((idx / v) % v);
+    const int j = (int)((idx / ((int64_t)v * v)) % o);
+    const int i = (int)(idx / ((int64_t)o * v * v));
+    const double den = ((eps[i] + eps[j]) - eps[o + a]) - eps[o + b];
+    t2[idx] = oovv[idx] / den;
+  }
+}
+
 // small helper: dst (contiguous dims d) = alpha * src(strides s) + beta * dst
 inline void perm(gfcc_ctx* ctx, const double* src, std::initializer_list<int64_t> d,
                  std::initializer_list<int64_t> s, double* dst, double alpha = 1.0,
@@ -231,6 +248,13 @@ inline void perm(gfcc_ctx* ctx, const double* src, std::initializer_list<int64_t
 }
 
 }  // namespace
+
+void first_order_t2(gfcc_ctx* ctx, int o, int v, const double* eps, const double* oovv,
+                    double* t2) {
+  hipLaunchKernelGGL(first_order_t2_kernel, dim3(grid_for((int64_t)o * o * v * v)), dim3(256), 0,
+                     ctx->stream, eps, oovv, o, v, t2);
+  GFCC_LAUNCH_CHECK();
+}
 
 void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double* t1,
                     const double* t2, const double* l1, const double* l2, const double* oooo,

@@ -44,6 +44,7 @@ def _load():
         "gfcc_destroy": (i32, [vp]),
         "gfcc_last_error": (ctypes.c_char_p, [vp]),
         "build_hbar_operands": (i32, [vp, i32, i32] + [vp] * 10 + [i32]),
+        "build_hbar_first_order": (i32, [vp, i32, i32] + [vp] * 6 + [i32]),
         "sigma_apply": (i32, [vp, i32, vp, vp, i32, i32]),
         "gfcc_solve": (i32, [vp, i32, vp, i32, vp, dbl, dbl, i32, i32, i32, i32, i32, vp, vp, vp,
                              vp]),
@@ -72,7 +73,7 @@ def _load():
 
 lib = _load()
 SYMBOLS = ("gfcc_dim", "gfcc_create", "gfcc_destroy", "gfcc_last_error", "build_hbar_operands",
-           "sigma_apply", "gfcc_solve", "gfcc_solve_x0", "gfcc_solve_diis", "gfcc_grad_eps",
+           "build_hbar_first_order", "sigma_apply", "gfcc_solve", "gfcc_solve_x0", "gfcc_solve_diis", "gfcc_grad_eps",
            "mor_build",
            "mor_build_diag", "mor_refine", "mor_eval", "mor_lift", "mor_info", "mor_destroy",
            "spectral_function", "gfcc_export", "gfcc_timer")
@@ -159,6 +160,27 @@ class Context:
                 raise ValueError("build_hbar_operands expects contiguous float64 device tensors")
         self._check(lib.build_hbar_operands(self.h, o, v, *[_ptr(a) for a in arrs], keep))
         self.o, self.v, self.D = o, v, dim(o, v)
+
+    def build_hbar_first_order(self, o, v, eps, oooo, ooov, oovv, ovvo, ovvv,
+                               keep: int = KEEP_FP64):
+        """The operator from first-order amplitudes formed on the device; arrays as in
+        build_hbar_operands."""
+        arrs = [eps, oooo, ooov, oovv, ovvo, ovvv]
+        for a in arrs:
+            if a.dtype != self.torch.float64 or not a.is_contiguous() or a.device != self.device:
+                raise ValueError("build_hbar_first_order expects contiguous float64 device tensors")
+        self._check(lib.build_hbar_first_order(self.h, o, v, *[_ptr(a) for a in arrs], keep))
+        self.o, self.v, self.D = o, v, dim(o, v)
+
+    def build_first_order_from_problem(self, prob, keep: int = KEEP_FP64):
+        """Upload a synthetic problem's energies and integrals (no amplitudes) and build the
+        operator from first-order amplitudes."""
+        T = self.torch
+        arrs = [prob.eps] + [prob.block(k) for k in ("oooo", "ooov", "oovv", "ovvo", "ovvv")]
+        dev = [T.from_numpy(np.ascontiguousarray(a)).to(self.device) for a in arrs]
+        self.build_hbar_first_order(prob.o, prob.v, *dev, keep=keep)
+        del dev
+        T.cuda.synchronize(self.device)
 
     def build_from_problem(self, prob, keep: int = KEEP_FP64):
         """Upload a synthetic problem (``synth.Problem``) and build the operator from it."""

@@ -77,6 +77,37 @@ def test_c1_diis_matches_gmres(gpu_ctx, c1):
             assert h[0] == 1.0 and (h[res.iters[w, k] + 1:] == -1.0).all()
 
 
+def test_c1_first_order_build(gpu_ctx, c1):
+    """The first-order-amplitude operator at the full size is the general build fed
+    T1 = Lambda1 = 0 (same bits), and its G differs from the full amplitudes' G only through
+    T1 and Lambda1."""
+    print("[c1 first order]", flush=True)
+    prob = c1
+    om = synth.omega_grid(CFG1["omega"])[[0, 199]]
+    ps = synth.valence_p(prob.o, CFG1["np"])
+    full = gpu_ctx.gfcc_solve(om, ps, CFG1["eta"], tol=1e-12)
+    D = gfcc.dim(prob.o, prob.v)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    x = torch.randn((4, D), dtype=torch.complex128, device="cuda", generator=g)
+    try:
+        gpu_ctx.build_first_order_from_problem(prob)
+        y1 = gpu_ctx.sigma_apply(x)
+        pert = gpu_ctx.gfcc_solve(om, ps, CFG1["eta"], tol=1e-12)
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+        z = np.zeros_like(prob.t1)
+        gpu_ctx.build_hbar_operands(prob.o, prob.v, dev(prob.eps), dev(z), dev(prob.t2), dev(z),
+                                    dev(prob.t2), *[dev(prob.block(k)) for k in
+                                                    ("oooo", "ooov", "oovv", "ovvo", "ovvv")])
+        y2 = gpu_ctx.sigma_apply(x)
+        assert torch.equal(y1, y2)
+    finally:
+        gpu_ctx.build_from_problem(prob)
+    Gf, Gp = full.G.cpu().numpy(), pert.G.cpu().numpy()
+    rel = np.abs(Gp - Gf).max() / np.abs(Gf).max()
+    print(f"  G(first order) vs G(full amplitudes): {rel:.2e}", flush=True)
+    assert 0.0 < rel < 0.1
+
+
 def test_c2_mor_workflow(gpu_ctx, c1):
     print("[c2 mor]", flush=True)
     cfg = synth.CONFIGS[2]
