@@ -28,7 +28,9 @@
 // position is scalar. Two loaders:
 //  - column-block (nc a multiple of 128): a tile's columns share one j, so liveness, sign and
 //    the X2 row address of every row are scalar; a structurally zero row (m = j, or k past
-//    the end) is read from a row of zeros, and the sign costs one XOR per row;
+//    the end) is read from a row of zeros, and the sign costs one XOR per row. The slabs that
+//    lie wholly inside the tile's zero segment m = j (v rows) are skipped: the slab sequence
+//    jumps over them, in the A offsets and in the B row bookkeeping alike;
 //  - general: j varies across the tile; a slab of BK <= v rows crosses at most one m boundary,
 //    so two per-lane row bases (for m and m+1) and a scalar carry per row give every address,
 //    and liveness / sign are per-lane selects.
@@ -141,6 +143,20 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
   // column read by this lane: of X2 (ovvo) or of B and the zero row (dense)
   const int c = DENSE ? (ncol ? n : 0) : (ncol ? n - j * p.nc : 0);
 
+  // ---- column-block: slabs [slo, slo + nd) lie inside the zero segment m = j and are skipped;
+  // the slab processed i-th is i, or i + nd from slo on
+  int slo = 1 << 30, nd = 0, ms_to = 0, es_to = 0;
+  if (BLOCKJ) {
+    const int lo = (j * v + BK - 1) / BK, hi = ((j + 1) * v) / BK;
+    if (hi > lo) {
+      slo = lo;
+      nd = hi - lo;
+      ms_to = hi * BK / v;
+      es_to = hi * BK - ms_to * v;
+    }
+  }
+  auto slab_k = [&](int i) { return (i + (i >= slo ? nd : 0)) * BK; };
+
   // ---- A ownership. Column-block loader: per-lane base pointers advanced by the slab offset;
   // reads past k = K land in the next row or in the zero padding after W, against B rows
   // that are zero.
@@ -164,6 +180,11 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
   // state moves to the "in registers" copy once that slab's loads are issued, and is used when
   // the registers are stored to LDS.
   int ms = 0, es = 0, kp = 0;
+  int sp = 0;                                             // column-block: slabs prepared
+  if (BLOCKJ && slo == 0) {
+    ms = ms_to;
+    es = es_to;
+  }
   typedef const T __attribute__((address_space(1)))* gptr;
   uint64_t prow[RB];                                      // column-block: row addresses
   unsigned pneg = 0, sneg = 0;                            // column-block: row r negated
@@ -232,6 +253,12 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
       const int cy = es + BK >= v;
       es = es + BK - (cy ? v : 0);
       ms += cy;
+      if (BLOCKJ) {
+        ++sp;
+        const bool jump = sp == slo;
+        ms = jump ? ms_to : ms;
+        es = jump ? es_to : es;
+      }
     }
   };
   auto prep_row = [&](int r) {
@@ -437,12 +464,12 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
   prep_all();
   commit();
 #pragma unroll
-  for (int t = 0; t < ACH + 4; ++t) load_op(t, 0);
+  for (int t = 0; t < ACH + 4; ++t) load_op(t, slab_k(0));
 #pragma unroll
   for (int t = 0; t < ACH + 4; ++t) store_op(IC<0>{}, t);
   prep_all();
 #pragma unroll
-  for (int t = 0; t < ACH + 4; ++t) load_op(t, BK);
+  for (int t = 0; t < ACH + 4; ++t) load_op(t, slab_k(1));
   commit();
   prep_all();
   __syncthreads();
@@ -454,10 +481,10 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
   // Every step stores and loads ahead. Past the last slab the B rows are structurally zero
   // and the A reads stay in range (clamped, or in the padding after W), and the stores go to
   // the buffer that is no longer read.
-  const int ns = p.nslabs;
+  const int ns = p.nslabs - nd;
   for (int s = 0; s < ns; s += 2) {
-    step(IC<0>{}, (s + 2) * BK);
-    if (s + 1 < ns) step(IC<1>{}, (s + 3) * BK);
+    step(IC<0>{}, slab_k(s + 2));
+    if (s + 1 < ns) step(IC<1>{}, slab_k(s + 3));
   }
 
   const int col_l = lane & 15;
