@@ -688,6 +688,10 @@ def main():
             "sigma_ms_total": sig_ms, "A_range": [float(A.min()), float(A.max())],
         },
     }
+    # the GEMM autotuner's choices for this workload's skinny products
+    out["autotune"] = [{k: e[k] for k in ("transA", "M", "N", "K", "splits")}
+                       | {"us": round(e["us"], 1), "generic_us": round(e["generic_us"], 1)}
+                       for e in ctx.autotune_entries()]
     out["rows"] = rows_report(o, v, D, nb, dt / args.steps, t_build, sig_ms / args.steps,
                               sig_n // args.steps, its, args.restart)
     forms = [f for f in args.forms.split(",") if f and f != "none"]

@@ -1,6 +1,7 @@
 // Context lifetime, operator build entry point, inspection and event timers.
 #include <algorithm>
 #include <initializer_list>
+#include <iterator>
 
 #include "common.h"
 
@@ -168,6 +169,27 @@ gfcc_status build_hbar_first_order(gfcc_ctx* ctx, int o, int v, const double* ep
                  bt2.as<double>(), oooo, ooov, oovv, ovvo, ovvv, precision_mask | GFCC_KEEP_FP64);
   GFCC_HIP(hipStreamSynchronize(ctx->stream));  // the amplitudes are freed on return
   GFCC_API_END(ctx)
+}
+
+gfcc_status gfcc_autotune(gfcc_ctx* ctx, int enable) {
+  if (!ctx) return GFCC_EINVAL;
+  ctx->tune_on = enable != 0;
+  ctx->tune.clear();
+  return GFCC_OK;
+}
+
+gfcc_status gfcc_autotune_entry(const gfcc_ctx* ctx, int index, int64_t* desc, double* us) {
+  if (!ctx || !desc || index < 0 || (size_t)index >= ctx->tune.size()) return GFCC_EINVAL;
+  auto it = ctx->tune.begin();
+  std::advance(it, index);
+  const gfcc::TuneKey& k = it->first;
+  for (int i = 0; i < 5; ++i) desc[i] = k[i];
+  desc[5] = it->second.splits;
+  if (us) {
+    us[0] = it->second.best_us;
+    us[1] = it->second.generic_us;
+  }
+  return GFCC_OK;
 }
 
 gfcc_status gfcc_export(gfcc_ctx* ctx, int which, void* dst) {

@@ -4,10 +4,12 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
+#include <array>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <stdexcept>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -94,6 +96,7 @@ __host__ __device__ inline int64_t pair_of(int i, int j, int o) {
 // so that every sigma term is a dense contraction.
 template <typename T> struct OpPieces {
   DevBuf W1, W4c, Woo, Vp, Weff;
+  DevBuf W1V;              // [W1 ; 0 | Vp^T] (FP64): sigma_1h and tau in one product
   DevBuf W4, T2p;          // split form of W4c (mixed precision: T2p may be bf16)
 };
 
@@ -112,6 +115,14 @@ struct Operator {
   // blocks kept for export
   DevBuf Foo, Fov, Fvv, Woooo, Wooov, Wovvo, Wovoo;
 };
+
+// GEMM autotuner: one choice per product shape {element bytes, transA, M, N, K, lda, ldb}.
+struct TuneChoice {
+  int splits = 0;          // 0: generic split-K kernel (heuristic split count); > 0: pipelined
+  double best_us = 0.0;    // measured time of the choice
+  double generic_us = 0.0; // measured time of the generic kernel
+};
+using TuneKey = std::array<int64_t, 7>;
 
 struct TimerSlot {
   bool enabled = false;
@@ -132,6 +143,8 @@ struct gfcc_ctx {
   gfcc::DevBuf ws_a, ws_b, ws_c, ws_d, ws_e;
   gfcc::DevBuf zrow;        // zeros (read for structurally zero rows of the ovvo operand)
   gfcc::TimerSlot timers[2];
+  bool tune_on = true;
+  std::map<gfcc::TuneKey, gfcc::TuneChoice> tune;
   std::vector<hipEvent_t> event_pool;
 };
 
@@ -174,6 +187,13 @@ inline int64_t ovvo_pad_bytes(int64_t M) { return 512 * M; }
 template <typename T>
 bool gemm_pipe(gfcc_ctx* ctx, bool transA, int M, int N, int K, T alpha, const T* A, int64_t lda,
                const T* B, int64_t ldb, T beta, T* C, int64_t ldc);
+
+// Split-K partial products on the same kernel: part[y][M][N] = op(A) B over the k range
+// [y kchunk, (y+1) kchunk) for y < splits (kchunk a multiple of 128 bytes of k); the caller
+// reduces the slices.
+template <typename T>
+void gemm_pipe_split(gfcc_ctx* ctx, bool transA, int M, int N, int K, const T* A, int64_t lda,
+                     const T* B, int64_t ldb, T* part, int splits, int kchunk);
 
 // A device buffer of at least `bytes` zero bytes, owned by the context (grown on demand).
 const void* zero_row(gfcc_ctx* ctx, size_t bytes);

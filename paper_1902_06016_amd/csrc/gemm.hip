@@ -8,6 +8,9 @@
 // The B operand has three modes: row-major [K][N], transposed ([N][K]), or the gather used by
 // the ovvo term of the IP sigma product, which expands the packed antisymmetric 2h1p block
 // on the fly (r_mj^e = +-X2[pair(m,j)][e], zero for m == j).
+#include <algorithm>
+#include <cstdlib>
+
 #include "common.h"
 
 namespace gfcc {
@@ -309,6 +312,92 @@ void gemm_impl(gfcc_ctx* ctx, bool transA, int bmode, int M, int N, int K, T alp
   GFCC_LAUNCH_CHECK();
 }
 
+// ---------------------------------------------------------------------------- autotuner
+// Products with a row-major B whose 128 x 128 tiles cannot fill the chip but whose K is long
+// (the skinny products of the sigma: [W1 ; Vp^T] . X, Vp^T . X2) run split-K. The variants
+// are the generic kernel with its heuristic split count and the pipelined kernel with the
+// split counts that fill one, two and four rounds of the 512 resident workgroups (two per CU),
+// each split keeping at least 8 slabs of k. The first time a
+// shape is seen on a context every variant is timed (HIP events, once to warm up and twice
+// timed, into a scratch output; this synchronises the stream), and the fastest is kept for
+// that context.
+inline bool tunable(int M, int N, int K, size_t elem) {
+  const int64_t tiles = (int64_t)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  return tiles < 256 && (int64_t)K * (int64_t)elem >= 8 * 128 * 4;
+}
+
+template <typename T>
+void run_variant(gfcc_ctx* ctx, int splits, bool transA, int M, int N, int K, T alpha,
+                 const T* A, int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc) {
+  if (splits == 0) {
+    gemm_impl<T>(ctx, transA, B_ROW, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 1, 0, 0, 0,
+                 nullptr, 0, 0, 0);
+    return;
+  }
+  constexpr int PBK = 128 / (int)sizeof(T);
+  int64_t kchunk = ((int64_t)K + splits - 1) / splits;
+  kchunk = (kchunk + PBK - 1) / PBK * PBK;
+  const int s = (int)(((int64_t)K + kchunk - 1) / kchunk);
+  const int64_t slab = (int64_t)M * N;
+  ws_ensure(ctx, ctx->ws_gemm, (size_t)slab * s * sizeof(T));
+  T* part = ctx->ws_gemm.as<T>();
+  gemm_pipe_split<T>(ctx, transA, M, N, K, A, lda, B, ldb, part, s, (int)kchunk);
+  hipLaunchKernelGGL(splitk_reduce<T>, dim3(blocks_for(slab, 256)), dim3(256), 0, ctx->stream,
+                     part, s, M, N, slab, C, ldc, alpha, beta);
+  GFCC_LAUNCH_CHECK();
+}
+
+template <typename T>
+const TuneChoice& tune_choice(gfcc_ctx* ctx, bool transA, int M, int N, int K, const T* A,
+                              int64_t lda, const T* B, int64_t ldb) {
+  const TuneKey key{(int64_t)sizeof(T), transA ? 1 : 0, M, N, K, lda, ldb};
+  auto it = ctx->tune.find(key);
+  if (it != ctx->tune.end()) return it->second;
+  TuneChoice ch;
+  if (!ctx->tune_on) return ctx->tune[key] = ch;
+  constexpr int PBK = 128 / (int)sizeof(T);
+  const int64_t tiles = (int64_t)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  const int64_t smax = std::max<int64_t>(1, (int64_t)K / (8 * PBK));
+  // split counts that fill r whole rounds of the 512 workgroups resident at once (two per CU)
+  std::vector<int> cand{0};
+  for (int64_t r : {1, 2, 4}) {
+    const int64_t sp = std::min<int64_t>(smax, std::max<int64_t>(1, r * 512 / tiles));
+    if (std::find(cand.begin(), cand.end(), (int)sp) == cand.end()) cand.push_back((int)sp);
+  }
+  const bool log = std::getenv("GFCC_TUNE_LOG") != nullptr;  // diagnostic: every timing
+  DevBuf scratch;
+  scratch.alloc(sizeof(T) * (size_t)M * N);
+  hipStream_t st = ctx->stream;
+  hipEvent_t e0, e1;
+  GFCC_HIP(hipEventCreate(&e0));
+  GFCC_HIP(hipEventCreate(&e1));
+  double best = 1e300;
+  for (int sp : cand) {
+    run_variant<T>(ctx, sp, transA, M, N, K, T(1), A, lda, B, ldb, T(0), scratch.as<T>(), N);
+    GFCC_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < 2; ++r)
+      run_variant<T>(ctx, sp, transA, M, N, K, T(1), A, lda, B, ldb, T(0), scratch.as<T>(), N);
+    GFCC_HIP(hipEventRecord(e1, st));
+    GFCC_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    GFCC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    const double us = ms * 1e3 / 2;
+    if (log) {
+      std::fprintf(stderr, "[gfcc autotune] %s M=%d N=%d K=%d transA=%d splits=%d: %.1f us\n",
+                   sizeof(T) == 8 ? "f64" : "f32", M, N, K, transA ? 1 : 0, sp, us);
+    }
+    if (sp == 0) ch.generic_us = us;
+    if (us < best) {
+      best = us;
+      ch.splits = sp;
+      ch.best_us = us;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ctx->tune[key] = ch;
+}
+
 }  // namespace
 
 template <typename T>
@@ -319,6 +408,12 @@ void gemm(gfcc_ctx* ctx, bool transA, bool transB, int M, int N, int K, T alpha,
   if (!transB && batch == 1 &&
       gemm_pipe<T>(ctx, transA, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc))
     return;
+  // skinny long-K products: split-K variant chosen by the autotuner
+  if (!transB && batch == 1 && M > 0 && N > 0 && tunable(M, N, K, sizeof(T))) {
+    const TuneChoice& ch = tune_choice<T>(ctx, transA, M, N, K, A, lda, B, ldb);
+    run_variant<T>(ctx, ch.splits, transA, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    return;
+  }
   gemm_impl<T>(ctx, transA, transB ? B_TRANS : B_ROW, M, N, K, alpha, A, lda, B, ldb, beta, C,
                ldc, batch, sA, sB, sC, nullptr, 0, 1, 1);
 }

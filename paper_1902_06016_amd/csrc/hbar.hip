@@ -400,6 +400,19 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
     double* Vp = B(f.Vp, PV * V);
     hipLaunchKernelGGL(assemble_Vp_kernel, dim3(grid_for(PV * V)), dim3(256), 0, st, oovv, o, v, PV, Vp);
     GFCC_LAUNCH_CHECK();
+    // [W1 ; 0 | Vp^T]: the forward sigma forms sigma_1h and the three-body intermediate tau
+    // in one skinny product over the whole vector (X read once per 128-row tile)
+    {
+      double* W1V = B(f.W1V, (O + V) * D);
+      GFCC_HIP(hipMemcpyAsync(W1V, W1, sizeof(double) * O * D, hipMemcpyDeviceToDevice, st));
+      fill(ctx, W1V + O * D, V * D, 0.0);
+      DevBuf bt;
+      double* vt = B(bt, V * PV);
+      transpose2d(ctx, Vp, PV, V, vt);  // [v][PV]
+      GFCC_HIP(hipMemcpy2DAsync(W1V + O * D + O, sizeof(double) * D, vt, sizeof(double) * PV,
+                                sizeof(double) * PV, V, hipMemcpyDeviceToDevice, st));
+      GFCC_HIP(hipStreamSynchronize(st));
+    }
     // Weff is followed by zero padding read by the ovvo kernels past the last k slab
     const int64_t wpad = ovvo_pad_bytes(OV) / (int64_t)sizeof(double);
     double* Weff = B(f.Weff, OV * OV + wpad);

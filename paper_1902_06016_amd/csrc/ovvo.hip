@@ -18,6 +18,10 @@
 //
 // The same kernel also runs plain products C = alpha op(A) B + beta C with a row-major B
 // (gemm_pipe): the B rows are then addressed like the column-block loader's, without sign.
+// Split-K (gemm_pipe_split): the (split y, tile) pairs are numbered tile-fastest and dealt to
+// the XCDs like tiles, so that the workgroups on one XCD share the k range of their split;
+// split y takes [y kchunk, (y+1) kchunk) and writes its partial product to slice y of a
+// workspace.
 //
 // LDS holds both tiles k-contiguous ([row][k]) with a 136-byte pitch, which keeps the
 // per-k-step fragment reads (lanes 0-15 on 16 rows) and the 8-byte stores free of bank
@@ -76,6 +80,9 @@ template <typename T> struct OvvoArgs {
   int64_t lda, ldb, ldc;
   T alpha, beta;     // C = alpha A B + beta C (beta == 0 never reads C)
   int mtiles, ntiles, nslabs;
+  int kchunk;        // dense split-K: k per split (a multiple of the slab), 0 without split
+  int nsplit;        // dense split-K: number of splits (1 without split)
+  int64_t sC;        // dense split-K: stride between the partial products
 };
 
 __device__ __forceinline__ int pair_index(int i, int j, int o) {  // i < j
@@ -119,9 +126,12 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
   // B slabs.
   constexpr int GM = 8;
   const int ntot = p.mtiles * p.ntiles;
-  const int T8 = (ntot + 7) / 8;
-  const int L = (int)(blockIdx.x & 7) * T8 + (int)(blockIdx.x >> 3);
-  if (L >= ntot) return;
+  const int nwork = DENSE ? ntot * p.nsplit : ntot;
+  const int T8 = (nwork + 7) / 8;
+  const int Lw = (int)(blockIdx.x & 7) * T8 + (int)(blockIdx.x >> 3);
+  if (Lw >= nwork) return;
+  const int ysplit = DENSE ? Lw / ntot : 0;
+  const int L = Lw - ysplit * ntot;
   const int grp = L / (GM * p.ntiles);
   const int rows = min(GM, p.mtiles - grp * GM);
   const int idx = L - grp * GM * p.ntiles;
@@ -131,6 +141,9 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
   const T* __restrict__ X2 = p.X2;
   const int K = p.K, M = p.M, v = p.v, o = p.o, ldx = p.ldx;
   const int64_t lda = p.lda;
+  // dense split-K: this workgroup's k range starts at kbeg and spans nsl slabs
+  const int kbeg = ysplit * p.kchunk;
+  const int nsl = (DENSE && p.kchunk > 0) ? (min(K - kbeg, p.kchunk) + BK - 1) / BK : p.nslabs;
 
   // ---- B ownership: column bn, rows kh * RB + r of every slab (kh is wave-uniform)
   const int bn = tid % BN;
@@ -155,7 +168,7 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
       es_to = hi * BK - ms_to * v;
     }
   }
-  auto slab_k = [&](int i) { return (i + (i >= slo ? nd : 0)) * BK; };
+  auto slab_k = [&](int i) { return kbeg + (i + (i >= slo ? nd : 0)) * BK; };
 
   // ---- A ownership. Column-block loader: per-lane base pointers advanced by the slab offset;
   // reads past k = K land in the next row or in the zero padding after W, against B rows
@@ -179,7 +192,7 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
   // k0 = ms * v + es for the ovvo operand, kp for a dense B, scalar); its sign / liveness
   // state moves to the "in registers" copy once that slab's loads are issued, and is used when
   // the registers are stored to LDS.
-  int ms = 0, es = 0, kp = 0;
+  int ms = 0, es = 0, kp = kbeg;
   int sp = 0;                                             // column-block: slabs prepared
   if (BLOCKJ && slo == 0) {
     ms = ms_to;
@@ -481,7 +494,7 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
   // Every step stores and loads ahead. Past the last slab the B rows are structurally zero
   // and the A reads stay in range (clamped, or in the padding after W), and the stores go to
   // the buffer that is no longer read.
-  const int ns = p.nslabs - nd;
+  const int ns = nsl - nd;
   for (int s = 0; s < ns; s += 2) {
     step(IC<0>{}, slab_k(s + 2));
     if (s + 1 < ns) step(IC<1>{}, slab_k(s + 3));
@@ -498,7 +511,7 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
       for (int e = 0; e < 4; ++e) {
         const int mrow = m0 + wm * 64 + i * 16 + M4::row(lane, e);
         if (mrow >= M) continue;
-        T* cp = p.Z + (int64_t)mrow * p.ldc + nn;
+        T* cp = p.Z + (int64_t)ysplit * p.sC + (int64_t)mrow * p.ldc + nn;
         if (DENSE) *cp = p.alpha * acc[i][q][e] + (p.beta != T(0) ? p.beta * *cp : T(0));
         else *cp = acc[i][q][e];
       }
@@ -570,6 +583,7 @@ bool gemm_pipe(gfcc_ctx* ctx, bool transA, int M, int N, int K, T alpha, const T
   p.X2 = B; p.ldb = ldb;
   p.Z = C; p.ldc = ldc;
   p.alpha = alpha; p.beta = beta;
+  p.nsplit = 1;
   p.nc = 1; p.o = 1; p.v = 1; p.ldx = 0;
   p.zrow = static_cast<const T*>(zero_row(ctx, (size_t)N * sizeof(T)));
   // 16-byte A chunks need aligned rows and a chunked dimension that is a multiple of the chunk
@@ -589,6 +603,50 @@ bool gemm_pipe(gfcc_ctx* ctx, bool transA, int M, int N, int K, T alpha, const T
   return true;
 }
 
+// Split-K partial products on the pipelined kernel: part[y][M][N] = op(A) B over the k range
+// [y kchunk, (y+1) kchunk), y < splits (kchunk a multiple of the slab). The caller reduces.
+template <typename T>
+void gemm_pipe_split(gfcc_ctx* ctx, bool transA, int M, int N, int K, const T* A, int64_t lda,
+                     const T* B, int64_t ldb, T* part, int splits, int kchunk) {
+  constexpr int BK = 128 / (int)sizeof(T);
+  constexpr int VPC = 16 / (int)sizeof(T);
+  GFCC_REQUIRE(M >= 1 && N >= 1 && K >= 1 && splits >= 1 && kchunk % BK == 0 &&
+                   (int64_t)splits * kchunk >= K && (int64_t)(splits - 1) * kchunk < K,
+               GFCC_EINVAL, "gemm_pipe_split: bad split");
+  OvvoArgs<T> p{};
+  p.M = M; p.N = N; p.K = K;
+  p.mtiles = (M + BM - 1) / BM;
+  p.ntiles = (N + BN - 1) / BN;
+  p.nslabs = (K + BK - 1) / BK;
+  p.kchunk = kchunk;
+  p.nsplit = splits;
+  p.sC = (int64_t)M * N;
+  const int64_t tiles = (int64_t)p.mtiles * p.ntiles;
+  GFCC_REQUIRE(tiles * splits < (1LL << 31) - 8, GFCC_EINVAL, "gemm_pipe_split: too many tiles");
+  p.W = A; p.lda = lda;
+  p.X2 = B; p.ldb = ldb;
+  p.Z = part; p.ldc = N;
+  p.alpha = T(1); p.beta = T(0);
+  p.nc = 1; p.o = 1; p.v = 1; p.ldx = 0;
+  p.zrow = static_cast<const T*>(zero_row(ctx, (size_t)N * sizeof(T)));
+  const bool vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (lda % VPC == 0) &&
+                   ((transA ? M : K) % VPC == 0);
+  dim3 grid((unsigned)((tiles * splits + 7) / 8 * 8));
+  hipStream_t st = ctx->stream;
+  if (transA) {
+    if (vec) hipLaunchKernelGGL((ovvo_kernel<T, true, B_DENSE, true>), grid, dim3(NT), 0, st, p);
+    else hipLaunchKernelGGL((ovvo_kernel<T, true, B_DENSE, false>), grid, dim3(NT), 0, st, p);
+  } else {
+    if (vec) hipLaunchKernelGGL((ovvo_kernel<T, false, B_DENSE, true>), grid, dim3(NT), 0, st, p);
+    else hipLaunchKernelGGL((ovvo_kernel<T, false, B_DENSE, false>), grid, dim3(NT), 0, st, p);
+  }
+  GFCC_LAUNCH_CHECK();
+}
+
+template void gemm_pipe_split<double>(gfcc_ctx*, bool, int, int, int, const double*, int64_t,
+                                      const double*, int64_t, double*, int, int);
+template void gemm_pipe_split<float>(gfcc_ctx*, bool, int, int, int, const float*, int64_t,
+                                     const float*, int64_t, float*, int, int);
 template bool ovvo_fast<double>(gfcc_ctx*, bool, int, int, int, const double*, const double*,
                                 int64_t, double*, const double*);
 template bool ovvo_fast<float>(gfcc_ctx*, bool, int, int, int, const float*, const float*,

@@ -5,6 +5,7 @@
 // the right-hand sides:
 //   sigma_1h   = W1 . X
 //   tau        = Vp^T . X_2h1p                 (three-body intermediate, v x nc)
+// (the FP64 forward product forms both at once from the stacked [W1 ; 0 | Vp^T])
 //   sigma_2h1p = W4c . [X_1h ; tau] + (Woo (x) I_v) . X_2h1p + antisym(Weff . r)
 // where r_mj^e is the antisymmetric expansion of the packed 2h1p block, generated inside
 // the ovvo product (gemm_ovvo), and antisym(Z)_(i<j),a = Z[(i,a)][j] - Z[(j,a)][i].
@@ -96,11 +97,13 @@ void sigma_block_f64(gfcc_ctx* ctx, int nc, const double* X, double* Y, bool tra
   hipEvent_t e_all = nullptr, e_ovvo = nullptr;
   timer_begin(ctx, 1, &e_all);
   if (!transpose) {
-    gemm<double>(ctx, false, false, o, nc, (int)D, 1.0, f.W1.as<double>(), D, X, nc, 0.0, Y1, nc);
+    // [sigma_1h ; tau] = [W1 ; 0 | Vp^T] . X, then S = [X_1h ; tau]
+    gemm<double>(ctx, false, false, o + v, nc, (int)D, 1.0, f.W1V.as<double>(), D, X, nc, 0.0,
+                 S, nc);
+    GFCC_HIP(hipMemcpyAsync(Y1, S, sizeof(double) * (size_t)o * nc, hipMemcpyDeviceToDevice,
+                            ctx->stream));
     GFCC_HIP(hipMemcpyAsync(S, X1, sizeof(double) * (size_t)o * nc, hipMemcpyDeviceToDevice,
                             ctx->stream));
-    gemm<double>(ctx, true, false, v, nc, (int)PV, 1.0, f.Vp.as<double>(), v, X2, nc, 0.0,
-                 S + (int64_t)o * nc, nc);
     gemm<double>(ctx, false, false, (int)PV, nc, o + v, 1.0, f.W4c.as<double>(), o + v, S, nc,
                  0.0, Y2, nc);
     gemm<double>(ctx, false, false, (int)P, v * nc, (int)P, 1.0, f.Woo.as<double>(), P, X2,

@@ -52,6 +52,8 @@ def _load():
                                 vp, vp, vp]),
         "gfcc_solve_diis": (i32, [vp, i32, vp, i32, vp, dbl, dbl, i32, i32, i32, i32, vp, vp,
                                   vp, vp, vp, vp]),
+        "gfcc_autotune": (i32, [vp, i32]),
+        "gfcc_autotune_entry": (i32, [vp, i32, vp, vp]),
         "gfcc_grad_eps": (i32, [vp, i32, vp, i32, vp, vp, vp]),
         "mor_build": (i32, [vp, i32, vp, i32, vp, dbl, dbl, dbl, P(vp)]),
         "mor_build_diag": (i32, [vp, i32, vp, i32, vp, dbl, dbl, dbl, vp]),
@@ -73,8 +75,8 @@ def _load():
 
 lib = _load()
 SYMBOLS = ("gfcc_dim", "gfcc_create", "gfcc_destroy", "gfcc_last_error", "build_hbar_operands",
-           "build_hbar_first_order", "sigma_apply", "gfcc_solve", "gfcc_solve_x0", "gfcc_solve_diis", "gfcc_grad_eps",
-           "mor_build",
+           "build_hbar_first_order", "sigma_apply", "gfcc_autotune", "gfcc_autotune_entry",
+           "gfcc_solve", "gfcc_solve_x0", "gfcc_solve_diis", "gfcc_grad_eps", "mor_build",
            "mor_build_diag", "mor_refine", "mor_eval", "mor_lift", "mor_info", "mor_destroy",
            "spectral_function", "gfcc_export", "gfcc_timer")
 
@@ -272,6 +274,24 @@ class Context:
         out = np.zeros(self.o + self.v)
         self._check(lib.gfcc_grad_eps(self.h, len(w), w_p, X.shape[1], _ptr(X.contiguous()),
                                       _ptr(Y.contiguous()), out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    # ------------------------------------------------------------- autotuner
+    def autotune(self, enable: bool = True):
+        self._check(lib.gfcc_autotune(self.h, int(enable)))
+
+    def autotune_entries(self):
+        """The tuner's choices: dicts with the product shape, the split count (0 = generic
+        kernel) and the measured times."""
+        out = []
+        desc = (ctypes.c_int64 * 6)()
+        us = (ctypes.c_double * 2)()
+        i = 0
+        while lib.gfcc_autotune_entry(self.h, i, desc, us) == GFCC_OK:
+            out.append({"elem_bytes": desc[0], "transA": bool(desc[1]), "M": desc[2],
+                        "N": desc[3], "K": desc[4], "splits": desc[5],
+                        "us": us[0], "generic_us": us[1]})
+            i += 1
         return out
 
     # ---------------------------------------------------------------- timers
