@@ -104,6 +104,7 @@ struct Operator {
   bool built = false;
   int o = 0, v = 0;
   int64_t D = 0, P = 0, PV = 0, OV = 0;
+  int64_t ldwoo = 0;            // row stride of Woo (P padded with zeros to a multiple of 4)
   int keep = 0;
   OpPieces<double> f64;
   OpPieces<float> f32;
@@ -184,9 +185,11 @@ inline int64_t ovvo_pad_bytes(int64_t M) { return 512 * M; }
 
 // C[M][N] = alpha op(A) B + beta C, B row-major [K][ldb], on the pipelined kernel of ovvo.hip;
 // false when the product has too few 128 x 128 tiles to fill the GPU.
+// a_padded: every row of A (its k dimension, or m when transposed) continues with finite
+// entries up to a multiple of 16 bytes inside lda, so that 16-byte loads may cover the tail.
 template <typename T>
 bool gemm_pipe(gfcc_ctx* ctx, bool transA, int M, int N, int K, T alpha, const T* A, int64_t lda,
-               const T* B, int64_t ldb, T beta, T* C, int64_t ldc);
+               const T* B, int64_t ldb, T beta, T* C, int64_t ldc, bool a_padded = false);
 
 // Split-K partial products on the same kernel: part[y][M][N] = op(A) B over the k range
 // [y kchunk, (y+1) kchunk) for y < splits (kchunk a multiple of 128 bytes of k); the caller

@@ -105,9 +105,9 @@ __global__ void assemble_W4c_kernel(const double* __restrict__ Wovoo, const doub
   }
 }
 
-// Woo[(ij)][(kl)] = Woooo[k][l][i][j]
+// Woo[(ij)][(kl)] = Woooo[k][l][i][j], rows of stride ldw (the padding is left untouched)
 __global__ void assemble_Woo_kernel(const double* __restrict__ Woooo, int o, int64_t P,
-                                    double* __restrict__ Woo) {
+                                    int64_t ldw, double* __restrict__ Woo) {
   int64_t n = P * P;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -115,7 +115,7 @@ __global__ void assemble_Woo_kernel(const double* __restrict__ Woooo, int o, int
     int i, j, k, l;
     unpair(r, o, &i, &j);
     unpair(c, o, &k, &l);
-    Woo[idx] = Woooo[(((int64_t)k * o + l) * o + i) * o + j];
+    Woo[r * ldw + c] = Woooo[(((int64_t)k * o + l) * o + i) * o + j];
   }
 }
 
@@ -155,9 +155,9 @@ __global__ void assemble_Weff_kernel(const double* __restrict__ Wovvo, const dou
 
 // diagonal of Hbar_N in the packed basis
 __global__ void diag_kernel(const double* __restrict__ W1, const double* __restrict__ Woo,
-                            const double* __restrict__ Weff, const double* __restrict__ t2,
-                            const double* __restrict__ oovv, int o, int v, int64_t D, int64_t P,
-                            double* __restrict__ diag) {
+                            int64_t ldw, const double* __restrict__ Weff,
+                            const double* __restrict__ t2, const double* __restrict__ oovv, int o,
+                            int v, int64_t D, double* __restrict__ diag) {
   const int64_t OV = (int64_t)o * v;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < D;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -170,7 +170,7 @@ __global__ void diag_kernel(const double* __restrict__ W1, const double* __restr
     int a = (int)(q - pr * v);
     int i, j;
     unpair(pr, o, &i, &j);
-    double val = Woo[pr * P + pr];
+    double val = Woo[pr * ldw + pr];
     int64_t ri = (int64_t)i * v + a, rj = (int64_t)j * v + a;
     val += Weff[ri * OV + ri] + Weff[rj * OV + rj];
     const double* tp = t2 + (((int64_t)i * o + j) * v + a) * v;
@@ -394,8 +394,13 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
     hipLaunchKernelGGL(assemble_W4c_kernel, dim3(grid_for(PV * (O + V))), dim3(256), 0, st,
                        Wovoo, t2, o, v, PV, W4c);
     GFCC_LAUNCH_CHECK();
-    double* Woo = B(f.Woo, P * P);
-    hipLaunchKernelGGL(assemble_Woo_kernel, dim3(grid_for(P * P)), dim3(256), 0, st, Woooo, o, P, Woo);
+    // rows padded with zeros to a multiple of 4 entries: 16-byte aligned rows for the
+    // vector loads of the pipelined kernel in FP64 and FP32
+    const int64_t ldw = op.ldwoo = (P + 3) / 4 * 4;
+    double* Woo = B(f.Woo, P * ldw);
+    fill(ctx, Woo, P * ldw, 0.0);
+    hipLaunchKernelGGL(assemble_Woo_kernel, dim3(grid_for(P * P)), dim3(256), 0, st, Woooo, o, P,
+                       ldw, Woo);
     GFCC_LAUNCH_CHECK();
     double* Vp = B(f.Vp, PV * V);
     hipLaunchKernelGGL(assemble_Vp_kernel, dim3(grid_for(PV * V)), dim3(256), 0, st, oovv, o, v, PV, Vp);
@@ -421,8 +426,8 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
                        Foo, Fvv, o, v, Weff);
     GFCC_LAUNCH_CHECK();
     double* dg = B(op.diag, D);
-    hipLaunchKernelGGL(diag_kernel, dim3(grid_for(D)), dim3(256), 0, st, W1, Woo, Weff, t2, oovv,
-                       o, v, D, P, dg);
+    hipLaunchKernelGGL(diag_kernel, dim3(grid_for(D)), dim3(256), 0, st, W1, Woo, ldw, Weff, t2,
+                       oovv, o, v, D, dg);
     GFCC_LAUNCH_CHECK();
 
     // c_q rows
@@ -444,7 +449,7 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
       auto F = [](DevBuf& b, int64_t n) { b.alloc((size_t)n * sizeof(float)); return b.as<float>(); };
       cast_f64_f32(ctx, W1, F(g.W1, O * D), O * D);
       cast_f64_f32(ctx, W4c, F(g.W4c, PV * (O + V)), PV * (O + V));
-      cast_f64_f32(ctx, Woo, F(g.Woo, P * P), P * P);
+      cast_f64_f32(ctx, Woo, F(g.Woo, P * ldw), P * ldw);
       cast_f64_f32(ctx, Vp, F(g.Vp, PV * V), PV * V);
       const int64_t wpadf = ovvo_pad_bytes(OV) / (int64_t)sizeof(float);
       float* Wf = F(g.Weff, OV * OV + wpadf);

@@ -68,6 +68,15 @@ inline unsigned grid_for(int64_t n) {
   return (unsigned)(b < 1 ? 1 : b);
 }
 
+// Y2 += (Woo (x) I_v) . X2 (or Woo^T): Woo's rows are padded with zeros to ldw, which lets the
+// pipelined kernel use 16-byte loads although P is odd
+template <typename T>
+void woo_product(gfcc_ctx* ctx, bool transW, int64_t P, int64_t N, const T* Woo, int64_t ldw,
+                 const T* X2, T* Y2) {
+  if (!gemm_pipe<T>(ctx, transW, (int)P, (int)N, (int)P, T(1), Woo, ldw, X2, N, T(1), Y2, N, true))
+    gemm<T>(ctx, transW, false, (int)P, (int)N, (int)P, T(1), Woo, ldw, X2, N, T(1), Y2, N);
+}
+
 }  // namespace
 
 void ctranspose(gfcc_ctx* ctx, const void* src, int64_t rows, int64_t cols, int64_t lds,
@@ -106,8 +115,7 @@ void sigma_block_f64(gfcc_ctx* ctx, int nc, const double* X, double* Y, bool tra
                             ctx->stream));
     gemm<double>(ctx, false, false, (int)PV, nc, o + v, 1.0, f.W4c.as<double>(), o + v, S, nc,
                  0.0, Y2, nc);
-    gemm<double>(ctx, false, false, (int)P, v * nc, (int)P, 1.0, f.Woo.as<double>(), P, X2,
-                 (int64_t)v * nc, 1.0, Y2, (int64_t)v * nc);
+    woo_product<double>(ctx, false, P, (int64_t)v * nc, f.Woo.as<double>(), op.ldwoo, X2, Y2);
   } else {
     gemm<double>(ctx, true, false, (int)D, nc, o, 1.0, f.W1.as<double>(), D, X1, nc, 0.0, Y, nc);
     gemm<double>(ctx, true, false, o + v, nc, (int)PV, 1.0, f.W4c.as<double>(), o + v, X2, nc,
@@ -117,8 +125,7 @@ void sigma_block_f64(gfcc_ctx* ctx, int nc, const double* X, double* Y, bool tra
     GFCC_LAUNCH_CHECK();
     gemm<double>(ctx, false, false, (int)PV, nc, v, 1.0, f.Vp.as<double>(), v,
                  S + (int64_t)o * nc, nc, 1.0, Y2, nc);
-    gemm<double>(ctx, true, false, (int)P, v * nc, (int)P, 1.0, f.Woo.as<double>(), P, X2,
-                 (int64_t)v * nc, 1.0, Y2, (int64_t)v * nc);
+    woo_product<double>(ctx, true, P, (int64_t)v * nc, f.Woo.as<double>(), op.ldwoo, X2, Y2);
   }
   timer_begin(ctx, 0, &e_ovvo);
   gemm_ovvo<double>(ctx, transpose, o, v, nc, f.Weff.as<double>(), X2, nc,
@@ -172,8 +179,7 @@ void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, bool bf16_
     gemm_bf16(ctx, false, (int)PV, nc, v, 1.0f, op.T2p_bf16.as<__hip_bfloat16>(), v, taub, nc,
               1.0f, Y2, nc);
   }
-  gemm<float>(ctx, false, false, (int)P, v * nc, (int)P, 1.0f, f.Woo.as<float>(), P, X2,
-              (int64_t)v * nc, 1.0f, Y2, (int64_t)v * nc);
+  woo_product<float>(ctx, false, P, (int64_t)v * nc, f.Woo.as<float>(), op.ldwoo, X2, Y2);
   timer_begin(ctx, 0, &e_ovvo);
   gemm_ovvo<float>(ctx, false, o, v, nc, f.Weff.as<float>(), X2, nc, op.pairlut.as<int>(), Z);
   timer_end(ctx, 0, e_ovvo);
