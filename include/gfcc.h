@@ -124,16 +124,18 @@ gfcc_status sigma_apply(gfcc_ctx* ctx, int nrhs, const void* x, void* y, int tra
 /*
  * gfcc_autotune -- switch the GEMM autotuner of ctx on (1, the default) or off (0) and forget
  * its choices. Products whose 128 x 128 tiles cannot fill the GPU but whose K is long (the
- * skinny products of the sigma) run split-K; with the tuner on, the first call on each new
- * shape times the generic kernel and the pipelined kernel at three split counts, synchronising
- * the context stream, and keeps the fastest for the context. Off: the generic kernel with its
- * heuristic split count. Results agree to rounding either way.
+ * skinny products of the sigma) run split-K; with the tuner on, the first call in each product
+ * class (tile counts, binary magnitude of K, 16-byte loads possible) times the generic kernel
+ * and the pipelined kernel at three split counts, synchronising the context stream, and keeps
+ * the fastest for the context. Off: the generic kernel with its heuristic split count. Results
+ * agree to rounding either way.
  */
 gfcc_status gfcc_autotune(gfcc_ctx* ctx, int enable);
 
 /*
- * gfcc_autotune_entry -- the tuner's choice number `index` (0-based, ordered by shape):
- * desc[6] (host) receives {element bytes, transA, M, N, K, splits} with splits = 0 for the
+ * gfcc_autotune_entry -- the tuner's choice number `index` (0-based, ordered by class):
+ * desc[6] (host) receives {element bytes, transA, M, N, K, splits} (the shape it was measured
+ * on) with splits = 0 for the
  * generic kernel; us[2] (host, may be NULL) the measured time of the choice and of the
  * generic kernel in microseconds. EINVAL past the last entry.
  */

@@ -183,7 +183,11 @@ gfcc_status gfcc_autotune_entry(const gfcc_ctx* ctx, int index, int64_t* desc, d
   auto it = ctx->tune.begin();
   std::advance(it, index);
   const gfcc::TuneKey& k = it->first;
-  for (int i = 0; i < 5; ++i) desc[i] = k[i];
+  desc[0] = k[0];
+  desc[1] = k[1];
+  desc[2] = it->second.M;
+  desc[3] = it->second.N;
+  desc[4] = it->second.K;
   desc[5] = it->second.splits;
   if (us) {
     us[0] = it->second.best_us;

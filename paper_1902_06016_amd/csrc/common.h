@@ -117,13 +117,16 @@ struct Operator {
   DevBuf Foo, Fov, Fvv, Woooo, Wooov, Wovvo, Wovoo;
 };
 
-// GEMM autotuner: one choice per product shape {element bytes, transA, M, N, K, lda, ldb}.
+// GEMM autotuner: one choice per product class {element bytes, transA, M tiles, N tiles,
+// floor(log2 K), 16-byte A loads possible}; products of one class behave alike, so shapes that
+// change a little (the reduced model's, round after round) are tuned once.
 struct TuneChoice {
   int splits = 0;          // 0: generic split-K kernel (heuristic split count); > 0: pipelined
   double best_us = 0.0;    // measured time of the choice
   double generic_us = 0.0; // measured time of the generic kernel
+  int M = 0, N = 0, K = 0; // the shape it was measured on
 };
-using TuneKey = std::array<int64_t, 7>;
+using TuneKey = std::array<int64_t, 6>;
 
 struct TimerSlot {
   bool enabled = false;

@@ -320,7 +320,7 @@ void gemm_impl(gfcc_ctx* ctx, bool transA, int bmode, int M, int N, int K, T alp
 // each split keeping at least 8 slabs of k. The first time a
 // shape is seen on a context every variant is timed (HIP events, once to warm up and twice
 // timed, into a scratch output; this synchronises the stream), and the fastest is kept for
-// that context.
+// that context and product class (tile counts, the binary magnitude of K, vector loads).
 inline bool tunable(int M, int N, int K, size_t elem) {
   const int64_t tiles = (int64_t)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   return tiles < 256 && (int64_t)K * (int64_t)elem >= 8 * 128 * 4;
@@ -350,13 +350,22 @@ void run_variant(gfcc_ctx* ctx, int splits, bool transA, int M, int N, int K, T 
 template <typename T>
 const TuneChoice& tune_choice(gfcc_ctx* ctx, bool transA, int M, int N, int K, const T* A,
                               int64_t lda, const T* B, int64_t ldb) {
-  const TuneKey key{(int64_t)sizeof(T), transA ? 1 : 0, M, N, K, lda, ldb};
+  constexpr int PBK = 128 / (int)sizeof(T);
+  constexpr int VPC = 16 / (int)sizeof(T);
+  const int64_t mt = (M + BM - 1) / BM, nt = (N + BN - 1) / BN;
+  const int64_t tiles = mt * nt;
+  int64_t kb = 0;
+  while ((int64_t(1) << (kb + 1)) <= K) ++kb;
+  const int64_t vec = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (lda % VPC == 0) &&
+                      ((transA ? M : K) % VPC == 0);
+  const TuneKey key{(int64_t)sizeof(T), transA ? 1 : 0, mt, nt, kb, vec};
   auto it = ctx->tune.find(key);
   if (it != ctx->tune.end()) return it->second;
   TuneChoice ch;
+  ch.M = M;
+  ch.N = N;
+  ch.K = K;
   if (!ctx->tune_on) return ctx->tune[key] = ch;
-  constexpr int PBK = 128 / (int)sizeof(T);
-  const int64_t tiles = (int64_t)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   const int64_t smax = std::max<int64_t>(1, (int64_t)K / (8 * PBK));
   // split counts that fill r whole rounds of the 512 workgroups resident at once (two per CU)
   std::vector<int> cand{0};
@@ -411,7 +420,11 @@ void gemm(gfcc_ctx* ctx, bool transA, bool transB, int M, int N, int K, T alpha,
   // skinny long-K products: split-K variant chosen by the autotuner
   if (!transB && batch == 1 && M > 0 && N > 0 && tunable(M, N, K, sizeof(T))) {
     const TuneChoice& ch = tune_choice<T>(ctx, transA, M, N, K, A, lda, B, ldb);
-    run_variant<T>(ctx, ch.splits, transA, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    // a class member measured on another K keeps at least 8 slabs of k per split
+    const int pbk = 128 / (int)sizeof(T);
+    const int sp = ch.splits > 0 ? (int)std::max<int64_t>(1, std::min<int64_t>(ch.splits, K / (8 * pbk)))
+                                 : 0;
+    run_variant<T>(ctx, sp, transA, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
     return;
   }
   gemm_impl<T>(ctx, transA, transB ? B_TRANS : B_ROW, M, N, K, alpha, A, lda, B, ldb, beta, C,
