@@ -7,9 +7,14 @@
 // right-preconditioned by the Jacobi matrix diag(M(omega)). Arnoldi uses classical
 // Gram-Schmidt with one full re-orthogonalisation pass (CGS2). Givens rotations, the
 // convergence test and the triangular solve run on the device, one thread per right-hand side.
-// Every restart cycle begins with the explicit FP64 residual b - M x, which is also the final
-// stopping test. With a reduced-precision sigma inside the cycle this is FP64 iterative
-// refinement around a low-precision GMRES (GMRES-IR).
+// A cycle ends with the residual of the updated iterate. In FP64 it is formed from the Arnoldi
+// relation M Z = V H (Z = P^-1 V, the sigma products of the cycle): r = V (beta e1 - H y),
+// which equals b - M x to rounding whether or not V stays orthogonal, and costs one pass over
+// the basis, fused with the update of x, instead of another sigma product. It is the stopping
+// test. A cycle started from a given x0 begins with the explicit b - M x0. With a
+// reduced-precision sigma inside the cycle the relation holds for that operator only, so every
+// cycle ends with the explicit FP64 residual: FP64 iterative refinement around a low-precision
+// GMRES (GMRES-IR).
 #include <algorithm>
 #include <cmath>
 
@@ -303,6 +308,8 @@ __global__ void scale_precond_kernel(const double2* __restrict__ W, const double
 
 struct BlockState {
   double2* H;      // [nb][m][m+1]  column k of RHS r at H + (r*m + k)*(m+1)
+  double2* Hraw;   // [nb][m][m+1]  the same columns before the Givens rotations
+  double* beta;    // [nb] norm of the residual the cycle started from (0: not in the cycle)
   double2* cs;     // [nb][m]
   double2* sn;     // [nb][m]
   double2* g;      // [nb][m+1]
@@ -325,9 +332,10 @@ __global__ void arnoldi_finish_kernel(const double2* __restrict__ h, const doubl
     return;
   }
   double2* col = s.H + ((int64_t)r * m + k) * (m + 1);
-  for (int i = 0; i <= k; ++i) col[i] = h[(int64_t)i * nb + r];
+  double2* raw = s.Hraw + ((int64_t)r * m + k) * (m + 1);
+  for (int i = 0; i <= k; ++i) raw[i] = col[i] = h[(int64_t)i * nb + r];
   double nrm = hn[r];
-  col[k + 1] = make_double2(nrm, 0.0);
+  raw[k + 1] = col[k + 1] = make_double2(nrm, 0.0);
   double2* cs = s.cs + (int64_t)r * m;
   double2* sn = s.sn + (int64_t)r * m;
   for (int i = 0; i < k; ++i) {  // previous rotations
@@ -408,6 +416,63 @@ __global__ void xupdate_kernel(const double2* __restrict__ V, int64_t vstride, i
   }
 }
 
+// Residual coefficients of the cycle, one thread per RHS: c = beta e1 - Hraw y over rows
+// 0..kend (zero beyond, and for a RHS not in the cycle); c[i][r].
+__global__ void rescoef_kernel(int m, int nb, BlockState s, const int* __restrict__ used,
+                               const double2* __restrict__ y, double2* __restrict__ c) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nb) return;
+  const int ke = used[r] ? s.kend[r] : -1;
+  const double2* H = s.Hraw + (int64_t)r * m * (m + 1);
+  for (int i = 0; i <= m; ++i) {
+    double2 acc = make_double2(i == 0 && ke >= 0 ? s.beta[r] : 0.0, 0.0);
+    if (i <= ke) {
+      for (int j = (i > 0 ? i - 1 : 0); j < ke; ++j) {  // H is upper Hessenberg
+        const double2 p = cmul(H[(int64_t)j * (m + 1) + i], y[(int64_t)j * nb + r]);
+        acc.x -= p.x;
+        acc.y -= p.y;
+      }
+    } else {
+      acc = make_double2(0.0, 0.0);
+    }
+    c[(int64_t)i * nb + r] = acc;
+  }
+}
+
+// The end of a cycle in one pass over the basis: X += (sum_{j<nj} V_j y_j) / (diag + z) and,
+// for the RHS in the cycle, R = sum_{i<=nj} V_i c_i (the residual of the updated X by the
+// Arnoldi relation); R of the others is left as it is.
+__global__ void xupdate_res_kernel(const double2* __restrict__ V, int64_t vstride, int nj,
+                                   const double2* __restrict__ y, const double2* __restrict__ c,
+                                   const int* __restrict__ used,
+                                   const double* __restrict__ diag,
+                                   const double2* __restrict__ z, int64_t D, int nb,
+                                   double2* __restrict__ X, double2* __restrict__ R) {
+  const int64_t n = D * nb;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx % nb);
+    const int64_t d = idx / nb;
+    double2 acc = make_double2(0.0, 0.0), res = make_double2(0.0, 0.0);
+    for (int j = 0; j <= nj; ++j) {
+      const double2 vj = V[(int64_t)j * vstride + idx];
+      const double2 q = cmul(vj, c[(int64_t)j * nb + r]);
+      res.x += q.x;
+      res.y += q.y;
+      if (j < nj) {
+        const double2 p = cmul(vj, y[(int64_t)j * nb + r]);
+        acc.x += p.x;
+        acc.y += p.y;
+      }
+    }
+    const double2 zz = z[r];
+    const double2 u = cdiv(acc, make_double2(diag[d] + zz.x, zz.y));
+    const double2 x = X[idx];
+    X[idx] = make_double2(x.x + u.x, x.y + u.y);
+    if (used[r]) R[idx] = res;
+  }
+}
+
 // right-hand sides: forward b = e_p, transpose b = c_p (row p of Crows)
 __global__ void rhs_kernel(const int* __restrict__ prow, const double* __restrict__ Crows,
                            int transpose, int64_t D, int nb, double2* __restrict__ B) {
@@ -481,7 +546,7 @@ struct GmresBlock {
   int precision = GFCC_FP64;
   bool transpose = false;
   DevBuf mem, mem_f32;
-  double2 *V, *W, *U, *X, *B, *Hh, *Hh2, *Y, *z;
+  double2 *V, *W, *U, *X, *B, *R, *Hh, *Hh2, *Y, *Cc, *z;
   double *nrm, *part_n;
   double2* part_h;
   int *used, *prow;
@@ -502,15 +567,18 @@ struct GmresBlock {
     int64_t bytes = 0;
     auto add = [&](int64_t n, int64_t sz) { bytes += ((n * sz + 255) / 256) * 256; };
     add(vec * (m + 1), 16);                                   // V
-    for (int i = 0; i < 4; ++i) add(vec, 16);                 // W U X B
+    for (int i = 0; i < 5; ++i) add(vec, 16);                 // W U X B R
     add((int64_t)(m + 1) * nb, 16); add((int64_t)(m + 1) * nb, 16);  // Hh Hh2
     add((int64_t)m * nb, 16);                                 // Y
+    add((int64_t)(m + 1) * nb, 16);                           // Cc
     add(nb, 16);                                              // z
     add(nb, 8);                                               // nrm
     add((int64_t)nblk_rows * nb, 8);                          // part_n
     add((int64_t)nblk_rows * JG * nb, 16);                    // part_h
     add(nb, 4); add(nb, 4);                                   // used prow
     add((int64_t)nb * m * (m + 1), 16);                       // H
+    add((int64_t)nb * m * (m + 1), 16);                       // Hraw
+    add(nb, 8);                                               // beta
     add((int64_t)nb * m, 16); add((int64_t)nb * m, 16);       // cs sn
     add((int64_t)nb * (m + 1), 16);                           // g
     for (int i = 0; i < 4; ++i) add(nb, 4);
@@ -522,9 +590,11 @@ struct GmresBlock {
     U = carve<double2>(cur, vec);
     X = carve<double2>(cur, vec);
     B = carve<double2>(cur, vec);
+    R = carve<double2>(cur, vec);
     Hh = carve<double2>(cur, (int64_t)(m + 1) * nb);
     Hh2 = carve<double2>(cur, (int64_t)(m + 1) * nb);
     Y = carve<double2>(cur, (int64_t)m * nb);
+    Cc = carve<double2>(cur, (int64_t)(m + 1) * nb);
     z = carve<double2>(cur, nb);
     nrm = carve<double>(cur, nb);
     part_n = carve<double>(cur, (int64_t)nblk_rows * nb);
@@ -532,6 +602,8 @@ struct GmresBlock {
     used = carve<int>(cur, nb);
     prow = carve<int>(cur, nb);
     s.H = carve<double2>(cur, (int64_t)nb * m * (m + 1));
+    s.Hraw = carve<double2>(cur, (int64_t)nb * m * (m + 1));
+    s.beta = carve<double>(cur, nb);
     s.cs = carve<double2>(cur, (int64_t)nb * m);
     s.sn = carve<double2>(cur, (int64_t)nb * m);
     s.g = carve<double2>(cur, (int64_t)nb * (m + 1));
@@ -654,18 +726,22 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
   bool first = X0 == nullptr;
   const bool mixed = gb.precision != GFCC_FP64;
   const double inner_rel = 1e-4;  // relative tolerance of a reduced-precision cycle
+  bool have_res = false;  // R holds the residual of X from the Arnoldi relation of the last cycle
+  std::vector<double> hbeta(nb);
   for (;;) {
-    // ---- explicit FP64 residual R = B - M X (in W) and its norm
+    // ---- residual R of the current X and its norm: b at the start, the explicit FP64
+    // b - M X after a given x0 or a reduced-precision cycle, else the relation residual
     if (first) {
-      GFCC_HIP(hipMemcpyAsync(gb.W, gb.B, sizeof(double2) * D * nb, hipMemcpyDeviceToDevice, st));
-    } else {
+      GFCC_HIP(hipMemcpyAsync(gb.R, gb.B, sizeof(double2) * D * nb, hipMemcpyDeviceToDevice, st));
+    } else if (!have_res) {
       gb.apply_M(gb.X, gb.U, true);
       hipLaunchKernelGGL(residual_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.B, gb.U,
-                         D * nb, gb.W);
+                         D * nb, gb.R);
       GFCC_LAUNCH_CHECK();
     }
     first = false;
-    gb.norms(gb.W, gb.nrm);
+    have_res = false;
+    gb.norms(gb.R, gb.nrm);
     GFCC_HIP(hipMemcpyAsync(rn.data(), gb.nrm, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
     GFCC_HIP(hipStreamSynchronize(st));
     int nact = 0;
@@ -679,6 +755,7 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
       thr[r] = mixed ? std::max(t_abs, inner_rel * rn[r]) : t_abs;
       for (int i = 0; i <= m; ++i) g0[(size_t)r * (m + 1) + i] = make_double2(0.0, 0.0);
       g0[(size_t)r * (m + 1)] = make_double2(act[r] ? rn[r] : 0.0, 0.0);
+      hbeta[r] = act[r] ? rn[r] : 0.0;
     }
     if (nact == 0) break;
     // ---- cycle start: V0 = R / ||R||, g = (||R||, 0, ...)
@@ -687,10 +764,11 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
     GFCC_HIP(hipMemcpyAsync(gb.s.thresh, thr.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st));
     GFCC_HIP(hipMemcpyAsync(gb.s.inv, inv0.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st));
     GFCC_HIP(hipMemcpyAsync(gb.s.g, g0.data(), sizeof(double2) * g0.size(), hipMemcpyHostToDevice, st));
+    GFCC_HIP(hipMemcpyAsync(gb.s.beta, hbeta.data(), sizeof(double) * nb, hipMemcpyHostToDevice, st));
     GFCC_HIP(hipMemcpyAsync(gb.s.kend, zeros.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
     GFCC_HIP(hipMemcpyAsync(gb.s.its, its.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
     // V0 = R / ||R|| and its preconditioned copy U
-    hipLaunchKernelGGL(scale_precond_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.W, gb.s.inv,
+    hipLaunchKernelGGL(scale_precond_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.R, gb.s.inv,
                        ctx->op.diag.as<double>(), gb.z, D, nb, gb.V, gb.U);
     GFCC_LAUNCH_CHECK();
     int ksteps = 0;  // Arnoldi steps taken in this cycle (basis vectors that y can weight)
@@ -748,9 +826,21 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
     hipLaunchKernelGGL(ysolve_kernel, dim3(blocks_for(nb, 64)), dim3(64), 0, st, m, nb, gb.s,
                        gb.used, gb.Y);
     GFCC_LAUNCH_CHECK();
-    hipLaunchKernelGGL(xupdate_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.V, D * nb, ksteps,
-                       gb.Y, ctx->op.diag.as<double>(), gb.z, D, nb, gb.X);
-    GFCC_LAUNCH_CHECK();
+    if (!mixed) {
+      // FP64: the update and the residual of the updated X (Arnoldi relation) in one pass
+      hipLaunchKernelGGL(rescoef_kernel, dim3(blocks_for(nb, 64)), dim3(64), 0, st, m, nb, gb.s,
+                         gb.used, gb.Y, gb.Cc);
+      GFCC_LAUNCH_CHECK();
+      hipLaunchKernelGGL(xupdate_res_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.V, D * nb,
+                         ksteps, gb.Y, gb.Cc, gb.used, ctx->op.diag.as<double>(), gb.z, D, nb,
+                         gb.X, gb.R);
+      GFCC_LAUNCH_CHECK();
+      have_res = true;
+    } else {
+      hipLaunchKernelGGL(xupdate_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.V, D * nb,
+                         ksteps, gb.Y, ctx->op.diag.as<double>(), gb.z, D, nb, gb.X);
+      GFCC_LAUNCH_CHECK();
+    }
     GFCC_HIP(hipMemcpyAsync(its.data(), gb.s.its, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
     GFCC_HIP(hipMemcpyAsync(brk.data(), gb.s.brk, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
     GFCC_HIP(hipStreamSynchronize(st));

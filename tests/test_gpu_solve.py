@@ -65,6 +65,33 @@ def test_near_poles_and_transpose(gpu_ctx):
     assert np.abs(adj.G.cpu().numpy() - Gr).max() / np.abs(Gr).max() < 1e-9
 
 
+@pytest.mark.parametrize("transpose", [False, True])
+def test_reported_residual_is_the_true_residual(gpu_ctx, transpose):
+    """The FP64 solver forms the residual at the end of each restart cycle from the Arnoldi
+    relation instead of a new sigma product. With short cycles (restart 10: up to about 20
+    cycles next to the poles) the reported residual must be ||b - M x|| / ||b|| of the returned
+    x, computed here by the oracle with the dense operator, up to rounding."""
+    print(f"[relation residual T={transpose}]", flush=True)
+    prob = synth.make_problem(6, 10, 17)
+    ps = np.array([3, 4, 5])
+    hb, H, B, C, _, _ = _dense_ref(prob, [-1.0], ps, 0.01)
+    lam = np.sort(np.linalg.eigvals(H).real)
+    om = np.concatenate([-lam[:2] + 0.05, np.linspace(-1.2, -0.3, 4)])
+    gpu_ctx.build_from_problem(prob)
+    res = gpu_ctx.gfcc_solve(om, ps, 0.01, tol=1e-12, restart=10, maxit=600, want_x=True,
+                             transpose=transpose)
+    assert res.resid.max() <= 1e-12
+    assert res.iters.max() > 100        # many restart cycles
+    X = res.X.cpu().numpy()
+    M0 = H.T if transpose else H
+    for w, w_om in enumerate(om):
+        Mw = M0 + (w_om - 0.01j) * np.eye(M0.shape[0])
+        for k in range(len(ps)):
+            b = C[k] if transpose else B[:, k]
+            true = np.linalg.norm(b - Mw @ X[w, k]) / np.linalg.norm(b)
+            assert abs(true - res.resid[w, k]) <= 1e-13, (w, k, true, res.resid[w, k])
+
+
 def test_errors(gpu_ctx):
     prob = synth.make_problem(4, 3, 1)
     gpu_ctx.build_from_problem(prob)
