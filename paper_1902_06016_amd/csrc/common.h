@@ -247,6 +247,12 @@ gfcc_status solve_all(gfcc_ctx* ctx, int nw, const double* omega, int np, const 
 // with prow[r] = -1 is zero. prow is a device array.
 void solve_rhs(gfcc_ctx* ctx, const int* prow, bool transpose, int64_t D, int nb, void* B);
 
+// Hbar_N U for the block U[d][r] = e_p / (diag_p + z_r), p = prow[r] (zero columns where
+// prow[r] < 0): column p of Hbar_N (of W1 in the 1h rows, of W4c in the 2h1p rows) scaled, the
+// first product of a forward solve started from x = 0, without a sigma product. z is complex
+// [nb], W complex [D][nb], all device.
+void unit_sigma(gfcc_ctx* ctx, const int* prow, const void* z, int nb, void* W);
+
 // DIIS workspace, grown on demand and reused across blocks.
 struct DiisWork {
   DevBuf mem;

@@ -373,12 +373,17 @@ const void* diis_block(gfcc_ctx* ctx, DiisWork& wk, int nb, int m, const double*
     }
   }
   bool xzero = X0 == nullptr;
+  // forward from x = 0: the first step gives x = e_p / P_pp, whose product is a column of Hbar_N
+  bool xunit = false;
   int k = 0;
   for (;;) {
     // ---- residual of the current iterate, into slot k
-    if (!xzero)
+    if (xunit)
+      unit_sigma(ctx, prow, z, nb, S);
+    else if (!xzero)
       sigma_block_f64(ctx, 2 * nb, reinterpret_cast<const double*>(X),
                       reinterpret_cast<double*>(S), transpose);
+    xunit = xzero && !transpose;
     hipLaunchKernelGGL(diis_resid_kernel, rgrid, dim3(CW), 0, st, B, X, S, z, xzero ? 0 : 1, D,
                        nb, E + (int64_t)k * vec, part_n);
     GFCC_LAUNCH_CHECK();

@@ -473,6 +473,31 @@ __global__ void xupdate_res_kernel(const double2* __restrict__ V, int64_t vstrid
   }
 }
 
+// The first sigma product of a forward cycle started from x = 0: there U = e_p / P_pp for
+// column r (p = prow[r], P_pp = diag[p] + z[r]), and Hbar_N e_p is column p of Hbar_N, i.e.
+// column p of W1 in the 1h rows and of W4c in the 2h1p rows (the three-body, Woo and ovvo
+// terms act on the zero 2h1p part). W[d][r] = Hbar_N[d][p] / P_pp, zero for padding columns.
+__global__ void unit_sigma_kernel(const int* __restrict__ prow, const double* __restrict__ W1,
+                                  const double* __restrict__ W4c, int64_t ldw4,
+                                  const double* __restrict__ diag, const double2* __restrict__ z,
+                                  int o, int64_t D, int nb, double2* __restrict__ W) {
+  const int64_t n = D * nb;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx % nb);
+    const int64_t d = idx / nb;
+    const int p = prow[r];
+    if (p < 0) {
+      W[idx] = make_double2(0.0, 0.0);
+      continue;
+    }
+    const double h = d < o ? W1[d * D + p] : W4c[(d - o) * ldw4 + p];
+    const double2 zz = z[r];
+    const double2 u = cdiv(make_double2(1.0, 0.0), make_double2(diag[p] + zz.x, zz.y));
+    W[idx] = make_double2(h * u.x, h * u.y);
+  }
+}
+
 // right-hand sides: forward b = e_p, transpose b = c_p (row p of Crows)
 __global__ void rhs_kernel(const int* __restrict__ prow, const double* __restrict__ Crows,
                            int transpose, int64_t D, int nb, double2* __restrict__ B) {
@@ -727,10 +752,12 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
   const bool mixed = gb.precision != GFCC_FP64;
   const double inner_rel = 1e-4;  // relative tolerance of a reduced-precision cycle
   bool have_res = false;  // R holds the residual of X from the Arnoldi relation of the last cycle
+  bool unit_start = false;  // this cycle starts from V0 = e_p (forward, x = 0)
   std::vector<double> hbeta(nb);
   for (;;) {
     // ---- residual R of the current X and its norm: b at the start, the explicit FP64
     // b - M X after a given x0 or a reduced-precision cycle, else the relation residual
+    unit_start = first && !gb.transpose;
     if (first) {
       GFCC_HIP(hipMemcpyAsync(gb.R, gb.B, sizeof(double2) * D * nb, hipMemcpyDeviceToDevice, st));
     } else if (!have_res) {
@@ -777,8 +804,13 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
       const int nj = k + 1;
       if (nj <= JG) {
         // W = sigma(U); the shift, both Gram-Schmidt passes (CGS2) and the norm in three
-        // fused sweeps over the basis; Hessenberg column = sum of both passes
-        gb.apply_M(gb.U, gb.W, false, false);
+        // fused sweeps over the basis; Hessenberg column = sum of both passes. The first
+        // product of a cycle started from b = e_p is a column of Hbar_N.
+        if (k == 0 && unit_start) {
+          unit_sigma(ctx, gb.prow, gb.z, nb, gb.W);
+        } else {
+          gb.apply_M(gb.U, gb.W, false, false);
+        }
         hipLaunchKernelGGL(Fused::shift_dots[nj - 1], rgrid, dim3(CW), 0, st, gb.V, D * nb, gb.U,
                            gb.z, gb.W, D, nb, gb.part_h);
         GFCC_LAUNCH_CHECK();
@@ -856,6 +888,15 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
 
 // Full driver shared by gfcc_solve and the reduced-order model: solves every (omega, p),
 // writes G (device, [nw][np][np]) and optionally X ([nw][np][D] device).
+void unit_sigma(gfcc_ctx* ctx, const int* prow, const void* z, int nb, void* W) {
+  const Operator& op = ctx->op;
+  hipLaunchKernelGGL(unit_sigma_kernel, dim3(gridn(op.D * nb)), dim3(256), 0, ctx->stream, prow,
+                     op.f64.W1.as<double>(), op.f64.W4c.as<double>(), (int64_t)(op.o + op.v),
+                     op.diag.as<double>(), static_cast<const double2*>(z), op.o, op.D, nb,
+                     static_cast<double2*>(W));
+  GFCC_LAUNCH_CHECK();
+}
+
 void solve_rhs(gfcc_ctx* ctx, const int* prow, bool transpose, int64_t D, int nb, void* B) {
   hipLaunchKernelGGL(rhs_kernel, dim3(gridn(D * nb)), dim3(256), 0, ctx->stream, prow,
                      ctx->op.Crows.as<double>(), transpose ? 1 : 0, D, nb,
