@@ -413,6 +413,17 @@ template <typename T>
 void gemm(gfcc_ctx* ctx, bool transA, bool transB, int M, int N, int K, T alpha, const T* A,
           int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc, int batch,
           int64_t sA, int64_t sB, int64_t sC) {
+  // a large transposed B ([N][K], contiguous; the operator build's l2 t2^T and oovv tau^T) is
+  // transposed once into a temporary so that the product takes the row-major paths below
+  if (transB && batch == 1 && sizeof(T) == 8 && ldb == K && (int64_t)K * N >= (1 << 20) &&
+      N < 65536 * 32) {
+    DevBuf bt;
+    bt.alloc(sizeof(T) * (size_t)K * N);
+    transpose2d(ctx, reinterpret_cast<const double*>(B), N, K, bt.as<double>());
+    gemm<T>(ctx, transA, false, M, N, K, alpha, A, lda, bt.as<T>(), N, beta, C, ldc);
+    GFCC_HIP(hipStreamSynchronize(ctx->stream));  // the temporary is freed on return
+    return;
+  }
   // large single products with a row-major B go to the pipelined kernel
   if (!transB && batch == 1 &&
       gemm_pipe<T>(ctx, transA, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc))
