@@ -5,8 +5,8 @@
 // sampled frequency and orbital. Since H-bar_N, b and c are real, a real basis makes
 // S^T = S^H, keeps the projected matrix real and preserves interpolation at omega_k. New
 // columns are orthogonalised against S by two block passes of classical Gram-Schmidt (matrix
-// products), then one by one against the columns accepted in the same round (two passes);
-// a column whose norm drops below defl_tol times its original norm is dropped.
+// products), then one by one against S and the columns accepted in the same round (two
+// passes); a column whose norm drops below defl_tol times its original norm is dropped.
 // Storage is row-major per basis vector: St[m][D], HSt[m][D] = (H-bar_N S)^T.
 //
 // Projection. Hhat = S^T H-bar_N S, bhat = S^T b_p, chat = c_q^T S.
@@ -272,6 +272,137 @@ __global__ __launch_bounds__(256) void rom_solve_kernel(
   if (t == 0 && resid) resid[w] = rmax;
 }
 
+// The same solve with one wavefront per frequency and the matrix and right-hand sides in LDS
+// (dynamic, (m^2 + np m) complex entries, at most ROM_LDS_MAX bytes): the pivot search is a
+// wavefront reduction and the back substitution runs column by column for all orbitals at
+// once, so no step waits on other wavefronts. Only the solutions go to the work buffer (at
+// the offset rom_solve_kernel uses, for lift_kernel).
+constexpr int ROM_LDS_MAX = 65536;
+
+__global__ __launch_bounds__(64) void rom_solve_wave_kernel(
+    const double* __restrict__ Hhat, const double* __restrict__ bhat,
+    const double* __restrict__ chat, const double* __restrict__ Rm,
+    const double* __restrict__ beta, const double* __restrict__ cnst, int rk,
+    const double* __restrict__ omega, double eta, int m, int np, int w0, int nw,
+    double2* __restrict__ work, double2* __restrict__ G, double* __restrict__ resid) {
+  extern __shared__ double2 rom_lds[];
+  const int wl = blockIdx.x;
+  const int w = w0 + wl;
+  if (w >= nw) return;
+  const int t = threadIdx.x;
+  double2* A = rom_lds;
+  double2* Xs = rom_lds + (int64_t)m * m;
+  const double2 z = make_double2(omega[w], -eta);
+  for (int e = t; e < m * m; e += 64) {
+    const int i = e / m, j = e - (e / m) * m;
+    A[e] = make_double2(Hhat[e] + (i == j ? z.x : 0.0), i == j ? z.y : 0.0);
+  }
+  for (int e = t; e < np * m; e += 64) Xs[e] = make_double2(bhat[e], 0.0);
+  __syncthreads();
+  const int ti = t / 8, tj = t % 8;  // 8 x 8 lane grid for the trailing update
+  for (int k = 0; k < m; ++k) {
+    // partial pivoting: largest |re| + |im| in column k, the smallest row among equals
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + t; i < m; i += 64) {
+      const double2 a = A[i * m + k];
+      const double mag = fabs(a.x) + fabs(a.y);
+      if (mag > best) { best = mag; bi = i; }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    const int pv = __shfl(bi, 0);
+    if (pv != k) {
+      for (int j = t; j < m; j += 64) {
+        const double2 a = A[k * m + j];
+        A[k * m + j] = A[pv * m + j];
+        A[pv * m + j] = a;
+      }
+      for (int q = t; q < np; q += 64) {
+        const double2 a = Xs[q * m + k];
+        Xs[q * m + k] = Xs[q * m + pv];
+        Xs[q * m + pv] = a;
+      }
+    }
+    __syncthreads();
+    const double2 akk = A[k * m + k];
+    if (k + 1 < m && (akk.x != 0.0 || akk.y != 0.0)) {
+      for (int i = k + 1 + t; i < m; i += 64) A[i * m + k] = cdv(A[i * m + k], akk);
+      __syncthreads();
+      for (int i = k + 1 + ti; i < m; i += 8) {
+        const double2 l = A[i * m + k];
+        for (int j = k + 1 + tj; j < m; j += 8) {
+          const double2 p = cm(l, A[k * m + j]);
+          A[i * m + j].x -= p.x;
+          A[i * m + j].y -= p.y;
+        }
+      }
+      for (int q = ti; q < np; q += 8) {
+        const double2 xk = Xs[q * m + k];
+        for (int i = k + 1 + tj; i < m; i += 8) {
+          const double2 p = cm(A[i * m + k], xk);
+          Xs[q * m + i].x -= p.x;
+          Xs[q * m + i].y -= p.y;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // back substitution, column by column, every orbital at once
+  for (int i = m - 1; i >= 0; --i) {
+    const double2 aii = A[i * m + i];
+    for (int q = t; q < np; q += 64) Xs[q * m + i] = cdv(Xs[q * m + i], aii);
+    __syncthreads();
+    for (int q = ti; q < np; q += 8) {
+      const double2 xi = Xs[q * m + i];
+      for (int r = tj; r < i; r += 8) {
+        const double2 p = cm(A[r * m + i], xi);
+        Xs[q * m + r].x -= p.x;
+        Xs[q * m + r].y -= p.y;
+      }
+    }
+    __syncthreads();
+  }
+  // Ghat[q][p] = chat_q . xhat_p
+  for (int e = t; e < np * np; e += 64) {
+    const int q = e / np, pk = e - (e / np) * np;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int i = 0; i < m; ++i) {
+      const double c = chat[(int64_t)q * m + i];
+      const double2 x = Xs[pk * m + i];
+      acc.x += c * x.x;
+      acc.y += c * x.y;
+    }
+    G[((int64_t)w * np + q) * np + pk] = acc;
+  }
+  // residual: max_p sqrt(cnst_p + ||beta_p - R xhat_p||^2)
+  double rmax = 0.0;
+  for (int pk = 0; pk < np; ++pk) {
+    double acc = 0.0;
+    const double2* x = Xs + pk * m;
+    for (int i = t; i < rk; i += 64) {
+      double2 rx = make_double2(0.0, 0.0);
+      const double* Ri = Rm + (int64_t)i * m;
+      for (int j = 0; j < m; ++j) {
+        rx.x += Ri[j] * x[j].x;
+        rx.y += Ri[j] * x[j].y;
+      }
+      const double dr = beta[(int64_t)pk * (rk > 0 ? rk : 1) + i] - rx.x, di = -rx.y;
+      acc += dr * dr + di * di;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    rmax = fmax(rmax, sqrt(cnst[pk] + __shfl(acc, 0)));
+  }
+  if (t == 0 && resid) resid[w] = rmax;
+  double2* xo = work + (int64_t)wl * ((int64_t)m * m + (int64_t)np * m) + (int64_t)m * m;
+  for (int e = t; e < np * m; e += 64) xo[e] = Xs[e];
+}
+
 // X[(w0 + wl) np + q][d] = sum_i xhat_wl,q[i] St[i][d] for the cnt frequencies of a chunk,
 // xhat read from rom_solve_kernel's work buffer (the m solution entries follow the m x m
 // factor of each frequency). Grid (ceil(D / 256), ceil(cnt np / LR)); LR rows per thread.
@@ -307,73 +438,216 @@ __global__ __launch_bounds__(256) void lift_kernel(const double* __restrict__ St
   }
 }
 
+// ---- row-by-row Gram-Schmidt on the device (orth_rows). The projection set is the nb fixed
+// rows B followed by the acc rows accepted so far (Out); acc lives in device memory, so the
+// loop over rows needs no host round trip.
+struct OrthState {
+  int acc;     // rows accepted so far
+  int slot;    // index in Out of the row being decided
+  int take;    // 1 if that row is accepted
+  int pad;
+  double inv;  // 1 / its norm
+};
+
+constexpr int ODR = 8;        // projection rows per dots workgroup
+constexpr int OSL = 4096;     // elements of D per dots slice
+
+__device__ __forceinline__ const double* orth_row(const double* B, int nb, const double* Out,
+                                                  int64_t D, int i) {
+  return i < nb ? B + (int64_t)i * D : Out + (int64_t)(i - nb) * D;
+}
+
+// sum of v over the 256 threads of the workgroup in a fixed order (wave shuffles, then the
+// four wave sums in turn); the result is valid in every thread
+__device__ __forceinline__ double orth_block_sum(double v, double* red4) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if (threadIdx.x % 64 == 0) red4[threadIdx.x / 64] = v;
+  __syncthreads();
+  return ((red4[0] + red4[1]) + red4[2]) + red4[3];
+}
+
+// partial[s][i] = sum over slice s of Q_i[d] w[d] for the rows i in
+// [blockIdx.y ODR, blockIdx.y ODR + ODR) below nb + acc. Grid (ceil(D / OSL), ceil(kmax / ODR)).
+__global__ __launch_bounds__(256) void orth_dots_kernel(const double* __restrict__ B, int nb,
+                                                        const double* __restrict__ Out,
+                                                        const OrthState* __restrict__ stt,
+                                                        const double* __restrict__ w, int64_t D,
+                                                        int kmax, double* __restrict__ partial) {
+  __shared__ double red4[4];
+  const int k = nb + stt->acc;
+  const int row0 = blockIdx.y * ODR;
+  if (row0 >= k) return;
+  const int64_t d0 = (int64_t)blockIdx.x * OSL;
+  const int64_t d1 = min(D, d0 + (int64_t)OSL);
+  const double* q[ODR];
+#pragma unroll
+  for (int r = 0; r < ODR; ++r) q[r] = orth_row(B, nb, Out, D, min(row0 + r, k - 1));
+  double acc[ODR];
+#pragma unroll
+  for (int r = 0; r < ODR; ++r) acc[r] = 0.0;
+  for (int64_t d = d0 + threadIdx.x; d < d1; d += 256) {
+    const double x = w[d];
+#pragma unroll
+    for (int r = 0; r < ODR; ++r) acc[r] += q[r][d] * x;
+  }
+#pragma unroll
+  for (int r = 0; r < ODR; ++r) {
+    const double t = orth_block_sum(acc[r], red4);
+    if (threadIdx.x == 0 && row0 + r < k) partial[(int64_t)blockIdx.x * kmax + row0 + r] = t;
+  }
+}
+
+// h[i] = sum_s partial[s][i] (fixed order) for i < nb + acc; coefficients along the accepted
+// rows are accumulated into coef_row[i - nb]. Grid ceil(kmax / 256).
+__global__ __launch_bounds__(256) void orth_reduce_kernel(const double* __restrict__ partial,
+                                                          int nsl, int kmax,
+                                                          const OrthState* __restrict__ stt,
+                                                          int nb, double* __restrict__ h,
+                                                          double* __restrict__ coef_row) {
+  const int k = nb + stt->acc;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= k) return;
+  double s = 0.0;
+  for (int sl = 0; sl < nsl; ++sl) s += partial[(int64_t)sl * kmax + i];
+  h[i] = s;
+  if (coef_row && i >= nb) coef_row[i - nb] += s;
+}
+
+// w[d] -= sum_{i < nb + acc} h[i] Q_i[d]; with nrm_part, the workgroup's partial sum of w[d]^2
+// after the update. Grid ceil(D / 256), one element per thread.
+__global__ __launch_bounds__(256) void orth_update_kernel(const double* __restrict__ B, int nb,
+                                                          const double* __restrict__ Out,
+                                                          const OrthState* __restrict__ stt,
+                                                          const double* __restrict__ h,
+                                                          double* __restrict__ w, int64_t D,
+                                                          double* __restrict__ nrm_part) {
+  __shared__ double red4[4];
+  const int k = nb + stt->acc;
+  const int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double ss = 0.0;
+  if (d < D) {
+    double x = w[d];
+    for (int i = 0; i < min(k, nb); ++i) x -= h[i] * B[(int64_t)i * D + d];
+    for (int i = nb; i < k; ++i) x -= h[i] * Out[(int64_t)(i - nb) * D + d];
+    w[d] = x;
+    ss = x * x;
+  }
+  if (nrm_part) {
+    const double t = orth_block_sum(ss, red4);
+    if (threadIdx.x == 0) nrm_part[blockIdx.x] = t;
+  }
+}
+
+// norm of the row from the update's partial sums; accept it if it exceeds thresh (its norm
+// becomes the coefficient along its own accepted row). One workgroup.
+__global__ __launch_bounds__(256) void orth_accept_kernel(const double* __restrict__ nrm_part,
+                                                          int npart, double thresh,
+                                                          OrthState* __restrict__ stt,
+                                                          double* __restrict__ coef_row) {
+  __shared__ double red4[4];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < npart; b += 256) s += nrm_part[b];
+  const double nrm = sqrt(orth_block_sum(s, red4));
+  if (threadIdx.x == 0) {
+    const int acc = stt->acc;
+    const int take = (nrm > 0.0 && nrm > thresh) ? 1 : 0;
+    stt->slot = acc;
+    stt->take = take;
+    stt->inv = take ? 1.0 / nrm : 0.0;
+    if (take) {
+      if (coef_row) coef_row[acc] = nrm;
+      stt->acc = acc + 1;
+    }
+  }
+}
+
+// Out[slot] = w / ||w|| for an accepted row
+__global__ void orth_store_kernel(const OrthState* __restrict__ stt, const double* __restrict__ w,
+                                  int64_t D, double* __restrict__ Out) {
+  if (!stt->take) return;
+  const double s = stt->inv;
+  double* o = Out + (int64_t)stt->slot * D;
+  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < D;
+       d += (int64_t)gridDim.x * blockDim.x)
+    o[d] = w[d] * s;
+}
+
 }  // namespace
 
 // Orthogonalise the rows W[0..n) ([n][D], overwritten) against the fixed orthonormal rows
 // B[0..nb) by two block passes of classical Gram-Schmidt, then one by one (two passes each,
-// every pass against B and against the rows accepted so far, which are written to Out).
-// Projecting each pass on B as well keeps accepted rows orthogonal to B even when a row's
-// remainder is many orders of magnitude below its original norm. Row j is accepted when its
-// norm after orthogonalisation exceeds thresh[j]. If coef is given ([ldc] per row j), it
-// receives the coefficients of row j along the accepted Out rows (the norm for its own row).
-// Returns the number of accepted rows.
+// every pass classical Gram-Schmidt against B and the rows accepted so far together; accepted
+// rows are written to Out). Projecting each pass on B as well keeps accepted rows orthogonal
+// to B even when a row's remainder is many orders of magnitude below its original norm. Row j
+// is accepted when its norm after orthogonalisation exceeds thresh[j]. If coef is given ([ldc]
+// per row j), it receives the coefficients of row j along the accepted Out rows (the norm for
+// its own row). The row loop runs on the device (the count of accepted rows stays in device
+// memory), with one synchronisation at the end. Returns the number of accepted rows.
 static int orth_rows(gfcc_ctx* ctx, int64_t D, const double* B, int nb, double* W, int n,
                      double* Out, const std::vector<double>& thresh, std::vector<double>* coef,
                      int ldc) {
   hipStream_t st = ctx->stream;
-  DevBuf bhb;
+  if (n == 0) return 0;
+  DevBuf bblk;  // freed after the final synchronisation, like every buffer below
   if (nb > 0) {
-    DevBuf bh;
-    bh.alloc(sizeof(double) * (size_t)nb * n);
+    bblk.alloc(sizeof(double) * (size_t)nb * n);
     for (int pass = 0; pass < 2; ++pass) {
-      gemm<double>(ctx, false, true, nb, n, (int)D, 1.0, B, D, W, D, 0.0, bh.as<double>(), n);
-      gemm<double>(ctx, true, false, n, (int)D, nb, -1.0, bh.as<double>(), n, B, D, 1.0, W, D);
+      gemm<double>(ctx, false, true, nb, n, (int)D, 1.0, B, D, W, D, 0.0, bblk.as<double>(), n);
+      gemm<double>(ctx, true, false, n, (int)D, nb, -1.0, bblk.as<double>(), n, B, D, 1.0, W, D);
     }
-    GFCC_HIP(hipStreamSynchronize(st));
-    bhb.alloc(sizeof(double) * (size_t)nb);
   }
-  int acc = 0;
-  DevBuf bh, bn;
-  bh.alloc(sizeof(double) * (size_t)(n + 1));
-  bn.alloc(sizeof(double));
-  std::vector<double> h(n + 1), hsum(n + 1);
-  double nrm = 0.0;
-  if (coef) coef->assign((size_t)n * ldc, 0.0);
+  const int kmax = nb + n;
+  const int nsl = (int)((D + OSL - 1) / OSL);
+  const unsigned nupd = (unsigned)((D + 255) / 256);
+  GFCC_REQUIRE(nupd < (1u << 31), GFCC_EINVAL, "orth_rows: D too large");
+  DevBuf bstate, bpart, bh, bnrm, bcoef;
+  bstate.alloc(sizeof(OrthState));
+  bpart.alloc(sizeof(double) * (size_t)nsl * kmax);
+  bh.alloc(sizeof(double) * (size_t)kmax);
+  bnrm.alloc(sizeof(double) * nupd);
+  OrthState s0{};
+  GFCC_HIP(hipMemcpyAsync(bstate.p, &s0, sizeof(OrthState), hipMemcpyHostToDevice, st));
+  if (coef) {
+    coef->assign((size_t)n * ldc, 0.0);
+    bcoef.alloc(sizeof(double) * coef->size());
+    GFCC_HIP(hipMemcpyAsync(bcoef.p, coef->data(), sizeof(double) * coef->size(),
+                            hipMemcpyHostToDevice, st));
+  }
+  OrthState* stt = bstate.as<OrthState>();
   for (int j = 0; j < n; ++j) {
     double* wj = W + (int64_t)j * D;
-    std::fill(hsum.begin(), hsum.end(), 0.0);
+    double* crow = coef ? bcoef.as<double>() + (size_t)j * ldc : nullptr;
+    const int kj = nb + j;  // bound on nb + acc before row j
     for (int pass = 0; pass < 2; ++pass) {
-      if (nb > 0) {
-        gemm<double>(ctx, false, false, nb, 1, (int)D, 1.0, B, D, wj, 1, 0.0, bhb.as<double>(), 1);
-        gemm<double>(ctx, false, false, 1, (int)D, nb, -1.0, bhb.as<double>(), nb, B, D, 1.0, wj, D);
+      if (kj > 0) {
+        hipLaunchKernelGGL(orth_dots_kernel, dim3(nsl, (kj + ODR - 1) / ODR), dim3(256), 0, st, B,
+                           nb, Out, stt, wj, D, kmax, bpart.as<double>());
+        GFCC_LAUNCH_CHECK();
+        hipLaunchKernelGGL(orth_reduce_kernel, dim3((kj + 255) / 256), dim3(256), 0, st,
+                           bpart.as<double>(), nsl, kmax, stt, nb, bh.as<double>(), crow);
+        GFCC_LAUNCH_CHECK();
       }
-      if (acc > 0) {
-        gemm<double>(ctx, false, false, acc, 1, (int)D, 1.0, Out, D, wj, 1, 0.0, bh.as<double>(), 1);
-        gemm<double>(ctx, false, false, 1, (int)D, acc, -1.0, bh.as<double>(), acc, Out, D, 1.0,
-                     wj, D);
-        if (coef) {
-          GFCC_HIP(hipMemcpyAsync(h.data(), bh.p, sizeof(double) * acc, hipMemcpyDeviceToHost, st));
-          GFCC_HIP(hipStreamSynchronize(st));
-          for (int i = 0; i < acc; ++i) hsum[i] += h[i];
-        }
+      if (kj > 0 || pass == 1) {
+        hipLaunchKernelGGL(orth_update_kernel, dim3(nupd), dim3(256), 0, st, B, nb, Out, stt,
+                           bh.as<double>(), wj, D, pass == 1 ? bnrm.as<double>() : nullptr);
+        GFCC_LAUNCH_CHECK();
       }
     }
-    hipLaunchKernelGGL(rownorm_kernel, dim3(1), dim3(256), 0, st, wj, D, bn.as<double>());
+    hipLaunchKernelGGL(orth_accept_kernel, dim3(1), dim3(256), 0, st, bnrm.as<double>(),
+                       (int)nupd, thresh[j], stt, crow);
     GFCC_LAUNCH_CHECK();
-    GFCC_HIP(hipMemcpyAsync(&nrm, bn.p, sizeof(double), hipMemcpyDeviceToHost, st));
-    GFCC_HIP(hipStreamSynchronize(st));
-    if (coef)
-      for (int i = 0; i < acc; ++i) (*coef)[(size_t)j * ldc + i] = hsum[i];
-    if (nrm > 0.0 && nrm > thresh[j]) {
-      hipLaunchKernelGGL(scale_row_kernel, dim3(gridn(D)), dim3(256), 0, st, wj, D, 1.0 / nrm,
-                         Out + (int64_t)acc * D);
-      GFCC_LAUNCH_CHECK();
-      if (coef) (*coef)[(size_t)j * ldc + acc] = nrm;
-      ++acc;
-    }
+    hipLaunchKernelGGL(orth_store_kernel, dim3(gridn(D)), dim3(256), 0, st, stt, wj, D, Out);
+    GFCC_LAUNCH_CHECK();
   }
+  OrthState sf{};
+  GFCC_HIP(hipMemcpyAsync(&sf, bstate.p, sizeof(OrthState), hipMemcpyDeviceToHost, st));
+  if (coef)
+    GFCC_HIP(hipMemcpyAsync(coef->data(), bcoef.p, sizeof(double) * coef->size(),
+                            hipMemcpyDeviceToHost, st));
   GFCC_HIP(hipStreamSynchronize(st));
-  return acc;
+  return sf.acc;
 }
 
 // Append the real and imaginary parts of nr full solutions X [nr][D] (device, complex; the
@@ -538,6 +812,28 @@ static void mor_project(gfcc_mor* M) {
   GFCC_HIP(hipStreamSynchronize(st));
 }
 
+// Solves of the reduced system at omega[w0 .. w0 + cnt) (work, G and resid as in
+// rom_solve_kernel): one wavefront per frequency with the matrix in LDS when it fits, else
+// one workgroup per frequency on the work buffer.
+static void rom_solve(gfcc_mor* M, const double* omega, int w0, int cnt, int nw, double2* work,
+                      double2* G, double* resid) {
+  hipStream_t st = M->ctx->stream;
+  const int m = M->m, np = M->np;
+  const int64_t lds = ((int64_t)m * m + (int64_t)np * m) * (int64_t)sizeof(double2);
+  if (lds <= ROM_LDS_MAX) {
+    hipLaunchKernelGGL(rom_solve_wave_kernel, dim3(cnt), dim3(64), (unsigned)lds, st,
+                       M->Hhat.as<double>(), M->bhat.as<double>(), M->chat.as<double>(),
+                       M->Rm.as<double>(), M->beta.as<double>(), M->cnst.as<double>(), M->r, omega,
+                       M->eta, m, np, w0, nw, work, G, resid);
+  } else {
+    hipLaunchKernelGGL(rom_solve_kernel, dim3(cnt), dim3(256), 0, st, M->Hhat.as<double>(),
+                       M->bhat.as<double>(), M->chat.as<double>(), M->Rm.as<double>(),
+                       M->beta.as<double>(), M->cnst.as<double>(), M->r, omega, M->eta, m, np, w0,
+                       nw, work, G, resid);
+  }
+  GFCC_LAUNCH_CHECK();
+}
+
 static void mor_eval_impl(gfcc_mor* M, int nw, const double* omega, double2* G, double* resid_host) {
   gfcc_ctx* ctx = M->ctx;
   hipStream_t st = ctx->stream;
@@ -552,11 +848,7 @@ static void mor_eval_impl(gfcc_mor* M, int nw, const double* omega, double2* G, 
   GFCC_HIP(hipMemcpyAsync(bom.p, omega, sizeof(double) * nw, hipMemcpyHostToDevice, st));
   for (int w0 = 0; w0 < nw; w0 += chunk) {
     int cnt = std::min(chunk, nw - w0);
-    hipLaunchKernelGGL(rom_solve_kernel, dim3(cnt), dim3(256), 0, st, M->Hhat.as<double>(),
-                       M->bhat.as<double>(), M->chat.as<double>(), M->Rm.as<double>(),
-                       M->beta.as<double>(), M->cnst.as<double>(), M->r, bom.as<double>(), M->eta, m,
-                       np, w0, nw, bw.as<double2>(), G, bres.as<double>());
-    GFCC_LAUNCH_CHECK();
+    rom_solve(M, bom.as<double>(), w0, cnt, nw, bw.as<double2>(), G, bres.as<double>());
   }
   if (resid_host)
     GFCC_HIP(hipMemcpyAsync(resid_host, bres.p, sizeof(double) * nw, hipMemcpyDeviceToHost, st));
@@ -579,11 +871,8 @@ static void mor_lift_impl(gfcc_mor* M, int nw, const double* omega, double2* X) 
   GFCC_HIP(hipMemcpyAsync(bom.p, omega, sizeof(double) * nw, hipMemcpyHostToDevice, st));
   for (int w0 = 0; w0 < nw; w0 += chunk) {
     const int cnt = std::min(chunk, nw - w0);
-    hipLaunchKernelGGL(rom_solve_kernel, dim3(cnt), dim3(256), 0, st, M->Hhat.as<double>(),
-                       M->bhat.as<double>(), M->chat.as<double>(), M->Rm.as<double>(),
-                       M->beta.as<double>(), M->cnst.as<double>(), M->r, bom.as<double>(), M->eta, m,
-                       np, w0, nw, bw.as<double2>(), bG.as<double2>(), bres.as<double>());
-    GFCC_LAUNCH_CHECK();
+    rom_solve(M, bom.as<double>(), w0, cnt, nw, bw.as<double2>(), bG.as<double2>(),
+              bres.as<double>());
     const int64_t gy = ((int64_t)cnt * np + LR - 1) / LR;
     GFCC_REQUIRE(gy < 65536, GFCC_EINVAL, "mor_lift: too many frequencies x orbitals per chunk");
     hipLaunchKernelGGL(lift_kernel, dim3((unsigned)((D + 255) / 256), (unsigned)gy), dim3(256), 0,

@@ -52,6 +52,46 @@ def test_mor_matches_oracle_model(gpu_ctx, model):
     m.close()
 
 
+@pytest.mark.parametrize("nq", [7, 9])
+def test_mor_both_reduced_solvers(gpu_ctx, nq):
+    """Orders 56 and 72 (o=9, v=16, 4 sampled frequencies): the first fits one wavefront's LDS,
+    the second runs on the workgroup-per-frequency solver. Both give the oracle's model,
+    residuals and lifted solutions. The frequencies are spread so that every column's
+    remainder after orthogonalisation stays above 1.5e-6 of its norm, far from the 1e-10
+    deflation threshold (with densely sampled frequencies many remainders fall near the
+    threshold and the order then depends on solver rounding: GMRES here, dense LU in the
+    oracle)."""
+    print(f"[mor_orders nq={nq}]", flush=True)
+    o, v, nk = 9, 16, 4
+    p = synth.make_problem(o, v, 4)
+    hb = ohbar.build_hbar_from_problem(p)
+    H = osolve.dense_hbar(hb)
+    lam0 = np.sort(np.linalg.eigvals(H).real)[0]
+    ps = np.arange(o - nq, o)
+    B = np.stack([osig.b_vector(o, v, q) for q in ps], 1)
+    C = np.stack([osig.c_vector(o, v, p.t1, p.t2, p.l1, p.l2, q) for q in ps], 0)
+    eta = 0.01
+    wk = np.linspace(-lam0 - 1.2, -lam0 + 1.0, nk)
+    gpu_ctx.build_from_problem(p)
+    m = gpu_ctx.mor_build(wk, ps, eta, solve_tol=1e-12, defl_tol=1e-10)
+    rom = omor.ROM(hb, ps, eta, C, omor.dense_solver(H, B, eta))
+    rom.extend(wk, 1e-10)
+    order, _ = m.info()
+    assert order == rom.m == 2 * nq * nk
+    grid = np.linspace(-lam0 - 1.4, -lam0 + 1.2, 57)
+    Gg, rg = m.eval(grid)
+    Go, ro = rom.eval(grid)
+    # The basis comes from GMRES solutions at relative residual 1e-12 (dense LU in the
+    # oracle). Next to a pole the model's values carry that error amplified by up to
+    # ||M|| / eta ~ 1e3, and the residual estimate moves with the basis directions.
+    assert np.abs(Gg.cpu().numpy() - Go).max() < 1e-8 * np.abs(Go).max()
+    assert np.all(np.abs(rg - ro) <= 1e-5 * ro + 1e-9)
+    Xg = m.lift(grid[::7]).cpu().numpy()
+    Xo = omor.lift(rom, grid[::7])
+    assert np.abs(Xg - Xo).max() < 1e-8 * np.abs(Xo).max()
+    m.close()
+
+
 def test_mor_refinement(gpu_ctx, model):
     print("[mor_refine]", flush=True)
     p, hb, H, lam, ps, B, C = model
