@@ -397,6 +397,8 @@ def form_pert(cfg, gfcc, inputs, A_full, t_build_full):
     ps = synth.valence_p(o, cfg["np"])
     eps, oooo, ooov, oovv, ovvo, ovvv = [inputs[i] for i in (0, 5, 6, 7, 8, 9)]
     ctx = gfcc.Context(0)
+    # untimed first build: a fresh context tunes its product classes once
+    ctx.build_hbar_first_order(o, v, eps, oooo, ooov, oovv, ovvo, ovvv)
     torch.cuda.synchronize()
     t0 = time.time()
     ctx.build_hbar_first_order(o, v, eps, oooo, ooov, oovv, ovvo, ovvv)

@@ -86,7 +86,10 @@ const char* gfcc_last_error(const gfcc_ctx* ctx);
  * eps [o+v] orbital energies (the Fock matrix is diag(eps)); t1 [o][v]; t2 [o][o][v][v];
  * l1 [o][v]; l2 [o][o][v][v]; oooo [o][o][o][o]; ooov [o][o][o][v]; oovv [o][o][v][v];
  * ovvo [o][v][v][o]; ovvv [o][v][v][v]. All FP64, device pointers, read only during the
- * call. precision_mask: GFCC_KEEP_* bits. Replaces any operator built before.
+ * call. precision_mask: GFCC_KEEP_* bits. Replaces any operator built before; a rebuild
+ * reuses the previous operator's device buffers where the sizes match, and the context keeps
+ * the build's work arrays (about 6 o^2 v^2 doubles) for the next build while they total at
+ * most 8 GiB (gfcc_destroy frees them).
  * Errors: EINVAL for o < 2, v < 1, null pointers or non-finite entries (checked on the
  * device); ENOMEM if the operator does not fit.
  */
@@ -127,17 +130,21 @@ gfcc_status sigma_apply(gfcc_ctx* ctx, int nrhs, const void* x, void* y, int tra
  * skinny products of the sigma) run split-K; with the tuner on, the first call in each product
  * class (tile counts, binary magnitude of K, 16-byte loads possible) times the generic kernel
  * and the pipelined kernel at three split counts, synchronising the context stream, and keeps
- * the fastest for the context. Off: the generic kernel with its heuristic split count. Results
- * agree to rounding either way.
+ * the fastest for the context. Products of 256 to 4095 tiles with a long K (the operator
+ * build's largest products) are timed as the plain pipelined kernel and with 2 to 6 k ranges,
+ * which moves the partly filled last round of workgroups. Off: the generic kernel with its
+ * heuristic split count for the first kind, the plain pipelined kernel for the second.
+ * Results agree to rounding either way.
  */
 gfcc_status gfcc_autotune(gfcc_ctx* ctx, int enable);
 
 /*
  * gfcc_autotune_entry -- the tuner's choice number `index` (0-based, ordered by class):
  * desc[6] (host) receives {element bytes, transA, M, N, K, splits} (the shape it was measured
- * on) with splits = 0 for the
- * generic kernel; us[2] (host, may be NULL) the measured time of the choice and of the
- * generic kernel in microseconds. EINVAL past the last entry.
+ * on) with splits = 0 for the generic kernel and, for products of 256 tiles or more, 1 for
+ * the plain pipelined kernel; us[2] (host, may be NULL) the measured time of the choice and
+ * of the reference variant (the generic kernel, or the plain pipelined kernel for products of
+ * 256 tiles or more) in microseconds. EINVAL past the last entry.
  */
 gfcc_status gfcc_autotune_entry(const gfcc_ctx* ctx, int index, int64_t* desc, double* us);
 

@@ -317,7 +317,10 @@ void gemm_impl(gfcc_ctx* ctx, bool transA, int bmode, int M, int N, int K, T alp
 // (the skinny products of the sigma: [W1 ; Vp^T] . X, Vp^T . X2) run split-K. The variants
 // are the generic kernel with its heuristic split count and the pipelined kernel with the
 // split counts that fill one, two and four rounds of the 512 resident workgroups (two per CU),
-// each split keeping at least 8 slabs of k. The first time a
+// each split keeping at least 8 slabs of k. Products with 256 to 4095 tiles and a long K (the
+// operator build's O(o^3 v^3) products) lose up to a third of a round to the last, partly
+// filled one; their variants are the plain pipelined kernel and 2 .. 6 splits, which move
+// the tail. The first time a
 // shape is seen on a context every variant is timed (HIP events, once to warm up and twice
 // timed, into a scratch output; this synchronises the stream), and the fastest is kept for
 // that context and product class (tile counts, the binary magnitude of K, vector loads).
@@ -326,14 +329,27 @@ inline bool tunable(int M, int N, int K, size_t elem) {
   return tiles < 256 && (int64_t)K * (int64_t)elem >= 8 * 128 * 4;
 }
 
+constexpr int64_t MID_TILES_MAX = 4096;
+constexpr size_t MID_SCRATCH_MAX = size_t(2) << 30;  // bytes of split-K partials
+inline bool tunable_mid(int M, int N, int K, size_t elem) {
+  const int64_t tiles = (int64_t)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  return tiles >= 256 && tiles < MID_TILES_MAX && (int64_t)K * (int64_t)elem >= 2 * 8 * 128 &&
+         (size_t)M * N * elem * 2 <= MID_SCRATCH_MAX;
+}
+
+// splits: 0 the generic kernel; 1 in a mid-size class the plain pipelined kernel; else the
+// pipelined kernel over that many k ranges plus a reduction
 template <typename T>
 void run_variant(gfcc_ctx* ctx, int splits, bool transA, int M, int N, int K, T alpha,
-                 const T* A, int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc) {
-  if (splits == 0) {
+                 const T* A, int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc,
+                 bool mid = false) {
+  if (splits == 0 ||
+      (mid && splits == 1 && !gemm_pipe<T>(ctx, transA, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc))) {
     gemm_impl<T>(ctx, transA, B_ROW, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 1, 0, 0, 0,
                  nullptr, 0, 0, 0);
     return;
   }
+  if (mid && splits == 1) return;
   constexpr int PBK = 128 / (int)sizeof(T);
   int64_t kchunk = ((int64_t)K + splits - 1) / splits;
   kchunk = (kchunk + PBK - 1) / PBK * PBK;
@@ -349,7 +365,7 @@ void run_variant(gfcc_ctx* ctx, int splits, bool transA, int M, int N, int K, T 
 
 template <typename T>
 const TuneChoice& tune_choice(gfcc_ctx* ctx, bool transA, int M, int N, int K, const T* A,
-                              int64_t lda, const T* B, int64_t ldb) {
+                              int64_t lda, const T* B, int64_t ldb, bool mid = false) {
   constexpr int PBK = 128 / (int)sizeof(T);
   constexpr int VPC = 16 / (int)sizeof(T);
   const int64_t mt = (M + BM - 1) / BM, nt = (N + BN - 1) / BN;
@@ -365,13 +381,22 @@ const TuneChoice& tune_choice(gfcc_ctx* ctx, bool transA, int M, int N, int K, c
   ch.M = M;
   ch.N = N;
   ch.K = K;
+  if (mid) ch.splits = 1;
   if (!ctx->tune_on) return ctx->tune[key] = ch;
   const int64_t smax = std::max<int64_t>(1, (int64_t)K / (8 * PBK));
-  // split counts that fill r whole rounds of the 512 workgroups resident at once (two per CU)
-  std::vector<int> cand{0};
-  for (int64_t r : {1, 2, 4}) {
-    const int64_t sp = std::min<int64_t>(smax, std::max<int64_t>(1, r * 512 / tiles));
-    if (std::find(cand.begin(), cand.end(), (int)sp) == cand.end()) cand.push_back((int)sp);
+  std::vector<int> cand;
+  if (mid) {
+    // the plain kernel, then 2 .. 6 k ranges while the partials fit the scratch bound
+    cand.push_back(1);
+    for (int64_t sp = 2; sp <= std::min<int64_t>(6, smax); ++sp)
+      if ((size_t)M * N * sizeof(T) * sp <= MID_SCRATCH_MAX) cand.push_back((int)sp);
+  } else {
+    // split counts that fill r whole rounds of the 512 workgroups resident at once (two per CU)
+    cand.push_back(0);
+    for (int64_t r : {1, 2, 4}) {
+      const int64_t sp = std::min<int64_t>(smax, std::max<int64_t>(1, r * 512 / tiles));
+      if (std::find(cand.begin(), cand.end(), (int)sp) == cand.end()) cand.push_back((int)sp);
+    }
   }
   const bool log = std::getenv("GFCC_TUNE_LOG") != nullptr;  // diagnostic: every timing
   DevBuf scratch;
@@ -382,10 +407,11 @@ const TuneChoice& tune_choice(gfcc_ctx* ctx, bool transA, int M, int N, int K, c
   GFCC_HIP(hipEventCreate(&e1));
   double best = 1e300;
   for (int sp : cand) {
-    run_variant<T>(ctx, sp, transA, M, N, K, T(1), A, lda, B, ldb, T(0), scratch.as<T>(), N);
+    run_variant<T>(ctx, sp, transA, M, N, K, T(1), A, lda, B, ldb, T(0), scratch.as<T>(), N, mid);
     GFCC_HIP(hipEventRecord(e0, st));
     for (int r = 0; r < 2; ++r)
-      run_variant<T>(ctx, sp, transA, M, N, K, T(1), A, lda, B, ldb, T(0), scratch.as<T>(), N);
+      run_variant<T>(ctx, sp, transA, M, N, K, T(1), A, lda, B, ldb, T(0), scratch.as<T>(), N,
+                     mid);
     GFCC_HIP(hipEventRecord(e1, st));
     GFCC_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -395,7 +421,7 @@ const TuneChoice& tune_choice(gfcc_ctx* ctx, bool transA, int M, int N, int K, c
       std::fprintf(stderr, "[gfcc autotune] %s M=%d N=%d K=%d transA=%d splits=%d: %.1f us\n",
                    sizeof(T) == 8 ? "f64" : "f32", M, N, K, transA ? 1 : 0, sp, us);
     }
-    if (sp == 0) ch.generic_us = us;
+    if (sp == (mid ? 1 : 0)) ch.generic_us = us;
     if (us < best) {
       best = us;
       ch.splits = sp;
@@ -414,14 +440,21 @@ void gemm(gfcc_ctx* ctx, bool transA, bool transB, int M, int N, int K, T alpha,
           int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc, int batch,
           int64_t sA, int64_t sB, int64_t sC) {
   // a large transposed B ([N][K], contiguous; the operator build's l2 t2^T and oovv tau^T) is
-  // transposed once into a temporary so that the product takes the row-major paths below
+  // transposed once into the context's transpose workspace so that the product takes the
+  // row-major paths below (stream order protects the workspace until the product has read it)
   if (transB && batch == 1 && sizeof(T) == 8 && ldb == K && (int64_t)K * N >= (1 << 20) &&
       N < 65536 * 32) {
-    DevBuf bt;
-    bt.alloc(sizeof(T) * (size_t)K * N);
-    transpose2d(ctx, reinterpret_cast<const double*>(B), N, K, bt.as<double>());
-    gemm<T>(ctx, transA, false, M, N, K, alpha, A, lda, bt.as<T>(), N, beta, C, ldc);
-    GFCC_HIP(hipStreamSynchronize(ctx->stream));  // the temporary is freed on return
+    ws_ensure(ctx, ctx->ws_trans, sizeof(T) * (size_t)K * N);
+    transpose2d(ctx, reinterpret_cast<const double*>(B), N, K, ctx->ws_trans.as<double>());
+    gemm<T>(ctx, transA, false, M, N, K, alpha, A, lda, ctx->ws_trans.as<T>(), N, beta, C, ldc);
+    return;
+  }
+  // mid-size products with a long K: plain pipelined kernel or split-K, as tuned
+  if (!transB && batch == 1 && M > 0 && N > 0 && tunable_mid(M, N, K, sizeof(T))) {
+    const TuneChoice& ch = tune_choice<T>(ctx, transA, M, N, K, A, lda, B, ldb, true);
+    const int pbk = 128 / (int)sizeof(T);
+    const int sp = (int)std::max<int64_t>(1, std::min<int64_t>(ch.splits, K / (8 * pbk)));
+    run_variant<T>(ctx, sp, transA, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, true);
     return;
   }
   // large single products with a row-major B go to the pipelined kernel

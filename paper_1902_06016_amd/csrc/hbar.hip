@@ -256,19 +256,84 @@ void first_order_t2(gfcc_ctx* ctx, int o, int v, const double* eps, const double
   GFCC_LAUNCH_CHECK();
 }
 
+namespace {
+
+// Device buffers are reused from build to build: the previous operator's pieces and the work
+// arrays of the previous build are taken back by size, so a rebuild of the same shape makes no
+// hipMalloc or hipFree (each of which waits for the device). Buffers not taken are freed at
+// the end of the build.
+void collect(OpPieces<double>& f, std::vector<DevBuf>& out) {
+  for (DevBuf* b : {&f.W1, &f.W4c, &f.Woo, &f.Vp, &f.Weff, &f.W1V, &f.W4, &f.T2p})
+    if (b->p) out.push_back(std::move(*b));
+}
+void collect(OpPieces<float>& f, std::vector<DevBuf>& out) {
+  for (DevBuf* b : {&f.W1, &f.W4c, &f.Woo, &f.Vp, &f.Weff, &f.W1V, &f.W4, &f.T2p})
+    if (b->p) out.push_back(std::move(*b));
+}
+void collect(Operator& op, std::vector<DevBuf>& out) {
+  collect(op.f64, out);
+  collect(op.f32, out);
+  for (DevBuf* b : {&op.Vp_bf16, &op.T2p_bf16, &op.WeffT, &op.W1T, &op.W4cT, &op.WooT, &op.VpT,
+                    &op.diag, &op.Crows, &op.pairlut, &op.Foo, &op.Fov, &op.Fvv, &op.Woooo,
+                    &op.Wooov, &op.Wovvo, &op.Wovoo})
+    if (b->p) out.push_back(std::move(*b));
+}
+
+struct BuildBuffers {
+  std::vector<DevBuf> avail;       // reusable buffers (freed when the build ends)
+  std::vector<DevBuf>* keep_pool;  // where this build's work arrays go for the next build
+  void* take(DevBuf& b, size_t bytes) {
+    for (size_t i = 0; i < avail.size(); ++i)
+      if (avail[i].bytes == bytes) {
+        b = std::move(avail[i]);
+        avail.erase(avail.begin() + (std::ptrdiff_t)i);
+        return b.p;
+      }
+    b.alloc(bytes);
+    return b.p;
+  }
+};
+
+// a work array of the build, handed to the next build when it goes out of scope
+struct WorkBuf {
+  std::vector<DevBuf>* pool;
+  DevBuf b;
+  explicit WorkBuf(BuildBuffers& bb) : pool(bb.keep_pool) {}
+  WorkBuf(const WorkBuf&) = delete;
+  WorkBuf& operator=(const WorkBuf&) = delete;
+  ~WorkBuf() {
+    if (b.p) pool->push_back(std::move(b));
+  }
+};
+
+// work arrays above this total are not kept between builds
+constexpr size_t BUILD_POOL_MAX = size_t(8) << 30;
+
+}  // namespace
+
 void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double* t1,
                     const double* t2, const double* l1, const double* l2, const double* oooo,
                     const double* ooov, const double* oovv, const double* ovvo,
                     const double* ovvv, int keep) {
   Operator& op = ctx->op;
   op.built = false;
+  BuildBuffers bb;
+  bb.avail = std::move(ctx->build_pool);
+  ctx->build_pool.clear();
+  bb.keep_pool = &ctx->build_pool;
+  collect(op, bb.avail);
   op = Operator();
   const int64_t O = o, V = v;
   const int64_t P = O * (O - 1) / 2, PV = P * V, OV = O * V, D = O + PV;
   op.o = o; op.v = v; op.P = P; op.PV = PV; op.OV = OV; op.D = D; op.keep = keep;
   const int64_t o2 = O * O, v2 = V * V, o2v2 = o2 * v2, o3v = o2 * O * V;
   hipStream_t st = ctx->stream;
-  auto B = [](DevBuf& b, int64_t n) { b.alloc((size_t)n * sizeof(double)); return b.as<double>(); };
+  auto B = [&bb](DevBuf& b, int64_t n) {
+    return static_cast<double*>(bb.take(b, (size_t)n * sizeof(double)));
+  };
+  auto BW = [&bb](WorkBuf& w, int64_t n) {
+    return static_cast<double*>(bb.take(w.b, (size_t)n * sizeof(double)));
+  };
 
   double* Foo = B(op.Foo, o2);
   double* Fov = B(op.Fov, OV);
@@ -278,13 +343,13 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
   double* Wovvo = B(op.Wovvo, o2v2);
   double* Wovoo = B(op.Wovoo, o3v);
 
-  DevBuf b_tau, b_P1, b_Q, b_K6, b_tmp1, b_tmp2;
-  double* tau = B(b_tau, o2v2);
-  double* P1 = B(b_P1, o2v2);    // <mn||ef> as [m][e][n][f]
-  double* Q = B(b_Q, o2v2);
-  double* K6 = B(b_K6, o2v2);
-  double* T1 = B(b_tmp1, std::max<int64_t>(o2v2, o3v));
-  double* T2b = B(b_tmp2, std::max<int64_t>(o2v2, o3v));
+  WorkBuf b_tau(bb), b_P1(bb), b_Q(bb), b_K6(bb), b_tmp1(bb), b_tmp2(bb);
+  double* tau = BW(b_tau, o2v2);
+  double* P1 = BW(b_P1, o2v2);    // <mn||ef> as [m][e][n][f]
+  double* Q = BW(b_Q, o2v2);
+  double* K6 = BW(b_K6, o2v2);
+  double* T1 = BW(b_tmp1, std::max<int64_t>(o2v2, o3v));
+  double* T2b = BW(b_tmp2, std::max<int64_t>(o2v2, o3v));
 
   hipLaunchKernelGGL(tau_kernel, dim3(grid_for(o2v2)), dim3(256), 0, st, t1, t2, o, v, tau);
   GFCC_LAUNCH_CHECK();
@@ -307,9 +372,9 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
   gemm<double>(ctx, false, true, v, v, (int)(o2 * V), -0.5, T1, o2 * V, T2b, o2 * V, 0.0, Fvv, v);
   {
     // Y[(ae)][m] = sum_f ovvv[m][a][e][f] t1[m][f]  (batched over m), then Fvv -= Y . 1
-    DevBuf b_y, b_one;
-    double* Y = B(b_y, v2 * O);
-    double* ones = B(b_one, O);
+    WorkBuf b_y(bb), b_one(bb);
+    double* Y = BW(b_y, v2 * O);
+    double* ones = BW(b_one, O);
     fill(ctx, ones, O, 1.0);
     gemm<double>(ctx, false, false, (int)v2, 1, v, 1.0, ovvv, V, t1, 1, 0.0, Y, O, o,
                  V * v2, V, 1);
@@ -317,7 +382,6 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
     hipLaunchKernelGGL(add_diag_kernel, dim3(blocks_for(v, 256)), dim3(256), 0, st, Fvv, v,
                        eps + o);
     GFCC_LAUNCH_CHECK();
-    GFCC_HIP(hipStreamSynchronize(st));
   }
 
   // ---- W_mnij = <mn||ij> + P(ij) t_j^e <mn||ie> + 1/2 tau_ij^ef <mn||ef>
@@ -362,8 +426,8 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
   perm(ctx, ooov, {O, O, O, V}, {O * O * V, V, O * V, 1}, T1);      // A5[m][i][n][e]
   perm(ctx, t2, {O, V, O, V}, {v2, 1, O * v2, V}, T2b);              // B5[n][e][j][b]
   {
-    DevBuf b_y5;
-    double* Y5 = B(b_y5, o3v);
+    WorkBuf b_y5(bb);
+    double* Y5 = BW(b_y5, o3v);
     gemm<double>(ctx, false, false, (int)o2, (int)OV, (int)OV, 1.0, T1, OV, T2b, OV, 0.0, Y5, OV);
     perm(ctx, Y5, {O, V, O, O}, {O * OV, 1, OV, V}, Wovoo, 1.0, 1.0);
     perm(ctx, Y5, {O, V, O, O}, {O * OV, 1, V, OV}, Wovoo, -1.0, 1.0);
@@ -371,17 +435,16 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
     GFCC_HIP(hipMemcpyAsync(T2b, ovvo, sizeof(double) * o2v2, hipMemcpyDeviceToDevice, st));
     perm(ctx, K6, {O, V, V, O}, {V * OV, 1, OV, V}, T2b, -1.0, 1.0);
     // Y6[(mb)][i][j] = sum_e t1[i][e] Z[(mb)][e][j]   (batched over (mb))
-    DevBuf b_y6;
-    double* Y6 = B(b_y6, OV * o2);
+    WorkBuf b_y6(bb);
+    double* Y6 = BW(b_y6, OV * o2);
     gemm<double>(ctx, false, false, o, o, v, 1.0, t1, V, T2b, O, 0.0, Y6, O, (int)OV, 0, V * O, o2);
     perm(ctx, Y6, {O, V, O, O}, {V * o2, o2, O, 1}, Wovoo, 1.0, 1.0);
     perm(ctx, Y6, {O, V, O, O}, {V * o2, o2, 1, O}, Wovoo, -1.0, 1.0);
-    GFCC_HIP(hipStreamSynchronize(st));
   }
 
   // ---- operator pieces
   {
-    op.pairlut.alloc(sizeof(int) * o2);
+    bb.take(op.pairlut, sizeof(int) * o2);
     hipLaunchKernelGGL(pairlut_kernel, dim3(blocks_for(o2, 256)), dim3(256), 0, st, o,
                        op.pairlut.as<int>());
     GFCC_LAUNCH_CHECK();
@@ -411,12 +474,11 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
       double* W1V = B(f.W1V, (O + V) * D);
       GFCC_HIP(hipMemcpyAsync(W1V, W1, sizeof(double) * O * D, hipMemcpyDeviceToDevice, st));
       fill(ctx, W1V + O * D, V * D, 0.0);
-      DevBuf bt;
-      double* vt = B(bt, V * PV);
+      WorkBuf bt(bb);
+      double* vt = BW(bt, V * PV);
       transpose2d(ctx, Vp, PV, V, vt);  // [v][PV]
       GFCC_HIP(hipMemcpy2DAsync(W1V + O * D + O, sizeof(double) * D, vt, sizeof(double) * PV,
                                 sizeof(double) * PV, V, hipMemcpyDeviceToDevice, st));
-      GFCC_HIP(hipStreamSynchronize(st));
     }
     // Weff is followed by zero padding read by the ovvo kernels past the last k slab
     const int64_t wpad = ovvo_pad_bytes(OV) / (int64_t)sizeof(double);
@@ -431,10 +493,10 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
     GFCC_LAUNCH_CHECK();
 
     // c_q rows
-    DevBuf b7, b8, b9;
-    double* Y7 = B(b7, o2);
-    double* Y8 = B(b8, o2);
-    double* Y9 = B(b9, o2 * O * V);
+    WorkBuf b7(bb), b8(bb), b9(bb);
+    double* Y7 = BW(b7, o2);
+    double* Y8 = BW(b8, o2);
+    double* Y9 = BW(b9, o2 * O * V);
     gemm<double>(ctx, false, true, o, o, (int)(O * v2), 1.0, l2, O * v2, t2, O * v2, 0.0, Y7, O);
     gemm<double>(ctx, false, true, o, o, v, 1.0, l1, V, t1, V, 0.0, Y8, O);
     gemm<double>(ctx, false, false, o, v, v, 1.0, t1, V, l2, V, 0.0, Y9, V, (int)o2, 0, v2, O * V);
@@ -442,11 +504,12 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
     hipLaunchKernelGGL(crows_kernel, dim3(grid_for(O * D)), dim3(256), 0, st, Y7, Y8, Y9, l1, o,
                        v, D, C);
     GFCC_LAUNCH_CHECK();
-    GFCC_HIP(hipStreamSynchronize(st));
 
     if (keep & GFCC_KEEP_FP32) {
       OpPieces<float>& g = op.f32;
-      auto F = [](DevBuf& b, int64_t n) { b.alloc((size_t)n * sizeof(float)); return b.as<float>(); };
+      auto F = [&bb](DevBuf& b, int64_t n) {
+        return static_cast<float*>(bb.take(b, (size_t)n * sizeof(float)));
+      };
       cast_f64_f32(ctx, W1, F(g.W1, O * D), O * D);
       cast_f64_f32(ctx, W4c, F(g.W4c, PV * (O + V)), PV * (O + V));
       cast_f64_f32(ctx, Woo, F(g.Woo, P * ldw), P * ldw);
@@ -456,33 +519,34 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
       cast_f64_f32(ctx, Weff, Wf, OV * OV);
       fill_f(ctx, Wf + OV * OV, wpadf, 0.0f);
       // bf16 three-body operands: Vp and -t2 packed as [(ij)a][d]
-      op.Vp_bf16.alloc((size_t)PV * V * sizeof(__hip_bfloat16));
+      bb.take(op.Vp_bf16, (size_t)PV * V * sizeof(__hip_bfloat16));
       cast_f64_bf16(ctx, Vp, op.Vp_bf16.as<__hip_bfloat16>(), PV * V);
-      DevBuf bt;
-      double* t2p = B(bt, PV * V);
+      WorkBuf bt(bb);
+      double* t2p = BW(bt, PV * V);
       // -t2 packed rows = columns o.. of W4c
       {
         int64_t d4[4] = {1, 1, PV, V};
         int64_t s4[4] = {0, 0, O + V, 1};
         permute4(ctx, W4c + o, d4, s4, t2p, 1.0, 0.0);
       }
-      op.T2p_bf16.alloc((size_t)PV * V * sizeof(__hip_bfloat16));
+      bb.take(op.T2p_bf16, (size_t)PV * V * sizeof(__hip_bfloat16));
       cast_f64_bf16(ctx, t2p, op.T2p_bf16.as<__hip_bfloat16>(), PV * V);
       // FP32 W4 = first o columns of W4c (the three-body columns go through bf16)
       {
-        DevBuf bw;
-        double* w4 = B(bw, PV * O);
+        WorkBuf bw(bb);
+        double* w4 = BW(bw, PV * O);
         int64_t d4[4] = {1, 1, PV, O};
         int64_t s4[4] = {0, 0, O + V, 1};
         permute4(ctx, W4c, d4, s4, w4, 1.0, 0.0);
         cast_f64_f32(ctx, w4, F(g.W4, PV * O), PV * O);
-        GFCC_HIP(hipStreamSynchronize(st));
       }
-      GFCC_HIP(hipStreamSynchronize(st));
     }
   }
   GFCC_HIP(hipStreamSynchronize(st));
   op.built = true;
+  size_t pooled = 0;
+  for (const DevBuf& b : ctx->build_pool) pooled += b.bytes;
+  if (pooled > BUILD_POOL_MAX) ctx->build_pool.clear();
 }
 
 }  // namespace gfcc
