@@ -134,7 +134,9 @@ gfcc_status sigma_apply(gfcc_ctx* ctx, int nrhs, const void* x, void* y, int tra
  * build's largest products) are timed as the plain pipelined kernel and with 2 to 6 k ranges,
  * which moves the partly filled last round of workgroups. Off: the generic kernel with its
  * heuristic split count for the first kind, the plain pipelined kernel for the second.
- * Results agree to rounding either way.
+ * enable = 2 skips the timing and takes the most split candidate of every class (so that
+ * tests reach the split-K paths). Results agree to rounding in every mode. EINVAL for
+ * another value of enable.
  */
 gfcc_status gfcc_autotune(gfcc_ctx* ctx, int enable);
 
@@ -281,8 +283,10 @@ gfcc_status mor_destroy(gfcc_mor* model);
 
 /*
  * spectral_function -- A(omega_w) = (1/pi) sum_p Im G[w][p][p] for G complex128
- * [nw][np][np] (device if is_device, else host). A_out [nw] (host). The sign makes the
- * peaks positive for the operator (omega - i eta + Hbar_N).
+ * [nw][np][np] (device if is_device, else host: copied to the device first; the sum runs on
+ * the device either way, on the null stream). A_out [nw] (host). The sign makes the peaks
+ * positive for the operator (omega - i eta + Hbar_N). nw = 0 or np = 0 is accepted (A = 0
+ * for np = 0); EINVAL for negative sizes or a null pointer that is needed.
  */
 gfcc_status spectral_function(int nw, int np, const void* G, int is_device, double* A_out);
 

@@ -172,8 +172,8 @@ gfcc_status build_hbar_first_order(gfcc_ctx* ctx, int o, int v, const double* ep
 }
 
 gfcc_status gfcc_autotune(gfcc_ctx* ctx, int enable) {
-  if (!ctx) return GFCC_EINVAL;
-  ctx->tune_on = enable != 0;
+  if (!ctx || enable < 0 || enable > 2) return GFCC_EINVAL;
+  ctx->tune_mode = enable;
   ctx->tune.clear();
   return GFCC_OK;
 }

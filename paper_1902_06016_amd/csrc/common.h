@@ -149,7 +149,7 @@ struct gfcc_ctx {
   std::vector<gfcc::DevBuf> build_pool;  // operator-build buffers kept for the next build
   gfcc::DevBuf zrow;        // zeros (read for structurally zero rows of the ovvo operand)
   gfcc::TimerSlot timers[2];
-  bool tune_on = true;
+  int tune_mode = 1;        // 0 off, 1 timed, 2 most split variant without timing
   std::map<gfcc::TuneKey, gfcc::TuneChoice> tune;
   std::vector<hipEvent_t> event_pool;
 };

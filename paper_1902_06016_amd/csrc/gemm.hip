@@ -382,7 +382,7 @@ const TuneChoice& tune_choice(gfcc_ctx* ctx, bool transA, int M, int N, int K, c
   ch.N = N;
   ch.K = K;
   if (mid) ch.splits = 1;
-  if (!ctx->tune_on) return ctx->tune[key] = ch;
+  if (ctx->tune_mode == 0) return ctx->tune[key] = ch;
   const int64_t smax = std::max<int64_t>(1, (int64_t)K / (8 * PBK));
   std::vector<int> cand;
   if (mid) {
@@ -397,6 +397,10 @@ const TuneChoice& tune_choice(gfcc_ctx* ctx, bool transA, int M, int N, int K, c
       const int64_t sp = std::min<int64_t>(smax, std::max<int64_t>(1, r * 512 / tiles));
       if (std::find(cand.begin(), cand.end(), (int)sp) == cand.end()) cand.push_back((int)sp);
     }
+  }
+  if (ctx->tune_mode == 2) {  // no timing: the most split variant (exercises split-K)
+    ch.splits = *std::max_element(cand.begin(), cand.end());
+    return ctx->tune[key] = ch;
   }
   const bool log = std::getenv("GFCC_TUNE_LOG") != nullptr;  // diagnostic: every timing
   DevBuf scratch;

@@ -1187,24 +1187,27 @@ gfcc_status gfcc_grad_eps(gfcc_ctx* ctx, int nw, const double* weight, int np, c
 }
 
 gfcc_status spectral_function(int nw, int np, const void* G, int is_device, double* A_out) {
-  if (nw < 0 || np < 0 || (nw > 0 && (!G || !A_out))) return GFCC_EINVAL;
+  if (nw < 0 || np < 0 || (nw > 0 && (!A_out || (np > 0 && !G)))) return GFCC_EINVAL;
   if (nw == 0) return GFCC_OK;
-  if (!is_device) {
-    const double* g = static_cast<const double*>(G);
-    for (int w = 0; w < nw; ++w) {
-      double s = 0.0;
-      for (int k = 0; k < np; ++k) s += g[2 * (((int64_t)w * np + k) * np + k) + 1];
-      A_out[w] = s / 3.14159265358979323846;
-    }
-    return GFCC_OK;
-  }
+  // a host G is copied to the device: the sum runs in the same kernel either way
+  const size_t gbytes = sizeof(double2) * (size_t)nw * np * np;
   double* dA = nullptr;
+  void* dG = nullptr;
   if (hipMalloc(&dA, sizeof(double) * nw) != hipSuccess) return GFCC_ENOMEM;
-  hipLaunchKernelGGL(gfcc::spectral_kernel, dim3((nw + 255) / 256), dim3(256), 0, nullptr,
-                     static_cast<const double2*>(G), nw, np, dA);
-  hipError_t e = hipGetLastError();
+  hipError_t e = hipSuccess;
+  if (!is_device && gbytes > 0) {
+    e = hipMalloc(&dG, gbytes);
+    if (e == hipSuccess) e = hipMemcpy(dG, G, gbytes, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(gfcc::spectral_kernel, dim3((nw + 255) / 256), dim3(256), 0, nullptr,
+                       static_cast<const double2*>(is_device ? G : dG), nw, np, dA);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) e = hipMemcpy(A_out, dA, sizeof(double) * nw, hipMemcpyDeviceToHost);
   (void)hipFree(dA);
+  if (dG) (void)hipFree(dG);
+  if (e == hipErrorOutOfMemory) return GFCC_ENOMEM;
   return e == hipSuccess ? GFCC_OK : GFCC_EHIP;
 }
 

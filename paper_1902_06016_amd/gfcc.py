@@ -277,7 +277,8 @@ class Context:
         return out
 
     # ------------------------------------------------------------- autotuner
-    def autotune(self, enable: bool = True):
+    def autotune(self, enable=True):
+        """enable: False/0 off, True/1 timed, 2 the most split variant of every class untimed."""
         self._check(lib.gfcc_autotune(self.h, int(enable)))
 
     def autotune_entries(self):

@@ -43,3 +43,35 @@ def test_sigma_with_and_without_the_tuner(gpu_ctx, transpose):
     # a fresh tuning may pick another variant; both agree to rounding
     assert np.abs(ys[0] - ys[2]).max() <= 1e-13 * scale
     gpu_ctx.autotune(True)
+
+
+def test_build_products_in_every_tuner_mode(gpu_ctx):
+    """o=24, v=90: the O(o^3 v^3) product K6 (2160^3) has 289 tiles, the class tuned between the
+    plain pipelined kernel and 2-6 k ranges; Wovoo and Y5 (85 tiles) are split-K products. The
+    blocks match the oracle with the tuner off (plain kernels), untimed at the most split
+    variants (mode 2) and timed."""
+    print("[autotune build modes]", flush=True)
+    o, v = 24, 90
+    prob = synth.make_problem(o, v, 21)
+    prob.t1 = synth.normal(21, 9, o * v, 0.1).reshape(o, v)
+    hb = ohbar.build_hbar_from_problem(prob)
+    blocks = {}
+    for mode in (0, 2, 1):
+        gpu_ctx.autotune(mode)
+        gpu_ctx.build_from_problem(prob)
+        got = {n: gpu_ctx.export(n).cpu().numpy() for n in ("Foo", "Fvv", "Woooo", "Wovvo",
+                                                             "Wovoo")}
+        for name, g in got.items():
+            ref = getattr(hb, name)
+            err = np.abs(g - ref).max()
+            assert err <= 1e-13 * max(1.0, np.abs(ref).max()), (mode, name, err)
+        if mode == 2:
+            ents = gpu_ctx.autotune_entries()
+            k6 = [e for e in ents if e["M"] == e["N"] == e["K"] == o * v]
+            assert k6 and k6[0]["splits"] > 1
+            assert any(e["splits"] > 1 and e["M"] == o * v and e["N"] == o * o for e in ents)
+        blocks[mode] = got
+    for name in blocks[0]:
+        scale = np.abs(blocks[0][name]).max()
+        assert np.abs(blocks[2][name] - blocks[0][name]).max() <= 1e-13 * max(1.0, scale)
+    gpu_ctx.autotune(True)

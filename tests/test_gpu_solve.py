@@ -123,3 +123,46 @@ def test_errors(gpu_ctx):
     with pytest.raises(gfcc.GfccError) as e:
         gpu_ctx.build_hbar_operands(4, 3, *bad)
     assert e.value.status == gfcc.GFCC_EINVAL
+
+
+def test_empty_inputs(gpu_ctx):
+    """No frequencies, no orbitals, no right-hand sides: every entry point returns empty
+    results without launching work."""
+    print("[empty inputs]", flush=True)
+    prob = synth.make_problem(4, 5, 2)
+    gpu_ctx.build_from_problem(prob)
+    D = gpu_ctx.D
+    r = gpu_ctx.gfcc_solve([], [0, 1], 0.01)
+    assert tuple(r.G.shape) == (0, 2, 2) and r.iters.size == 0
+    r = gpu_ctx.gfcc_solve([-0.5, -0.4], [], 0.01)
+    assert tuple(r.G.shape) == (2, 0, 0)
+    assert np.array_equal(gfcc.spectral_function(r.G), np.zeros(2))
+    r = gpu_ctx.gfcc_solve_diis([], [0], 0.01)
+    assert tuple(r.G.shape) == (0, 1, 1)
+    y = gpu_ctx.sigma_apply(torch.zeros((0, D), dtype=torch.complex128, device="cuda"))
+    assert tuple(y.shape) == (0, D)
+    assert gfcc.spectral_function(np.zeros((0, 3, 3), dtype=complex)).shape == (0,)
+    m = gpu_ctx.mor_build([-0.6, -0.4], [2, 3], 0.01)
+    G, res = m.eval([])
+    assert tuple(G.shape) == (0, 2, 2) and res.size == 0
+    assert tuple(m.lift([]).shape) == (0, 2, D)
+    m.close()
+
+
+def test_spectral_function_host_and_device_agree(gpu_ctx):
+    """A(omega) from a host G and from the same G on the device: the same kernel, the same
+    bits; checked against (1/pi) sum_p Im G_pp written out."""
+    print("[spectral host/device]", flush=True)
+    rng = np.random.default_rng(3)
+    G = rng.standard_normal((37, 5, 5)) + 1j * rng.standard_normal((37, 5, 5))
+    Ah = gfcc.spectral_function(G)
+    Ad = gfcc.spectral_function(torch.from_numpy(G).cuda())
+    assert np.array_equal(Ah, Ad)
+    ref = np.array([sum(G[w, k, k].imag for k in range(5)) / np.pi for w in range(37)])
+    assert np.abs(Ah - ref).max() <= 1e-15 * np.abs(ref).max()
+    # off-diagonal entries do not enter
+    G2 = np.zeros((3, 2, 2), dtype=np.complex128)
+    G2[:, 0, 0] = 1j * np.pi
+    G2[:, 1, 1] = 2j * np.pi
+    G2[:, 0, 1] = 5j
+    assert np.allclose(gfcc.spectral_function(G2), 3.0)
