@@ -30,9 +30,12 @@ static void check_build_args(gfcc_ctx* ctx, const char* fn, int o, int v, int pr
     GFCC_REQUIRE(a.p != nullptr, GFCC_EINVAL, std::string(fn) + ": null pointer");
   GFCC_REQUIRE((precision_mask & ~(GFCC_KEEP_FP64 | GFCC_KEEP_FP32 | GFCC_KEEP_TRANSPOSE)) == 0,
                GFCC_EINVAL, std::string(fn) + ": unknown precision_mask bits");
+  std::vector<std::pair<const double*, int64_t>> list;
+  for (auto& a : arrs) list.emplace_back(a.p, a.n);
+  const std::vector<int64_t> bad = count_nonfinite(ctx, list);
+  size_t k = 0;
   for (auto& a : arrs)
-    GFCC_REQUIRE(count_nonfinite(ctx, a.p, a.n) == 0, GFCC_EINVAL,
-                 std::string(fn) + ": non-finite entries in " + a.name);
+    GFCC_REQUIRE(bad[k++] == 0, GFCC_EINVAL, std::string(fn) + ": non-finite entries in " + a.name);
 }
 
 static hipEvent_t event_get(gfcc_ctx* ctx) {

@@ -11,6 +11,7 @@
 #include <stdexcept>
 #include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/gfcc.h"
@@ -227,7 +228,9 @@ void transpose2d(gfcc_ctx* ctx, const double* src, int64_t rows, int64_t cols, d
 void ctranspose(gfcc_ctx* ctx, const void* src, int64_t rows, int64_t cols, int64_t lds,
                 void* dst, int64_t ldd);
 // count of non-finite entries of a device array (synchronises)
-int64_t count_nonfinite(gfcc_ctx* ctx, const double* p, int64_t n);
+// number of non-finite entries of each device array (one synchronisation for all)
+std::vector<int64_t> count_nonfinite(gfcc_ctx* ctx,
+                                     const std::vector<std::pair<const double*, int64_t>>& arrs);
 
 // -------------------------------------------------------------------- sigma products
 // Y[D][nc] = Hbar_N X[D][nc] (or Hbar_N^T). Real columns; X and Y D-major with ld = nc.

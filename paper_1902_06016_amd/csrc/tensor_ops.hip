@@ -89,7 +89,8 @@ __global__ void nonfinite_kernel(const double* __restrict__ p, int64_t n,
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ void sum_u64_kernel(unsigned long long* __restrict__ partial, int n) {
+__global__ void sum_u64_kernel(const unsigned long long* __restrict__ partial, int n,
+                               unsigned long long* __restrict__ out) {
   __shared__ unsigned long long red[256];
   unsigned long long local = 0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) local += partial[i];
@@ -99,7 +100,7 @@ __global__ void sum_u64_kernel(unsigned long long* __restrict__ partial, int n) 
     if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[0] = red[0];
+  if (threadIdx.x == 0) *out = red[0];
 }
 
 inline unsigned grid_for(int64_t n) {
@@ -172,19 +173,31 @@ void transpose2d(gfcc_ctx* ctx, const double* src, int64_t rows, int64_t cols, d
   GFCC_LAUNCH_CHECK();
 }
 
-int64_t count_nonfinite(gfcc_ctx* ctx, const double* p, int64_t n) {
-  if (n == 0) return 0;
+std::vector<int64_t> count_nonfinite(gfcc_ctx* ctx,
+                                     const std::vector<std::pair<const double*, int64_t>>& arrs) {
   const int nb = 1024;
-  ws_ensure(ctx, ctx->ws_e, sizeof(unsigned long long) * nb);
+  const size_t na = arrs.size();
+  std::vector<int64_t> out(na, 0);
+  if (na == 0) return out;
+  // per-array partial counts, then one total per array; one copy and one wait for all
+  ws_ensure(ctx, ctx->ws_e, sizeof(unsigned long long) * (size_t)(nb + 1) * na);
   auto* part = ctx->ws_e.as<unsigned long long>();
-  hipLaunchKernelGGL(nonfinite_kernel, dim3(nb), dim3(256), 0, ctx->stream, p, n, part);
-  GFCC_LAUNCH_CHECK();
-  hipLaunchKernelGGL(sum_u64_kernel, dim3(1), dim3(256), 0, ctx->stream, part, nb);
-  GFCC_LAUNCH_CHECK();
-  unsigned long long h = 0;
-  GFCC_HIP(hipMemcpyAsync(&h, part, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+  auto* tot = part + (size_t)nb * na;
+  for (size_t k = 0; k < na; ++k) {
+    const int64_t n = arrs[k].second;
+    hipLaunchKernelGGL(nonfinite_kernel, dim3(n > 0 ? nb : 1), dim3(256), 0, ctx->stream,
+                       arrs[k].first, n, part + (size_t)k * nb);
+    GFCC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(sum_u64_kernel, dim3(1), dim3(256), 0, ctx->stream, part + (size_t)k * nb,
+                       n > 0 ? nb : 1, tot + k);
+    GFCC_LAUNCH_CHECK();
+  }
+  std::vector<unsigned long long> h(na);
+  GFCC_HIP(hipMemcpyAsync(h.data(), tot, sizeof(unsigned long long) * na, hipMemcpyDeviceToHost,
+                          ctx->stream));
   GFCC_HIP(hipStreamSynchronize(ctx->stream));
-  return (int64_t)h;
+  for (size_t k = 0; k < na; ++k) out[k] = (int64_t)h[k];
+  return out;
 }
 
 }  // namespace gfcc
