@@ -578,6 +578,20 @@ struct GmresBlock {
   float *Uf = nullptr, *Sf = nullptr;
   BlockState s;
   int nblk_rows = 1, nbrows_y = 1;
+  // convergence flags copied to pinned host memory after every Arnoldi step, for the
+  // one-step-late check of small blocks
+  int* hflags = nullptr;
+  int hflags_nb = 0;
+  hipEvent_t flag_ev[2] = {nullptr, nullptr};
+
+  GmresBlock() = default;
+  GmresBlock(const GmresBlock&) = delete;
+  GmresBlock& operator=(const GmresBlock&) = delete;
+  ~GmresBlock() {
+    if (hflags) (void)hipHostFree(hflags);
+    for (hipEvent_t e : flag_ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 
   void setup(gfcc_ctx* c, int nb_, int m_, int prec, bool tr) {
     ctx = c;
@@ -644,6 +658,16 @@ struct GmresBlock {
       Uf = mem_f32.as<float>();
       Sf = Uf + vec * 2;
     }
+    if (nb > hflags_nb) {
+      if (hflags) GFCC_HIP(hipHostFree(hflags));
+      hflags = nullptr;
+      hflags_nb = 0;
+      GFCC_HIP(hipHostMalloc(reinterpret_cast<void**>(&hflags), sizeof(int) * 2 * (size_t)nb,
+                             hipHostMallocDefault));
+      hflags_nb = nb;
+    }
+    for (hipEvent_t& e : flag_ev)
+      if (!e) GFCC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
 
   hipStream_t st() const { return ctx->stream; }
@@ -750,6 +774,10 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
   std::vector<double2> g0((size_t)nb * (m + 1));
   bool first = X0 == nullptr;
   const bool mixed = gb.precision != GFCC_FP64;
+  // small blocks (sigma work of a step below about 0.3 ms at 70 TF/s: 4 (ov)^2 o flops per
+  // complex right-hand side in the ovvo product) read the convergence flags one step late
+  const double ov = (double)ctx->op.OV;
+  const bool late = (double)nb * 4.0 * ov * ov * (double)ctx->op.o < 2e10;
   const double inner_rel = 1e-4;  // relative tolerance of a reduced-precision cycle
   bool have_res = false;  // R holds the residual of X from the Arnoldi relation of the last cycle
   bool unit_start = false;  // this cycle starts from V0 = e_p (forward, x = 0)
@@ -846,6 +874,24 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
                          gb.s.inv, ctx->op.diag.as<double>(), gb.z, D, nb,
                          gb.V + (int64_t)(k + 1) * D * nb, gb.U);
       GFCC_LAUNCH_CHECK();
+      if (late) {
+        // Step k is queued before the flags of step k - 1 are read, so the GPU does not wait
+        // for the host. When step k - 1 has stopped every right-hand side, step k only met
+        // inactive ones (their next basis vectors and inputs are zero, their state is left
+        // alone) and does not count.
+        GFCC_HIP(hipMemcpyAsync(gb.hflags + (size_t)(k & 1) * nb, gb.s.active, sizeof(int) * nb,
+                                hipMemcpyDeviceToHost, st));
+        GFCC_HIP(hipEventRecord(gb.flag_ev[k & 1], st));
+        if (k > 0) {
+          GFCC_HIP(hipEventSynchronize(gb.flag_ev[(k - 1) & 1]));
+          const int* f = gb.hflags + (size_t)((k - 1) & 1) * nb;
+          int any = 0;
+          for (int r = 0; r < nb; ++r) any |= f[r];
+          if (!any) break;
+        }
+        ksteps = k + 1;
+        continue;
+      }
       ksteps = k + 1;
       GFCC_HIP(hipMemcpyAsync(act.data(), gb.s.active, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
       GFCC_HIP(hipStreamSynchronize(st));
