@@ -37,6 +37,12 @@ def test_c1_sampled_parity_with_oracle(gpu_ctx, c1):
     res = gpu_ctx.gfcc_solve(om_all, ps, CFG1["eta"], tol=1e-12, restart=30, block=320)
     assert res.resid.max() <= 1e-12
     G = res.G.cpu().numpy()
+    # the benchmark's own tolerance (1e-10)
+    loose = gpu_ctx.gfcc_solve(om_all, ps, CFG1["eta"], tol=1e-10, restart=30, block=320)
+    GL = loose.G.cpu().numpy()
+    A1 = gfcc.spectral_function(loose.G)
+    A2 = gfcc.spectral_function(res.G)
+    amax = np.abs(A2).max()
     hb = ohbar.build_hbar_from_problem(prob)
     op = osolve.Operator(hb)
     C = np.stack([osig.c_vector(o, v, prob.t1, prob.t2, prob.l1, prob.l2, int(q)) for q in ps], 0)
@@ -47,11 +53,13 @@ def test_c1_sampled_parity_with_oracle(gpu_ctx, c1):
         err = np.abs(G[w_idx, :, k] - g).max() / np.abs(g).max()
         print(f"  omega={om_all[w_idx]:.3f} p={ps[k]} iters={it} rel err {err:.2e}", flush=True)
         assert err < 1e-10
-    # the benchmark's tolerance (1e-10) against the tight solve: A differs below 1e-9 relative
-    loose = gpu_ctx.gfcc_solve(om_all, ps, CFG1["eta"], tol=1e-10, restart=30, block=320)
-    A1 = gfcc.spectral_function(loose.G)
-    A2 = gfcc.spectral_function(res.G)
-    assert np.abs(A1 - A2).max() / np.abs(A2).max() < 1e-9
+        # at the benchmark's tolerance, the term (1/pi) Im G_pp that this orbital adds to A
+        # matches the oracle to 1e-10 of max |A| (the measure of the accuracy target)
+        eterm = abs((GL[w_idx, k, k] - g[k]).imag) / np.pi / amax
+        print(f"    tol 1e-10: A-term error {eterm:.2e} of max |A|", flush=True)
+        assert eterm < 1e-10
+    # and A over the whole grid at tol 1e-10 against tol 1e-12
+    assert np.abs(A1 - A2).max() / amax < 1e-10
 
 
 def test_c1_diis_matches_gmres(gpu_ctx, c1):
