@@ -169,7 +169,7 @@ def sigma_flops_per_rhs(o, v):
 def form_small(gfcc, torch):
     """The small case (o=10, v=20, D=910): 64 omega x 10 p, tol 1e-10. Latency-bound."""
     import synth
-    cfg = synth.CONFIGS[0]
+    cfg = synth.WORKLOADS["o10v20"]
     o, v = cfg["o"], cfg["v"]
     prob = synth.make_problem(o, v, cfg["seed"])
     dev = torch.device("cuda", 0)
@@ -301,7 +301,7 @@ def guess_small(gfcc, torch):
     """The same comparison on the small case, whose window lies next to the first pole, with
     models from 2 and 4 frequencies of the window."""
     import synth
-    cfg = synth.CONFIGS[0]
+    cfg = synth.WORKLOADS["o10v20"]
     o, v = cfg["o"], cfg["v"]
     prob = synth.make_problem(o, v, cfg["seed"])
     ctx = gfcc.Context(0)
@@ -362,7 +362,7 @@ def diis_fig3(gfcc, torch):
     eight-frequency reduced model built on a narrower window above them; 80 micro-iterations
     at most. Residual profiles are the worst over the orbitals p."""
     import synth
-    cfg = synth.CONFIGS[0]
+    cfg = synth.WORKLOADS["o10v20"]
     o, v = cfg["o"], cfg["v"]
     prob = synth.make_problem(o, v, cfg["seed"])
     ctx = gfcc.Context(0)
@@ -437,7 +437,7 @@ def pert_small(gfcc, torch):
     """Peak positions of A over a window that holds the poles (small case, [-1.6, -0.3] Ha,
     1301 points): full amplitudes against first-order ones."""
     import synth
-    cfg = synth.CONFIGS[0]
+    cfg = synth.WORKLOADS["o10v20"]
     o, v = cfg["o"], cfg["v"]
     prob = synth.make_problem(o, v, cfg["seed"])
     om = np.linspace(-1.6, -0.3, 1301)
@@ -557,7 +557,7 @@ def form_mixed(cfg, gfcc, torch):
         Am = gfcc.spectral_function(res[name][0].G)
         out[name]["A_max_rel_err_vs_fp64"] = float(np.abs(Am - Ad).max() / np.abs(Ad).max())
         out[name]["speedup_vs_fp64"] = res["fp64"][1] / res[name][1]
-    # kept at the top level for the configured form (FP32 with the bf16 three-body term)
+    # kept at the top level for the FP32 form with the bf16 three-body term
     out["A_max_rel_err_vs_fp64"] = out["fp32_bf16"]["A_max_rel_err_vs_fp64"]
     out["speedup_vs_fp64"] = out["fp32_bf16"]["speedup_vs_fp64"]
     del res
@@ -586,7 +586,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--block", type=int, default=320)
     ap.add_argument("--restart", type=int, default=30)
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--workload", default="o42v186", help="plain-path workload (synth.WORKLOADS)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-p", type=int, default=2)
     ap.add_argument("--sigma-only", type=int, default=0,
@@ -607,7 +607,7 @@ def main():
     import synth
     from paper_1902_06016_amd import gfcc
 
-    cfg = synth.CONFIGS[args.config]
+    cfg = synth.WORKLOADS[args.workload]
     o, v = cfg["o"], cfg["v"]
     omega = synth.omega_grid(cfg["omega"])
     ps = synth.valence_p(o, cfg["np"])
@@ -722,7 +722,7 @@ def main():
     if "small" in forms:
         out["small"] = form_small(gfcc, torch)
     if "mor" in forms:
-        out["mor"] = form_mor(ctx, prob, synth.CONFIGS[2], gfcc)
+        out["mor"] = form_mor(ctx, prob, synth.WORKLOADS["o42v186_mor"], gfcc)
     if "guess" in forms:
         out["guess"] = form_guess(ctx, cfg, gfcc)
     if "diis" in forms:
@@ -730,7 +730,7 @@ def main():
     if "pert" in forms:
         out["pert"] = form_pert(cfg, gfcc, inputs, A, t_build)
     if "adjoint" in forms:
-        out["adjoint"] = form_adjoint(ctx, synth.CONFIGS[4], gfcc, inputs)
+        out["adjoint"] = form_adjoint(ctx, synth.WORKLOADS["o42v186_adjoint"], gfcc, inputs)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample) ...")
         G = res.G.cpu().numpy()
@@ -743,7 +743,7 @@ def main():
     if "mixed" in forms:
         del inputs
         torch.cuda.empty_cache()
-        out["mixed"] = form_mixed(synth.CONFIGS[3], gfcc, torch)
+        out["mixed"] = form_mixed(synth.WORKLOADS["o70v260_mixed"], gfcc, torch)
     print(json.dumps(out))
 
 

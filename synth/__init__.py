@@ -150,15 +150,17 @@ def make_problem(o: int, v: int, seed: int, t1_sigma: float = T1_SIGMA,
     return p
 
 
-# Workload shapes (spin orbitals) and grids of the five standard configurations.
-CONFIGS = {
-    0: dict(o=10, v=20, seed=0, omega=(-1.0, -0.3, 64), eta=0.01, np=10, tol=1e-10),
-    1: dict(o=42, v=186, seed=1, omega=(-0.8, -0.2, 200), eta=0.005, np=8, tol=1e-10),
-    2: dict(o=42, v=186, seed=1, omega=(-0.9, -0.1, 4000), eta=0.005, np=8, tol=1e-10,
+# Workloads by their shapes (spin orbitals) and grids: the small case, the benzene/cc-pVDZ
+# shape (plain solves, its reduced model, its adjoint gradient) and the adenine/cc-pVDZ shape
+# (one batched mixed-precision block).
+WORKLOADS = {
+    "o10v20": dict(o=10, v=20, seed=0, omega=(-1.0, -0.3, 64), eta=0.01, np=10, tol=1e-10),
+    "o42v186": dict(o=42, v=186, seed=1, omega=(-0.8, -0.2, 200), eta=0.005, np=8, tol=1e-10),
+    "o42v186_mor": dict(o=42, v=186, seed=1, omega=(-0.9, -0.1, 4000), eta=0.005, np=8, tol=1e-10,
             sample_window=(-0.8, -0.2), per_round=8, resid_tol=1e-6,
             check=(-0.9, -0.1, 200)),
-    3: dict(o=70, v=260, seed=3, omega=(-0.5, -0.3, 32), eta=0.005, np=16, tol=1e-8),
-    4: dict(o=42, v=186, seed=1, omega=(-0.6, -0.3, 100), eta=0.005, np=8, tol=1e-10),
+    "o70v260_mixed": dict(o=70, v=260, seed=3, omega=(-0.5, -0.3, 32), eta=0.005, np=16, tol=1e-8),
+    "o42v186_adjoint": dict(o=42, v=186, seed=1, omega=(-0.6, -0.3, 100), eta=0.005, np=8, tol=1e-10),
 }
 
 

@@ -1,4 +1,4 @@
-"""GPU tests at the configured workload sizes (benzene/cc-pVDZ shape, D = 160,188).
+"""GPU tests at the full workload sizes (benzene/cc-pVDZ shape o=42, v=186, D = 160,188).
 
 The oracle cannot solve all 1,600 systems in reasonable time, so it is compared with the GPU on
 a sample of right-hand sides computed one by one; the other checks are properties that hold at
@@ -15,30 +15,30 @@ from paper_1902_06016_amd import gfcc
 
 pytestmark = pytest.mark.gpu
 
-CFG1 = synth.CONFIGS[1]
+W = synth.WORKLOADS["o42v186"]
 
 
 @pytest.fixture(scope="module")
-def c1(gpu_ctx):
-    print("[c1 setup]", flush=True)
-    prob = synth.make_problem(CFG1["o"], CFG1["v"], CFG1["seed"])
+def benzene(gpu_ctx):
+    print("[o42v186 setup]", flush=True)
+    prob = synth.make_problem(W["o"], W["v"], W["seed"])
     gpu_ctx.build_from_problem(prob)
     return prob
 
 
-def test_c1_sampled_parity_with_oracle(gpu_ctx, c1):
+def test_o42v186_sampled_parity_with_oracle(gpu_ctx, benzene):
     """G_qp(omega) for every q at two frequencies and one orbital, in the launch configuration of
     the benchmark (block 320, restart 30), against the oracle's GMRES at tol 1e-13."""
-    print("[c1 parity]", flush=True)
-    prob = c1
+    print("[o42v186 parity]", flush=True)
+    prob = benzene
     o, v = prob.o, prob.v
-    om_all = synth.omega_grid(CFG1["omega"])
-    ps = synth.valence_p(o, CFG1["np"])
-    res = gpu_ctx.gfcc_solve(om_all, ps, CFG1["eta"], tol=1e-12, restart=30, block=320)
+    om_all = synth.omega_grid(W["omega"])
+    ps = synth.valence_p(o, W["np"])
+    res = gpu_ctx.gfcc_solve(om_all, ps, W["eta"], tol=1e-12, restart=30, block=320)
     assert res.resid.max() <= 1e-12
     G = res.G.cpu().numpy()
     # the benchmark's own tolerance (1e-10)
-    loose = gpu_ctx.gfcc_solve(om_all, ps, CFG1["eta"], tol=1e-10, restart=30, block=320)
+    loose = gpu_ctx.gfcc_solve(om_all, ps, W["eta"], tol=1e-10, restart=30, block=320)
     GL = loose.G.cpu().numpy()
     A1 = gfcc.spectral_function(loose.G)
     A2 = gfcc.spectral_function(res.G)
@@ -48,7 +48,7 @@ def test_c1_sampled_parity_with_oracle(gpu_ctx, c1):
     C = np.stack([osig.c_vector(o, v, prob.t1, prob.t2, prob.l1, prob.l2, int(q)) for q in ps], 0)
     for w_idx, k in ((0, len(ps) - 1), (len(om_all) - 1, 0)):
         x, it, r = osolve.gmres(op, osig.b_vector(o, v, int(ps[k])), float(om_all[w_idx]),
-                                CFG1["eta"], tol=1e-13)
+                                W["eta"], tol=1e-13)
         g = C @ x
         err = np.abs(G[w_idx, :, k] - g).max() / np.abs(g).max()
         print(f"  omega={om_all[w_idx]:.3f} p={ps[k]} iters={it} rel err {err:.2e}", flush=True)
@@ -62,15 +62,15 @@ def test_c1_sampled_parity_with_oracle(gpu_ctx, c1):
     assert np.abs(A1 - A2).max() / amax < 1e-10
 
 
-def test_c1_diis_matches_gmres(gpu_ctx, c1):
+def test_o42v186_diis_matches_gmres(gpu_ctx, benzene):
     """The complex DIIS solver at the full operator size: four frequencies of the benchmark grid
     (both ends and two inside) for all eight valence orbitals, against GMRES at tol 1e-12."""
-    print("[c1 diis]", flush=True)
-    om_all = synth.omega_grid(CFG1["omega"])
+    print("[o42v186 diis]", flush=True)
+    om_all = synth.omega_grid(W["omega"])
     om = om_all[[0, 67, 133, len(om_all) - 1]]
-    ps = synth.valence_p(c1.o, CFG1["np"])
-    ref = gpu_ctx.gfcc_solve(om, ps, CFG1["eta"], tol=1e-12, restart=30)
-    res = gpu_ctx.gfcc_solve_diis(om, ps, CFG1["eta"], tol=1e-10, maxit=400, ndiis=10,
+    ps = synth.valence_p(benzene.o, W["np"])
+    ref = gpu_ctx.gfcc_solve(om, ps, W["eta"], tol=1e-12, restart=30)
+    res = gpu_ctx.gfcc_solve_diis(om, ps, W["eta"], tol=1e-10, maxit=400, ndiis=10,
                                   want_hist=True)
     print(f"  DIIS micro-iterations {res.iters.min()}..{res.iters.max()}, "
           f"GMRES {ref.iters.min()}..{ref.iters.max()}", flush=True)
@@ -85,22 +85,22 @@ def test_c1_diis_matches_gmres(gpu_ctx, c1):
             assert h[0] == 1.0 and (h[res.iters[w, k] + 1:] == -1.0).all()
 
 
-def test_c1_first_order_build(gpu_ctx, c1):
+def test_o42v186_first_order_build(gpu_ctx, benzene):
     """The first-order-amplitude operator at the full size is the general build fed
     T1 = Lambda1 = 0 (same bits), and its G differs from the full amplitudes' G only through
     T1 and Lambda1."""
-    print("[c1 first order]", flush=True)
-    prob = c1
-    om = synth.omega_grid(CFG1["omega"])[[0, 199]]
-    ps = synth.valence_p(prob.o, CFG1["np"])
-    full = gpu_ctx.gfcc_solve(om, ps, CFG1["eta"], tol=1e-12)
+    print("[o42v186 first order]", flush=True)
+    prob = benzene
+    om = synth.omega_grid(W["omega"])[[0, 199]]
+    ps = synth.valence_p(prob.o, W["np"])
+    full = gpu_ctx.gfcc_solve(om, ps, W["eta"], tol=1e-12)
     D = gfcc.dim(prob.o, prob.v)
     g = torch.Generator(device="cuda").manual_seed(3)
     x = torch.randn((4, D), dtype=torch.complex128, device="cuda", generator=g)
     try:
         gpu_ctx.build_first_order_from_problem(prob)
         y1 = gpu_ctx.sigma_apply(x)
-        pert = gpu_ctx.gfcc_solve(om, ps, CFG1["eta"], tol=1e-12)
+        pert = gpu_ctx.gfcc_solve(om, ps, W["eta"], tol=1e-12)
         dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
         z = np.zeros_like(prob.t1)
         gpu_ctx.build_hbar_operands(prob.o, prob.v, dev(prob.eps), dev(z), dev(prob.t2), dev(z),
@@ -116,10 +116,10 @@ def test_c1_first_order_build(gpu_ctx, c1):
     assert 0.0 < rel < 0.1
 
 
-def test_c2_mor_workflow(gpu_ctx, c1):
-    print("[c2 mor]", flush=True)
-    cfg = synth.CONFIGS[2]
-    ps = synth.valence_p(c1.o, cfg["np"])
+def test_o42v186_mor_workflow(gpu_ctx, benzene):
+    print("[o42v186 mor]", flush=True)
+    cfg = synth.WORKLOADS["o42v186_mor"]
+    ps = synth.valence_p(benzene.o, cfg["np"])
     lo, hi = cfg["sample_window"]
     grid = synth.omega_grid(cfg["omega"])
     m = gpu_ctx.mor_build(np.linspace(lo, hi, cfg["per_round"]), ps, cfg["eta"], solve_tol=1e-10)
@@ -143,10 +143,10 @@ def test_c2_mor_workflow(gpu_ctx, c1):
     m.close()
 
 
-def test_c4_adjoint_vs_finite_differences(gpu_ctx, c1):
-    print("[c4 adjoint]", flush=True)
-    cfg = synth.CONFIGS[4]
-    prob = c1
+def test_o42v186_adjoint_vs_finite_differences(gpu_ctx, benzene):
+    print("[o42v186 adjoint]", flush=True)
+    cfg = synth.WORKLOADS["o42v186_adjoint"]
+    prob = benzene
     o = prob.o
     ps = synth.valence_p(o, cfg["np"])
     om = synth.omega_grid(cfg["omega"])
@@ -188,7 +188,7 @@ def test_mixed_block_reduced_shape(gpu_ctx):
     three-body term in bf16 and FP64 refinement reach the FP64 residual target and match the
     FP64 solve's A within 1e-6."""
     print("[mixed block]", flush=True)
-    cfg = synth.CONFIGS[3]
+    cfg = synth.WORKLOADS["o70v260_mixed"]
     o, v = 30, 90
     prob = synth.make_problem(o, v, cfg["seed"])
     gpu_ctx.build_from_problem(prob, keep=gfcc.KEEP_FP32)

@@ -113,7 +113,7 @@ def test_mor_refinement(gpu_ctx, model):
 @pytest.mark.parametrize("prec", [gfcc.FP32, gfcc.FP32_BF16_3BODY])
 def test_mixed_precision_solve(gpu_ctx, prec):
     print(f"[mixed prec={prec}]", flush=True)
-    cfg = synth.CONFIGS[0]
+    cfg = synth.WORKLOADS["o10v20"]
     p = synth.make_problem(cfg["o"], cfg["v"], cfg["seed"])
     hb = ohbar.build_hbar_from_problem(p)
     H = osolve.dense_hbar(hb)

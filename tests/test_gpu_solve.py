@@ -24,9 +24,9 @@ def _dense_ref(prob, omegas, ps, eta, transpose=False):
 
 
 @pytest.mark.parametrize("block", [0, 7, 640])
-def test_config0_fp64(gpu_ctx, block):
-    cfg = synth.CONFIGS[0]
-    print(f"[solve c0 block={block}]", flush=True)
+def test_o10v20_fp64(gpu_ctx, block):
+    cfg = synth.WORKLOADS["o10v20"]
+    print(f"[solve o10v20 block={block}]", flush=True)
     prob = synth.make_problem(cfg["o"], cfg["v"], cfg["seed"])
     om = synth.omega_grid(cfg["omega"])
     ps = synth.valence_p(cfg["o"], cfg["np"])

@@ -86,10 +86,10 @@ def test_bj_sign_convention_is_complex_conjugate(small):
     assert np.abs(Xp - X.conj()).max() < 1e-13
 
 
-def test_config0_spectrum_report():
-    """Config 0: dense eigenvalues of H-bar_N are real-dominated (max |Im| < eta) and lie above
+def test_o10v20_spectrum_report():
+    """Small case (o=10, v=20): dense eigenvalues of H-bar_N are real-dominated (max |Im| < eta) and lie above
     the frequency window, so A(omega) > 0 on it."""
-    cfg = synth.CONFIGS[0]
+    cfg = synth.WORKLOADS["o10v20"]
     p = synth.make_problem(cfg["o"], cfg["v"], cfg["seed"])
     hb = ohbar.build_hbar_from_problem(p)
     H = osolve.dense_hbar(hb)
