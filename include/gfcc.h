@@ -170,6 +170,8 @@ gfcc_status gfcc_autotune_entry(const gfcc_ctx* ctx, int index, int64_t* desc, d
  *   (device). iters_out, resid_out: host arrays [nw*np] or NULL.
  * Returns ENOCONV (after filling every output with the best iterate) if some right-hand side
  * did not reach tol; EBREAKDOWN if a shifted operator is exactly singular on a Krylov space.
+ * Memory: the context keeps the solver's work arrays (chiefly the Krylov basis,
+ * (restart + 1) D block complex128 entries) for later solves; gfcc_destroy frees them.
  */
 gfcc_status gfcc_solve(gfcc_ctx* ctx, int nw, const double* omega, int np, const int* p,
                        double eta, double tol, int maxit, int restart, int block,

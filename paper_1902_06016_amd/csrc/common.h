@@ -147,6 +147,7 @@ struct gfcc_ctx {
   gfcc::DevBuf ws_gemm;     // split-K partials
   gfcc::DevBuf ws_a, ws_b, ws_c, ws_d, ws_e;
   gfcc::DevBuf ws_trans;    // transposed B operands of the row-major product paths
+  gfcc::DevBuf ws_solve, ws_solve_f32;  // GMRES block work arrays (Krylov basis, state)
   std::vector<gfcc::DevBuf> build_pool;  // operator-build buffers kept for the next build
   gfcc::DevBuf zrow;        // zeros (read for structurally zero rows of the ovvo operand)
   gfcc::TimerSlot timers[2];

@@ -570,7 +570,8 @@ struct GmresBlock {
   int nb = 0, m = 0;
   int precision = GFCC_FP64;
   bool transpose = false;
-  DevBuf mem, mem_f32;
+  // work arrays live in the context (ws_solve, ws_solve_f32), so that consecutive solves
+  // reuse them instead of allocating and freeing the Krylov basis every call
   double2 *V, *W, *U, *X, *B, *R, *Hh, *Hh2, *Y, *Cc, *z;
   double *nrm, *part_n;
   double2* part_h;
@@ -622,8 +623,8 @@ struct GmresBlock {
     add((int64_t)nb * (m + 1), 16);                           // g
     for (int i = 0; i < 4; ++i) add(nb, 4);
     for (int i = 0; i < 3; ++i) add(nb, 8);
-    mem.ensure((size_t)bytes);
-    char* cur = mem.as<char>();
+    ws_ensure(ctx, ctx->ws_solve, (size_t)bytes);
+    char* cur = ctx->ws_solve.as<char>();
     V = carve<double2>(cur, vec * (m + 1));
     W = carve<double2>(cur, vec);
     U = carve<double2>(cur, vec);
@@ -654,8 +655,8 @@ struct GmresBlock {
     s.thresh = carve<double>(cur, nb);
     s.inv = carve<double>(cur, nb);
     if (precision != GFCC_FP64) {
-      mem_f32.ensure(sizeof(float) * (size_t)vec * 2 * 2);
-      Uf = mem_f32.as<float>();
+      ws_ensure(ctx, ctx->ws_solve_f32, sizeof(float) * (size_t)vec * 2 * 2);
+      Uf = ctx->ws_solve_f32.as<float>();
       Sf = Uf + vec * 2;
     }
     if (nb > hflags_nb) {
