@@ -37,6 +37,7 @@ struct gfcc_mor {
   int r = 0;                        // rank of F
   std::vector<double> omega_k;
   int solve_maxit = 2000, solve_restart = 30;
+  gfcc::DevBuf ews, eom, eres;  // evaluation work arrays, kept between calls
 };
 
 namespace gfcc {
@@ -841,17 +842,16 @@ static void mor_eval_impl(gfcc_mor* M, int nw, const double* omega, double2* G, 
   const int64_t per = (int64_t)m * m + (int64_t)np * m;
   int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(nw, (int64_t)(1ULL << 31) / (per * 16)));
   chunk = std::min(chunk, 2048);
-  DevBuf bw, bom, bres;
-  bw.alloc(sizeof(double2) * (size_t)per * chunk);
-  bom.alloc(sizeof(double) * nw);
-  bres.alloc(sizeof(double) * nw);
-  GFCC_HIP(hipMemcpyAsync(bom.p, omega, sizeof(double) * nw, hipMemcpyHostToDevice, st));
+  M->ews.ensure(sizeof(double2) * (size_t)per * chunk);
+  M->eom.ensure(sizeof(double) * nw);
+  M->eres.ensure(sizeof(double) * nw);
+  GFCC_HIP(hipMemcpyAsync(M->eom.p, omega, sizeof(double) * nw, hipMemcpyHostToDevice, st));
   for (int w0 = 0; w0 < nw; w0 += chunk) {
     int cnt = std::min(chunk, nw - w0);
-    rom_solve(M, bom.as<double>(), w0, cnt, nw, bw.as<double2>(), G, bres.as<double>());
+    rom_solve(M, M->eom.as<double>(), w0, cnt, nw, M->ews.as<double2>(), G, M->eres.as<double>());
   }
   if (resid_host)
-    GFCC_HIP(hipMemcpyAsync(resid_host, bres.p, sizeof(double) * nw, hipMemcpyDeviceToHost, st));
+    GFCC_HIP(hipMemcpyAsync(resid_host, M->eres.p, sizeof(double) * nw, hipMemcpyDeviceToHost, st));
   GFCC_HIP(hipStreamSynchronize(st));
 }
 
