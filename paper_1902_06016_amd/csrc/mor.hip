@@ -500,20 +500,35 @@ __global__ __launch_bounds__(256) void orth_dots_kernel(const double* __restrict
   }
 }
 
-// h[i] = sum_s partial[s][i] (fixed order) for i < nb + acc; coefficients along the accepted
-// rows are accumulated into coef_row[i - nb]. Grid ceil(kmax / 256).
+// h[i] = sum_s partial[s][i] for i < nb + acc; coefficients along the accepted rows are
+// accumulated into coef_row[i - nb]. Grid ceil(kmax / 64), 256 threads: lane r of wavefront g
+// sums the slices g, g + 4, ... of row i = 64 blockIdx.x + r (independent loads), and the four
+// wavefront sums are added in a fixed order.
 __global__ __launch_bounds__(256) void orth_reduce_kernel(const double* __restrict__ partial,
                                                           int nsl, int kmax,
                                                           const OrthState* __restrict__ stt,
                                                           int nb, double* __restrict__ h,
                                                           double* __restrict__ coef_row) {
+  __shared__ double red[4][64];
   const int k = nb + stt->acc;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= k) return;
-  double s = 0.0;
-  for (int sl = 0; sl < nsl; ++sl) s += partial[(int64_t)sl * kmax + i];
-  h[i] = s;
-  if (coef_row && i >= nb) coef_row[i - nb] += s;
+  const int r = threadIdx.x % 64, g = threadIdx.x / 64;
+  const int i = blockIdx.x * 64 + r;
+  double s0 = 0.0, s1 = 0.0;
+  if (i < k) {
+    int sl = g;
+    for (; sl + 4 < nsl; sl += 8) {
+      s0 += partial[(int64_t)sl * kmax + i];
+      s1 += partial[(int64_t)(sl + 4) * kmax + i];
+    }
+    for (; sl < nsl; sl += 4) s0 += partial[(int64_t)sl * kmax + i];
+  }
+  red[g][r] = s0 + s1;
+  __syncthreads();
+  if (g == 0 && i < k) {
+    const double s = ((red[0][r] + red[1][r]) + red[2][r]) + red[3][r];
+    h[i] = s;
+    if (coef_row && i >= nb) coef_row[i - nb] += s;
+  }
 }
 
 // w[d] -= sum_{i < nb + acc} h[i] Q_i[d]; with nrm_part, the workgroup's partial sum of w[d]^2
@@ -626,7 +641,7 @@ static int orth_rows(gfcc_ctx* ctx, int64_t D, const double* B, int nb, double* 
         hipLaunchKernelGGL(orth_dots_kernel, dim3(nsl, (kj + ODR - 1) / ODR), dim3(256), 0, st, B,
                            nb, Out, stt, wj, D, kmax, bpart.as<double>());
         GFCC_LAUNCH_CHECK();
-        hipLaunchKernelGGL(orth_reduce_kernel, dim3((kj + 255) / 256), dim3(256), 0, st,
+        hipLaunchKernelGGL(orth_reduce_kernel, dim3((kj + 63) / 64), dim3(256), 0, st,
                            bpart.as<double>(), nsl, kmax, stt, nb, bh.as<double>(), crow);
         GFCC_LAUNCH_CHECK();
       }
