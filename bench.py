@@ -494,8 +494,9 @@ def form_adjoint(ctx, cfg, gfcc, inputs):
     w[1:] += 0.5 * h
     torch.cuda.synchronize()
     t0 = time.time()
-    fwd = ctx.gfcc_solve(om, ps, cfg["eta"], tol=cfg["tol"], want_x=True)
-    adj = ctx.gfcc_solve(om, ps, cfg["eta"], tol=cfg["tol"], transpose=True, want_x=True)
+    fwd = ctx.gfcc_solve(om, ps, cfg["eta"], tol=cfg["tol"], block=320, want_x=True)
+    adj = ctx.gfcc_solve(om, ps, cfg["eta"], tol=cfg["tol"], block=320, transpose=True,
+                         want_x=True)
     g = ctx.gfcc_grad_eps(w, fwd.X, adj.X)
     torch.cuda.synchronize()
     dt = time.time() - t0
