@@ -92,6 +92,27 @@ def test_mor_both_reduced_solvers(gpu_ctx, nq):
     m.close()
 
 
+def test_mor_smallest_models(gpu_ctx, model):
+    """One sampled frequency: order 2 (Re and Im of one solution) and 4 (two orbitals), the
+    smallest reduced systems the wavefront solver meets, against the oracle's model."""
+    print("[mor smallest]", flush=True)
+    p, hb, H, lam, ps, B, C = model
+    eta = 0.01
+    gpu_ctx.build_from_problem(p)
+    grid = np.linspace(-lam[0] - 0.3, -lam[0] + 0.3, 13)
+    for cols in ([1], [0, 1]):
+        wk = np.array([-lam[0] + 0.1])
+        m = gpu_ctx.mor_build(wk, ps[cols], eta, solve_tol=1e-13)
+        rom = omor.ROM(hb, ps[cols], eta, C[cols], omor.dense_solver(H, B[:, cols], eta))
+        rom.extend(wk, 1e-10)
+        assert m.info()[0] == rom.m == 2 * len(cols)
+        Gg, rg = m.eval(grid)
+        Go, ro = rom.eval(grid)
+        assert np.abs(Gg.cpu().numpy() - Go).max() < 1e-10 * np.abs(Go).max()
+        assert np.all(np.abs(rg - ro) <= 1e-8 * ro + 1e-12)
+        m.close()
+
+
 def test_mor_refinement(gpu_ctx, model):
     print("[mor_refine]", flush=True)
     p, hb, H, lam, ps, B, C = model
