@@ -165,7 +165,10 @@ gfcc_status gfcc_autotune_entry(const gfcc_ctx* ctx, int index, int64_t* desc, d
  *   the FP64 true relative residual).
  * tol: relative residual ||b - M x|| / ||b||. maxit: max iterations per right-hand side
  *   (inner+outer). restart: Krylov restart length (1..200). block: number of right-hand
- *   sides solved together (0 = library default).
+ *   sides solved together (0 = library default, at most 2048). Multiples of 64 keep the
+ *   fastest ovvo loader; a block that holds every right-hand side is padded with zero
+ *   right-hand sides up to the next multiple of 64 when that adds at most a quarter; the last
+ *   of several blocks is padded up to a multiple of 64 (at most the block size).
  * X_out: optional complex128 [nw][np][D] (device) or NULL. G_out: complex128 [nw][np][np]
  *   (device). iters_out, resid_out: host arrays [nw*np] or NULL.
  * Returns ENOCONV (after filling every output with the best iterate) if some right-hand side
