@@ -166,3 +166,20 @@ def test_spectral_function_host_and_device_agree(gpu_ctx):
     G2[:, 1, 1] = 2j * np.pi
     G2[:, 0, 1] = 5j
     assert np.allclose(gfcc.spectral_function(G2), 3.0)
+
+
+@pytest.mark.parametrize("block", [0, 60, 64, 13])
+def test_block_padding(gpu_ctx, block):
+    """60 right-hand sides: a block holding all of them is padded to 64 with zero right-hand
+    sides (block 0, 60 and 64 give one block of 64); block 13 gives four blocks of 13 and a
+    last one padded from 8 to 13. Every layout gives the dense-LU solution."""
+    print(f"[block padding block={block}]", flush=True)
+    prob = synth.make_problem(6, 10, 23)
+    om = np.linspace(-1.1, -0.4, 10)
+    ps = np.arange(6)
+    _, _, _, _, Xr, Gr = _dense_ref(prob, om, ps, 0.01)
+    gpu_ctx.build_from_problem(prob)
+    res = gpu_ctx.gfcc_solve(om, ps, 0.01, tol=1e-12, restart=40, block=block, want_x=True)
+    assert res.resid.max() <= 1e-12 and res.iters.shape == (10, 6)
+    assert np.abs(res.G.cpu().numpy() - Gr).max() <= 1e-10 * np.abs(Gr).max()
+    assert np.abs(res.X.cpu().numpy() - Xr).max() <= 1e-9 * np.abs(Xr).max()
