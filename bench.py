@@ -613,7 +613,7 @@ def main():
                          "adjoint, mixed, small, none")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the (omega, p) right-hand "
+        print(json.dumps({"error": "bench.py runs on one GPU only; the (omega, p) right-hand "
                                    "sides would be sharded across GPUs with the operator "
                                    "replicated", "n_gpus": args.gpus}))
         sys.exit(2)
