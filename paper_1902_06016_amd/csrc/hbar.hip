@@ -281,7 +281,7 @@ void collect(Operator& op, std::vector<DevBuf>& out) {
 
 struct BuildBuffers {
   std::vector<DevBuf> avail;       // reusable buffers (freed when the build ends)
-  std::vector<DevBuf>* keep_pool;  // where this build's work arrays go for the next build
+  std::vector<DevBuf>* keep_pool;  // receives the current operator build's work arrays
   void* take(DevBuf& b, size_t bytes) {
     for (size_t i = 0; i < avail.size(); ++i)
       if (avail[i].bytes == bytes) {
