@@ -106,6 +106,24 @@ def test_errors(gpu_ctx):
     assert e.value.status == gfcc.GFCC_EINVAL
     r = gpu_ctx.gfcc_solve([-0.5, -0.4], [0, 1], 0.01, tol=1e-14, maxit=1, allow_noconv=True)
     assert r.status == gfcc.GFCC_ENOCONV and r.iters.max() == 1
+    # limits: block at most 2048, restart 1..200
+    om = np.linspace(-0.6, -0.4, 700)
+    with pytest.raises(gfcc.GfccError) as e:
+        gpu_ctx.gfcc_solve(om, [0, 1, 2], 0.01, block=2049)   # 2100 right-hand sides
+    assert e.value.status == gfcc.GFCC_EINVAL
+    for rs in (0, 201):
+        with pytest.raises(gfcc.GfccError) as e:
+            gpu_ctx.gfcc_solve([-0.5], [0], 0.01, restart=rs)
+        assert e.value.status == gfcc.GFCC_EINVAL
+    r = gpu_ctx.gfcc_solve([-0.5], [0], 0.01, tol=1e-12, restart=200)
+    assert r.resid.max() <= 1e-12
+    # the largest block: 2048 right-hand sides at once, against dense LU
+    om = np.linspace(-0.9, -0.3, 512)
+    ps = np.arange(4)
+    _, _, _, _, _, Gr = _dense_ref(prob, om, ps, 0.01)
+    r = gpu_ctx.gfcc_solve(om, ps, 0.01, tol=1e-12, block=2048)
+    assert r.resid.max() <= 1e-12
+    assert np.abs(r.G.cpu().numpy() - Gr).max() <= 1e-10 * np.abs(Gr).max()
     with pytest.raises(ValueError):
         gpu_ctx.sigma_apply(torch.zeros((1, 5), dtype=torch.complex128, device="cuda"))
     fresh = gfcc.Context(0)
