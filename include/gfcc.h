@@ -119,7 +119,8 @@ gfcc_status build_hbar_first_order(gfcc_ctx* ctx, int o, int v, const double* ep
  * Hbar_N acting on X_p (Eq. xplin), the product every Krylov iteration needs.
  * precision: GFCC_FP64, GFCC_FP32 or GFCC_FP32_BF16_3BODY (the latter two need
  * GFCC_KEEP_FP32 at build time; transpose needs GFCC_KEEP_TRANSPOSE for speed but works
- * without it). x and y must not overlap. ESTATE if no operator is built.
+ * without it). x and y must not overlap. ESTATE if no operator is built. Any nrhs >= 0;
+ * the products run in chunks of at most 2048 vectors.
  */
 gfcc_status sigma_apply(gfcc_ctx* ctx, int nrhs, const void* x, void* y, int transpose,
                         int precision);

@@ -207,24 +207,32 @@ extern "C" gfcc_status sigma_apply(gfcc_ctx* ctx, int nrhs, const void* x, void*
                "sigma_apply: the transpose product is FP64 only");
   GFCC_REQUIRE(x != y, GFCC_EINVAL, "sigma_apply: x and y must not overlap");
   const int64_t D = ctx->op.D;
-  const int nc = 2 * nrhs;
-  DevBuf bx, by;
-  bx.alloc(sizeof(double) * (size_t)D * nc);
-  by.alloc(sizeof(double) * (size_t)D * nc);
-  // [nrhs][D] complex -> [D][nrhs] complex
-  ctranspose(ctx, x, nrhs, D, D, bx.p, nrhs);
-  if (precision == GFCC_FP64) {
-    sigma_block_f64(ctx, nc, bx.as<double>(), by.as<double>(), transpose != 0);
-  } else {
-    DevBuf fx, fy;
-    fx.alloc(sizeof(float) * (size_t)D * nc);
-    fy.alloc(sizeof(float) * (size_t)D * nc);
-    cast_f64_f32(ctx, bx.as<double>(), fx.as<float>(), D * nc);
-    sigma_block_f32(ctx, nc, fx.as<float>(), fy.as<float>(), precision == GFCC_FP32_BF16_3BODY);
-    cast_f32_f64(ctx, fy.as<float>(), by.as<double>(), D * nc);
-    GFCC_HIP(hipStreamSynchronize(ctx->stream));
+  // chunks of at most 2048 right-hand sides (the solver's largest block)
+  constexpr int CH = 2048;
+  const int nb = std::min(nrhs, CH);
+  DevBuf bx, by, fx, fy;
+  bx.alloc(sizeof(double) * (size_t)D * 2 * nb);
+  by.alloc(sizeof(double) * (size_t)D * 2 * nb);
+  if (precision != GFCC_FP64) {
+    fx.alloc(sizeof(float) * (size_t)D * 2 * nb);
+    fy.alloc(sizeof(float) * (size_t)D * 2 * nb);
   }
-  ctranspose(ctx, by.p, D, nrhs, nrhs, y, D);
+  const double2* xc = static_cast<const double2*>(x);
+  double2* yc = static_cast<double2*>(y);
+  for (int r0 = 0; r0 < nrhs; r0 += CH) {
+    const int cnt = std::min(CH, nrhs - r0);
+    const int nc = 2 * cnt;
+    // [cnt][D] complex -> [D][cnt] complex
+    ctranspose(ctx, xc + (int64_t)r0 * D, cnt, D, D, bx.p, cnt);
+    if (precision == GFCC_FP64) {
+      sigma_block_f64(ctx, nc, bx.as<double>(), by.as<double>(), transpose != 0);
+    } else {
+      cast_f64_f32(ctx, bx.as<double>(), fx.as<float>(), D * nc);
+      sigma_block_f32(ctx, nc, fx.as<float>(), fy.as<float>(), precision == GFCC_FP32_BF16_3BODY);
+      cast_f32_f64(ctx, fy.as<float>(), by.as<double>(), D * nc);
+    }
+    ctranspose(ctx, by.p, D, cnt, cnt, yc + (int64_t)r0 * D, D);
+  }
   GFCC_HIP(hipStreamSynchronize(ctx->stream));
   timers_collect(ctx);
   GFCC_API_END(ctx)

@@ -74,3 +74,20 @@ def test_sigma_reduced_precision(gpu_ctx, prec, tol, nrhs):
         rest = ref - t9
         e9 = np.abs(y - rest - t9).max() / np.abs(t9).max()
         assert e9 < 3e-2, e9
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_sigma_more_than_one_chunk(gpu_ctx, transpose):
+    """sigma_apply works through chunks of 2048 right-hand sides: 2100 vectors (a full chunk
+    and a ragged one) against the oracle."""
+    print(f"[sigma chunks T={transpose}]", flush=True)
+    o, v, seed = 5, 7, 11
+    prob = synth.make_problem(o, v, seed)
+    hb = ohbar.build_hbar_from_problem(prob)
+    gpu_ctx.build_from_problem(prob)
+    D = osig.dim(o, v)
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((2100, D)) + 1j * rng.standard_normal((2100, D))
+    y = gpu_ctx.sigma_apply(torch.from_numpy(x).cuda(), transpose=transpose).cpu().numpy()
+    ref = osig.sigma_t(hb, x) if transpose else osig.sigma(hb, x)
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
