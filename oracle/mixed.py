@@ -7,6 +7,9 @@ rotations and least-squares solves stay in FP64. (Carson & Higham's GMRES-IR sch
 
 The reduced-precision sigma is emulated with float32 copies of the operator blocks and
 float32 arithmetic; bfloat16 rounding is round-to-nearest-even on the float32 bit pattern.
+The three-body term's bfloat16 operands are two-term values x = hi + lo (hi = bf16(x),
+lo = bf16(x - hi)), and each of its two products is hi.hi + hi.lo + lo.hi accumulated in
+float32: the products run on bfloat16 inputs while the term keeps about 16 significant bits.
 """
 from __future__ import annotations
 
@@ -27,6 +30,14 @@ def bf16_round(x: np.ndarray) -> np.ndarray:
     return u.astype(np.uint32).view(np.float32).reshape(a.shape)
 
 
+def bf16_split(x: np.ndarray):
+    """x (float32 or float64) as hi + lo: hi = bf16(x), lo = bf16(x - hi), both float32."""
+    a = np.asarray(x)
+    hi = bf16_round(a.astype(np.float32))
+    lo = bf16_round((a - hi.astype(a.dtype)).astype(np.float32))
+    return hi, lo
+
+
 def f32_hbar(hb):
     h = copy.copy(hb)
     for name in ("Fov", "Foo", "Fvv", "Woooo", "Wooov", "Wovvo", "Wovoo", "oovv", "t2"):
@@ -43,9 +54,16 @@ def sigma_reduced(h32, x: np.ndarray, bf16_3body: bool) -> np.ndarray:
         parts = sg.sigma_parts(h32, part)
         if bf16_3body:
             o, v = h32.o, h32.v
-            _, r2 = sg.unpack(bf16_round(part), o, v)
-            tau = np.einsum("klcd,...klc->...d", bf16_round(h32.oovv), r2).astype(np.float32)
-            t9 = -0.5 * np.einsum("ijad,...d->...ija", bf16_round(h32.t2), bf16_round(tau))
+            xh, xl = bf16_split(part)
+            _, rh = sg.unpack(xh, o, v)
+            _, rl = sg.unpack(xl, o, v)
+            vh, vl = bf16_split(h32.oovv)
+            tau = (np.einsum("klcd,...klc->...d", vh, rh) + np.einsum("klcd,...klc->...d", vh, rl)
+                   + np.einsum("klcd,...klc->...d", vl, rh)).astype(np.float32)
+            th, tl = bf16_split(h32.t2)
+            uh, ul = bf16_split(tau)
+            t9 = -0.5 * (np.einsum("ijad,...d->...ija", th, uh) + np.einsum("ijad,...d->...ija", th, ul)
+                         + np.einsum("ijad,...d->...ija", tl, uh))
             parts["T9"] = sg.pack(np.zeros(part.shape[:-1] + (o,), np.float32), t9.astype(np.float32))
         out.append(sum(parts.values()).astype(np.float32))
     return out[0].astype(np.float64) + 1j * out[1].astype(np.float64)

@@ -109,7 +109,8 @@ struct Operator {
   int keep = 0;
   OpPieces<double> f64;
   OpPieces<float> f32;
-  DevBuf Vp_bf16, T2p_bf16;     // bf16 three-body operands (mixed precision)
+  DevBuf Vp_bf16, T2p_bf16;     // bf16 three-body operands (mixed precision): high parts
+  DevBuf Vp_bf16_lo, T2p_bf16_lo;  // and the bf16 remainders (x = hi + lo)
   DevBuf WeffT, W1T, W4cT, WooT, VpT;  // transposed copies (adjoint)
   DevBuf diag;                  // [D] diagonal of Hbar_N
   DevBuf Crows;                 // [o][D] c_q rows for all occupied q
@@ -224,6 +225,11 @@ void cast_f64_f32(gfcc_ctx* ctx, const double* s, float* d, int64_t n);
 void cast_f64_bf16(gfcc_ctx* ctx, const double* s, __hip_bfloat16* d, int64_t n);
 void cast_f32_f64(gfcc_ctx* ctx, const float* s, double* d, int64_t n);
 void cast_f32_bf16(gfcc_ctx* ctx, const float* s, __hip_bfloat16* d, int64_t n);
+// x = hi + lo in bf16 (hi = bf16(x), lo = bf16(x - hi)): about 16 significant bits
+void split_f64_bf16(gfcc_ctx* ctx, const double* s, __hip_bfloat16* hi, __hip_bfloat16* lo,
+                    int64_t n);
+void split_f32_bf16(gfcc_ctx* ctx, const float* s, __hip_bfloat16* hi, __hip_bfloat16* lo,
+                    int64_t n);
 void transpose2d(gfcc_ctx* ctx, const double* src, int64_t rows, int64_t cols, double* dst);
 // complex128 transpose: dst[c*ldd + r] = src[r*lds + c] for r < rows, c < cols
 void ctranspose(gfcc_ctx* ctx, const void* src, int64_t rows, int64_t cols, int64_t lds,

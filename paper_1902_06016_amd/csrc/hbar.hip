@@ -273,7 +273,7 @@ void collect(OpPieces<float>& f, std::vector<DevBuf>& out) {
 void collect(Operator& op, std::vector<DevBuf>& out) {
   collect(op.f64, out);
   collect(op.f32, out);
-  for (DevBuf* b : {&op.Vp_bf16, &op.T2p_bf16, &op.WeffT, &op.W1T, &op.W4cT, &op.WooT, &op.VpT,
+  for (DevBuf* b : {&op.Vp_bf16, &op.T2p_bf16, &op.Vp_bf16_lo, &op.T2p_bf16_lo, &op.WeffT, &op.W1T, &op.W4cT, &op.WooT, &op.VpT,
                     &op.diag, &op.Crows, &op.pairlut, &op.Foo, &op.Fov, &op.Fvv, &op.Woooo,
                     &op.Wooov, &op.Wovvo, &op.Wovoo})
     if (b->p) out.push_back(std::move(*b));
@@ -520,7 +520,9 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
       fill_f(ctx, Wf + OV * OV, wpadf, 0.0f);
       // bf16 three-body operands: Vp and -t2 packed as [(ij)a][d]
       bb.take(op.Vp_bf16, (size_t)PV * V * sizeof(__hip_bfloat16));
-      cast_f64_bf16(ctx, Vp, op.Vp_bf16.as<__hip_bfloat16>(), PV * V);
+      bb.take(op.Vp_bf16_lo, (size_t)PV * V * sizeof(__hip_bfloat16));
+      split_f64_bf16(ctx, Vp, op.Vp_bf16.as<__hip_bfloat16>(),
+                     op.Vp_bf16_lo.as<__hip_bfloat16>(), PV * V);
       WorkBuf bt(bb);
       double* t2p = BW(bt, PV * V);
       // -t2 packed rows = columns o.. of W4c
@@ -530,7 +532,9 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
         permute4(ctx, W4c + o, d4, s4, t2p, 1.0, 0.0);
       }
       bb.take(op.T2p_bf16, (size_t)PV * V * sizeof(__hip_bfloat16));
-      cast_f64_bf16(ctx, t2p, op.T2p_bf16.as<__hip_bfloat16>(), PV * V);
+      bb.take(op.T2p_bf16_lo, (size_t)PV * V * sizeof(__hip_bfloat16));
+      split_f64_bf16(ctx, t2p, op.T2p_bf16.as<__hip_bfloat16>(),
+                     op.T2p_bf16_lo.as<__hip_bfloat16>(), PV * V);
       // FP32 W4 = first o columns of W4c (the three-body columns go through bf16)
       {
         WorkBuf bw(bb);

@@ -158,6 +158,36 @@ def test_bf16_rounding():
     assert np.all(np.abs(r - x) <= np.abs(x) * 2.0 ** -8)
 
 
+def test_bf16_split():
+    """Two-term bf16 values: hi is the bf16 rounding, hi + lo recovers x to about 2^-16
+    relative, and values that fit two bf16 halves are exact."""
+    x = np.array([1.0 + 2.0 ** -10, np.pi, -0.05, 3.0e-7], dtype=np.float64)
+    hi, lo = omix.bf16_split(x)
+    assert np.array_equal(hi, omix.bf16_round(x.astype(np.float32)))
+    assert hi[0] == 1.0 and lo[0] == 2.0 ** -10          # 1 + 2^-10: exact in two halves
+    assert hi[1] == np.float32(3.140625)                  # pi: 8 significant bits, then the rest
+    err = np.abs(hi.astype(np.float64) + lo - x)
+    assert np.all(err <= np.abs(x) * 2.0 ** -16)
+    assert np.all(np.abs(lo) <= np.abs(x) * 2.0 ** -8)
+
+
+def test_bf16_three_body_term_keeps_16_bits(model):
+    """The emulated bf16 three-body term (hi.hi + hi.lo + lo.hi in float32) differs from the
+    float32 term by about 2^-17 of its size here (bound 2^-14); plain bf16 operands are off by
+    about 2^-8.4 and fail the bound."""
+    p, hb, H, lam, ps, B, C = model
+    rng = np.random.default_rng(3)
+    D = osig.dim(p.o, p.v)
+    x = rng.standard_normal((4, D)) + 1j * rng.standard_normal((4, D))
+    t9 = osig.sigma_parts(hb, x.real)["T9"] + 1j * osig.sigma_parts(hb, x.imag)["T9"]
+    h32 = omix.f32_hbar(hb)
+    full = omix.sigma_reduced(h32, x, bf16_3body=True)
+    plain = omix.sigma_reduced(h32, x, bf16_3body=False)   # float32 throughout
+    # the difference between the two reduced forms is the three-body term's bf16 error
+    assert np.abs(full - plain).max() <= 2.0 ** -14 * np.abs(t9).max()
+    assert np.abs(full - osig.sigma(hb, x)).max() <= 1e-6 * np.abs(osig.sigma(hb, x)).max()
+
+
 def test_gmres_ir_reaches_fp64_tolerance(model):
     p, hb, H, lam, ps, B, C = model
     om, eta = -lam[0] + 0.05, 0.005
