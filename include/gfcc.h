@@ -55,7 +55,12 @@ typedef enum {
 enum {
   GFCC_FP64 = 0,            /* all terms in FP64 (MFMA f64) */
   GFCC_FP32 = 1,            /* all terms in FP32 (MFMA f32, FP32 accumulation) */
-  GFCC_FP32_BF16_3BODY = 2  /* FP32, with the three-body T2*<kl||cd> term on BF16 MFMA */
+  GFCC_FP32_BF16_3BODY = 2, /* FP32, with the three-body T2*<kl||cd> term on BF16 MFMA */
+  GFCC_BF16_PAIRS = 3       /* FP32 vectors; the ovvo (T5, T6, T8 through Weff) and three-body
+                               contractions on BF16 MFMA with two-term operands x = hi + lo
+                               (hi.hi + hi.lo + lo.hi, FP32 accumulation, about 16 bits); the
+                               ovvo takes this path when 2 * nrhs of a block is a multiple of
+                               128 and the FP32 kernel otherwise */
 };
 
 /* Bit mask for build_hbar_operands: which operator copies to keep on the device. */
@@ -117,8 +122,8 @@ gfcc_status build_hbar_first_order(gfcc_ctx* ctx, int o, int v, const double* ep
  * sigma_apply -- y = Hbar_N x (transpose = 0) or y = Hbar_N^T x (transpose = 1) for nrhs
  * complex vectors: x, y are complex128 [nrhs][D] (device). This is the connected part of
  * Hbar_N acting on X_p (Eq. xplin), the product every Krylov iteration needs.
- * precision: GFCC_FP64, GFCC_FP32 or GFCC_FP32_BF16_3BODY (the latter two need
- * GFCC_KEEP_FP32 at build time; transpose needs GFCC_KEEP_TRANSPOSE for speed but works
+ * precision: GFCC_FP64, GFCC_FP32, GFCC_FP32_BF16_3BODY or GFCC_BF16_PAIRS (the reduced
+ * ones need GFCC_KEEP_FP32 at build time; transpose needs GFCC_KEEP_TRANSPOSE for speed but works
  * without it). x and y must not overlap. ESTATE if no operator is built. Any nrhs >= 0;
  * the products run in chunks of at most 2048 vectors.
  */
@@ -161,7 +166,8 @@ gfcc_status gfcc_autotune_entry(const gfcc_ctx* ctx, int index, int64_t* desc, d
  *   b_p^T Y_q = c_q^T X_p, G_out[w][q][p] is filled from b_p^T Y_q: the same G as the
  *   forward solve, up to the solve tolerance.
  * precision: GFCC_FP64 (right-preconditioned restarted GMRES with CGS2 Arnoldi, Jacobi
- *   preconditioner) or GFCC_FP32 / GFCC_FP32_BF16_3BODY (FP64 iterative refinement around
+ *   preconditioner) or GFCC_FP32 / GFCC_FP32_BF16_3BODY / GFCC_BF16_PAIRS (FP64 iterative
+ *   refinement around
  *   an inner GMRES whose sigma product runs in that precision; the stopping test is always
  *   the FP64 true relative residual).
  * tol: relative residual ||b - M x|| / ||b||. maxit: max iterations per right-hand side

@@ -10,6 +10,8 @@ float32 arithmetic; bfloat16 rounding is round-to-nearest-even on the float32 bi
 The three-body term's bfloat16 operands are two-term values x = hi + lo (hi = bf16(x),
 lo = bf16(x - hi)), and each of its two products is hi.hi + hi.lo + lo.hi accumulated in
 float32: the products run on bfloat16 inputs while the term keeps about 16 significant bits.
+With pairs=True the terms that contract the 2h1p block with Fvv, Foo and Wovvo are formed the
+same way (each block and the vector split into two-term pairs).
 """
 from __future__ import annotations
 
@@ -45,13 +47,34 @@ def f32_hbar(hb):
     return h
 
 
-def sigma_reduced(h32, x: np.ndarray, bf16_3body: bool) -> np.ndarray:
-    """sigma in float32 (complex64) arithmetic; three-body operands optionally in bf16."""
+def _pair_product(spec, a, b):
+    """a.b on two-term bf16 operands: ah.bh + ah.bl + al.bh in float32."""
+    ah, al = bf16_split(a)
+    bh, bl = bf16_split(b)
+    return (np.einsum(spec, ah, bh) + np.einsum(spec, ah, bl)
+            + np.einsum(spec, al, bh)).astype(np.float32)
+
+
+def sigma_reduced(h32, x: np.ndarray, bf16_3body: bool, pairs: bool = False) -> np.ndarray:
+    """sigma in float32 (complex64) arithmetic; three-body operands optionally in bf16.
+
+    pairs: also the terms that contract the 2h1p block with Fvv, Foo and Wovvo (T5, T6, T8 of
+    the IP sigma) on two-term bf16 operands; implies bf16_3body."""
+    bf16_3body = bf16_3body or pairs
     xr = x.real.astype(np.float32)
     xi = x.imag.astype(np.float32)
     out = []
     for part in (xr, xi):
         parts = sg.sigma_parts(h32, part)
+        if pairs:
+            o = h32.o
+            _, r2 = sg.unpack(part, o, h32.v)
+            z1 = np.zeros(part.shape[:-1] + (o,), np.float32)
+            parts["T5"] = sg.pack(z1, _pair_product("ae,...ije->...ija", h32.Fvv, r2))
+            t6 = _pair_product("ki,...kja->...ija", h32.Foo, r2)
+            parts["T6"] = sg.pack(z1, -(t6 - np.swapaxes(t6, -3, -2)))
+            t8 = _pair_product("maei,...mje->...ija", h32.Wovvo, r2)
+            parts["T8"] = sg.pack(z1, t8 - np.swapaxes(t8, -3, -2))
         if bf16_3body:
             o, v = h32.o, h32.v
             xh, xl = bf16_split(part)
@@ -70,21 +93,22 @@ def sigma_reduced(h32, x: np.ndarray, bf16_3body: bool) -> np.ndarray:
 
 
 class ReducedOperator(so.Operator):
-    def __init__(self, hb, bf16_3body: bool):
+    def __init__(self, hb, bf16_3body: bool, pairs: bool = False):
         super().__init__(hb)
         self.h32 = f32_hbar(hb)
         self.bf16 = bf16_3body
+        self.pairs = pairs
 
     def hbar(self, x):
         self.nmatvec += 1
-        return sigma_reduced(self.h32, x, self.bf16)
+        return sigma_reduced(self.h32, x, self.bf16, self.pairs)
 
 
 def gmres_ir(hb, b, omega, eta, tol=1e-8, inner_tol=1e-4, inner_maxit=100, restart=50,
-             max_outer=30, bf16_3body=True):
+             max_outer=30, bf16_3body=True, pairs=False):
     """Returns (x, outer steps, total inner iterations, final FP64 relative residual)."""
     op64 = so.Operator(hb)
-    lo = ReducedOperator(hb, bf16_3body)
+    lo = ReducedOperator(hb, bf16_3body, pairs)
     shift = omega - 1j * eta
     x = np.zeros(op64.D, dtype=complex)
     bn = np.linalg.norm(b)

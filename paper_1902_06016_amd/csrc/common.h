@@ -111,6 +111,8 @@ struct Operator {
   OpPieces<float> f32;
   DevBuf Vp_bf16, T2p_bf16;     // bf16 three-body operands (mixed precision): high parts
   DevBuf Vp_bf16_lo, T2p_bf16_lo;  // and the bf16 remainders (x = hi + lo)
+  DevBuf Weff_bf16, Weff_bf16_lo;  // Weff as bf16 pairs, rows padded to ldweff_bf, then zeros
+  int64_t ldweff_bf = 0;
   DevBuf WeffT, W1T, W4cT, WooT, VpT;  // transposed copies (adjoint)
   DevBuf diag;                  // [D] diagonal of Hbar_N
   DevBuf Crows;                 // [o][D] c_q rows for all occupied q
@@ -226,6 +228,14 @@ void cast_f64_bf16(gfcc_ctx* ctx, const double* s, __hip_bfloat16* d, int64_t n)
 void cast_f32_f64(gfcc_ctx* ctx, const float* s, double* d, int64_t n);
 void cast_f32_bf16(gfcc_ctx* ctx, const float* s, __hip_bfloat16* d, int64_t n);
 // x = hi + lo in bf16 (hi = bf16(x), lo = bf16(x - hi)): about 16 significant bits
+// hi/lo pairs of a [rows][cols] matrix into rows of ld >= cols, zero-filled up to total
+// elements (total >= rows * ld)
+void split_pad_f64_bf16(gfcc_ctx* ctx, const double* s, int64_t rows, int64_t cols,
+                        __hip_bfloat16* hi, __hip_bfloat16* lo, int64_t ld, int64_t total);
+// ovvo contraction with two-term bf16 operands (FP32 X2 and Z); false when the shape is not
+// the column-block one (the caller then uses the FP32 kernel)
+bool ovvo_bf3(gfcc_ctx* ctx, int o, int v, int nc, const void* Wh, const void* Wl, int64_t ldw,
+              const float* X2, int64_t ldx, float* Z);
 void split_f64_bf16(gfcc_ctx* ctx, const double* s, __hip_bfloat16* hi, __hip_bfloat16* lo,
                     int64_t n);
 void split_f32_bf16(gfcc_ctx* ctx, const float* s, __hip_bfloat16* hi, __hip_bfloat16* lo,
@@ -242,7 +252,7 @@ std::vector<int64_t> count_nonfinite(gfcc_ctx* ctx,
 // -------------------------------------------------------------------- sigma products
 // Y[D][nc] = Hbar_N X[D][nc] (or Hbar_N^T). Real columns; X and Y D-major with ld = nc.
 void sigma_block_f64(gfcc_ctx* ctx, int nc, const double* X, double* Y, bool transpose);
-void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, bool bf16_3body);
+void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, int precision);
 
 // -------------------------------------------------------------------- shifted solves
 // Every (omega, p) of the grid, solved in blocks of right-hand sides (solve.hip). G_out is

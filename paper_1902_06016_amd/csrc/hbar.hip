@@ -273,8 +273,8 @@ void collect(OpPieces<float>& f, std::vector<DevBuf>& out) {
 void collect(Operator& op, std::vector<DevBuf>& out) {
   collect(op.f64, out);
   collect(op.f32, out);
-  for (DevBuf* b : {&op.Vp_bf16, &op.T2p_bf16, &op.Vp_bf16_lo, &op.T2p_bf16_lo, &op.WeffT, &op.W1T, &op.W4cT, &op.WooT, &op.VpT,
-                    &op.diag, &op.Crows, &op.pairlut, &op.Foo, &op.Fov, &op.Fvv, &op.Woooo,
+  for (DevBuf* b : {&op.Vp_bf16, &op.T2p_bf16, &op.Vp_bf16_lo, &op.T2p_bf16_lo, &op.Weff_bf16,
+                    &op.Weff_bf16_lo, &op.WeffT, &op.W1T, &op.W4cT, &op.WooT, &op.VpT, &op.diag, &op.Crows, &op.pairlut, &op.Foo, &op.Fov, &op.Fvv, &op.Woooo,
                     &op.Wooov, &op.Wovvo, &op.Wovoo})
     if (b->p) out.push_back(std::move(*b));
 }
@@ -518,6 +518,14 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
       float* Wf = F(g.Weff, OV * OV + wpadf);
       cast_f64_f32(ctx, Weff, Wf, OV * OV);
       fill_f(ctx, Wf + OV * OV, wpadf, 0.0f);
+      // Weff as bf16 pairs for the two-term ovvo: rows padded to a multiple of 8 (16-byte
+      // chunks), then one slab (64) of zeros read past the last row
+      op.ldweff_bf = (OV + 7) / 8 * 8;
+      const int64_t nwb = OV * op.ldweff_bf + 64;
+      bb.take(op.Weff_bf16, (size_t)nwb * sizeof(__hip_bfloat16));
+      bb.take(op.Weff_bf16_lo, (size_t)nwb * sizeof(__hip_bfloat16));
+      split_pad_f64_bf16(ctx, Weff, OV, OV, op.Weff_bf16.as<__hip_bfloat16>(),
+                         op.Weff_bf16_lo.as<__hip_bfloat16>(), op.ldweff_bf, nwb);
       // bf16 three-body operands: Vp and -t2 packed as [(ij)a][d]
       bb.take(op.Vp_bf16, (size_t)PV * V * sizeof(__hip_bfloat16));
       bb.take(op.Vp_bf16_lo, (size_t)PV * V * sizeof(__hip_bfloat16));

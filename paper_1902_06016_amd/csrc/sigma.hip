@@ -137,7 +137,7 @@ void sigma_block_f64(gfcc_ctx* ctx, int nc, const double* X, double* Y, bool tra
   timer_end(ctx, 1, e_all);
 }
 
-void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, bool bf16_3body) {
+void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, int precision) {
   Operator& op = ctx->op;
   GFCC_REQUIRE(op.built, GFCC_ESTATE, "sigma: no operator built");
   GFCC_REQUIRE(op.keep & GFCC_KEEP_FP32, GFCC_ESTATE,
@@ -156,7 +156,7 @@ void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, bool bf16_
   hipEvent_t e_all = nullptr, e_ovvo = nullptr;
   timer_begin(ctx, 1, &e_all);
   gemm<float>(ctx, false, false, o, nc, (int)D, 1.0f, f.W1.as<float>(), D, X, nc, 0.0f, Y1, nc);
-  if (!bf16_3body) {
+  if (precision == GFCC_FP32) {
     GFCC_HIP(hipMemcpyAsync(S, X1, sizeof(float) * (size_t)o * nc, hipMemcpyDeviceToDevice,
                             ctx->stream));
     gemm<float>(ctx, true, false, v, nc, (int)PV, 1.0f, f.Vp.as<float>(), v, X2, nc, 0.0f,
@@ -195,7 +195,9 @@ void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, bool bf16_
   }
   woo_product<float>(ctx, false, P, (int64_t)v * nc, f.Woo.as<float>(), op.ldwoo, X2, Y2);
   timer_begin(ctx, 0, &e_ovvo);
-  gemm_ovvo<float>(ctx, false, o, v, nc, f.Weff.as<float>(), X2, nc, op.pairlut.as<int>(), Z);
+  if (!(precision == GFCC_BF16_PAIRS &&
+        ovvo_bf3(ctx, o, v, nc, op.Weff_bf16.p, op.Weff_bf16_lo.p, op.ldweff_bf, X2, nc, Z)))
+    gemm_ovvo<float>(ctx, false, o, v, nc, f.Weff.as<float>(), X2, nc, op.pairlut.as<int>(), Z);
   timer_end(ctx, 0, e_ovvo);
   hipLaunchKernelGGL(antisym_add_kernel<float>, dim3(grid_for(PV * nc)), dim3(256), 0,
                      ctx->stream, Z, o, v, nc, Y2);
@@ -214,9 +216,8 @@ extern "C" gfcc_status sigma_apply(gfcc_ctx* ctx, int nrhs, const void* x, void*
   GFCC_REQUIRE(nrhs >= 0, GFCC_EINVAL, "sigma_apply: nrhs < 0");
   if (nrhs == 0) return GFCC_OK;
   GFCC_REQUIRE(x && y, GFCC_EINVAL, "sigma_apply: null pointer");
-  GFCC_REQUIRE(precision == GFCC_FP64 || precision == GFCC_FP32 ||
-                   precision == GFCC_FP32_BF16_3BODY,
-               GFCC_EINVAL, "sigma_apply: unknown precision");
+  GFCC_REQUIRE(precision >= GFCC_FP64 && precision <= GFCC_BF16_PAIRS, GFCC_EINVAL,
+               "sigma_apply: unknown precision");
   GFCC_REQUIRE(!(transpose && precision != GFCC_FP64), GFCC_EINVAL,
                "sigma_apply: the transpose product is FP64 only");
   GFCC_REQUIRE(x != y, GFCC_EINVAL, "sigma_apply: x and y must not overlap");
@@ -242,7 +243,7 @@ extern "C" gfcc_status sigma_apply(gfcc_ctx* ctx, int nrhs, const void* x, void*
       sigma_block_f64(ctx, nc, bx.as<double>(), by.as<double>(), transpose != 0);
     } else {
       cast_f64_f32(ctx, bx.as<double>(), fx.as<float>(), D * nc);
-      sigma_block_f32(ctx, nc, fx.as<float>(), fy.as<float>(), precision == GFCC_FP32_BF16_3BODY);
+      sigma_block_f32(ctx, nc, fx.as<float>(), fy.as<float>(), precision);
       cast_f32_f64(ctx, fy.as<float>(), by.as<double>(), D * nc);
     }
     ctranspose(ctx, by.p, D, cnt, cnt, yc + (int64_t)r0 * D, D);

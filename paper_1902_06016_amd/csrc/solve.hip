@@ -708,7 +708,7 @@ struct GmresBlock {
       hipLaunchKernelGGL(f64_to_f32_kernel, dim3(gridn(n)), dim3(256), 0, st(),
                          reinterpret_cast<const double*>(Uv), Uf, n);
       GFCC_LAUNCH_CHECK();
-      sigma_block_f32(ctx, nc, Uf, Sf, precision == GFCC_FP32_BF16_3BODY);
+      sigma_block_f32(ctx, nc, Uf, Sf, precision);
       hipLaunchKernelGGL(f32_to_f64_kernel, dim3(gridn(n)), dim3(256), 0, st(), Sf,
                          reinterpret_cast<double*>(Wv), n);
       GFCC_LAUNCH_CHECK();
@@ -1128,9 +1128,8 @@ static void check_solve_args(gfcc_ctx* ctx, int nw, const double* omega, int np,
   GFCC_REQUIRE(tol > 0.0 && tol < 1.0, GFCC_EINVAL, "gfcc_solve: tol must be in (0, 1)");
   GFCC_REQUIRE(maxit >= 1, GFCC_EINVAL, "gfcc_solve: maxit must be >= 1");
   GFCC_REQUIRE(restart >= 1 && restart <= 200, GFCC_EINVAL, "gfcc_solve: restart in [1, 200]");
-  GFCC_REQUIRE(precision == GFCC_FP64 || precision == GFCC_FP32 ||
-                   precision == GFCC_FP32_BF16_3BODY,
-               GFCC_EINVAL, "gfcc_solve: unknown precision");
+  GFCC_REQUIRE(precision >= GFCC_FP64 && precision <= GFCC_BF16_PAIRS, GFCC_EINVAL,
+               "gfcc_solve: unknown precision");
   GFCC_REQUIRE(precision == GFCC_FP64 || (ctx->op.keep & GFCC_KEEP_FP32), GFCC_ESTATE,
                "gfcc_solve: reduced precision needs GFCC_KEEP_FP32 at build time");
   GFCC_REQUIRE(!(transpose && precision != GFCC_FP64), GFCC_EINVAL,

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libgfcc.so")
 GFCC_OK, GFCC_EINVAL, GFCC_ENOMEM, GFCC_EHIP, GFCC_ENOCONV, GFCC_EBREAKDOWN, GFCC_ESTATE = range(7)
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ENOCONV", 5: "EBREAKDOWN",
                 6: "ESTATE"}
-FP64, FP32, FP32_BF16_3BODY = 0, 1, 2
+FP64, FP32, FP32_BF16_3BODY, BF16_PAIRS = 0, 1, 2, 3
 KEEP_FP64, KEEP_FP32, KEEP_TRANSPOSE = 1, 2, 4
 EXPORT_BLOCKS = {"Foo": 0, "Fov": 1, "Fvv": 2, "Woooo": 3, "Wooov": 4, "Wovvo": 5, "Wovoo": 6,
                  "diag": 7}

@@ -188,11 +188,12 @@ def test_o42v186_adjoint_vs_finite_differences(gpu_ctx, benzene):
     gpu_ctx.build_from_problem(prob)
 
 
-def test_mixed_block_reduced_shape(gpu_ctx):
+@pytest.mark.parametrize("prec", [gfcc.FP32_BF16_3BODY, gfcc.BF16_PAIRS])
+def test_mixed_block_reduced_shape(gpu_ctx, prec):
     """A 32 omega x 16 p block in one launch at a reduced adenine-like shape: FP32 sigma with the
-    three-body term in bf16 and FP64 refinement reach the FP64 residual target and match the
-    FP64 solve's A within 1e-6."""
-    print("[mixed block]", flush=True)
+    three-body term (or every large contraction) on two-term bf16 and FP64 refinement reach the
+    FP64 residual target and match the FP64 solve's A within 1e-6."""
+    print(f"[mixed block prec={prec}]", flush=True)
     cfg = synth.WORKLOADS["o70v260_mixed"]
     o, v = 30, 90
     prob = synth.make_problem(o, v, cfg["seed"])
@@ -200,7 +201,7 @@ def test_mixed_block_reduced_shape(gpu_ctx):
     om = synth.omega_grid(cfg["omega"])
     ps = synth.valence_p(o, cfg["np"])
     mixed = gpu_ctx.gfcc_solve(om, ps, cfg["eta"], tol=1e-8, restart=12, block=512,
-                               precision=gfcc.FP32_BF16_3BODY)
+                               precision=prec)
     full = gpu_ctx.gfcc_solve(om, ps, cfg["eta"], tol=1e-12, restart=30, block=512)
     assert mixed.resid.max() <= 1e-8
     Am, Af = gfcc.spectral_function(mixed.G), gfcc.spectral_function(full.G)

@@ -131,7 +131,7 @@ def test_mor_refinement(gpu_ctx, model):
     m.close()
 
 
-@pytest.mark.parametrize("prec", [gfcc.FP32, gfcc.FP32_BF16_3BODY])
+@pytest.mark.parametrize("prec", [gfcc.FP32, gfcc.FP32_BF16_3BODY, gfcc.BF16_PAIRS])
 def test_mixed_precision_solve(gpu_ctx, prec):
     print(f"[mixed prec={prec}]", flush=True)
     cfg = synth.WORKLOADS["o10v20"]

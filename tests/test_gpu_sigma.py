@@ -52,9 +52,14 @@ def test_sigma_fp64(gpu_ctx, o, v, seed, nrhs, transpose):
     assert err < 1e-13, err
 
 
-@pytest.mark.parametrize("prec,tol", [(1, 2e-6), (2, 2e-6)])
-@pytest.mark.parametrize("nrhs", [5, 64])
-def test_sigma_reduced_precision(gpu_ctx, prec, tol, nrhs):
+# FP32 and FP32 + two-term bf16 three-body: a few float32 roundings of the largest terms
+# (measured 2e-7 against FP64). BF16_PAIRS: every large contraction carries about 16 bits, and
+# sums over o v terms grow that by their cancellation (the oracle's emulation is 8e-6 off FP64
+# at this shape), so 5e-5 against FP64 and 4e-5 against the emulation, which rounds the
+# Fvv, Foo and Wovvo blocks one by one where the kernel rounds their sum.
+@pytest.mark.parametrize("prec,tol,tol_emu", [(1, 2e-6, 2e-6), (2, 2e-6, 2e-6), (3, 5e-5, 4e-5)])
+@pytest.mark.parametrize("nrhs", [5, 64, 128])
+def test_sigma_reduced_precision(gpu_ctx, prec, tol, tol_emu, nrhs):
     o, v, seed = 13, 37, 2
     print(f"[sigma_mixed prec={prec} nrhs={nrhs}]", flush=True)
     prob = synth.make_problem(o, v, seed)
@@ -71,8 +76,8 @@ def test_sigma_reduced_precision(gpu_ctx, prec, tol, nrhs):
     # the oracle's emulation of the same reduced-precision product (float32 operator, the
     # three-body term from two-term bf16 operands)
     from oracle import mixed as omix
-    emu = omix.sigma_reduced(omix.f32_hbar(hb), x, bf16_3body=prec == 2)
-    assert np.abs(y - emu).max() <= 2e-6 * np.abs(ref).max()
+    emu = omix.sigma_reduced(omix.f32_hbar(hb), x, bf16_3body=prec >= 2, pairs=prec == 3)
+    assert np.abs(y - emu).max() <= tol_emu * np.abs(ref).max()
     if prec == 2:
         # the two-term bf16 three-body term: error within 1e-4 of that term's size
         t9 = osig.sigma_parts(hb, x)["T9"]

@@ -188,13 +188,45 @@ def test_bf16_three_body_term_keeps_16_bits(model):
     assert np.abs(full - osig.sigma(hb, x)).max() <= 1e-6 * np.abs(osig.sigma(hb, x)).max()
 
 
+def test_bf16_pair_products_within_their_bound(model):
+    """The two-term bf16 forms of the T5, T6 and T8 contractions differ from the FP64 ones by
+    at most 2^-14 of sum |a||b| over the contracted index (operand pairs carry 16 bits, the
+    dropped lo.lo term is 2^-18 of a product, float32 accumulation adds K 2^-24 at most);
+    plain bf16 operands miss this bound."""
+    p, hb, H, lam, ps, B, C = model
+    o, v = p.o, p.v
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((3, osig.dim(o, v)))
+    _, r2 = osig.unpack(x, o, v)
+    for spec, blk in (("ae,...ije->...ija", hb.Fvv), ("ki,...kja->...ija", hb.Foo),
+                      ("maei,...mje->...ija", hb.Wovvo)):
+        exact = np.einsum(spec, blk, r2)
+        bound = 2.0 ** -14 * np.einsum(spec, np.abs(blk), np.abs(r2))
+        got = omix._pair_product(spec, blk.astype(np.float32), r2.astype(np.float32))
+        assert np.all(np.abs(got - exact) <= bound), spec
+        single = np.einsum(spec, omix.bf16_round(blk), omix.bf16_round(r2))
+        assert np.any(np.abs(single - exact) > bound), spec
+
+
+def test_bf16_pairs_sigma_close_to_fp64(model):
+    p, hb, H, lam, ps, B, C = model
+    rng = np.random.default_rng(6)
+    D = osig.dim(p.o, p.v)
+    x = rng.standard_normal((2, D)) + 1j * rng.standard_normal((2, D))
+    y = osig.sigma(hb, x)
+    got = omix.sigma_reduced(omix.f32_hbar(hb), x, bf16_3body=False, pairs=True)
+    assert np.abs(got - y).max() <= 1e-4 * np.abs(y).max()
+
+
 def test_gmres_ir_reaches_fp64_tolerance(model):
     p, hb, H, lam, ps, B, C = model
     om, eta = -lam[0] + 0.05, 0.005
-    x, outer, inner, rel = omix.gmres_ir(hb, B[:, 1].astype(complex), om, eta, tol=1e-10)
-    assert rel <= 1e-10 and outer >= 2
     xd = np.linalg.solve(osolve.shifted(H, om, eta), B[:, 1].astype(complex))
-    assert np.abs(x - xd).max() < 1e-8 * np.abs(xd).max()
+    for pairs in (False, True):
+        x, outer, inner, rel = omix.gmres_ir(hb, B[:, 1].astype(complex), om, eta, tol=1e-10,
+                                             pairs=pairs)
+        assert rel <= 1e-10 and outer >= 2
+        assert np.abs(x - xd).max() < 1e-8 * np.abs(xd).max()
 
 
 def test_adjoint_gradient_matches_finite_differences(model):
