@@ -19,9 +19,7 @@
 namespace gfcc {
 namespace {
 
-constexpr int BM = 128, BN = 128, BK = 64, NT = 256, LDK = BK + 8;   // 144-byte LDS pitch
-constexpr int ACH = BM * (BK / 8) / NT;   // 16-byte A chunks per thread, slab and half (4)
-constexpr int RB = BK / 2;                // B rows per thread and slab (32)
+constexpr int BM = 128, BN = 128, NT = 256;
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -35,7 +33,7 @@ struct Bf3Args {
   const float* zrow;          // >= nc zeros
   float* Z;                   // [M][N]
   int64_t ldx;
-  int o, v, nc, M, N, K, mtiles, ntiles, nslabs;
+  int o, v, nc, M, N, K, mtiles, ntiles;
 };
 
 // round to nearest even bfloat16 (finite inputs), as raw bits
@@ -45,7 +43,12 @@ __device__ __forceinline__ unsigned short bf16_bits(float x) {
   return (unsigned short)(u >> 16);
 }
 
-__global__ __launch_bounds__(NT, 2) void ovvo_bf3_kernel(Bf3Args p) {
+template <int BK, int OCC>
+__global__ __launch_bounds__(NT, OCC) void ovvo_bf3_kernel(Bf3Args p) {
+  constexpr int LDK = BK + 8;               // LDS row pitch (16 bytes of padding)
+  constexpr int CPR = BK / 8;               // 16-byte A chunks per tile row and slab
+  constexpr int ACH = BM * CPR / NT;        // A chunks per thread, slab and half
+  constexpr int RB = BK / 2;                // B rows per thread and slab
   __shared__ __attribute__((aligned(16))) unsigned short Ah[BM][LDK];
   __shared__ __attribute__((aligned(16))) unsigned short Al[BM][LDK];
   __shared__ __attribute__((aligned(16))) unsigned short Bh[BN][LDK];
@@ -64,7 +67,7 @@ __global__ __launch_bounds__(NT, 2) void ovvo_bf3_kernel(Bf3Args p) {
   const int idx = L - grp * GM * p.ntiles;
   const int mt = grp * GM + idx % rows, nt = idx / rows;
   const int m0 = mt * BM, n0 = nt * BN;
-  const int o = p.o, v = p.v, M = p.M;
+  const int o = p.o, v = p.v, M = p.M, nslabs = (p.K + BK - 1) / BK;
 
   // B ownership: column bn of the tile, rows kh * RB .. kh * RB + RB - 1 of every slab
   const int j = n0 / p.nc;
@@ -75,12 +78,12 @@ __global__ __launch_bounds__(NT, 2) void ovvo_bf3_kernel(Bf3Args p) {
   const int zlo = (j * v + BK - 1) / BK, zhi = ((j + 1) * v) / BK;
   auto skip = [&](int s) { return (s >= zlo && s < zhi) ? zhi : s; };
 
-  // A ownership: chunk r is row (tid + NT r) / 8, k offset 8 ((tid + NT r) % 8) of the slab
+  // A ownership: chunk r is row (tid + NT r) / CPR, k offset 8 ((tid + NT r) % CPR) of the slab
   int64_t aoff[ACH];
 #pragma unroll
   for (int r = 0; r < ACH; ++r) {
     const int f = tid + NT * r;
-    aoff[r] = (int64_t)min(m0 + (f >> 3), M - 1) * p.ldw + (f & 7) * 8;
+    aoff[r] = (int64_t)min(m0 + f / CPR, M - 1) * p.ldw + (f % CPR) * 8;
   }
 
   // scalar base address and row stride of X2 row (pair(mm, j), ee), or of the zero row
@@ -126,8 +129,8 @@ __global__ __launch_bounds__(NT, 2) void ovvo_bf3_kernel(Bf3Args p) {
 #pragma unroll
     for (int r = 0; r < ACH; ++r) {
       const int f = tid + NT * r;
-      *reinterpret_cast<us8*>(&Ah[f >> 3][(f & 7) * 8]) = rah[r];
-      *reinterpret_cast<us8*>(&Al[f >> 3][(f & 7) * 8]) = ral[r];
+      *reinterpret_cast<us8*>(&Ah[f / CPR][(f % CPR) * 8]) = rah[r];
+      *reinterpret_cast<us8*>(&Al[f / CPR][(f % CPR) * 8]) = ral[r];
     }
 #pragma unroll
     for (int g = 0; g < RB / 8; ++g) {
@@ -184,10 +187,10 @@ __global__ __launch_bounds__(NT, 2) void ovvo_bf3_kernel(Bf3Args p) {
     store();
     __syncthreads();
     const int sn = skip(s + 1);
-    if (sn < p.nslabs) load(sn);
+    if (sn < nslabs) load(sn);
     compute();
     __syncthreads();
-    if (sn >= p.nslabs) break;
+    if (sn >= nslabs) break;
     s = sn;
   }
 
@@ -207,7 +210,7 @@ __global__ __launch_bounds__(NT, 2) void ovvo_bf3_kernel(Bf3Args p) {
 
 bool ovvo_bf3(gfcc_ctx* ctx, int o, int v, int nc, const void* Wh, const void* Wl, int64_t ldw,
               const float* X2, int64_t ldx, float* Z) {
-  if (o < 2 || v < RB || nc < BN || nc % BN != 0 || ldx < nc) return false;
+  if (o < 2 || v < 32 || nc < BN || nc % BN != 0 || ldx < nc) return false;
   const int64_t OV = (int64_t)o * v;
   if (!Wh || !Wl || ldw < OV || ldw % 8 != 0 || reinterpret_cast<uintptr_t>(Wh) % 16 != 0 ||
       reinterpret_cast<uintptr_t>(Wl) % 16 != 0)
@@ -224,12 +227,13 @@ bool ovvo_bf3(gfcc_ctx* ctx, int o, int v, int nc, const void* Wh, const void* W
   p.M = (int)OV; p.K = (int)OV; p.N = o * nc;
   p.mtiles = (p.M + BM - 1) / BM;
   p.ntiles = p.N / BN;
-  p.nslabs = (p.K + BK - 1) / BK;
   const int64_t tiles = (int64_t)p.mtiles * p.ntiles;
   if (tiles >= (1LL << 31) - 8) return false;
   p.zrow = static_cast<const float*>(zero_row(ctx, (size_t)nc * sizeof(float)));
-  hipLaunchKernelGGL(ovvo_bf3_kernel, dim3((unsigned)((tiles + 7) / 8 * 8)), dim3(NT), 0,
-                     ctx->stream, p);
+  const dim3 grid((unsigned)((tiles + 7) / 8 * 8));
+  // 128 x 128 x 32 slabs with three workgroups per CU measured the same (250 TF/s useful at
+  // o=70, v=260, 512 right-hand sides): the tile's operand traffic, not occupancy, limits it
+  hipLaunchKernelGGL((ovvo_bf3_kernel<64, 2>), grid, dim3(NT), 0, ctx->stream, p);
   GFCC_LAUNCH_CHECK();
   return true;
 }
