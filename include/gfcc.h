@@ -56,11 +56,11 @@ enum {
   GFCC_FP64 = 0,            /* all terms in FP64 (MFMA f64) */
   GFCC_FP32 = 1,            /* all terms in FP32 (MFMA f32, FP32 accumulation) */
   GFCC_FP32_BF16_3BODY = 2, /* FP32, with the three-body T2*<kl||cd> term on BF16 MFMA */
-  GFCC_BF16_PAIRS = 3       /* FP32 vectors; the ovvo (T5, T6, T8 through Weff) and three-body
-                               contractions on BF16 MFMA with two-term operands x = hi + lo
-                               (hi.hi + hi.lo + lo.hi, FP32 accumulation, about 16 bits); the
-                               ovvo takes this path when 2 * nrhs of a block is a multiple of
-                               128 and the FP32 kernel otherwise */
+  GFCC_BF16_PAIRS = 3       /* FP32, with the ovvo contraction (T5, T6, T8 through Weff, most
+                               of the flops) on BF16 MFMA with two-term operands x = hi + lo
+                               (hi.hi + hi.lo + lo.hi, FP32 accumulation, about 16 bits) when
+                               2 * nrhs of a block is a multiple of 128 and v >= 32, on FP32
+                               MFMA otherwise */
 };
 
 /* Bit mask for build_hbar_operands: which operator copies to keep on the device. */

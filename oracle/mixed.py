@@ -11,7 +11,7 @@ The three-body term's bfloat16 operands are two-term values x = hi + lo (hi = bf
 lo = bf16(x - hi)), and each of its two products is hi.hi + hi.lo + lo.hi accumulated in
 float32: the products run on bfloat16 inputs while the term keeps about 16 significant bits.
 With pairs=True the terms that contract the 2h1p block with Fvv, Foo and Wovvo are formed the
-same way (each block and the vector split into two-term pairs).
+same way (each block and the vector split into two-term pairs) instead.
 """
 from __future__ import annotations
 
@@ -58,9 +58,8 @@ def _pair_product(spec, a, b):
 def sigma_reduced(h32, x: np.ndarray, bf16_3body: bool, pairs: bool = False) -> np.ndarray:
     """sigma in float32 (complex64) arithmetic; three-body operands optionally in bf16.
 
-    pairs: also the terms that contract the 2h1p block with Fvv, Foo and Wovvo (T5, T6, T8 of
-    the IP sigma) on two-term bf16 operands; implies bf16_3body."""
-    bf16_3body = bf16_3body or pairs
+    pairs: the terms that contract the 2h1p block with Fvv, Foo and Wovvo (T5, T6, T8 of the
+    IP sigma) on two-term bf16 operands."""
     xr = x.real.astype(np.float32)
     xi = x.imag.astype(np.float32)
     out = []

@@ -156,7 +156,7 @@ void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, int precis
   hipEvent_t e_all = nullptr, e_ovvo = nullptr;
   timer_begin(ctx, 1, &e_all);
   gemm<float>(ctx, false, false, o, nc, (int)D, 1.0f, f.W1.as<float>(), D, X, nc, 0.0f, Y1, nc);
-  if (precision == GFCC_FP32) {
+  if (precision != GFCC_FP32_BF16_3BODY) {
     GFCC_HIP(hipMemcpyAsync(S, X1, sizeof(float) * (size_t)o * nc, hipMemcpyDeviceToDevice,
                             ctx->stream));
     gemm<float>(ctx, true, false, v, nc, (int)PV, 1.0f, f.Vp.as<float>(), v, X2, nc, 0.0f,

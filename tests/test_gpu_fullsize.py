@@ -191,7 +191,7 @@ def test_o42v186_adjoint_vs_finite_differences(gpu_ctx, benzene):
 @pytest.mark.parametrize("prec", [gfcc.FP32_BF16_3BODY, gfcc.BF16_PAIRS])
 def test_mixed_block_reduced_shape(gpu_ctx, prec):
     """A 32 omega x 16 p block in one launch at a reduced adenine-like shape: FP32 sigma with the
-    three-body term (or every large contraction) on two-term bf16 and FP64 refinement reach the
+    three-body term (or the ovvo contraction) on two-term bf16 and FP64 refinement reach the
     FP64 residual target and match the FP64 solve's A within 1e-6."""
     print(f"[mixed block prec={prec}]", flush=True)
     cfg = synth.WORKLOADS["o70v260_mixed"]

@@ -76,7 +76,7 @@ def test_sigma_reduced_precision(gpu_ctx, prec, tol, tol_emu, nrhs):
     # the oracle's emulation of the same reduced-precision product (float32 operator, the
     # three-body term from two-term bf16 operands)
     from oracle import mixed as omix
-    emu = omix.sigma_reduced(omix.f32_hbar(hb), x, bf16_3body=prec >= 2, pairs=prec == 3)
+    emu = omix.sigma_reduced(omix.f32_hbar(hb), x, bf16_3body=prec == 2, pairs=prec == 3)
     assert np.abs(y - emu).max() <= tol_emu * np.abs(ref).max()
     if prec == 2:
         # the two-term bf16 three-body term: error within 1e-4 of that term's size

@@ -104,6 +104,23 @@ def test_errors(gpu_ctx):
     with pytest.raises(gfcc.GfccError) as e:
         gpu_ctx.gfcc_solve([-0.5], [1], 0.0)  # eta = 0
     assert e.value.status == gfcc.GFCC_EINVAL
+    # precisions: unknown values, reduced ones without the FP32 copies, reduced transposes
+    for prec in (-1, 4):
+        with pytest.raises(gfcc.GfccError) as e:
+            gpu_ctx.gfcc_solve([-0.5], [0], 0.01, precision=prec)
+        assert e.value.status == gfcc.GFCC_EINVAL
+        with pytest.raises(gfcc.GfccError) as e:
+            gpu_ctx.sigma_apply(torch.zeros((1, gpu_ctx.D), dtype=torch.complex128,
+                                            device="cuda"), precision=prec)
+        assert e.value.status == gfcc.GFCC_EINVAL
+    for prec in (gfcc.FP32, gfcc.FP32_BF16_3BODY, gfcc.BF16_PAIRS):
+        with pytest.raises(gfcc.GfccError) as e:
+            gpu_ctx.gfcc_solve([-0.5], [0], 0.01, precision=prec)
+        assert e.value.status == gfcc.GFCC_ESTATE
+        with pytest.raises(gfcc.GfccError) as e:
+            gpu_ctx.sigma_apply(torch.zeros((1, gpu_ctx.D), dtype=torch.complex128,
+                                            device="cuda"), transpose=True, precision=prec)
+        assert e.value.status == gfcc.GFCC_EINVAL
     r = gpu_ctx.gfcc_solve([-0.5, -0.4], [0, 1], 0.01, tol=1e-14, maxit=1, allow_noconv=True)
     assert r.status == gfcc.GFCC_ENOCONV and r.iters.max() == 1
     # limits: block at most 2048, restart 1..200

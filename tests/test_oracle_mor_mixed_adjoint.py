@@ -224,7 +224,7 @@ def test_gmres_ir_reaches_fp64_tolerance(model):
     xd = np.linalg.solve(osolve.shifted(H, om, eta), B[:, 1].astype(complex))
     for pairs in (False, True):
         x, outer, inner, rel = omix.gmres_ir(hb, B[:, 1].astype(complex), om, eta, tol=1e-10,
-                                             pairs=pairs)
+                                             bf16_3body=not pairs, pairs=pairs)
         assert rel <= 1e-10 and outer >= 2
         assert np.abs(x - xd).max() < 1e-8 * np.abs(xd).max()
 
