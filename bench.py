@@ -525,8 +525,9 @@ def form_adjoint(ctx, cfg, gfcc, inputs):
 
 def form_mixed(cfg, gfcc, torch):
     """Batched mixed precision at the adenine/cc-pVDZ shape: one launch of 32 omega x 16 p
-    right-hand sides, FP32 sigma with the three-body term on bf16 matrix cores, FP64
-    refinement to relative residual 1e-8; the same block in FP64 for the error and the rate."""
+    right-hand sides, FP64 refinement to relative residual 1e-8 around a reduced sigma (ovvo on
+    two-term bf16 pairs; FP32 with the three-body term on two-term bf16; FP32), and the same
+    block in FP64 for the error and the rate."""
     import synth
     o, v = cfg["o"], cfg["v"]
     t0 = time.time()

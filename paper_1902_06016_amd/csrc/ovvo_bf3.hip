@@ -19,7 +19,7 @@
 namespace gfcc {
 namespace {
 
-constexpr int BM = 128, BN = 128, NT = 256;
+constexpr int BN = 128;
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -43,12 +43,14 @@ __device__ __forceinline__ unsigned short bf16_bits(float x) {
   return (unsigned short)(u >> 16);
 }
 
-template <int BK, int OCC>
-__global__ __launch_bounds__(NT, OCC) void ovvo_bf3_kernel(Bf3Args p) {
+// WM x 2 wavefronts of 64 x 64: tile (64 WM) x 128
+template <int BK, int WM, int OCC>
+__global__ __launch_bounds__(128 * WM, OCC) void ovvo_bf3_kernel(Bf3Args p) {
+  constexpr int BM = 64 * WM, NT = 128 * WM;
   constexpr int LDK = BK + 8;               // LDS row pitch (16 bytes of padding)
   constexpr int CPR = BK / 8;               // 16-byte A chunks per tile row and slab
   constexpr int ACH = BM * CPR / NT;        // A chunks per thread, slab and half
-  constexpr int RB = BK / 2;                // B rows per thread and slab
+  constexpr int RB = BK * BN / NT;          // B rows per thread and slab
   __shared__ __attribute__((aligned(16))) unsigned short Ah[BM][LDK];
   __shared__ __attribute__((aligned(16))) unsigned short Al[BM][LDK];
   __shared__ __attribute__((aligned(16))) unsigned short Bh[BN][LDK];
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(NT, OCC) void ovvo_bf3_kernel(Bf3Args p) {
   // B ownership: column bn of the tile, rows kh * RB .. kh * RB + RB - 1 of every slab
   const int j = n0 / p.nc;
   const int bn = tid & (BN - 1);
-  const int kh = __builtin_amdgcn_readfirstlane(tid >> 7);
+  const int kh = __builtin_amdgcn_readfirstlane(tid / BN);
   const int c = n0 + bn - j * p.nc;
   // slabs [zlo, zhi) lie wholly inside the zero segment m = j
   const int zlo = (j * v + BK - 1) / BK, zhi = ((j + 1) * v) / BK;
@@ -225,15 +227,17 @@ bool ovvo_bf3(gfcc_ctx* ctx, int o, int v, int nc, const void* Wh, const void* W
   p.Z = Z;
   p.o = o; p.v = v; p.nc = nc;
   p.M = (int)OV; p.K = (int)OV; p.N = o * nc;
+  constexpr int WM = 2, BM = 64 * WM;
   p.mtiles = (p.M + BM - 1) / BM;
   p.ntiles = p.N / BN;
   const int64_t tiles = (int64_t)p.mtiles * p.ntiles;
   if (tiles >= (1LL << 31) - 8) return false;
   p.zrow = static_cast<const float*>(zero_row(ctx, (size_t)nc * sizeof(float)));
   const dim3 grid((unsigned)((tiles + 7) / 8 * 8));
-  // 128 x 128 x 32 slabs with three workgroups per CU measured the same (250 TF/s useful at
-  // o=70, v=260, 512 right-hand sides): the tile's operand traffic, not occupancy, limits it
-  hipLaunchKernelGGL((ovvo_bf3_kernel<64, 2>), grid, dim3(NT), 0, ctx->stream, p);
+  // Measured alternatives at o=70, v=260, 512 right-hand sides, all within 3% of this one
+  // (about 250 TF/s useful): 32-deep slabs at three workgroups per CU, 256 x 128 tiles of 8
+  // wavefronts, and XOR-swizzled LDS rows (half the bank conflicts)
+  hipLaunchKernelGGL((ovvo_bf3_kernel<64, WM, 2>), grid, dim3(128 * WM), 0, ctx->stream, p);
   GFCC_LAUNCH_CHECK();
   return true;
 }
