@@ -85,6 +85,27 @@ def test_sigma_reduced_precision(gpu_ctx, prec, tol, tol_emu, nrhs):
         assert e9 < 1e-4, e9
 
 
+@pytest.mark.parametrize("o,v,nrhs", [(5, 130, 64), (3, 64, 128)])
+def test_sigma_pairs_skip_and_tiles(gpu_ctx, o, v, nrhs):
+    """The two-term bf16 ovvo where whole 64-row slabs lie inside a tile's zero segment m = j
+    (v >= 64, skipped), with a ragged last M-tile and several column blocks: against FP64 and
+    the oracle's emulation, at the bounds of the reduced-precision test above."""
+    print(f"[sigma pairs o={o} v={v} nrhs={nrhs}]", flush=True)
+    prob = synth.make_problem(o, v, 4)
+    hb = ohbar.build_hbar_from_problem(prob)
+    from paper_1902_06016_amd import gfcc
+    from oracle import mixed as omix
+    gpu_ctx.build_from_problem(prob, keep=gfcc.KEEP_FP32)
+    D = osig.dim(o, v)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((nrhs, D)) + 1j * rng.standard_normal((nrhs, D))
+    y = gpu_ctx.sigma_apply(torch.from_numpy(x).cuda(), precision=gfcc.BF16_PAIRS).cpu().numpy()
+    ref = osig.sigma(hb, x)
+    assert np.abs(y - ref).max() <= 5e-5 * np.abs(ref).max()
+    emu = omix.sigma_reduced(omix.f32_hbar(hb), x, bf16_3body=False, pairs=True)
+    assert np.abs(y - emu).max() <= 4e-5 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("transpose", [False, True])
 def test_sigma_more_than_one_chunk(gpu_ctx, transpose):
     """sigma_apply works through chunks of 2048 right-hand sides: 2100 vectors (a full chunk
