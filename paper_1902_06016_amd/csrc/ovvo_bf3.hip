@@ -102,7 +102,8 @@ __global__ __launch_bounds__(128 * WM, OCC) void ovvo_bf3_kernel(Bf3Args p) {
   us8 rah[ACH], ral[ACH];
   float rb[RB];
   unsigned rneg = 0;
-  auto load = [&](int s) {
+  // (m, e) of the first B row this thread loads in slab s: k = s BK + kh RB = m v + e
+  auto load = [&](int s, int m, int e) {
     const int k0 = s * BK;
 #pragma unroll
     for (int r = 0; r < ACH; ++r) {
@@ -113,16 +114,18 @@ __global__ __launch_bounds__(128 * WM, OCC) void ovvo_bf3_kernel(Bf3Args p) {
     // (v >= RB); rows r < rc lie in segment m. Rows with m >= o (past K) or m = j read the
     // zero row with stride 0. All of it is wavefront-uniform, written as masks so that it
     // stays branch-free scalar code.
-    const int kb = k0 + kh * RB;
-    const int m = kb / v, e = kb - m * v, rc = v - e;
+    const int rc = v - e;
     uint64_t q0, d0, q1, d1;
     seg(m, e, q0, d0);
     seg(m + 1, 0, q1, d1);
+    // row r of segment m + 1 sits at q1 + (r - rc) d1: both bases advance by one row stride
+    // per row (wrapping arithmetic), so each row costs two 64-bit adds and one select
+    uint64_t a0 = q0, a1 = q1 - (uint64_t)rc * d1;
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      const uint64_t mk = 0ull - (uint64_t)(r >= rc);
-      const uint64_t a = ((q1 + (uint64_t)(r - rc) * d1) & mk) | ((q0 + (uint64_t)r * d0) & ~mk);
-      rb[r] = reinterpret_cast<gptr>(a)[c];
+      rb[r] = reinterpret_cast<gptr>(r < rc ? a0 : a1)[c];
+      a0 += d0;
+      a1 += d1;
     }
     const unsigned hi = rc >= RB ? 0u : ~0u << rc;   // rows in segment m + 1
     rneg = (m > j ? ~hi : 0u) | (m + 1 > j ? hi : 0u);
@@ -184,12 +187,21 @@ __global__ __launch_bounds__(128 * WM, OCC) void ovvo_bf3_kernel(Bf3Args p) {
 
   // at least one slab lies outside the zero segment (o >= 2)
   int s = skip(0);
-  load(s);
+  int lm = (s * BK + kh * RB) / v, le = s * BK + kh * RB - lm * v;
+  load(s, lm, le);
   while (true) {
     store();
     __syncthreads();
     const int sn = skip(s + 1);
-    if (sn < nslabs) load(sn);
+    if (sn < nslabs) {
+      // advance (m, e) by the slabs moved over (at most v + 2 BK rows after a skip)
+      le += (sn - s) * BK;
+      while (le >= v) {
+        le -= v;
+        ++lm;
+      }
+      load(sn, lm, le);
+    }
     compute();
     __syncthreads();
     if (sn >= nslabs) break;
