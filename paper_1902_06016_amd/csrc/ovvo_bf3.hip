@@ -112,8 +112,7 @@ __global__ __launch_bounds__(128 * WM, OCC) void ovvo_bf3_kernel(Bf3Args p) {
     }
     // rows k = (m, e): the RB rows start at (m, e) and cross at most into segment m + 1
     // (v >= RB); rows r < rc lie in segment m. Rows with m >= o (past K) or m = j read the
-    // zero row with stride 0. All of it is wavefront-uniform, written as masks so that it
-    // stays branch-free scalar code.
+    // zero row with stride 0. All of it is wavefront-uniform scalar code without branches.
     const int rc = v - e;
     uint64_t q0, d0, q1, d1;
     seg(m, e, q0, d0);
@@ -171,8 +170,8 @@ __global__ __launch_bounds__(128 * WM, OCC) void ovvo_bf3_kernel(Bf3Args p) {
         bh[i] = *reinterpret_cast<const bf8*>(&Bh[wn * 64 + i * 16 + rl][ks * 32 + kq]);
         bl[i] = *reinterpret_cast<const bf8*>(&Bl[wn * 64 + i * 16 + rl][ks * 32 + kq]);
       }
-      // the three products in separate passes over the 16 blocks, so that no MFMA waits on
-      // the previous one's accumulator
+      // lo.hi, hi.lo, then hi.hi, in separate passes over the 16 blocks, so that no MFMA
+      // waits on the previous one's accumulator
 #pragma unroll
       for (int t = 0; t < 3; ++t)
 #pragma unroll
@@ -180,8 +179,7 @@ __global__ __launch_bounds__(128 * WM, OCC) void ovvo_bf3_kernel(Bf3Args p) {
 #pragma unroll
           for (int q = 0; q < 4; ++q)
             acc[i][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                t == 2 ? ah[i] : (t == 0 ? al[i] : ah[i]), t == 1 ? bl[q] : bh[q], acc[i][q],
-                0, 0, 0);
+                t == 0 ? al[i] : ah[i], t == 1 ? bl[q] : bh[q], acc[i][q], 0, 0, 0);
     }
   };
 
