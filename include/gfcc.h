@@ -66,7 +66,7 @@ enum {
 /* Bit mask for build_hbar_operands: which operator copies to keep on the device. */
 enum {
   GFCC_KEEP_FP64 = 1,       /* always kept */
-  GFCC_KEEP_FP32 = 2,       /* FP32 copies (and BF16 three-body operands) for mixed solves */
+  GFCC_KEEP_FP32 = 2,       /* FP32 copies and BF16 pairs (three-body, Weff) for mixed solves */
   GFCC_KEEP_TRANSPOSE = 4   /* transposed copies for fast H-bar^T products (adjoint) */
 };
 

@@ -41,3 +41,14 @@ def test_host_only_entry_points():
                                None, None) == gfcc.GFCC_EINVAL
     assert gfcc.lib.mor_eval(None, 1, None, None, None) == gfcc.GFCC_EINVAL
     assert gfcc.lib.gfcc_destroy(None) == gfcc.GFCC_OK
+
+
+def test_binding_constants_match_header():
+    """Every enum value the header defines has the same value in the Python binding."""
+    from paper_1902_06016_amd import gfcc
+    text = open(os.path.join(ROOT, "include", "gfcc.h")).read()
+    found = dict((k, int(v)) for k, v in re.findall(r"^\s*GFCC_([A-Z0-9_]+) = (\d+)", text, re.M))
+    assert {"FP64", "FP32", "FP32_BF16_3BODY", "BF16_PAIRS", "KEEP_FP32", "ESTATE"} <= set(found)
+    for name, val in found.items():
+        py = getattr(gfcc, name, getattr(gfcc, "GFCC_" + name, None))
+        assert py == val, (name, py, val)
