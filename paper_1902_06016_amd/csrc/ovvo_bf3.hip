@@ -23,6 +23,9 @@ constexpr int BN = 128;
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
 typedef const float __attribute__((address_space(1)))* gptr;   // global loads, not flat
 
 struct Bf3Args {
@@ -35,13 +38,6 @@ struct Bf3Args {
   int64_t ldx;
   int o, v, nc, M, N, K, mtiles, ntiles;
 };
-
-// round to nearest even bfloat16 (finite inputs), as raw bits
-__device__ __forceinline__ unsigned short bf16_bits(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
 
 // WM x 2 wavefronts of 64 x 64: tile (64 WM) x 128
 template <int BK, int WM, int OCC>
@@ -138,17 +134,21 @@ __global__ __launch_bounds__(128 * WM, OCC) void ovvo_bf3_kernel(Bf3Args p) {
     }
 #pragma unroll
     for (int g = 0; g < RB / 8; ++g) {
-      us8 hh, ll;
+      u4 hh, ll;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int r = g * 8 + u;
-        const float x = ((rneg >> r) & 1u) ? -rb[r] : rb[r];
-        const unsigned short h = bf16_bits(x);
-        hh[u] = h;
-        ll[u] = bf16_bits(x - __uint_as_float((unsigned)h << 16));
+      for (int u = 0; u < 4; ++u) {
+        const int r = g * 8 + 2 * u;
+        const f2 x = {((rneg >> r) & 1u) ? -rb[r] : rb[r],
+                      ((rneg >> (r + 1)) & 1u) ? -rb[r + 1] : rb[r + 1]};
+        // round to nearest even on the packed converter; bf16 -> f32 is exact
+        const b2 h = __builtin_convertvector(x, b2);
+        const f2 hf = __builtin_convertvector(h, f2);
+        const f2 rem = {x[0] - hf[0], x[1] - hf[1]};
+        hh[u] = __builtin_bit_cast(unsigned, h);
+        ll[u] = __builtin_bit_cast(unsigned, __builtin_convertvector(rem, b2));
       }
-      *reinterpret_cast<us8*>(&Bh[bn][kh * RB + g * 8]) = hh;
-      *reinterpret_cast<us8*>(&Bl[bn][kh * RB + g * 8]) = ll;
+      *reinterpret_cast<u4*>(&Bh[bn][kh * RB + g * 8]) = hh;
+      *reinterpret_cast<u4*>(&Bl[bn][kh * RB + g * 8]) = ll;
     }
   };
 
