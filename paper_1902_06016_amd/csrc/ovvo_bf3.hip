@@ -3,10 +3,11 @@
 // solver:
 //   Z[(i,a)][(j,c)] = sum_(m,e) W[(i,a)][(m,e)] r_mj^e[c],     r_mj^e = +-X2[pair(m,j)][e][c]
 // W is held as bf16 pairs W = Wh + Wl; the FP32 packed block X2 is expanded (sign, zero
-// segment m = j) and split into hi + lo while the B tile is staged in LDS. Every 16 x 16 block
-// takes hi.hi + hi.lo + lo.hi on v_mfma_f32_16x16x32_bf16 with FP32 accumulation: about 16
-// significant bits per operand (the dropped lo.lo term is 2^-16 of the product), at three
-// bf16 products per FP32 one.
+// segment m = j) and split into hi + lo (round to nearest even on the packed converter) while
+// the B tile is staged in LDS. Every 16 x 16 block takes hi.hi + hi.lo + lo.hi on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation: about 16 significant bits per operand
+// (|lo| <= 2^-9 |x|, so the dropped lo.lo term is at most 2^-18 of the product), at three bf16
+// products per FP32 one.
 //
 // Tile 128 x 128 x 64, 256 threads as 2 x 2 wavefronts of 64 x 64 (4 x 4 blocks of 16 x 16),
 // two workgroups per CU (74 KB of LDS each). The next slab's global loads are issued before
