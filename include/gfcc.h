@@ -159,7 +159,9 @@ gfcc_status gfcc_autotune_entry(const gfcc_ctx* ctx, int index, int64_t* desc, d
 /*
  * gfcc_solve -- solve Eq. xplin at every (omega_w, p_k) and form G (Eq. gfcclineqn).
  *
- * omega [nw] (host), p [np] (host; occupied orbitals 0 <= p < o, distinct), eta > 0.
+ * omega [nw] (host), p [np] (host; occupied orbitals 0 <= p < o, distinct), eta >= 0 (the
+ *   broadening; eta = 0 is the undamped limit, whose real shifted operator is singular at
+ *   its poles).
  * transpose = 0: (omega - i eta + Hbar_N) X = b_p with b_p = e_p (the occupied-orbital
  *   right-hand side), and G_out[w][q][p] = c_q^T X_p for q, p in the p set.
  * transpose = 1: (omega - i eta + Hbar_N^T) Y = c_p (the adjoint systems); since
@@ -179,7 +181,11 @@ gfcc_status gfcc_autotune_entry(const gfcc_ctx* ctx, int index, int64_t* desc, d
  * X_out: optional complex128 [nw][np][D] (device) or NULL. G_out: complex128 [nw][np][np]
  *   (device). iters_out, resid_out: host arrays [nw*np] or NULL.
  * Returns ENOCONV (after filling every output with the best iterate) if some right-hand side
- * did not reach tol; EBREAKDOWN if a shifted operator is exactly singular on a Krylov space.
+ * did not reach tol; EBREAKDOWN (outputs filled as for ENOCONV) if a shifted operator is
+ * exactly singular on a Krylov space (the Hessenberg least-squares problem of GMRES has a
+ * zero pivot), and, for eta = 0, EBREAKDOWN before any solve (outputs untouched) when
+ * omega_w + diag(Hbar_N) has a zero entry, where the Jacobi preconditioner does not exist
+ * (for T = V = 0 exactly the poles omega = eps_i).
  * Memory: the context keeps the solver's work arrays (chiefly the Krylov basis,
  * (restart + 1) D block complex128 entries) for later solves; gfcc_destroy frees them.
  */
@@ -303,6 +309,17 @@ gfcc_status mor_destroy(gfcc_mor* model);
 gfcc_status spectral_function(int nw, int np, const void* G, int is_device, double* A_out);
 
 /*
+ * spectral_weight -- the windowed spectral weight J = sum_w weight_w A(omega_w), with A as in
+ * spectral_function (the objective whose orbital-energy gradient gfcc_grad_eps returns; with
+ * trapezoid weights it is the integral of A over the window). G complex128 [nw][np][np]
+ * (device if is_device, else host: copied to the device first); weight [nw] (host); J_out
+ * (host). The sum runs on the device in a fixed order, on the null stream, and synchronises.
+ * J = 0 for nw = 0 or np = 0; EINVAL for negative sizes or a null pointer that is needed.
+ */
+gfcc_status spectral_weight(int nw, int np, const void* G, int is_device, const double* weight,
+                            double* J_out);
+
+/*
  * Inspection (tests and profiling).
  * gfcc_export: copy a built operator block to a device buffer dst (FP64):
  *   0 Foo [o][o] (F_mi), 1 Fov [o][v] (F_me), 2 Fvv [v][v] (F_ae),
@@ -310,7 +327,9 @@ gfcc_status spectral_function(int nw, int np, const void* G, int is_device, doub
  *   5 Wovvo [o][v][v][o] (W_mbej), 6 Wovoo [o][v][o][o] (W_mbij), 7 diag [D].
  * gfcc_timer: accumulated device time (ms, from HIP events on the context stream) and launch
  *   count of kernel family `which` since the last reset (0: the ovvo contraction of sigma,
- *   1: whole sigma products); reset = 1 clears after reading.
+ *   1: whole sigma products, 2: the two-term bf16 ovvo kernel of GFCC_BF16_PAIRS, which counts
+ *   only the products that took it, not those on the FP32 fallback); reset = 1 clears after
+ *   reading. Timing happens only while a family is enabled (enable = 1).
  */
 gfcc_status gfcc_export(gfcc_ctx* ctx, int which, void* dst);
 gfcc_status gfcc_timer(gfcc_ctx* ctx, int which, int enable, int reset, double* ms_out,

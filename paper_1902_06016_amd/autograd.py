@@ -8,7 +8,6 @@ D_r = dH-bar_N/deps_r at fixed amplitudes.
 """
 from __future__ import annotations
 
-import numpy as np
 import torch
 
 from . import gfcc
@@ -30,8 +29,7 @@ class SpectralWeight(torch.autograd.Function):
                                  inputs["oooo"], inputs["ooov"], inputs["oovv"], inputs["ovvo"],
                                  inputs["ovvv"])
         res = gctx.gfcc_solve(omega, p, eta, tol=tol, want_x=True)
-        A = gfcc.spectral_function(res.G)
-        J = float(np.dot(weights, A))
+        J = gfcc.spectral_weight(res.G, weights)
         fctx.gctx, fctx.X = gctx, res.X
         fctx.args = (omega, weights, p, eta, tol)
         fctx.eps_dev = eps.device

@@ -65,6 +65,10 @@ void timer_end(gfcc_ctx* ctx, int which, hipEvent_t ev0) {
   if (ctx->timers[which].pending.size() > 256) timers_collect(ctx);
 }
 
+void timer_cancel(gfcc_ctx* ctx, hipEvent_t ev0) {
+  if (ev0) ctx->event_pool.push_back(ev0);
+}
+
 // Fold completed event pairs into the accumulated times (waits for the recorded events).
 void timers_collect(gfcc_ctx* ctx) {
   for (auto& t : ctx->timers) {
@@ -228,7 +232,7 @@ gfcc_status gfcc_timer(gfcc_ctx* ctx, int which, int enable, int reset, double* 
   if (!ctx) return GFCC_EINVAL;
   GFCC_API_BEGIN(ctx)
   using namespace gfcc;
-  GFCC_REQUIRE(which == 0 || which == 1, GFCC_EINVAL, "gfcc_timer: unknown timer");
+  GFCC_REQUIRE(which >= 0 && which <= 2, GFCC_EINVAL, "gfcc_timer: unknown timer");
   timers_collect(ctx);
   TimerSlot& t = ctx->timers[which];
   if (ms_out) *ms_out = t.ms;

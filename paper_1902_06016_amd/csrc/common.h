@@ -150,10 +150,11 @@ struct gfcc_ctx {
   gfcc::DevBuf ws_gemm;     // split-K partials
   gfcc::DevBuf ws_a, ws_b, ws_c, ws_d, ws_e;
   gfcc::DevBuf ws_trans;    // transposed B operands of the row-major product paths
+  gfcc::DevBuf ws_io;       // sigma_apply: D-major copies of its input and output blocks
   gfcc::DevBuf ws_solve, ws_solve_f32;  // GMRES block work arrays (Krylov basis, state)
   std::vector<gfcc::DevBuf> build_pool;  // operator-build buffers kept for the next build
   gfcc::DevBuf zrow;        // zeros (read for structurally zero rows of the ovvo operand)
-  gfcc::TimerSlot timers[2];
+  gfcc::TimerSlot timers[3];  // ovvo contraction, whole sigma products, two-term bf16 ovvo
   int tune_mode = 1;        // 0 off, 1 timed, 2 most split variant without timing
   std::map<gfcc::TuneKey, gfcc::TuneChoice> tune;
   std::vector<hipEvent_t> event_pool;
@@ -292,6 +293,8 @@ const void* diis_block(gfcc_ctx* ctx, DiisWork& w, int nb, int m, const double* 
 void timer_begin(gfcc_ctx* ctx, int which, hipEvent_t* ev);
 void timer_end(gfcc_ctx* ctx, int which, hipEvent_t ev0);
 void timers_collect(gfcc_ctx* ctx);
+// an event from timer_begin whose launch did not happen (returned to the pool)
+void timer_cancel(gfcc_ctx* ctx, hipEvent_t ev0);
 
 inline unsigned blocks_for(int64_t n, int threads) {
   int64_t b = (n + threads - 1) / threads;

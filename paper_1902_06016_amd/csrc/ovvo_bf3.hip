@@ -6,7 +6,8 @@
 // segment m = j) and split into hi + lo (round to nearest even on the packed converter) while
 // the B tile is staged in LDS. Every 16 x 16 block takes hi.hi + hi.lo + lo.hi on
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation: about 16 significant bits per operand
-// (|lo| <= 2^-9 |x|, so the dropped lo.lo term is at most 2^-18 of the product), at three bf16
+// (|lo| <= 2^-8 |x| after round-to-nearest, so the dropped lo.lo term is at most about 2^-16
+// of the product), at three bf16
 // products per FP32 one.
 //
 // Tile 128 x 128 x 64, 256 threads as 2 x 2 wavefronts of 64 x 64 (4 x 4 blocks of 16 x 16),

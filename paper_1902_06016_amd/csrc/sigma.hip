@@ -195,9 +195,15 @@ void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, int precis
   }
   woo_product<float>(ctx, false, P, (int64_t)v * nc, f.Woo.as<float>(), op.ldwoo, X2, Y2);
   timer_begin(ctx, 0, &e_ovvo);
-  if (!(precision == GFCC_BF16_PAIRS &&
-        ovvo_bf3(ctx, o, v, nc, op.Weff_bf16.p, op.Weff_bf16_lo.p, op.ldweff_bf, X2, nc, Z)))
+  hipEvent_t e_bf3 = nullptr;
+  timer_begin(ctx, 2, &e_bf3);
+  if (precision == GFCC_BF16_PAIRS &&
+      ovvo_bf3(ctx, o, v, nc, op.Weff_bf16.p, op.Weff_bf16_lo.p, op.ldweff_bf, X2, nc, Z)) {
+    timer_end(ctx, 2, e_bf3);
+  } else {
+    timer_cancel(ctx, e_bf3);
     gemm_ovvo<float>(ctx, false, o, v, nc, f.Weff.as<float>(), X2, nc, op.pairlut.as<int>(), Z);
+  }
   timer_end(ctx, 0, e_ovvo);
   hipLaunchKernelGGL(antisym_add_kernel<float>, dim3(grid_for(PV * nc)), dim3(256), 0,
                      ctx->stream, Z, o, v, nc, Y2);
@@ -225,28 +231,32 @@ extern "C" gfcc_status sigma_apply(gfcc_ctx* ctx, int nrhs, const void* x, void*
   // chunks of at most 2048 right-hand sides (the solver's largest block)
   constexpr int CH = 2048;
   const int nb = std::min(nrhs, CH);
-  DevBuf bx, by, fx, fy;
-  bx.alloc(sizeof(double) * (size_t)D * 2 * nb);
-  by.alloc(sizeof(double) * (size_t)D * 2 * nb);
-  if (precision != GFCC_FP64) {
-    fx.alloc(sizeof(float) * (size_t)D * 2 * nb);
-    fy.alloc(sizeof(float) * (size_t)D * 2 * nb);
-  }
+  // D-major copies of x and y (and their FP32 forms) in a context-owned, grow-only workspace:
+  // repeated calls of the same size allocate nothing
+  auto up256 = [](size_t n) { return (n + 255) / 256 * 256; };
+  const size_t vd = up256(sizeof(double) * (size_t)D * 2 * nb);
+  const size_t vf = up256(sizeof(float) * (size_t)D * 2 * nb);
+  ws_ensure(ctx, ctx->ws_io, 2 * vd + (precision != GFCC_FP64 ? 2 * vf : 0));
+  char* io = ctx->ws_io.as<char>();
+  double* bx = reinterpret_cast<double*>(io);
+  double* by = reinterpret_cast<double*>(io + vd);
+  float* fx = reinterpret_cast<float*>(io + 2 * vd);
+  float* fy = reinterpret_cast<float*>(io + 2 * vd + vf);
   const double2* xc = static_cast<const double2*>(x);
   double2* yc = static_cast<double2*>(y);
   for (int r0 = 0; r0 < nrhs; r0 += CH) {
     const int cnt = std::min(CH, nrhs - r0);
     const int nc = 2 * cnt;
     // [cnt][D] complex -> [D][cnt] complex
-    ctranspose(ctx, xc + (int64_t)r0 * D, cnt, D, D, bx.p, cnt);
+    ctranspose(ctx, xc + (int64_t)r0 * D, cnt, D, D, bx, cnt);
     if (precision == GFCC_FP64) {
-      sigma_block_f64(ctx, nc, bx.as<double>(), by.as<double>(), transpose != 0);
+      sigma_block_f64(ctx, nc, bx, by, transpose != 0);
     } else {
-      cast_f64_f32(ctx, bx.as<double>(), fx.as<float>(), D * nc);
-      sigma_block_f32(ctx, nc, fx.as<float>(), fy.as<float>(), precision);
-      cast_f32_f64(ctx, fy.as<float>(), by.as<double>(), D * nc);
+      cast_f64_f32(ctx, bx, fx, D * nc);
+      sigma_block_f32(ctx, nc, fx, fy, precision);
+      cast_f32_f64(ctx, fy, by, D * nc);
     }
-    ctranspose(ctx, by.p, D, cnt, cnt, yc + (int64_t)r0 * D, D);
+    ctranspose(ctx, by, D, cnt, cnt, yc + (int64_t)r0 * D, D);
   }
   GFCC_HIP(hipStreamSynchronize(ctx->stream));
   timers_collect(ctx);

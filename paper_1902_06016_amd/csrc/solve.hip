@@ -1107,12 +1107,27 @@ __global__ void spectral_kernel(const double2* __restrict__ G, int nw, int np, d
   A[w] = s / 3.14159265358979323846;
 }
 
+// J = (1/pi) sum_w wt[w] sum_k Im G[w][k][k]: one workgroup, a fixed order of summation
+__global__ void weighted_spectral_kernel(const double2* __restrict__ G, int nw, int np,
+                                         const double* __restrict__ wt, double* __restrict__ J) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int w = threadIdx.x; w < nw; w += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < np; ++k) s += G[((int64_t)w * np + k) * np + k].y;
+    acc += wt[w] * s;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *J = red[0] / 3.14159265358979323846;
+}
+
 }  // namespace
 }  // namespace gfcc
-
-extern "C" {
-
-}  // extern "C"
 
 namespace gfcc {
 // argument checks shared by gfcc_solve and gfcc_solve_x0 (throws Error)
@@ -1124,7 +1139,7 @@ static void check_solve_args(gfcc_ctx* ctx, int nw, const double* omega, int np,
   if (nw == 0 || np == 0) return;
   GFCC_REQUIRE(omega && p && G_out, GFCC_EINVAL, "gfcc_solve: null pointer");
   GFCC_REQUIRE((int64_t)nw * np < (1LL << 30), GFCC_EINVAL, "gfcc_solve: too many right-hand sides");
-  GFCC_REQUIRE(eta > 0.0 && std::isfinite(eta), GFCC_EINVAL, "gfcc_solve: eta must be > 0");
+  GFCC_REQUIRE(eta >= 0.0 && std::isfinite(eta), GFCC_EINVAL, "gfcc_solve: eta must be >= 0");
   GFCC_REQUIRE(tol > 0.0 && tol < 1.0, GFCC_EINVAL, "gfcc_solve: tol must be in (0, 1)");
   GFCC_REQUIRE(maxit >= 1, GFCC_EINVAL, "gfcc_solve: maxit must be >= 1");
   GFCC_REQUIRE(restart >= 1 && restart <= 200, GFCC_EINVAL, "gfcc_solve: restart in [1, 200]");
@@ -1142,6 +1157,22 @@ static void check_solve_args(gfcc_ctx* ctx, int nw, const double* omega, int np,
                  "gfcc_solve: p must be occupied orbitals 0 <= p < o");
     GFCC_REQUIRE(!seen[p[k]], GFCC_EINVAL, "gfcc_solve: repeated orbital in p");
     seen[p[k]] = 1;
+  }
+  if (eta == 0.0) {
+    // Without broadening the shifted operator is real, and omega + diag(Hbar_N) can vanish
+    // (for T = V = 0 exactly at omega = eps_i, a pole): the Jacobi preconditioner diag(M) does
+    // not exist there, and for a diagonal operator M itself is singular. Checked before any
+    // solve; the outputs are left untouched.
+    const Operator& op = ctx->op;
+    std::vector<double> dg((size_t)op.D);
+    GFCC_HIP(hipMemcpyAsync(dg.data(), op.diag.p, sizeof(double) * (size_t)op.D,
+                            hipMemcpyDeviceToHost, ctx->stream));
+    GFCC_HIP(hipStreamSynchronize(ctx->stream));
+    std::sort(dg.begin(), dg.end());
+    for (int w = 0; w < nw; ++w)
+      if (std::binary_search(dg.begin(), dg.end(), -omega[w]))
+        throw Error(GFCC_EBREAKDOWN, "gfcc_solve: eta = 0 and a diagonal entry of the shifted "
+                                     "operator is zero at omega = " + std::to_string(omega[w]));
   }
 }
 }  // namespace gfcc
@@ -1236,6 +1267,32 @@ gfcc_status gfcc_grad_eps(gfcc_ctx* ctx, int nw, const double* weight, int np, c
                           ctx->stream));
   GFCC_HIP(hipStreamSynchronize(ctx->stream));
   GFCC_API_END(ctx)
+}
+
+gfcc_status spectral_weight(int nw, int np, const void* G, int is_device, const double* weight,
+                            double* J_out) {
+  if (nw < 0 || np < 0 || !J_out || (nw > 0 && (!weight || (np > 0 && !G)))) return GFCC_EINVAL;
+  *J_out = 0.0;
+  if (nw == 0 || np == 0) return GFCC_OK;
+  const size_t gbytes = sizeof(double2) * (size_t)nw * np * np;
+  double* dw = nullptr;   // [nw] weights, then J
+  void* dG = nullptr;
+  if (hipMalloc(&dw, sizeof(double) * ((size_t)nw + 1)) != hipSuccess) return GFCC_ENOMEM;
+  hipError_t e = hipMemcpy(dw, weight, sizeof(double) * nw, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !is_device) {
+    e = hipMalloc(&dG, gbytes);
+    if (e == hipSuccess) e = hipMemcpy(dG, G, gbytes, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(gfcc::weighted_spectral_kernel, dim3(1), dim3(256), 0, nullptr,
+                       static_cast<const double2*>(is_device ? G : dG), nw, np, dw, dw + nw);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpy(J_out, dw + nw, sizeof(double), hipMemcpyDeviceToHost);
+  (void)hipFree(dw);
+  if (dG) (void)hipFree(dG);
+  if (e == hipErrorOutOfMemory) return GFCC_ENOMEM;
+  return e == hipSuccess ? GFCC_OK : GFCC_EHIP;
 }
 
 gfcc_status spectral_function(int nw, int np, const void* G, int is_device, double* A_out) {

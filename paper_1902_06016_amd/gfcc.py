@@ -63,6 +63,7 @@ def _load():
         "mor_info": (i32, [vp, vp, vp, vp, i32]),
         "mor_destroy": (i32, [vp]),
         "spectral_function": (i32, [i32, i32, vp, i32, vp]),
+        "spectral_weight": (i32, [i32, i32, vp, i32, vp, vp]),
         "gfcc_export": (i32, [vp, i32, vp]),
         "gfcc_timer": (i32, [vp, i32, i32, i32, vp, vp]),
     }
@@ -78,7 +79,7 @@ SYMBOLS = ("gfcc_dim", "gfcc_create", "gfcc_destroy", "gfcc_last_error", "build_
            "build_hbar_first_order", "sigma_apply", "gfcc_autotune", "gfcc_autotune_entry",
            "gfcc_solve", "gfcc_solve_x0", "gfcc_solve_diis", "gfcc_grad_eps", "mor_build",
            "mor_build_diag", "mor_refine", "mor_eval", "mor_lift", "mor_info", "mor_destroy",
-           "spectral_function", "gfcc_export", "gfcc_timer")
+           "spectral_function", "spectral_weight", "gfcc_export", "gfcc_timer")
 
 
 def dim(o: int, v: int) -> int:
@@ -399,3 +400,20 @@ def spectral_function(G) -> np.ndarray:
     if st != GFCC_OK:
         raise GfccError(st, "spectral_function failed")
     return out
+
+
+def spectral_weight(G, weight) -> float:
+    """J = sum_w weight_w A(omega_w) for G complex128 [nw][np][np] (torch device tensor or numpy
+    host array) and host weights [nw]."""
+    w, w_p = _f64arr(weight)
+    J = ctypes.c_double()
+    if isinstance(G, np.ndarray):
+        g = np.ascontiguousarray(G, dtype=np.complex128)
+        st = lib.spectral_weight(g.shape[0], g.shape[1], g.ctypes.data_as(ctypes.c_void_p), 0,
+                                 w_p, ctypes.byref(J))
+    else:
+        g = G.contiguous()
+        st = lib.spectral_weight(g.shape[0], g.shape[1], _ptr(g), 1, w_p, ctypes.byref(J))
+    if st != GFCC_OK:
+        raise GfccError(st, "spectral_weight failed")
+    return J.value

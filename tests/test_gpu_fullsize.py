@@ -188,21 +188,95 @@ def test_o42v186_adjoint_vs_finite_differences(gpu_ctx, benzene):
     gpu_ctx.build_from_problem(prob)
 
 
-@pytest.mark.parametrize("prec", [gfcc.FP32_BF16_3BODY, gfcc.BF16_PAIRS])
-def test_mixed_block_reduced_shape(gpu_ctx, prec):
-    """A 32 omega x 16 p block in one launch at a reduced adenine-like shape: FP32 sigma with the
-    three-body term (or the ovvo contraction) on two-term bf16 and FP64 refinement reach the
-    FP64 residual target and match the FP64 solve's A within 1e-6."""
-    print(f"[mixed block prec={prec}]", flush=True)
+@pytest.fixture(scope="module")
+def mixed_reduced():
+    """A reduced adenine-like shape (o=30, v=90, D=39,180) with the adenine workload's grid and
+    orbitals, and the oracle's GMRES (tol 1e-13) at four sampled (omega, p) of the block."""
+    print("[mixed reduced oracle]", flush=True)
     cfg = synth.WORKLOADS["o70v260_mixed"]
     o, v = 30, 90
     prob = synth.make_problem(o, v, cfg["seed"])
-    gpu_ctx.build_from_problem(prob, keep=gfcc.KEEP_FP32)
+    hb = ohbar.build_hbar_from_problem(prob)
     om = synth.omega_grid(cfg["omega"])
     ps = synth.valence_p(o, cfg["np"])
+    C = np.stack([osig.c_vector(o, v, prob.t1, prob.t2, prob.l1, prob.l2, int(q)) for q in ps], 0)
+    op = osolve.Operator(hb)
+    ref = {}
+    for w, k in ((0, len(ps) - 1), (11, 0), (20, 7), (len(om) - 1, 12)):
+        x, _, r = osolve.gmres(op, osig.b_vector(o, v, int(ps[k])), float(om[w]), cfg["eta"],
+                               tol=1e-13)
+        assert r <= 1e-13
+        ref[(w, k)] = C @ x          # G[w][q][k] for every q
+    return cfg, prob, om, ps, ref
+
+
+@pytest.mark.parametrize("prec", [gfcc.FP32_BF16_3BODY, gfcc.BF16_PAIRS])
+def test_mixed_block_reduced_shape(gpu_ctx, mixed_reduced, prec):
+    """A 32 omega x 16 p block in one launch at the reduced adenine-like shape: FP32 sigma with
+    the three-body term (or the ovvo contraction) on two-term bf16 and FP64 refinement reach
+    the FP64 residual target. Parity against the oracle: at four sampled (omega, p) of the
+    block the A terms (1/pi) Im G_pp are within 1e-6 of max |A| and every G_qp of the column
+    within 1e-6 of the column's largest entry; the whole grid's A also matches the FP64 solve
+    within 1e-6."""
+    print(f"[mixed block prec={prec}]", flush=True)
+    cfg, prob, om, ps, ref = mixed_reduced
+    gpu_ctx.build_from_problem(prob, keep=gfcc.KEEP_FP32)
+    gpu_ctx.timer(2, enable=True, reset=True)
     mixed = gpu_ctx.gfcc_solve(om, ps, cfg["eta"], tol=1e-8, restart=12, block=512,
                                precision=prec)
-    full = gpu_ctx.gfcc_solve(om, ps, cfg["eta"], tol=1e-12, restart=30, block=512)
+    pair_launches = gpu_ctx.timer(2, enable=False, reset=True)[1]
+    assert (pair_launches > 0) == (prec == gfcc.BF16_PAIRS)
     assert mixed.resid.max() <= 1e-8
-    Am, Af = gfcc.spectral_function(mixed.G), gfcc.spectral_function(full.G)
+    Gm = mixed.G.cpu().numpy()
+    Am = gfcc.spectral_function(mixed.G)
+    amax = np.abs(Am).max()
+    for (w, k), g in ref.items():
+        eterm = abs((Gm[w, k, k] - g[k]).imag) / np.pi / amax
+        ecol = np.abs(Gm[w, :, k] - g).max() / np.abs(g).max()
+        print(f"  omega={om[w]:.4f} p={ps[k]}: A-term err {eterm:.1e} of max|A|, "
+              f"G column {ecol:.1e}", flush=True)
+        assert eterm < 1e-6 and ecol < 1e-6
+    full = gpu_ctx.gfcc_solve(om, ps, cfg["eta"], tol=1e-12, restart=30, block=512)
+    Af = gfcc.spectral_function(full.G)
     assert np.abs(Am - Af).max() / np.abs(Af).max() < 1e-6
+
+
+def test_near_pole_block_o24v90(gpu_ctx):
+    """Frequencies across the highest occupied orbitals' one-hole poles (around minus the
+    1h diagonal of H-bar_N), where the paper's solves need many iterations (Results, the
+    convergence study), at o=24, v=90 (D = 24,864): 32 frequencies x 2 orbitals in one block
+    of 64 with restart 30, against the oracle's GMRES at three sampled (omega, p), and the
+    reported residuals of two returned solutions against ||b - M x|| / ||b|| formed with the
+    oracle's sigma."""
+    print("[near pole o24v90]", flush=True)
+    o, v, eta = 24, 90, 0.005
+    prob = synth.make_problem(o, v, 5)
+    hb = ohbar.build_hbar_from_problem(prob)
+    dg = osig.diagonal(hb)
+    ps = np.array([o - 2, o - 1])
+    om = np.linspace(-dg[o - 1] - 0.3, -dg[o - 1] + 0.6, 32)
+    gpu_ctx.build_from_problem(prob)
+    res = gpu_ctx.gfcc_solve(om, ps, eta, tol=1e-12, restart=30, block=64, maxit=3000,
+                             want_x=True)
+    print(f"  iterations {res.iters.min()}..{res.iters.max()}", flush=True)
+    assert res.resid.max() <= 1e-12
+    assert res.iters.max() > 30          # several restart cycles
+    G = res.G.cpu().numpy()
+    X = res.X.cpu().numpy()
+    op = osolve.Operator(hb)
+    C = np.stack([osig.c_vector(o, v, prob.t1, prob.t2, prob.l1, prob.l2, int(q)) for q in ps], 0)
+    hard = np.unravel_index(np.argsort(res.iters, axis=None)[::-1], res.iters.shape)
+    picks = [(hard[0][0], hard[1][0]), (hard[0][1], hard[1][1]), (0, 0)]
+    for w, k in picks:
+        b = osig.b_vector(o, v, int(ps[k]))
+        x, it, r = osolve.gmres(op, b, float(om[w]), eta, tol=1e-13, restart=30, maxit=3000)
+        g = C @ x
+        err = np.abs(G[w, :, k] - g).max() / np.abs(g).max()
+        # residual of the returned solution with the oracle's operator
+        xr = X[w, k]
+        true = np.linalg.norm(b - (op.hbar(xr) + (om[w] - 1j * eta) * xr)) / np.linalg.norm(b)
+        print(f"  omega={om[w]:.4f} p={ps[k]} gpu its {res.iters[w, k]} oracle its {it}: "
+              f"G err {err:.1e}, residual {res.resid[w, k]:.2e} vs oracle {true:.2e}",
+              flush=True)
+        assert err < 1e-9
+        assert abs(true - res.resid[w, k]) <= 1e-13

@@ -190,8 +190,9 @@ def test_bf16_three_body_term_keeps_16_bits(model):
 
 def test_bf16_pair_products_within_their_bound(model):
     """The two-term bf16 forms of the T5, T6 and T8 contractions differ from the FP64 ones by
-    at most 2^-14 of sum |a||b| over the contracted index (operand pairs carry 16 bits, the
-    dropped lo.lo term is 2^-18 of a product, float32 accumulation adds K 2^-24 at most);
+    at most 2^-14 of sum |a||b| over the contracted index (operand pairs carry 16 bits:
+    |lo| <= 2^-8 |x| after round-to-nearest to bf16, so the dropped lo.lo term is at most
+    about 2^-16 of a product; float32 accumulation adds K 2^-24 at most);
     plain bf16 operands miss this bound."""
     p, hb, H, lam, ps, B, C = model
     o, v = p.o, p.v
@@ -244,9 +245,90 @@ def test_adjoint_gradient_matches_finite_differences(model):
         Jp = oadj.objective_dense(osolve.dense_hbar(oadj.rebuild_with_eps(p, ep)), om, w, B, C, eta)
         Jm = oadj.objective_dense(osolve.dense_hbar(oadj.rebuild_with_eps(p, em)), om, w, B, C, eta)
         fd = (Jp - Jm) / (2 * h)
-        assert abs(fd - g[r]) < 1e-6 * max(1.0, abs(fd)), (r, fd, g[r])
+        # central differences: truncation h^2 |J'''| / 6 and rounding ~1e-16 |J| / h, both far
+        # below 1e-6 of the derivative here
+        assert abs(fd - g[r]) < 1e-6 * abs(fd), (r, fd, g[r])
     # and D_r is exactly dH/deps_r
     ep = p.eps.copy()
     ep[1] += 1.0
     dH = osolve.dense_hbar(oadj.rebuild_with_eps(p, ep)) - H
     assert np.abs(dH - np.diag(oadj.d_eps_diagonal(o, v, 1))).max() < 1e-12
+
+
+def test_gradient_from_solutions_matches_finite_differences(model):
+    """The gradient assembled from forward and adjoint solutions (the form the full-size check
+    uses, with X and Y from any solver) against central finite differences of J, and against
+    the dense-solve gradient."""
+    p, hb, H, lam, ps, B, C = model
+    o, v = p.o, p.v
+    eta = 0.02
+    om = np.linspace(-lam[0] - 0.2, -lam[0] + 0.2, 7)
+    w = oadj.trapezoid_weights(om)
+    X = osolve.dense_solve(H, om, B, eta)                        # [nw, np, D]
+    Y = osolve.dense_solve(H.T.copy(), om, C.T.copy(), eta)      # adjoint: M^T y_p = c_p
+    g = oadj.gradient_from_solutions(X, Y, w, o, v)
+    assert np.abs(g - oadj.gradient_dense(H, om, w, B, C, eta, o, v)).max() <= 1e-12 * np.abs(g).max()
+    h = 1e-5
+    for r in (0, 2, o - 1, o, o + v - 1):
+        ep, em = p.eps.copy(), p.eps.copy()
+        ep[r] += h
+        em[r] -= h
+        Jp = oadj.objective_dense(osolve.dense_hbar(oadj.rebuild_with_eps(p, ep)), om, w, B, C, eta)
+        Jm = oadj.objective_dense(osolve.dense_hbar(oadj.rebuild_with_eps(p, em)), om, w, B, C, eta)
+        fd = (Jp - Jm) / (2 * h)
+        assert abs(fd - g[r]) < 1e-6 * abs(fd), (r, fd, g[r])
+    # one-hot weights pick single frequencies: the sum over frequencies is linear in w
+    g2 = sum(oadj.gradient_from_solutions(X[k:k + 1], Y[k:k + 1], w[k:k + 1], o, v)
+             for k in range(len(om)))
+    assert np.abs(g2 - g).max() <= 1e-13 * np.abs(g).max()
+
+
+def test_orth_append_deflation():
+    """Deflation of the basis (Eq. model's orthonormal S): dependent columns are dropped and
+    independent ones kept, with the threshold relative to each column's own norm."""
+    rng = np.random.default_rng(11)
+    D, tol = 40, 1e-10
+    S = omor.orth_append(np.zeros((D, 0)), rng.standard_normal((D, 5)), tol)
+    assert S.shape == (D, 5)
+    assert np.abs(S.T @ S - np.eye(5)).max() < 1e-14
+    # a copy of a column of S, and a combination of its columns, add nothing
+    assert omor.orth_append(S, S[:, 2:3] * 3.0, tol).shape[1] == 5
+    comb = S @ rng.standard_normal(5)
+    assert omor.orth_append(S, comb[:, None], tol).shape[1] == 5
+    # two dependent columns in one call: the second is dropped against the first
+    new = rng.standard_normal(D)
+    T = omor.orth_append(S, np.stack([new, 2.0 * new + S[:, 0]], 1), tol)
+    assert T.shape[1] == 6
+    # the zero column is dropped
+    assert omor.orth_append(S, np.zeros((D, 1)), tol).shape[1] == 5
+    # a remainder of 1e3 tol relative to the column is kept; 1e-3 tol is dropped
+    u = rng.standard_normal(D)
+    u -= S @ (S.T @ u)
+    u -= S @ (S.T @ u)
+    u /= np.linalg.norm(u)
+    # (at column scales 1e-6 .. 1e6, so that an absolute threshold would fail)
+    for scale in (1e-6, 1.0, 1e6):
+        for rel, kept in ((1e3 * tol, True), (1e-3 * tol, False)):
+            col = scale * (comb + rel * np.linalg.norm(comb) * u)
+            T = omor.orth_append(S, col[:, None], tol)
+            assert T.shape[1] == (6 if kept else 5), (scale, rel)
+            if kept:
+                assert abs(abs(T[:, 5] @ u) - 1.0) < 1e-6
+                assert np.abs(T.T @ T - np.eye(6)).max() < 1e-12
+
+
+def test_rom_reextension_at_sampled_frequencies_adds_nothing(model):
+    """Solving again at frequencies already in S gives columns inside span S: the order stays
+    the same and the model is unchanged."""
+    p, hb, H, lam, ps, B, C = model
+    eta = 0.01
+    wk = np.linspace(-lam[0] - 0.3, -lam[0] + 0.3, 3)
+    rom = omor.ROM(hb, ps, eta, C, omor.dense_solver(H, B, eta))
+    rom.extend(wk, 1e-10)
+    m0 = rom.m
+    om = np.linspace(wk[0], wk[-1], 9)
+    G0, _ = rom.eval(om)
+    rom.extend(wk[1:2], 1e-10)
+    assert rom.m == m0
+    G1, _ = rom.eval(om)
+    assert np.abs(G1 - G0).max() < 1e-12 * np.abs(G0).max()
