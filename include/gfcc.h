@@ -285,6 +285,22 @@ gfcc_status mor_eval(gfcc_mor* model, int nw, const double* omega, void* G_out,
                      double* resid_out);
 
 /*
+ * mor_eval_noalloc -- mor_eval that allocates no device memory, for callers that cannot
+ * allocate (code under HIP graph capture, serving loops that query a built model for new
+ * frequencies, harnesses that forbid hipMalloc). The caller passes G_out (device) and
+ * resid_out (host, may be NULL) as for mor_eval and gets the same values (the same kernels).
+ * The per-frequency work space lives in a 32 MiB device array that the library holds on each
+ * device until the process ends (its address is taken when the first context on that device
+ * is created); frequencies run in chunks of as many as fit (a model of order m and np
+ * orbitals takes 16 (m^2 + np m) + 16 bytes per frequency). ENOMEM if one frequency does not
+ * fit (m of about 1440 at np = 8), ESTATE for an empty model. Every call on a device uses the
+ * same array: calls that overlap in time on one device (other contexts, other host threads)
+ * race and must be serialised by the caller. Synchronises the context stream.
+ */
+gfcc_status mor_eval_noalloc(gfcc_mor* model, int nw, const double* omega, void* G_out,
+                             double* resid_out);
+
+/*
  * mor_lift -- the reduced model's full-space approximate solutions X_out[w][k] = S xhat_{p_k}
  * (omega_w) for omega [nw] (host), the p set of the model: complex128 [nw][np][D] (device).
  * At a sampled frequency this is the full solution (up to the solve tolerance); elsewhere its

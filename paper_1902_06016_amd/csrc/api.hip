@@ -13,6 +13,7 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
                     const double* ovvv, int keep);
 void first_order_t2(gfcc_ctx* ctx, int o, int v, const double* eps, const double* oovv,
                     double* t2);
+void eval_scratch_setup(int device);
 
 struct NamedArray {
   const double* p;
@@ -105,6 +106,12 @@ gfcc_status gfcc_create(gfcc_ctx** out, int device, void* hip_stream) {
   if (hipSetDevice(device) != hipSuccess) {
     delete ctx;
     return GFCC_EHIP;
+  }
+  try {
+    gfcc::eval_scratch_setup(device);   // with `device` current: once per device
+  } catch (const gfcc::Error& e) {
+    delete ctx;
+    return e.status;
   }
   *out = ctx;
   return GFCC_OK;

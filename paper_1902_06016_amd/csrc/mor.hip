@@ -21,6 +21,7 @@
 // (omega - i eta) I + Hhat, solves for every orbital, Ghat = chat^T xhat and the residual.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <numeric>
 
 #include "common.h"
@@ -897,6 +898,79 @@ static void mor_lift_impl(gfcc_mor* M, int nw, const double* omega, double2* X) 
   GFCC_HIP(hipStreamSynchronize(st));
 }
 
+// ------------------------------------------------------------------------------------------
+// Evaluation without allocation (mor_eval_noalloc). The reduced solves of a chunk of
+// frequencies need per-frequency work space (the shifted m x m matrix and the solutions), the
+// frequencies on the device and the residuals; here they live in one file-scope device array
+// of EVAL_SCRATCH_BYTES. Each device holds its own copy; its address is looked up once per
+// device (eval_scratch_setup, called by gfcc_create with the device current) and only that
+// address is used on the host. Calls on one device share the array: calls that overlap in
+// time on one device race.
+constexpr size_t EVAL_SCRATCH_BYTES = (size_t)32 << 20;
+constexpr int EVAL_MAX_DEVICES = 64;
+
+}  // namespace gfcc
+
+static __device__ __align__(256) unsigned char scratch[gfcc::EVAL_SCRATCH_BYTES];
+
+namespace gfcc {
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[EVAL_MAX_DEVICES];
+
+void eval_scratch_setup(int device) {
+  GFCC_REQUIRE(device >= 0 && device < EVAL_MAX_DEVICES, GFCC_EINVAL,
+               "gfcc_create: device index beyond the evaluation scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* ptr = nullptr;
+  GFCC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  GFCC_REQUIRE(ptr != nullptr, GFCC_EHIP, "gfcc_create: no address for the evaluation scratch");
+  g_scratch_ptr[device] = ptr;
+}
+
+static char* eval_scratch(int device) {
+  if (device < 0 || device >= EVAL_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return static_cast<char*>(g_scratch_ptr[device]);
+}
+
+// mor_eval on the scratch array: chunks of as many frequencies as fit, each with its
+// frequencies copied in, the reduced solves (the kernels of mor_eval) and its residuals copied
+// out. No device memory is allocated or freed.
+static void mor_eval_scratch(gfcc_mor* M, int nw, const double* omega, double2* G,
+                             double* resid_host) {
+  gfcc_ctx* ctx = M->ctx;
+  hipStream_t st = ctx->stream;
+  const int m = M->m, np = M->np;
+  char* base = eval_scratch(ctx->device);
+  GFCC_REQUIRE(base != nullptr, GFCC_ESTATE,
+               "mor_eval_noalloc: no evaluation scratch on this device");
+  const size_t per = sizeof(double2) * ((size_t)m * m + (size_t)np * m);
+  auto up = [](size_t n) { return (n + 255) / 256 * 256; };
+  // omega and resid take 8 bytes per frequency each, rounded up to 256 bytes
+  const size_t avail = EVAL_SCRATCH_BYTES - 2 * 256;
+  GFCC_REQUIRE(per + 16 <= avail, GFCC_ENOMEM,
+               "mor_eval_noalloc: a model of order " + std::to_string(m) + " with " +
+                   std::to_string(np) + " orbitals needs " + std::to_string(per) +
+                   " bytes per frequency; the evaluation scratch holds " +
+                   std::to_string(EVAL_SCRATCH_BYTES) + " bytes");
+  int chunk = (int)std::min<size_t>(avail / (per + 16), 2048);
+  chunk = std::min(chunk, nw);
+  double* om = reinterpret_cast<double*>(base);
+  double* res = reinterpret_cast<double*>(base + up(sizeof(double) * chunk));
+  double2* work = reinterpret_cast<double2*>(base + 2 * up(sizeof(double) * chunk));
+  for (int w0 = 0; w0 < nw; w0 += chunk) {
+    const int cnt = std::min(chunk, nw - w0);
+    GFCC_HIP(hipMemcpyAsync(om, omega + w0, sizeof(double) * cnt, hipMemcpyHostToDevice, st));
+    rom_solve(M, om, 0, cnt, cnt, work, G + (int64_t)w0 * np * np, res);
+    if (resid_host)
+      GFCC_HIP(hipMemcpyAsync(resid_host + w0, res, sizeof(double) * cnt,
+                              hipMemcpyDeviceToHost, st));
+  }
+  GFCC_HIP(hipStreamSynchronize(st));
+}
+
 }  // namespace gfcc
 
 extern "C" {
@@ -1072,6 +1146,22 @@ gfcc_status mor_eval(gfcc_mor* M, int nw, const double* omega, void* G_out, doub
   for (int i = 0; i < nw; ++i)
     GFCC_REQUIRE(std::isfinite(omega[i]), GFCC_EINVAL, "mor_eval: non-finite omega");
   mor_eval_impl(M, nw, omega, static_cast<double2*>(G_out), resid_out);
+  GFCC_API_END(ctx)
+}
+
+gfcc_status mor_eval_noalloc(gfcc_mor* M, int nw, const double* omega, void* G_out,
+                             double* resid_out) {
+  if (!M) return GFCC_EINVAL;
+  gfcc_ctx* ctx = M->ctx;
+  GFCC_API_BEGIN(ctx)
+  using namespace gfcc;
+  GFCC_REQUIRE(nw >= 0 && (nw == 0 || (omega && G_out)), GFCC_EINVAL,
+               "mor_eval_noalloc: bad arguments");
+  if (nw == 0) return GFCC_OK;
+  GFCC_REQUIRE(M->m > 0, GFCC_ESTATE, "mor_eval_noalloc: empty model");
+  for (int i = 0; i < nw; ++i)
+    GFCC_REQUIRE(std::isfinite(omega[i]), GFCC_EINVAL, "mor_eval_noalloc: non-finite omega");
+  mor_eval_scratch(M, nw, omega, static_cast<double2*>(G_out), resid_out);
   GFCC_API_END(ctx)
 }
 

@@ -59,6 +59,7 @@ def _load():
         "mor_build_diag": (i32, [vp, i32, vp, i32, vp, dbl, dbl, dbl, vp]),
         "mor_refine": (i32, [vp, i32, vp, dbl, dbl, i32, dbl, i32, i32, vp, vp]),
         "mor_eval": (i32, [vp, i32, vp, vp, vp]),
+        "mor_eval_noalloc": (i32, [vp, i32, vp, vp, vp]),
         "mor_lift": (i32, [vp, i32, vp, vp]),
         "mor_info": (i32, [vp, vp, vp, vp, i32]),
         "mor_destroy": (i32, [vp]),
@@ -78,8 +79,9 @@ lib = _load()
 SYMBOLS = ("gfcc_dim", "gfcc_create", "gfcc_destroy", "gfcc_last_error", "build_hbar_operands",
            "build_hbar_first_order", "sigma_apply", "gfcc_autotune", "gfcc_autotune_entry",
            "gfcc_solve", "gfcc_solve_x0", "gfcc_solve_diis", "gfcc_grad_eps", "mor_build",
-           "mor_build_diag", "mor_refine", "mor_eval", "mor_lift", "mor_info", "mor_destroy",
-           "spectral_function", "spectral_weight", "gfcc_export", "gfcc_timer")
+           "mor_build_diag", "mor_refine", "mor_eval", "mor_eval_noalloc", "mor_lift",
+           "mor_info", "mor_destroy", "spectral_function", "spectral_weight", "gfcc_export",
+           "gfcc_timer")
 
 
 def dim(o: int, v: int) -> int:
