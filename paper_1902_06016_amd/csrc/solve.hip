@@ -783,6 +783,16 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
   bool have_res = false;  // R holds the residual of X from the Arnoldi relation of the last cycle
   bool unit_start = false;  // this cycle starts from V0 = e_p (forward, x = 0)
   std::vector<double> hbeta(nb);
+  std::vector<char> fin(nb, 0);  // stopped: its residual and iteration count are final
+  auto explicit_residual = [&]() {
+    gb.apply_M(gb.X, gb.U, true);
+    hipLaunchKernelGGL(residual_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.B, gb.U,
+                       D * nb, gb.R);
+    GFCC_LAUNCH_CHECK();
+  };
+  auto stops = [&](int r, double rl) {
+    return bnorm[r] == 0.0 || rl <= tol || its[r] >= maxit || brk[r];
+  };
   for (;;) {
     // ---- residual R of the current X and its norm: b at the start, the explicit FP64
     // b - M X after a given x0 or a reduced-precision cycle, else the relation residual
@@ -790,20 +800,45 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
     if (first) {
       GFCC_HIP(hipMemcpyAsync(gb.R, gb.B, sizeof(double2) * D * nb, hipMemcpyDeviceToDevice, st));
     } else if (!have_res) {
-      gb.apply_M(gb.X, gb.U, true);
-      hipLaunchKernelGGL(residual_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.B, gb.U,
-                         D * nb, gb.R);
-      GFCC_LAUNCH_CHECK();
+      explicit_residual();
     }
     first = false;
-    have_res = false;
     gb.norms(gb.R, gb.nrm);
     GFCC_HIP(hipMemcpyAsync(rn.data(), gb.nrm, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
     GFCC_HIP(hipStreamSynchronize(st));
+    if (have_res) {
+      // The relation residual of a cycle equals b - M X up to the rounding of that cycle only
+      // when the cycle started from an explicit (or exact) residual: carried from cycle to
+      // cycle, its rounding accumulates, and next to a pole, after tens of short cycles, it
+      // fell 30 times below the true residual. So it decides only for the right-hand sides it
+      // stops; if another cycle is needed, every other one restarts from the explicit FP64
+      // residual of its iterate (one sigma product per extra cycle; none when one cycle
+      // suffices, as far from the poles).
+      bool more = false;
+      for (int r = 0; r < nb; ++r) {
+        if (fin[r]) continue;
+        const double rl = bnorm[r] > 0 ? rn[r] / bnorm[r] : 0.0;
+        if (stops(r, rl)) {
+          fin[r] = 1;
+          rel[r] = rl;
+        } else {
+          more = true;
+        }
+      }
+      if (more) {
+        explicit_residual();
+        gb.norms(gb.R, gb.nrm);
+        GFCC_HIP(hipMemcpyAsync(rn.data(), gb.nrm, sizeof(double) * nb, hipMemcpyDeviceToHost,
+                                st));
+        GFCC_HIP(hipStreamSynchronize(st));
+      }
+    }
+    have_res = false;
     int nact = 0;
     for (int r = 0; r < nb; ++r) {
-      rel[r] = bnorm[r] > 0 ? rn[r] / bnorm[r] : 0.0;
-      bool done = (bnorm[r] == 0.0) || rel[r] <= tol || its[r] >= maxit || brk[r];
+      if (!fin[r]) rel[r] = bnorm[r] > 0 ? rn[r] / bnorm[r] : 0.0;
+      const bool done = fin[r] || stops(r, rel[r]);
+      fin[r] = done ? 1 : 0;
       act[r] = done ? 0 : 1;
       nact += act[r];
       inv0[r] = act[r] ? 1.0 / rn[r] : 0.0;

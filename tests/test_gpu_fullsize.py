@@ -26,7 +26,14 @@ def benzene(gpu_ctx):
     return prob
 
 
-def test_o42v186_sampled_parity_with_oracle(gpu_ctx, benzene):
+@pytest.fixture(scope="module")
+def benzene_oracle(benzene):
+    """The oracle's H-bar of the benzene-shaped operator (about half a minute on the host)."""
+    print("[o42v186 oracle build]", flush=True)
+    return ohbar.build_hbar_from_problem(benzene)
+
+
+def test_o42v186_sampled_parity_with_oracle(gpu_ctx, benzene, benzene_oracle):
     """G_qp(omega) for every q at two frequencies and one orbital, in the launch configuration of
     the benchmark (all 1600 right-hand sides in one block, restart 30), against the oracle's
     GMRES at tol 1e-13. A context of its own holds that block's work arrays (about 150 GB) and
@@ -48,8 +55,7 @@ def test_o42v186_sampled_parity_with_oracle(gpu_ctx, benzene):
         A2 = gfcc.spectral_function(res.G)
         del res, loose
     amax = np.abs(A2).max()
-    hb = ohbar.build_hbar_from_problem(prob)
-    op = osolve.Operator(hb)
+    op = osolve.Operator(benzene_oracle)
     C = np.stack([osig.c_vector(o, v, prob.t1, prob.t2, prob.l1, prob.l2, int(q)) for q in ps], 0)
     for w_idx, k in ((0, len(ps) - 1), (len(om_all) - 1, 0)):
         x, it, r = osolve.gmres(op, osig.b_vector(o, v, int(ps[k])), float(om_all[w_idx]),
@@ -188,6 +194,42 @@ def test_o42v186_adjoint_vs_finite_differences(gpu_ctx, benzene):
     gpu_ctx.build_from_problem(prob)
 
 
+def test_o42v186_adjoint_gradient_vs_oracle(gpu_ctx, benzene, benzene_oracle):
+    """The adjoint gradient at the full size against the oracle: weight 1 at one frequency of
+    the adjoint workload's grid for two valence orbitals, the GPU's forward and transposed
+    solves reduced by gfcc_grad_eps, against the oracle's GMRES (tol 1e-13, forward and
+    transposed sigma) reduced by the oracle's gradient formula. Every one of the o + v
+    components agrees to 1e-8 of itself, including the small ones of inner occupied (r = o-20)
+    and virtual orbitals (1e-14 against 4e-9 for the largest); the components move by about
+    1e-10 of themselves between solves at tol 1e-10 and 1e-13."""
+    print("[o42v186 adjoint vs oracle]", flush=True)
+    from oracle import adjoint as oadj
+    cfg = synth.WORKLOADS["o42v186_adjoint"]
+    prob = benzene
+    o, v = prob.o, prob.v
+    om = synth.omega_grid(cfg["omega"])[[50]]
+    ps = synth.valence_p(o, 2)
+    fwd = gpu_ctx.gfcc_solve(om, ps, cfg["eta"], tol=1e-13, want_x=True)
+    adj = gpu_ctx.gfcc_solve(om, ps, cfg["eta"], tol=1e-13, transpose=True, want_x=True)
+    g = gpu_ctx.gfcc_grad_eps(np.ones(1), fwd.X, adj.X)
+    opf = osolve.Operator(benzene_oracle)
+    opt = osolve.Operator(benzene_oracle, transpose=True)
+    X = np.empty((1, len(ps), gfcc.dim(o, v)), dtype=complex)
+    Y = np.empty_like(X)
+    for k, q in enumerate(ps):
+        X[0, k], _, rx = osolve.gmres(opf, osig.b_vector(o, v, int(q)), float(om[0]), cfg["eta"],
+                                      tol=1e-13)
+        c = osig.c_vector(o, v, prob.t1, prob.t2, prob.l1, prob.l2, int(q))
+        Y[0, k], _, ry = osolve.gmres(opt, c, float(om[0]), cfg["eta"], tol=1e-13)
+        assert rx <= 1e-13 and ry <= 1e-13
+    gref = oadj.gradient_from_solutions(X, Y, np.ones(1), o, v)
+    rel = np.abs(g - gref) / np.abs(gref)
+    for r in (o - 1, o - 20, o, o + 5):
+        print(f"  r={r}: gpu {g[r]:.12e} oracle {gref[r]:.12e} rel {rel[r]:.1e}", flush=True)
+    print(f"  max relative difference over all {o + v} components: {rel.max():.1e}", flush=True)
+    assert rel.max() <= 1e-8
+
+
 @pytest.fixture(scope="module")
 def mixed_reduced():
     """A reduced adenine-like shape (o=30, v=90, D=39,180) with the adenine workload's grid and
@@ -242,25 +284,31 @@ def test_mixed_block_reduced_shape(gpu_ctx, mixed_reduced, prec):
 
 
 def test_near_pole_block_o24v90(gpu_ctx):
-    """Frequencies across the highest occupied orbitals' one-hole poles (around minus the
-    1h diagonal of H-bar_N), where the paper's solves need many iterations (Results, the
-    convergence study), at o=24, v=90 (D = 24,864): 32 frequencies x 2 orbitals in one block
-    of 64 with restart 30, against the oracle's GMRES at three sampled (omega, p), and the
-    reported residuals of two returned solutions against ||b - M x|| / ||b|| formed with the
-    oracle's sigma."""
+    """Frequencies across a main-line pole of the highest occupied orbital (located by a scan of
+    |G_pp| around minus its 1h diagonal element), where the paper's solves need the most
+    iterations (Results, the convergence study), at o=24, v=90 (D = 24,864): 32 frequencies x
+    2 orbitals in one block of 64 with restart 10 (several restart cycles), against the
+    oracle's GMRES at three sampled (omega, p), and the reported residuals of the returned
+    solutions against ||b - M x|| / ||b|| formed with the oracle's sigma."""
     print("[near pole o24v90]", flush=True)
     o, v, eta = 24, 90, 0.005
     prob = synth.make_problem(o, v, 5)
     hb = ohbar.build_hbar_from_problem(prob)
     dg = osig.diagonal(hb)
     ps = np.array([o - 2, o - 1])
-    om = np.linspace(-dg[o - 1] - 0.3, -dg[o - 1] + 0.6, 32)
     gpu_ctx.build_from_problem(prob)
-    res = gpu_ctx.gfcc_solve(om, ps, eta, tol=1e-12, restart=30, block=64, maxit=3000,
+    scan = np.linspace(-dg[o - 1] - 1.0, -dg[o - 1] + 1.0, 256)
+    sc = gpu_ctx.gfcc_solve(scan, ps[1:], eta, tol=1e-8, restart=30, block=256, maxit=3000)
+    wstar = scan[np.argmax(np.abs(sc.G.cpu().numpy()[:, 0, 0]))]
+    om = np.linspace(wstar - 0.05, wstar + 0.05, 32)
+    # tol 1e-11: the residual's rounding floor here is a few 1e-12 (see below), and short
+    # restarted cycles take 100 to 600 iterations (unrestarted GMRES about 30)
+    tol = 1e-11
+    res = gpu_ctx.gfcc_solve(om, ps, eta, tol=tol, restart=10, block=64, maxit=3000,
                              want_x=True)
-    print(f"  iterations {res.iters.min()}..{res.iters.max()}", flush=True)
-    assert res.resid.max() <= 1e-12
-    assert res.iters.max() > 30          # several restart cycles
+    print(f"  pole near {wstar:.4f}; iterations {res.iters.min()}..{res.iters.max()}", flush=True)
+    assert res.resid.max() <= tol
+    assert res.iters.min() > 20          # three restart cycles or more
     G = res.G.cpu().numpy()
     X = res.X.cpu().numpy()
     op = osolve.Operator(hb)
@@ -269,14 +317,27 @@ def test_near_pole_block_o24v90(gpu_ctx):
     picks = [(hard[0][0], hard[1][0]), (hard[0][1], hard[1][1]), (0, 0)]
     for w, k in picks:
         b = osig.b_vector(o, v, int(ps[k]))
-        x, it, r = osolve.gmres(op, b, float(om[w]), eta, tol=1e-13, restart=30, maxit=3000)
+        # unrestarted (up to 200 steps): about 35 iterations here, where restarted GMRES
+        # needs hundreds
+        x, it, r = osolve.gmres(op, b, float(om[w]), eta, tol=1e-12, restart=200, maxit=1000)
+        assert r <= 1e-12
         g = C @ x
         err = np.abs(G[w, :, k] - g).max() / np.abs(g).max()
-        # residual of the returned solution with the oracle's operator
+        # The residual of the returned solution with the oracle's operator. The two operators
+        # are built with different summation orders, so H x differs between them by about eps
+        # (||H x|| + |z| ||x||) per unit ||b|| (fl, about 4e-12 here, where ||x|| ~ 200 next to
+        # the pole): the reported residual must agree with the oracle's to a small multiple of
+        # that, and so stay below tol plus it (a relation residual carried over tens of cycles
+        # instead of restarting from explicit residuals fell 30 times below it)
         xr = X[w, k]
-        true = np.linalg.norm(b - (op.hbar(xr) + (om[w] - 1j * eta) * xr)) / np.linalg.norm(b)
+        z = om[w] - 1j * eta
+        hx = op.hbar(xr)
+        true = np.linalg.norm(b - (hx + z * xr)) / np.linalg.norm(b)
+        scale = (np.linalg.norm(hx) + abs(z) * np.linalg.norm(xr)) / np.linalg.norm(b)
+        fl = np.finfo(float).eps * scale
         print(f"  omega={om[w]:.4f} p={ps[k]} gpu its {res.iters[w, k]} oracle its {it}: "
-              f"G err {err:.1e}, residual {res.resid[w, k]:.2e} vs oracle {true:.2e}",
-              flush=True)
+              f"G err {err:.1e}, residual {res.resid[w, k]:.2e} vs oracle {true:.2e} "
+              f"(rounding scale {fl:.1e})", flush=True)
         assert err < 1e-9
-        assert abs(true - res.resid[w, k]) <= 1e-13
+        assert abs(true - res.resid[w, k]) <= 1e-13 + 16 * fl
+        assert true <= tol + 16 * fl

@@ -169,7 +169,10 @@ def test_bf16_pairs_solve_takes_the_pair_kernel(gpu_ctx):
     Ar = osolve.spectral(Gr)
     gpu_ctx.build_from_problem(p, keep=gfcc.KEEP_FP32)
     gpu_ctx.timer(2, enable=True, reset=True)
-    res = gpu_ctx.gfcc_solve(om, ps, eta, tol=1e-8, restart=20, block=64,
+    # the spectrum is dense next to the lowest poles: restarted inner solves take hundreds of
+    # iterations here (the oracle's emulation of the same refinement needs 225 at the window's
+    # centre), so the iteration cap is generous
+    res = gpu_ctx.gfcc_solve(om, ps, eta, tol=1e-8, restart=30, block=64, maxit=4000,
                              precision=gfcc.BF16_PAIRS)
     _, launches = gpu_ctx.timer(2, enable=False, reset=True)
     assert launches > 0
@@ -178,7 +181,8 @@ def test_bf16_pairs_solve_takes_the_pair_kernel(gpu_ctx):
     assert np.abs(A - Ar).max() / np.abs(Ar).max() < 1e-6
     # the same solve in FP32 never takes the pair kernel
     gpu_ctx.timer(2, enable=True, reset=True)
-    gpu_ctx.gfcc_solve(om[:4], ps, eta, tol=1e-8, block=64, precision=gfcc.FP32)
+    gpu_ctx.gfcc_solve(om[:4], ps, eta, tol=1e-8, restart=30, block=64, maxit=4000,
+                       precision=gfcc.FP32)
     assert gpu_ctx.timer(2, enable=False, reset=True)[1] == 0
 
 

@@ -102,7 +102,7 @@ def test_errors(gpu_ctx):
         gpu_ctx.gfcc_solve([-0.5], [1, 1], 0.01)  # repeated p
     assert e.value.status == gfcc.GFCC_EINVAL
     with pytest.raises(gfcc.GfccError) as e:
-        gpu_ctx.gfcc_solve([-0.5], [1], 0.0)  # eta = 0
+        gpu_ctx.gfcc_solve([-0.5], [1], -0.01)  # eta < 0
     assert e.value.status == gfcc.GFCC_EINVAL
     # precisions: unknown values, reduced ones without the FP32 copies, reduced transposes
     for prec in (-1, 4):
