@@ -111,7 +111,7 @@ struct Operator {
   OpPieces<float> f32;
   DevBuf Vp_bf16, T2p_bf16;     // bf16 three-body operands (mixed precision): high parts
   DevBuf Vp_bf16_lo, T2p_bf16_lo;  // and the bf16 remainders (x = hi + lo)
-  DevBuf Weff_bf16, Weff_bf16_lo;  // Weff as bf16 pairs, rows padded to ldweff_bf, then zeros
+  DevBuf Weff_bf16, Weff_bf16_lo;  // Weff as bf16 pairs [o v][ldweff_bf] (pairs_split_rows)
   int64_t ldweff_bf = 0;
   DevBuf WeffT, W1T, W4cT, WooT, VpT;  // transposed copies (adjoint)
   DevBuf diag;                  // [D] diagonal of Hbar_N
@@ -151,6 +151,7 @@ struct gfcc_ctx {
   gfcc::DevBuf ws_a, ws_b, ws_c, ws_d, ws_e;
   gfcc::DevBuf ws_trans;    // transposed B operands of the row-major product paths
   gfcc::DevBuf ws_io;       // sigma_apply: D-major copies of its input and output blocks
+  gfcc::DevBuf ws_pairs;    // the expanded bf16-pair operand of the two-term ovvo product
   gfcc::DevBuf ws_solve, ws_solve_f32;  // GMRES block work arrays (Krylov basis, state)
   std::vector<gfcc::DevBuf> build_pool;  // operator-build buffers kept for the next build
   gfcc::DevBuf zrow;        // zeros (read for structurally zero rows of the ovvo operand)
@@ -233,10 +234,18 @@ void cast_f32_bf16(gfcc_ctx* ctx, const float* s, __hip_bfloat16* d, int64_t n);
 // elements (total >= rows * ld)
 void split_pad_f64_bf16(gfcc_ctx* ctx, const double* s, int64_t rows, int64_t cols,
                         __hip_bfloat16* hi, __hip_bfloat16* lo, int64_t ld, int64_t total);
-// ovvo contraction with two-term bf16 operands (FP32 X2 and Z); false when the shape is not
-// the column-block one (the caller then uses the FP32 kernel)
-bool ovvo_bf3(gfcc_ctx* ctx, int o, int v, int nc, const void* Wh, const void* Wl, int64_t ldw,
+// ovvo contraction with two-term bf16 operands (FP32 X2 and Z; W as pairs from
+// pairs_split_rows); false when nc is not a multiple of 128 (the caller then uses the FP32
+// kernel)
+bool ovvo_bf3(gfcc_ctx* ctx, int o, int v, int nc, const void* Wh, const void* Wl,
               const float* X2, int64_t ldx, float* Z);
+// row length (bf16 elements) of the pairs of the o v x o v ovvo matrix: o segments of v rounded
+// up to 8, rounded up to a 32-deep slab
+int64_t pairs_ldk(int o, int v);
+// rows of those pairs: o v rounded up to a multiple of 256 (the extra rows are zero)
+int64_t pairs_rows(int o, int v);
+// those pairs from the FP64 matrix S [o v][o v]: hi and lo are [pairs_rows][pairs_ldk] bf16
+void pairs_split_rows(gfcc_ctx* ctx, const double* S, int o, int v, void* hi, void* lo);
 void split_f64_bf16(gfcc_ctx* ctx, const double* s, __hip_bfloat16* hi, __hip_bfloat16* lo,
                     int64_t n);
 void split_f32_bf16(gfcc_ctx* ctx, const float* s, __hip_bfloat16* hi, __hip_bfloat16* lo,

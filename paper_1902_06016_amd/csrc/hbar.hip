@@ -518,14 +518,13 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
       float* Wf = F(g.Weff, OV * OV + wpadf);
       cast_f64_f32(ctx, Weff, Wf, OV * OV);
       fill_f(ctx, Wf + OV * OV, wpadf, 0.0f);
-      // Weff as bf16 pairs for the two-term ovvo: rows padded to a multiple of 8 (16-byte
-      // chunks), then one slab (64) of zeros read past the last row
-      op.ldweff_bf = (OV + 7) / 8 * 8;
-      const int64_t nwb = OV * op.ldweff_bf + 64;
+      // Weff as bf16 pairs for the two-term ovvo: k segments of v padded to a multiple of 8,
+      // rows padded to the 32-deep slab
+      op.ldweff_bf = pairs_ldk(o, v);
+      const int64_t nwb = pairs_rows(o, v) * op.ldweff_bf;
       bb.take(op.Weff_bf16, (size_t)nwb * sizeof(__hip_bfloat16));
       bb.take(op.Weff_bf16_lo, (size_t)nwb * sizeof(__hip_bfloat16));
-      split_pad_f64_bf16(ctx, Weff, OV, OV, op.Weff_bf16.as<__hip_bfloat16>(),
-                         op.Weff_bf16_lo.as<__hip_bfloat16>(), op.ldweff_bf, nwb);
+      pairs_split_rows(ctx, Weff, o, v, op.Weff_bf16.p, op.Weff_bf16_lo.p);
       // bf16 three-body operands: Vp and -t2 packed as [(ij)a][d]
       bb.take(op.Vp_bf16, (size_t)PV * V * sizeof(__hip_bfloat16));
       bb.take(op.Vp_bf16_lo, (size_t)PV * V * sizeof(__hip_bfloat16));

@@ -198,7 +198,7 @@ void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, int precis
   hipEvent_t e_bf3 = nullptr;
   timer_begin(ctx, 2, &e_bf3);
   if (precision == GFCC_BF16_PAIRS &&
-      ovvo_bf3(ctx, o, v, nc, op.Weff_bf16.p, op.Weff_bf16_lo.p, op.ldweff_bf, X2, nc, Z)) {
+      ovvo_bf3(ctx, o, v, nc, op.Weff_bf16.p, op.Weff_bf16_lo.p, X2, nc, Z)) {
     timer_end(ctx, 2, e_bf3);
   } else {
     timer_cancel(ctx, e_bf3);
