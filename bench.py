@@ -57,7 +57,7 @@ def measured_traffic(o, v, nb):
     return traffic if (rec == sha and block == nb) else None
 
 
-def cpu_baseline(prob, cfg, omega, ps, gpu_G, gpu_A, n_p_sample):
+def cpu_baseline(prob, cfg, omega, ps, gpu_G, gpu_A, n_p_sample, hb=None, t_build=None):
     """Oracle on a bounded sample: H-bar build once, then GMRES at one frequency for
     n_p_sample orbitals. Scaled to frequency points/s of the full workload. Also returns the
     GPU's errors against these oracle solutions: every sampled entry G_qp relative to itself
@@ -69,9 +69,10 @@ def cpu_baseline(prob, cfg, omega, ps, gpu_G, gpu_A, n_p_sample):
     from oracle import sigma as osig
     from oracle import solve as osolve
 
-    t0 = time.time()
-    hb = ohbar.build_hbar_from_problem(prob)
-    t_build = time.time() - t0
+    if hb is None:
+        t0 = time.time()
+        hb = ohbar.build_hbar_from_problem(prob)
+        t_build = time.time() - t0
     w_idx = len(omega) // 2
     op = osolve.Operator(hb)
     t1 = time.time()
@@ -523,7 +524,245 @@ def form_adjoint(ctx, cfg, gfcc, inputs):
             "max_rel_resid_adj": float(adj.resid.max())}
 
 
-def form_mixed(cfg, gfcc, torch):
+def vector_bytes(its, restart, D):
+    """Algorithmic vector traffic of restarted GMRES: 16 D (2j + 3) bytes per iteration of
+    Krylov index j and right-hand side (one Gram-Schmidt pass over the basis and the update)."""
+    tot = 0.0
+    for n in np.asarray(its).reshape(-1):
+        for it in range(int(n)):
+            j = it % restart
+            tot += 16.0 * D * (2 * j + 3)
+    return tot
+
+
+def form_poles(ctx, prob, gfcc, oracle_hb=None):
+    """The regime the paper's convergence study is about: frequencies at the poles of the
+    benzene-shaped operator instead of far below them. A main-line window across the pole of
+    the highest occupied orbital (at minus its 1h diagonal element of H-bar_N, which the
+    recipe's correlation puts near 560 Ha) and a narrow window inside the 2h1p satellite band.
+    GMRES iterations and rates, the vector kernels' bandwidth at these Krylov indices, a
+    reduced model refined on the main-line window against full solves, guesses from it, DIIS,
+    and the reported residual of two returned solutions against the oracle's."""
+    import torch
+    import synth
+    o, v, eta, tol = prob.o, prob.v, 0.005, 1e-10
+    D = gfcc.dim(o, v)
+    ps = synth.valence_p(o, 8)
+    dg = ctx.export("diag").cpu().numpy()
+    top = float(dg[o - 1])
+    sat = float(0.5 * (dg[o:].min() + dg[o:].max()))
+    out = {"eta": eta, "tol": tol, "orbitals": len(ps),
+           "one_hole_diagonal_top_Ha": top, "satellite_band_Ha": [float(dg[o:].min()),
+                                                                  float(dg[o:].max())]}
+
+    def solve(name, om, restart, maxit, want_x=False, x0=None):
+        ctx.timer(1, enable=True, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        r = ctx.gfcc_solve(om, ps, eta, tol=tol, restart=restart, block=len(om) * len(ps),
+                           maxit=maxit, allow_noconv=True, want_x=want_x, x0=x0)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        sig_ms, sig_n = ctx.timer(1, enable=False, reset=True)
+        t_vec = max(dt - sig_ms * 1e-3, 1e-9)
+        byt = vector_bytes(r.iters, restart, D)
+        rec = {"window_Ha": [float(om[0]), float(om[-1])], "points": len(om),
+               "right_hand_sides": len(om) * len(ps), "restart": restart, "maxit": maxit,
+               "s": dt, "points_per_s": len(om) / dt,
+               "iterations_mean": float(r.iters.mean()), "iterations_max": int(r.iters.max()),
+               "not_converged": int((r.resid > tol).sum()), "max_rel_resid": float(r.resid.max()),
+               "sigma_products": sig_n, "sigma_s": sig_ms * 1e-3,
+               "vector_s": t_vec, "vector_bytes_algorithmic": byt,
+               "vector_gbps_algorithmic": byt / t_vec / 1e9,
+               "vector_frac_hbm_algorithmic": byt / t_vec / 1e9 / PEAK_HBM_GBPS}
+        log(f"[bench] poles: {name} {dt:.2f} s, iterations {rec['iterations_mean']:.1f} mean, "
+            f"{rec['iterations_max']} max, {rec['not_converged']} not converged")
+        return r, rec
+
+    om1 = np.linspace(-top - 0.25, -top + 0.25, 40)
+    r1, out["main_line"] = solve("main line", om1, 30, 600, want_x=True)
+    A1 = gfcc.spectral_function(r1.G)
+    out["main_line"]["A_range"] = [float(A1.min()), float(A1.max())]
+    om2 = np.linspace(-sat - 0.05, -sat + 0.05, 8)
+    _, out["satellite"] = solve("satellite", om2, 60, 300)
+    # reported residuals of two returned solutions against the oracle's ||b - M x|| / ||b||
+    if oracle_hb is not None:
+        from oracle import sigma as osig
+        from oracle import solve as osolve
+        op = osolve.Operator(oracle_hb)
+        chk = []
+        hard = np.unravel_index(np.argsort(r1.iters, axis=None)[::-1][:2], r1.iters.shape)
+        X = r1.X
+        for w, k in zip(*hard):
+            x = X[w, k].cpu().numpy()
+            b = osig.b_vector(o, v, int(ps[k]))
+            hx = op.hbar(x)
+            z = om1[w] - 1j * eta
+            true = float(np.linalg.norm(b - (hx + z * x)) / np.linalg.norm(b))
+            scale = float((np.linalg.norm(hx) + abs(z) * np.linalg.norm(x)) / np.linalg.norm(b))
+            chk.append({"omega": float(om1[w]), "p": int(ps[k]), "iterations": int(r1.iters[w, k]),
+                        "reported": float(r1.resid[w, k]), "oracle": true,
+                        "rounding_scale": scale * float(np.finfo(float).eps)})
+        out["main_line"]["residual_vs_oracle"] = chk
+    G1 = r1.G.cpu().numpy()
+    del X, r1
+    # DIIS on the main-line window, beside GMRES
+    torch.cuda.synchronize()
+    t0 = time.time()
+    d = ctx.gfcc_solve_diis(om1, ps, eta, tol=tol, maxit=600, ndiis=10, block=320,
+                            allow_noconv=True)
+    torch.cuda.synchronize()
+    Ad = gfcc.spectral_function(d.G)
+    out["diis"] = {"s": time.time() - t0, "iterations_mean": float(d.iters.mean()),
+                   "iterations_max": int(d.iters.max()),
+                   "not_converged": int((d.resid > tol).sum()),
+                   "A_max_rel_diff_vs_gmres": float(np.abs(Ad - A1).max() / np.abs(A1).max())}
+    # reduced model on the window: 4 sampled frequencies, midpoint refinement to residual 1e-6,
+    # 2000 evaluation points, checked against the 40 full solves
+    lo, hi = float(om1[0]), float(om1[-1])
+    grid = np.linspace(lo, hi, 2000)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    m = ctx.mor_build(np.linspace(lo, hi, 4), ps, eta, solve_tol=tol)
+    rounds, rmax = m.refine(grid, lo, hi, per_round=4, resid_tol=1e-6)
+    torch.cuda.synchronize()
+    t1 = time.time()
+    Gm, res = m.eval(grid)
+    torch.cuda.synchronize()
+    t2 = time.time()
+    order, oks = m.info()
+    Gc, _ = m.eval(om1)
+    Am = gfcc.spectral_function(Gc)
+    x0 = m.lift(om1)
+    m.close()
+    out["mor"] = {"rounds": rounds, "order_m": order, "sampled_omegas": len(oks),
+                  "max_resid_window": float(rmax), "points": len(grid),
+                  "points_per_s_end_to_end": len(grid) / (t2 - t0),
+                  "points_per_s_eval_only": len(grid) / (t2 - t1),
+                  "A_max_rel_err_vs_full": float(np.abs(Am - A1).max() / np.abs(A1).max()),
+                  "G_max_err_rel_to_max_G": float(np.abs(Gc.cpu().numpy() - G1).max()
+                                                  / np.abs(G1).max())}
+    # the refined model's lifted solutions as initial guesses for the full solves
+    rg, rec = solve("guess", om1, 30, 600, x0=x0)
+    out["guess"] = {"iterations_mean": rec["iterations_mean"], "iterations_max":
+                    rec["iterations_max"], "s": rec["s"], "not_converged": rec["not_converged"],
+                    "speedup_solve": out["main_line"]["s"] / rec["s"]}
+    del x0
+    return out
+
+
+def oracle_rates(hb, prob, gfcc, forms_out, cfg_mor, cfg_adj):
+    """The oracle beside the GPU forms, on bounded samples (seconds each; the H-bar build of
+    the benzene shape is shared and counted once in the plain form's baseline)."""
+    from oracle import adjoint as oadj
+    from oracle import mor as omor
+    from oracle import sigma as osig
+    from oracle import solve as osolve
+    import synth
+    o, v = prob.o, prob.v
+    res = {}
+    op = osolve.Operator(hb)
+    # reduced model: one full solve of the 64, one sigma product for the projection of each of
+    # the m basis columns, and the oracle's evaluation (it forms each residual explicitly) of
+    # 200 of the 4000 points on a model of the GPU model's order m; scaled to the GPU run's
+    # counts
+    if "mor" in forms_out:
+        g = forms_out["mor"]
+        ps = synth.valence_p(o, cfg_mor["np"])
+        lo, hi = cfg_mor["sample_window"]
+        t0 = time.time()
+        osolve.gmres(op, osig.b_vector(o, v, int(ps[-1])), lo, cfg_mor["eta"], tol=cfg_mor["tol"])
+        t_solve = time.time() - t0
+        mm, nsolve = g["order_m"], g["full_solves"]
+        D = gfcc.dim(o, v)
+        rng = np.random.default_rng(0)
+        t0 = time.time()
+        osig.sigma(hb, rng.standard_normal((1, D)))
+        t_sig = time.time() - t0
+        C = np.stack([osig.c_vector(o, v, prob.t1, prob.t2, prob.l1, prob.l2, int(q))
+                      for q in ps], 0)
+        rom = omor.ROM(hb, ps, cfg_mor["eta"], C, None)
+        rom.S = np.linalg.qr(rng.standard_normal((D, mm)))[0]
+        rom.HS = rng.standard_normal((D, mm))
+        t0 = time.time()
+        rom.eval(np.linspace(-0.9, -0.1, 200))
+        t_eval = (time.time() - t0) * g["points"] / 200
+        t_tot = t_solve * nsolve + t_sig * mm + t_eval
+        res["mor"] = {"points_per_s_end_to_end": g["points"] / t_tot,
+                      "points_per_s_eval_only": g["points"] / t_eval,
+                      "sample": f"1 of {nsolve} full solves ({t_solve:.1f} s), one sigma "
+                                f"product ({t_sig:.2f} s) for each of the {mm} basis columns, "
+                                f"and the evaluation of 200 of {g['points']} points at order "
+                                f"{mm}, scaled to the workload"}
+    # adjoint: one forward and one transposed solve at one frequency, scaled to all orbitals
+    # and frequencies of the workload
+    if "adjoint" in forms_out:
+        g = forms_out["adjoint"]
+        ps = synth.valence_p(o, cfg_adj["np"])
+        om = synth.omega_grid(cfg_adj["omega"])
+        t0 = time.time()
+        x, _, _ = osolve.gmres(op, osig.b_vector(o, v, int(ps[-1])), float(om[50]),
+                               cfg_adj["eta"], tol=cfg_adj["tol"])
+        opt = osolve.Operator(hb, transpose=True)
+        c = osig.c_vector(o, v, prob.t1, prob.t2, prob.l1, prob.l2, int(ps[-1]))
+        y, _, _ = osolve.gmres(opt, c, float(om[50]), cfg_adj["eta"], tol=cfg_adj["tol"])
+        oadj.gradient_from_solutions(x[None, None], y[None, None], [1.0], o, v)
+        t_pair = time.time() - t0
+        per_point = t_pair * len(ps)
+        res["adjoint"] = {"points_per_s": 1.0 / per_point,
+                          "sample": f"one forward and one transposed solve and the gradient "
+                                    f"reduction at omega={om[50]:.4f} for 1 of {len(ps)} "
+                                    f"orbitals ({t_pair:.1f} s), scaled to all orbitals"}
+    return res
+
+
+def small_oracle(gfcc):
+    """The small case's oracle as the oracle defines it there: the dense H-bar from sigma on
+    unit vectors and dense LU at every (omega, p), plus its GMRES on a sample."""
+    import synth
+    from oracle import hbar as ohbar
+    from oracle import sigma as osig
+    from oracle import solve as osolve
+    cfg = synth.WORKLOADS["o10v20"]
+    o, v = cfg["o"], cfg["v"]
+    prob = synth.make_problem(o, v, cfg["seed"])
+    om = synth.omega_grid(cfg["omega"])
+    ps = synth.valence_p(o, cfg["np"])
+    t0 = time.time()
+    hb = ohbar.build_hbar_from_problem(prob)
+    H = osolve.dense_hbar(hb)
+    B = np.stack([osig.b_vector(o, v, int(p)) for p in ps], 1)
+    C = np.stack([osig.c_vector(o, v, prob.t1, prob.t2, prob.l1, prob.l2, int(q)) for q in ps], 0)
+    osolve.spectral(osolve.green(C, osolve.dense_solve(H, om, B, cfg["eta"])))
+    t_dense = time.time() - t0
+    op = osolve.Operator(hb)
+    t0 = time.time()
+    for w in (0, 32, 63):
+        osolve.gmres(op, B[:, -1], float(om[w]), cfg["eta"], tol=cfg["tol"])
+    t_g = (time.time() - t0) / 3
+    return {"dense_lu": {"points_per_s": len(om) / t_dense,
+                         "sample": f"the whole workload: dense H-bar and LU at {len(om)} omega x "
+                                   f"{len(ps)} p ({t_dense:.2f} s)"},
+            "gmres": {"points_per_s": 1.0 / (t_g * len(ps)),
+                      "sample": f"GMRES (tol {cfg['tol']}) at 3 omega for 1 of {len(ps)} orbitals "
+                                f"({t_g:.3f} s per system), scaled to all orbitals"}}
+
+
+def cpu_info():
+    import multiprocessing
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": multiprocessing.cpu_count(), "model": model,
+            "threads_used": int(os.environ.get("OMP_NUM_THREADS", multiprocessing.cpu_count()))}
+
+
+def form_mixed(cfg, gfcc, torch, n_oracle=0):
     """Batched mixed precision at the adenine/cc-pVDZ shape: one launch of 32 omega x 16 p
     right-hand sides, FP64 refinement to relative residual 1e-8 around a reduced sigma (ovvo on
     two-term bf16 pairs; FP32 with the three-body term on two-term bf16; FP32), and the same
@@ -538,7 +777,9 @@ def form_mixed(cfg, gfcc, torch):
     dev = torch.device("cuda", 0)
     ctx = gfcc.Context(0)
     inputs = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in host]
-    del host, prob
+    del host
+    if not n_oracle:
+        del prob
     torch.cuda.synchronize()
     t0 = time.time()
     ctx.build_hbar_operands(o, v, *inputs, keep=gfcc.KEEP_FP32)
@@ -573,6 +814,46 @@ def form_mixed(cfg, gfcc, torch):
         Am = gfcc.spectral_function(res[name][0].G)
         out[name]["A_max_rel_err_vs_fp64"] = float(np.abs(Am - Ad).max() / np.abs(Ad).max())
         out[name]["speedup_vs_fp64"] = res["fp64"][1] / res[name][1]
+    if n_oracle:
+        # the FP64 oracle at n_oracle of the 512 right-hand sides: its H-bar build at this shape
+        # and GMRES at tol 1e-13; every variant's G column and A term against it
+        from oracle import hbar as ohbar
+        from oracle import sigma as osig
+        from oracle import solve as osolve
+        log("[bench] mixed: oracle H-bar build ...")
+        t0 = time.time()
+        hb = ohbar.build_hbar_from_problem(prob)
+        t_b = time.time() - t0
+        op = osolve.Operator(hb)
+        C = np.stack([osig.c_vector(o, v, prob.t1, prob.t2, prob.l1, prob.l2, int(q))
+                      for q in ps], 0)
+        Gs = {name: res[name][0].G.cpu().numpy() for name in res}
+        amax = float(np.abs(Ad).max())
+        errs = {name: {"A_term_max_err_rel_to_max_A": 0.0, "G_column_max_rel_err": 0.0}
+                for name in res}
+        t0 = time.time()
+        picks = ((0, len(ps) - 1), (len(om) - 1, 0), (11, 7), (20, 12))[:max(1, min(4, n_oracle))]
+        for w, k in picks:
+            x, _, _ = osolve.gmres(op, osig.b_vector(o, v, int(ps[k])), float(om[w]),
+                                   cfg["eta"], tol=1e-13)
+            g = C @ x
+            for name in res:
+                e = errs[name]
+                e["A_term_max_err_rel_to_max_A"] = max(
+                    e["A_term_max_err_rel_to_max_A"],
+                    float(abs((Gs[name][w, k, k] - g[k]).imag) / np.pi / amax))
+                e["G_column_max_rel_err"] = max(e["G_column_max_rel_err"], float(
+                    np.abs(Gs[name][w, :, k] - g).max() / np.abs(g).max()))
+        t_s = time.time() - t0
+        for name in res:
+            out[name]["vs_oracle"] = errs[name]
+        nk = len(picks)
+        out["oracle"] = {"right_hand_sides_per_s": nk / (t_b + t_s),
+                         "points_per_s": nk / (t_b + t_s) / len(ps),
+                         "build_s": t_b, "solve_s_per_rhs": t_s / nk, "cpu": cpu_info(),
+                         "sample": f"H-bar build ({t_b:.0f} s) and GMRES (tol 1e-13) at {nk} of "
+                                   f"the {nrhs} right-hand sides ({t_s:.0f} s)"}
+        del hb, op, Gs
     # kept at the top level for the fastest form: every large contraction on two-term bf16
     out["A_max_rel_err_vs_fp64"] = out["bf16_pairs"]["A_max_rel_err_vs_fp64"]
     out["speedup_vs_fp64"] = out["bf16_pairs"]["speedup_vs_fp64"]
@@ -613,9 +894,13 @@ def main():
     ap.add_argument("--sigma-only", type=int, default=0,
                     help="profiling driver: K sigma products of one block in the benchmark's "
                          "launch configuration, then a 1 GiB device copy (counter calibration)")
-    ap.add_argument("--forms", default="mor,guess,diis,pert,adjoint,mixed,small",
+    ap.add_argument("--forms", default="mor,guess,diis,pert,adjoint,poles,mixed,small",
                     help="extra forms reported beside the plain path: mor, guess, diis, pert, "
-                         "adjoint, mixed, small, none")
+                         "adjoint, poles, mixed, small, none")
+    ap.add_argument("--oracle-mixed", type=int, default=2,
+                    help="right-hand sides of the mixed form on which the FP64 oracle is run and "
+                         "timed (0 to skip; its H-bar build at the adenine shape takes about a "
+                         "minute, each solve about half a minute)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py runs on one GPU only; the (omega, p) right-hand "
@@ -740,8 +1025,19 @@ def main():
     out["rows"] = rows_report(o, v, D, nb, dt / args.steps, t_build, sig_ms / args.steps,
                               sig_n // args.steps, its, args.restart)
     forms = [f for f in args.forms.split(",") if f and f != "none"]
+    # the oracle's H-bar of this operator, shared by the baseline, the oracle rates of the
+    # reduced-model and adjoint forms and the residual check of the pole form
+    hb_oracle, t_hb = None, None
+    if not args.no_cpu_baseline:
+        from oracle import hbar as ohbar
+        log("[bench] oracle H-bar build ...")
+        t0 = time.time()
+        hb_oracle = ohbar.build_hbar_from_problem(prob)
+        t_hb = time.time() - t0
     if "small" in forms:
         out["small"] = form_small(gfcc, torch)
+        if hb_oracle is not None:
+            out["small"]["oracle"] = small_oracle(gfcc)
     if "mor" in forms:
         out["mor"] = form_mor(ctx, prob, synth.WORKLOADS["o42v186_mor"], gfcc)
     if "guess" in forms:
@@ -752,19 +1048,29 @@ def main():
         out["pert"] = form_pert(cfg, gfcc, inputs, A, t_build)
     if "adjoint" in forms:
         out["adjoint"] = form_adjoint(ctx, synth.WORKLOADS["o42v186_adjoint"], gfcc, inputs)
+    if "poles" in forms:
+        out["poles"] = form_poles(ctx, prob, gfcc, hb_oracle)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample) ...")
         G = res.G.cpu().numpy()
-        cb, errs = cpu_baseline(prob, cfg, omega, ps, G, A, args.cpu_sample_p)
+        cb, errs = cpu_baseline(prob, cfg, omega, ps, G, A, args.cpu_sample_p, hb_oracle, t_hb)
+        cb["cpu"] = cpu_info()
         out["cpu_baseline"] = cb
         out["solver"]["vs_oracle"] = errs
+        log("[bench] oracle rates of the other forms ...")
+        rates = oracle_rates(hb_oracle, prob, gfcc, out, synth.WORKLOADS["o42v186_mor"],
+                             synth.WORKLOADS["o42v186_adjoint"])
+        for k, val in rates.items():
+            out[k]["oracle"] = val
+        del hb_oracle
     else:
         out["cpu_baseline"] = None
     ctx.close()
     if "mixed" in forms:
         del inputs
         torch.cuda.empty_cache()
-        out["mixed"] = form_mixed(synth.WORKLOADS["o70v260_mixed"], gfcc, torch)
+        out["mixed"] = form_mixed(synth.WORKLOADS["o70v260_mixed"], gfcc, torch,
+                                  0 if args.no_cpu_baseline else args.oracle_mixed)
     print(json.dumps(out))
 
 
