@@ -24,12 +24,15 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
 constexpr int JG = 16;  // basis vectors per dot pass
 constexpr int CW = 64;  // right-hand sides per reduction block: one wavefront, one per lane
 
-// h[(j0+jj)][r] = sum_blk partial[blk][jj][r]. Grid (ceil(nb/64), nj), 256 threads: the lanes
-// are 64 consecutive right-hand sides (coalesced reads), wave w sums the blocks w, w+4, ...,
-// and the four wave sums are added in a fixed order.
-__global__ __launch_bounds__(256) void dots_reduce(const double2* __restrict__ partial, int nblk,
-                                                   int j0, int nj, int nb,
-                                                   double2* __restrict__ h) {
+// h[(j0+jj)][r] = sum_blk partial[blk][jj][r] (partial rows STRIDE apart per block). Grid
+// (ceil(nb/64), nj), 256 threads: the lanes are 64 consecutive right-hand sides (coalesced
+// reads), wave w sums the blocks w, w+4, ..., and the four wave sums are added in a fixed
+// order.
+template <int STRIDE>
+__global__ __launch_bounds__(256) void dots_reduce_s(const double2* __restrict__ partial,
+                                                     int nblk, int j0, int nj, int nb,
+                                                     double2* __restrict__ h) {
+  constexpr int JG = STRIDE;
   __shared__ double2 red[4][CW];
   const int lane = threadIdx.x % CW, w = threadIdx.x / CW;
   const int r = blockIdx.x * CW + lane, jj = blockIdx.y;

@@ -415,13 +415,13 @@ const void* diis_block(gfcc_ctx* ctx, DiisWork& wk, int nb, int m, const double*
     const int j = k - 1;
     if (j >= 0) {
       if (j > 0) {
-        hipLaunchKernelGGL(dots_reduce, dim3(ncb, j), dim3(256), 0, st, part_h, nblk, 0, j, nb,
+        hipLaunchKernelGGL(dots_reduce_s<JG>, dim3(ncb, j), dim3(256), 0, st, part_h, nblk, 0, j, nb,
                            h1);
         GFCC_LAUNCH_CHECK();
         hipLaunchKernelGGL(diis_orth_kernel, rgrid, dim3(CW), 0, st, Q, vec, j, h1, 1, D, nb,
                            part_h, part_n);
         GFCC_LAUNCH_CHECK();
-        hipLaunchKernelGGL(dots_reduce, dim3(ncb, j), dim3(256), 0, st, part_h, nblk, 0, j, nb,
+        hipLaunchKernelGGL(dots_reduce_s<JG>, dim3(ncb, j), dim3(256), 0, st, part_h, nblk, 0, j, nb,
                            h2);
         GFCC_LAUNCH_CHECK();
       }
@@ -445,7 +445,7 @@ const void* diis_block(gfcc_ctx* ctx, DiisWork& wk, int nb, int m, const double*
         hipLaunchKernelGGL(diis_proj_kernel, rgrid, dim3(CW), 0, st, Q, vec, m - 1,
                            E + (int64_t)(m - 1) * vec, D, nb, part_h);
         GFCC_LAUNCH_CHECK();
-        hipLaunchKernelGGL(dots_reduce, dim3(ncb, m - 1), dim3(256), 0, st, part_h, nblk, 0,
+        hipLaunchKernelGGL(dots_reduce_s<JG>, dim3(ncb, m - 1), dim3(256), 0, st, part_h, nblk, 0,
                            m - 1, nb, g);
         GFCC_LAUNCH_CHECK();
         hipLaunchKernelGGL(diis_gamma_kernel, cgrid, dim3(64), 0, st, Rm, g, m - 1, nb, actd,

@@ -23,6 +23,10 @@
 namespace gfcc {
 namespace {
 
+// basis vectors covered by one sweep of the fused Arnoldi kernels (restart lengths up to 32 run
+// every step on them; longer ones continue on dots_kernel and update_kernel)
+constexpr int FJ = 32;
+
 
 // partial[blk][jj][r] = sum over this block's rows of conj(V_j[d][r]) * W[d][r], j = j0 + jj.
 // Grid (nblk, ceil(nb / 64)), one wavefront per block; every lane owns one right-hand side
@@ -56,9 +60,9 @@ __global__ __launch_bounds__(CW) void dots_kernel(const double2* __restrict__ V,
     if (jj < nj) partial[((int64_t)blockIdx.x * JG + jj) * nb + r] = acc[jj];
 }
 
-// ---- fused Arnoldi passes over NJ <= JG basis vectors (same grid and partial layout as
-// dots_kernel). NJ is a template parameter so that every load of a row is issued before the
-// arithmetic that consumes it.
+// ---- fused Arnoldi passes over NJ <= FJ basis vectors (the grid of dots_kernel; partial rows are
+// FJ apart per block). NJ is a template parameter so that every load of a row is issued before
+// the arithmetic that consumes it.
 
 // W += z U (the shift of M(omega) after the sigma product), then the first Gram-Schmidt
 // pass's dots with V_0 .. V_{NJ-1}
@@ -96,7 +100,7 @@ __global__ __launch_bounds__(CW) void shift_dots_kernel(const double2* __restric
     }
   }
 #pragma unroll
-  for (int jj = 0; jj < NJ; ++jj) partial[((int64_t)blockIdx.x * JG + jj) * nb + r] = acc[jj];
+  for (int jj = 0; jj < NJ; ++jj) partial[((int64_t)blockIdx.x * FJ + jj) * nb + r] = acc[jj];
 }
 
 // W -= sum_j V_j h[j]; then, with the same V_j in registers, the dots of the next pass
@@ -138,7 +142,7 @@ __global__ __launch_bounds__(CW) void update_dots_kernel(const double2* __restri
     }
   }
 #pragma unroll
-  for (int jj = 0; jj < NJ; ++jj) partial[((int64_t)blockIdx.x * JG + jj) * nb + r] = acc[jj];
+  for (int jj = 0; jj < NJ; ++jj) partial[((int64_t)blockIdx.x * FJ + jj) * nb + r] = acc[jj];
 }
 
 // W -= sum_j V_j h[j]; partial |W|^2 (the norm_kernel layout)
@@ -175,7 +179,7 @@ __global__ __launch_bounds__(CW) void update_norm_kernel(const double2* __restri
   partial[(int64_t)blockIdx.x * nb + r] = acc;
 }
 
-// launch tables over NJ = 1 .. JG
+// launch tables over NJ = 1 .. FJ
 typedef void (*ShiftDotsFn)(const double2*, int64_t, const double2*, const double2*, double2*,
                             int64_t, int, double2*);
 typedef void (*UpdateDotsFn)(const double2*, int64_t, const double2*, double2*, int64_t, int,
@@ -187,8 +191,9 @@ template <int... I> struct FusedTables {
   static constexpr UpdateDotsFn update_dots[] = {update_dots_kernel<I + 1>...};
   static constexpr UpdateNormFn update_norm[] = {update_norm_kernel<I + 1>...};
 };
-using Fused = FusedTables<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15>;
-static_assert(JG == 16, "the launch tables cover NJ = 1 .. 16");
+using Fused = FusedTables<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20,
+                          21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31>;
+static_assert(FJ == 32, "the launch tables cover NJ = 1 .. 32");
 
 
 // W[d][r] -= sum_{j<=k} V_j[d][r] * h[j][r]
@@ -614,7 +619,7 @@ struct GmresBlock {
     add(nb, 16);                                              // z
     add(nb, 8);                                               // nrm
     add((int64_t)nblk_rows * nb, 8);                          // part_n
-    add((int64_t)nblk_rows * JG * nb, 16);                    // part_h
+    add((int64_t)nblk_rows * FJ * nb, 16);                    // part_h
     add(nb, 4); add(nb, 4);                                   // used prow
     add((int64_t)nb * m * (m + 1), 16);                       // H
     add((int64_t)nb * m * (m + 1), 16);                       // Hraw
@@ -638,7 +643,7 @@ struct GmresBlock {
     z = carve<double2>(cur, nb);
     nrm = carve<double>(cur, nb);
     part_n = carve<double>(cur, (int64_t)nblk_rows * nb);
-    part_h = carve<double2>(cur, (int64_t)nblk_rows * JG * nb);
+    part_h = carve<double2>(cur, (int64_t)nblk_rows * FJ * nb);
     used = carve<int>(cur, nb);
     prow = carve<int>(cur, nb);
     s.H = carve<double2>(cur, (int64_t)nb * m * (m + 1));
@@ -689,7 +694,7 @@ struct GmresBlock {
       hipLaunchKernelGGL(dots_kernel, dim3(nblk_rows, nbrows_y), dim3(CW), 0, st(), V, D * nb,
                          j0, cnt, W, D, nb, part_h);
       GFCC_LAUNCH_CHECK();
-      hipLaunchKernelGGL(dots_reduce, dim3(nbrows_y, cnt), dim3(256), 0, st(), part_h, nblk_rows,
+      hipLaunchKernelGGL(dots_reduce_s<JG>, dim3(nbrows_y, cnt), dim3(256), 0, st(), part_h, nblk_rows,
                          j0, cnt, nb, h);
       GFCC_LAUNCH_CHECK();
     }
@@ -718,9 +723,9 @@ struct GmresBlock {
     GFCC_LAUNCH_CHECK();
   }
 
-  // h[j][r] = sum over blocks of the partial dots (nj <= JG)
+  // h[j][r] = sum over blocks of the partial dots of the fused kernels (nj <= FJ)
   void reduce_dots(int nj, double2* h) {
-    hipLaunchKernelGGL(dots_reduce, dim3(nbrows_y, nj), dim3(256), 0, st(), part_h, nblk_rows, 0,
+    hipLaunchKernelGGL(dots_reduce_s<FJ>, dim3(nbrows_y, nj), dim3(256), 0, st(), part_h, nblk_rows, 0,
                        nj, nb, h);
     GFCC_LAUNCH_CHECK();
   }
@@ -866,7 +871,7 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
     const dim3 rgrid(gb.nblk_rows, gb.nbrows_y);
     for (int k = 0; k < m; ++k) {
       const int nj = k + 1;
-      if (nj <= JG) {
+      if (nj <= FJ) {
         // W = sigma(U); the shift, both Gram-Schmidt passes (CGS2) and the norm in three
         // fused sweeps over the basis; Hessenberg column = sum of both passes. The first
         // product of a cycle started from b = e_p is a column of Hbar_N.
