@@ -15,26 +15,38 @@
 namespace gfcc {
 namespace {
 
+// Y2[(i<j, a)][c] += Z[(i,a)][j*nc + c] - Z[(j,a)][i*nc + c]; one workgroup per 2h1p row
+// (pair, a), whose (i, j) it recovers once, with a wave-uniform scan over i
 template <typename T>
-__global__ void antisym_add_kernel(const T* __restrict__ Z, int o, int v, int nc,
-                                   T* __restrict__ Y2) {
-  const int64_t P = (int64_t)o * (o - 1) / 2;
-  const int64_t n = P * v * nc;
+__global__ __launch_bounds__(256) void antisym_add_kernel(const T* __restrict__ Z, int o, int v,
+                                                          int nc, T* __restrict__ Y2) {
+  const int64_t row = blockIdx.x;
+  const int a = (int)(row % v);
+  const int64_t pr = row / v;
+  int i = 0;
+  int64_t base = 0;
+  while (i < o - 1 && pr >= base + (o - 1 - i)) {
+    base += o - 1 - i;
+    ++i;
+  }
+  const int j = (int)(i + 1 + (pr - base));
   const int64_t ldz = (int64_t)o * nc;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    int64_t t = idx;
-    int c = (int)(t % nc); t /= nc;
-    int a = (int)(t % v); t /= v;
-    int64_t pr = t;
-    // pair -> (i, j)
-    int i = 0;
-    int64_t base = 0;
-    while (i < o - 1 && pr >= base + (o - 1 - i)) { base += o - 1 - i; ++i; }
-    int j = (int)(i + 1 + (pr - base));
-    T zij = Z[((int64_t)i * v + a) * ldz + (int64_t)j * nc + c];
-    T zji = Z[((int64_t)j * v + a) * ldz + (int64_t)i * nc + c];
-    Y2[idx] += zij - zji;
+  const T* zij = Z + ((int64_t)i * v + a) * ldz + (int64_t)j * nc;
+  const T* zji = Z + ((int64_t)j * v + a) * ldz + (int64_t)i * nc;
+  T* y = Y2 + row * nc;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) y[c] += zij[c] - zji[c];
+}
+
+// Y1 = S[0:n] and S[0:n] = X1 (the 1h head of the stacked product and its replacement by
+// the 1h block of x), one pass
+template <typename T>
+__global__ void head_swap_kernel(T* __restrict__ S, const T* __restrict__ X1, T* __restrict__ Y1,
+                                 int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const T sv = S[i];
+    Y1[i] = sv;
+    S[i] = X1[i];
   }
 }
 
@@ -109,10 +121,9 @@ void sigma_block_f64(gfcc_ctx* ctx, int nc, const double* X, double* Y, bool tra
     // [sigma_1h ; tau] = [W1 ; 0 | Vp^T] . X, then S = [X_1h ; tau]
     gemm<double>(ctx, false, false, o + v, nc, (int)D, 1.0, f.W1V.as<double>(), D, X, nc, 0.0,
                  S, nc);
-    GFCC_HIP(hipMemcpyAsync(Y1, S, sizeof(double) * (size_t)o * nc, hipMemcpyDeviceToDevice,
-                            ctx->stream));
-    GFCC_HIP(hipMemcpyAsync(S, X1, sizeof(double) * (size_t)o * nc, hipMemcpyDeviceToDevice,
-                            ctx->stream));
+    hipLaunchKernelGGL(head_swap_kernel<double>, dim3(grid_for((int64_t)o * nc)), dim3(256), 0,
+                       ctx->stream, S, X1, Y1, (int64_t)o * nc);
+    GFCC_LAUNCH_CHECK();
     gemm<double>(ctx, false, false, (int)PV, nc, o + v, 1.0, f.W4c.as<double>(), o + v, S, nc,
                  0.0, Y2, nc);
     woo_product<double>(ctx, false, P, (int64_t)v * nc, f.Woo.as<double>(), op.ldwoo, X2, Y2);
@@ -131,7 +142,8 @@ void sigma_block_f64(gfcc_ctx* ctx, int nc, const double* X, double* Y, bool tra
   gemm_ovvo<double>(ctx, transpose, o, v, nc, f.Weff.as<double>(), X2, nc,
                     op.pairlut.as<int>(), Z);
   timer_end(ctx, 0, e_ovvo);
-  hipLaunchKernelGGL(antisym_add_kernel<double>, dim3(grid_for(PV * nc)), dim3(256), 0,
+  GFCC_REQUIRE(PV < (1LL << 31), GFCC_EINVAL, "sigma: too many 2h1p rows");
+  hipLaunchKernelGGL(antisym_add_kernel<double>, dim3((unsigned)PV), dim3(256), 0,
                      ctx->stream, Z, o, v, nc, Y2);
   GFCC_LAUNCH_CHECK();
   timer_end(ctx, 1, e_all);
@@ -205,7 +217,8 @@ void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, int precis
     gemm_ovvo<float>(ctx, false, o, v, nc, f.Weff.as<float>(), X2, nc, op.pairlut.as<int>(), Z);
   }
   timer_end(ctx, 0, e_ovvo);
-  hipLaunchKernelGGL(antisym_add_kernel<float>, dim3(grid_for(PV * nc)), dim3(256), 0,
+  GFCC_REQUIRE(PV < (1LL << 31), GFCC_EINVAL, "sigma: too many 2h1p rows");
+  hipLaunchKernelGGL(antisym_add_kernel<float>, dim3((unsigned)PV), dim3(256), 0,
                      ctx->stream, Z, o, v, nc, Y2);
   GFCC_LAUNCH_CHECK();
   timer_end(ctx, 1, e_all);

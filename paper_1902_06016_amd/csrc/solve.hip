@@ -269,15 +269,6 @@ __global__ void residual_kernel(const double2* __restrict__ B, const double2* __
   }
 }
 
-// a += b (complex, n entries)
-__global__ void cadd_kernel(double2* __restrict__ a, const double2* __restrict__ b, int64_t n) {
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    a[idx].x += b[idx].x;
-    a[idx].y += b[idx].y;
-  }
-}
-
 // V0 = R / beta (zero for inactive)
 __global__ void scale_kernel(const double2* __restrict__ W, const double* __restrict__ inv,
                              int64_t D, int nb, double2* __restrict__ V) {
@@ -312,12 +303,14 @@ __global__ void scale_precond_kernel(const double2* __restrict__ W, const double
 }
 
 struct BlockState {
-  double2* H;      // [nb][m][m+1]  column k of RHS r at H + (r*m + k)*(m+1)
-  double2* Hraw;   // [nb][m][m+1]  the same columns before the Givens rotations
+  // Per-RHS arrays are stored with the RHS index fastest, so that the one-thread-per-RHS
+  // kernels below read and write consecutive addresses across a wavefront.
+  double2* H;      // [m][m+1][nb]  row i of column k of RHS r at H[(k*(m+1) + i)*nb + r]
+  double2* Hraw;   // [m][m+1][nb]  the same columns before the Givens rotations
   double* beta;    // [nb] norm of the residual the cycle started from (0: not in the cycle)
-  double2* cs;     // [nb][m]
-  double2* sn;     // [nb][m]
-  double2* g;      // [nb][m+1]
+  double2* cs;     // [m][nb]
+  double2* sn;     // [m][nb]
+  double2* g;      // [m+1][nb]
   int* active;     // [nb]
   int* kend;       // [nb] steps taken this cycle
   int* its;        // [nb] total iterations
@@ -327,55 +320,95 @@ struct BlockState {
   double* inv;     // [nb] 1/||w|| for the new basis vector
 };
 
-// one thread per RHS: Hessenberg column k, Givens rotation, residual estimate, flags
-__global__ void arnoldi_finish_kernel(const double2* __restrict__ h, const double* __restrict__ hn,
-                                      int k, int m, int nb, int maxit, BlockState s) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nb) return;
-  if (!s.active[r]) {
+// One thread per RHS: Hessenberg column k = h1 + h2 (the two Gram-Schmidt passes), the
+// previous Givens rotations, the new one, the residual estimate and the flags. The rotation
+// chain is serial in i; its operands are loaded eight rows at a time ahead of the arithmetic.
+// flag_out (optional, host-visible): one word per 64 RHS, nonzero while any of them is active.
+__global__ __launch_bounds__(64) void arnoldi_finish_kernel(
+    const double2* __restrict__ h1, const double2* __restrict__ h2,
+    const double* __restrict__ hn, int k, int m, int nb, int maxit, BlockState s,
+    int* __restrict__ flag_out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  bool act = false;
+  if (r < nb && s.active[r]) {
+    const int64_t NB = nb;
+    double2* col = s.H + (int64_t)k * (m + 1) * NB + r;
+    double2* raw = s.Hraw + (int64_t)k * (m + 1) * NB + r;
+    const double2* cs = s.cs + r;
+    const double2* sn = s.sn + r;
+    const double nrm = hn[r];
+    double2 a = h1[r];
+    {
+      const double2 t = h2[r];
+      a.x += t.x;
+      a.y += t.y;
+    }
+    raw[0] = a;
+    for (int i0 = 0; i0 < k; i0 += 8) {
+      double2 hb[8], cb[8], sb[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (i0 + t < k) {
+          const int64_t o = (int64_t)(i0 + t + 1) * NB + r;
+          hb[t] = h1[o];
+          const double2 u = h2[o];
+          hb[t].x += u.x;
+          hb[t].y += u.y;
+          cb[t] = cs[(int64_t)(i0 + t) * NB];
+          sb[t] = sn[(int64_t)(i0 + t) * NB];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (i0 + t < k) {
+          const int i = i0 + t;
+          const double2 b = hb[t];
+          raw[(int64_t)(i + 1) * NB] = b;
+          const double2 t1 = cconjmul(cb[t], a), t2 = cconjmul(sb[t], b);
+          const double2 u1 = cmul(sb[t], a), u2 = cmul(cb[t], b);
+          col[(int64_t)i * NB] = make_double2(t1.x + t2.x, t1.y + t2.y);
+          a = make_double2(u2.x - u1.x, u2.y - u1.y);
+        }
+      }
+    }
+    const double2 b = make_double2(nrm, 0.0);
+    raw[(int64_t)(k + 1) * NB] = b;
+    const double den = hypot(hypot(a.x, a.y), nrm);
+    s.its[r] += 1;
+    s.kend[r] = k + 1;
+    if (den == 0.0) {  // singular least-squares problem
+      col[(int64_t)k * NB] = a;
+      col[(int64_t)(k + 1) * NB] = b;
+      s.brk[r] = 1;
+      s.active[r] = 0;
+      s.inv[r] = 0.0;
+      s.kend[r] = k;  // exclude the singular column
+    } else {
+      const double2 c = make_double2(a.x / den, a.y / den), sv = make_double2(nrm / den, 0.0);
+      s.cs[(int64_t)k * NB + r] = c;
+      s.sn[(int64_t)k * NB + r] = sv;
+      col[(int64_t)k * NB] = make_double2(den, 0.0);
+      col[(int64_t)(k + 1) * NB] = make_double2(0.0, 0.0);
+      double2* g = s.g + r;
+      const double2 gk = g[(int64_t)k * NB];
+      const double2 ng = cmul(sv, gk);
+      const double2 gk1 = make_double2(-ng.x, -ng.y);
+      g[(int64_t)(k + 1) * NB] = gk1;
+      g[(int64_t)k * NB] = cconjmul(c, gk);
+      const double est = hypot(gk1.x, gk1.y);
+      s.resest[r] = est;
+      const bool stop = est <= s.thresh[r] || nrm == 0.0 || s.its[r] >= maxit || k + 1 == m;
+      s.inv[r] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
+      if (stop) s.active[r] = 0;
+      act = !stop;
+    }
+  } else if (r < nb) {
     s.inv[r] = 0.0;
-    return;
   }
-  double2* col = s.H + ((int64_t)r * m + k) * (m + 1);
-  double2* raw = s.Hraw + ((int64_t)r * m + k) * (m + 1);
-  for (int i = 0; i <= k; ++i) raw[i] = col[i] = h[(int64_t)i * nb + r];
-  double nrm = hn[r];
-  raw[k + 1] = col[k + 1] = make_double2(nrm, 0.0);
-  double2* cs = s.cs + (int64_t)r * m;
-  double2* sn = s.sn + (int64_t)r * m;
-  for (int i = 0; i < k; ++i) {  // previous rotations
-    double2 a = col[i], b = col[i + 1];
-    double2 t1 = cconjmul(cs[i], a), t2 = cconjmul(sn[i], b);
-    double2 u1 = cmul(sn[i], a), u2 = cmul(cs[i], b);
-    col[i] = make_double2(t1.x + t2.x, t1.y + t2.y);
-    col[i + 1] = make_double2(u2.x - u1.x, u2.y - u1.y);
+  if (flag_out) {
+    const unsigned long long any = __ballot(act);
+    if (threadIdx.x == 0) flag_out[blockIdx.x] = any != 0ull ? 1 : 0;
   }
-  double2 a = col[k], b = col[k + 1];
-  double den = hypot(hypot(a.x, a.y), hypot(b.x, b.y));
-  double2* g = s.g + (int64_t)r * (m + 1);
-  s.its[r] += 1;
-  s.kend[r] = k + 1;
-  if (den == 0.0) {  // singular least-squares problem
-    s.brk[r] = 1;
-    s.active[r] = 0;
-    s.inv[r] = 0.0;
-    s.kend[r] = k;  // exclude the singular column
-    return;
-  }
-  double2 c = make_double2(a.x / den, a.y / den), sv = make_double2(b.x / den, b.y / den);
-  cs[k] = c;
-  sn[k] = sv;
-  col[k] = make_double2(den, 0.0);
-  col[k + 1] = make_double2(0.0, 0.0);
-  double2 gk = g[k];
-  double2 ng = cmul(sv, gk);
-  g[k + 1] = make_double2(-ng.x, -ng.y);
-  g[k] = cconjmul(c, gk);
-  double est = hypot(g[k + 1].x, g[k + 1].y);
-  s.resest[r] = est;
-  bool stop = est <= s.thresh[r] || nrm == 0.0 || s.its[r] >= maxit || k + 1 == m;
-  s.inv[r] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
-  if (stop) s.active[r] = 0;
 }
 
 // y = H(0:kend,0:kend)^{-1} g(0:kend), written to yout[j][r] (zero beyond kend)
@@ -384,17 +417,18 @@ __global__ void ysolve_kernel(int m, int nb, BlockState s, const int* __restrict
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nb) return;
   int ke = used[r] ? s.kend[r] : 0;
-  const double2* H = s.H + (int64_t)r * m * (m + 1);
-  const double2* g = s.g + (int64_t)r * (m + 1);
-  for (int j = ke; j < m; ++j) yout[(int64_t)j * nb + r] = make_double2(0.0, 0.0);
+  const int64_t NB = nb;
+  const double2* H = s.H + r;  // H[(j*(m+1) + i)*nb]: row i of column j
+  const double2* g = s.g + r;
+  for (int j = ke; j < m; ++j) yout[(int64_t)j * NB + r] = make_double2(0.0, 0.0);
   for (int i = ke - 1; i >= 0; --i) {
-    double2 acc = g[i];
+    double2 acc = g[(int64_t)i * NB];
     for (int j = i + 1; j < ke; ++j) {
-      double2 p = cmul(H[(int64_t)j * (m + 1) + i], yout[(int64_t)j * nb + r]);
+      double2 p = cmul(H[((int64_t)j * (m + 1) + i) * NB], yout[(int64_t)j * NB + r]);
       acc.x -= p.x;
       acc.y -= p.y;
     }
-    yout[(int64_t)i * nb + r] = cdiv(acc, H[(int64_t)i * (m + 1) + i]);
+    yout[(int64_t)i * NB + r] = cdiv(acc, H[((int64_t)i * (m + 1) + i) * NB]);
   }
 }
 
@@ -428,12 +462,12 @@ __global__ void rescoef_kernel(int m, int nb, BlockState s, const int* __restric
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nb) return;
   const int ke = used[r] ? s.kend[r] : -1;
-  const double2* H = s.Hraw + (int64_t)r * m * (m + 1);
+  const double2* H = s.Hraw + r;  // H[(j*(m+1) + i)*nb]
   for (int i = 0; i <= m; ++i) {
     double2 acc = make_double2(i == 0 && ke >= 0 ? s.beta[r] : 0.0, 0.0);
     if (i <= ke) {
       for (int j = (i > 0 ? i - 1 : 0); j < ke; ++j) {  // H is upper Hessenberg
-        const double2 p = cmul(H[(int64_t)j * (m + 1) + i], y[(int64_t)j * nb + r]);
+        const double2 p = cmul(H[((int64_t)j * (m + 1) + i) * nb], y[(int64_t)j * nb + r]);
         acc.x -= p.x;
         acc.y -= p.y;
       }
@@ -584,9 +618,10 @@ struct GmresBlock {
   float *Uf = nullptr, *Sf = nullptr;
   BlockState s;
   int nblk_rows = 1, nbrows_y = 1;
-  // convergence flags copied to pinned host memory after every Arnoldi step, for the
-  // one-step-late check of small blocks
+  // convergence flags written by arnoldi_finish_kernel straight into host-visible memory (one
+  // word per 64 RHS, two slots by step parity), for the one-step-late check of small blocks
   int* hflags = nullptr;
+  int* dflags = nullptr;  // the same memory as the kernel sees it
   int hflags_nb = 0;
   hipEvent_t flag_ev[2] = {nullptr, nullptr};
 
@@ -669,7 +704,8 @@ struct GmresBlock {
       hflags = nullptr;
       hflags_nb = 0;
       GFCC_HIP(hipHostMalloc(reinterpret_cast<void**>(&hflags), sizeof(int) * 2 * (size_t)nb,
-                             hipHostMallocDefault));
+                             hipHostMallocMapped | hipHostMallocCoherent));
+      GFCC_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&dflags), hflags, 0));
       hflags_nb = nb;
     }
     for (hipEvent_t& e : flag_ev)
@@ -849,8 +885,8 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
       inv0[r] = act[r] ? 1.0 / rn[r] : 0.0;
       const double t_abs = 0.5 * tol * bnorm[r];
       thr[r] = mixed ? std::max(t_abs, inner_rel * rn[r]) : t_abs;
-      for (int i = 0; i <= m; ++i) g0[(size_t)r * (m + 1) + i] = make_double2(0.0, 0.0);
-      g0[(size_t)r * (m + 1)] = make_double2(act[r] ? rn[r] : 0.0, 0.0);
+      for (int i = 0; i <= m; ++i) g0[(size_t)i * nb + r] = make_double2(0.0, 0.0);
+      g0[r] = make_double2(act[r] ? rn[r] : 0.0, 0.0);
       hbeta[r] = act[r] ? rn[r] : 0.0;
     }
     if (nact == 0) break;
@@ -904,11 +940,9 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
         GFCC_LAUNCH_CHECK();
         gb.norms(gb.W, gb.nrm);
       }
-      hipLaunchKernelGGL(cadd_kernel, dim3(blocks_for((int64_t)nj * nb, 256)), dim3(256), 0,
-                         st, gb.Hh, gb.Hh2, (int64_t)nj * nb);
-      GFCC_LAUNCH_CHECK();
-      hipLaunchKernelGGL(arnoldi_finish_kernel, dim3(blocks_for(nb, 64)), dim3(64), 0, st, gb.Hh,
-                         gb.nrm, k, m, nb, maxit, gb.s);
+      int* fslot = late ? gb.dflags + (size_t)(k & 1) * gb.nbrows_y : nullptr;
+      hipLaunchKernelGGL(arnoldi_finish_kernel, dim3(gb.nbrows_y), dim3(CW), 0, st, gb.Hh,
+                         gb.Hh2, gb.nrm, k, m, nb, maxit, gb.s, fslot);
       GFCC_LAUNCH_CHECK();
       // V_{k+1} and the preconditioned input of the next step
       hipLaunchKernelGGL(scale_precond_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.W,
@@ -920,14 +954,12 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
         // for the host. When step k - 1 has stopped every right-hand side, step k only met
         // inactive ones (their next basis vectors and inputs are zero, their state is left
         // alone) and does not count.
-        GFCC_HIP(hipMemcpyAsync(gb.hflags + (size_t)(k & 1) * nb, gb.s.active, sizeof(int) * nb,
-                                hipMemcpyDeviceToHost, st));
         GFCC_HIP(hipEventRecord(gb.flag_ev[k & 1], st));
         if (k > 0) {
           GFCC_HIP(hipEventSynchronize(gb.flag_ev[(k - 1) & 1]));
-          const int* f = gb.hflags + (size_t)((k - 1) & 1) * nb;
+          const volatile int* f = gb.hflags + (size_t)((k - 1) & 1) * gb.nbrows_y;
           int any = 0;
-          for (int r = 0; r < nb; ++r) any |= f[r];
+          for (int b = 0; b < gb.nbrows_y; ++b) any |= f[b];
           if (!any) break;
         }
         ksteps = k + 1;
