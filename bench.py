@@ -1019,7 +1019,7 @@ def main():
         },
     }
     # the GEMM autotuner's choices for this workload's skinny products
-    out["autotune"] = [{k: e[k] for k in ("transA", "M", "N", "K", "splits")}
+    out["autotune"] = [{k: e[k] for k in ("kind", "M", "N", "K", "splits", "tile")}
                        | {"us": round(e["us"], 1), "generic_us": round(e["generic_us"], 1)}
                        for e in ctx.autotune_entries()]
     out["rows"] = rows_report(o, v, D, nb, dt / args.steps, t_build, sig_ms / args.steps,

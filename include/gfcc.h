@@ -138,23 +138,40 @@ gfcc_status sigma_apply(gfcc_ctx* ctx, int nrhs, const void* x, void* y, int tra
  * and the pipelined kernel at three split counts, synchronising the context stream, and keeps
  * the fastest for the context. Products of 256 to 4095 tiles with a long K (the operator
  * build's largest products) are timed as the plain pipelined kernel and with 2 to 6 k ranges,
- * which moves the partly filled last round of workgroups. Off: the generic kernel with its
- * heuristic split count for the first kind, the plain pipelined kernel for the second.
- * enable = 2 skips the timing and takes the most split candidate of every class (so that
- * tests reach the split-K paths). Results agree to rounding in every mode. EINVAL for
- * another value of enable.
+ * which moves the partly filled last round of workgroups. The forward FP64 sigma's two linear
+ * products ([W1 ; 0 | Vp^T] . x, and the 2h1p products W4c . [x_1h ; tau] + (Woo (x) I_v) .
+ * x_2h1p summed in one pass as a product batched over the virtual index) are timed as their
+ * unfused route and as a segmented product on every candidate tile (32, 64 or 128 rows by 64
+ * or 128 columns) and split count. Off: the generic kernel with its heuristic split count for
+ * the first kind, the plain pipelined kernel for the second, the unfused route for the sigma's
+ * products. enable = 2 skips the timing and takes the most split candidate of every class
+ * (the fused segmented product for the sigma's), so that tests reach the split-K and fused
+ * paths. Results agree to rounding in every mode. EINVAL for another value of enable.
  */
 gfcc_status gfcc_autotune(gfcc_ctx* ctx, int enable);
 
 /*
  * gfcc_autotune_entry -- the tuner's choice number `index` (0-based, ordered by class):
- * desc[6] (host) receives {element bytes, transA, M, N, K, splits} (the shape it was measured
- * on) with splits = 0 for the generic kernel and, for products of 256 tiles or more, 1 for
- * the plain pipelined kernel; us[2] (host, may be NULL) the measured time of the choice and
- * of the reference variant (the generic kernel, or the plain pipelined kernel for products of
- * 256 tiles or more) in microseconds. EINVAL past the last entry.
+ * desc[8] (host) receives {element bytes, kind, M, N, K, splits, tile rows, tile columns}.
+ * kind: 0 or 1 a plain product (transA); 20 the sigma's [W1 ; 0 | Vp^T] . x; 21 the sigma's
+ * linear 2h1p products. M, N, K: the shape it was measured on (for kind 21 the fused
+ * product's: M = P pairs, N = columns, K = o + v + P, batched over the v virtual orbitals). splits: 0 for the generic kernel and,
+ * for plain products of 256 tiles or more, 1 for the plain pipelined kernel. The tile is 0 x 0
+ * for a plain product and for a sigma product that runs unfused. us[2] (host, may be NULL):
+ * the measured time of the choice and of the reference variant (the generic kernel, the plain
+ * pipelined kernel for products of 256 tiles or more, the unfused route of a sigma product) in
+ * microseconds. EINVAL past the last entry.
  */
 gfcc_status gfcc_autotune_entry(const gfcc_ctx* ctx, int index, int64_t* desc, double* us);
+
+/*
+ * gfcc_autotune_pin -- fix the choice of every later sigma product of one kind on ctx,
+ * bypassing the timing (until the next gfcc_autotune call): kind 20 or 21 (see
+ * gfcc_autotune_entry). tile_m in {32, 64, 128}, tile_n in {64, 128}, splits >= 1 (split-K
+ * applies to the unbatched kind 20 only); tile 0 x 0 selects the unfused route. For
+ * measurements and tests of each variant. EINVAL for another kind or tile.
+ */
+gfcc_status gfcc_autotune_pin(gfcc_ctx* ctx, int kind, int tile_m, int tile_n, int splits);
 
 /*
  * gfcc_solve -- solve Eq. xplin at every (omega_w, p_k) and form G (Eq. gfcclineqn).

@@ -189,6 +189,18 @@ gfcc_status gfcc_autotune(gfcc_ctx* ctx, int enable) {
   if (!ctx || enable < 0 || enable > 2) return GFCC_EINVAL;
   ctx->tune_mode = enable;
   ctx->tune.clear();
+  ctx->tune_pins.clear();
+  return GFCC_OK;
+}
+
+gfcc_status gfcc_autotune_pin(gfcc_ctx* ctx, int kind, int tile_m, int tile_n, int splits) {
+  if (!ctx) return GFCC_EINVAL;
+  if (kind != gfcc::TUNE_SIGMA_1H && kind != gfcc::TUNE_SIGMA_2H1P) return GFCC_EINVAL;
+  const bool unfused = tile_m == 0 && tile_n == 0;
+  if (!unfused && ((tile_m != 32 && tile_m != 64 && tile_m != 128) ||
+                   (tile_n != 64 && tile_n != 128) || splits < 1))
+    return GFCC_EINVAL;
+  ctx->tune_pins[kind] = {tile_m, tile_n, unfused ? 0 : splits};
   return GFCC_OK;
 }
 
@@ -203,6 +215,8 @@ gfcc_status gfcc_autotune_entry(const gfcc_ctx* ctx, int index, int64_t* desc, d
   desc[3] = it->second.N;
   desc[4] = it->second.K;
   desc[5] = it->second.splits;
+  desc[6] = it->second.tile_m;
+  desc[7] = it->second.tile_n;
   if (us) {
     us[0] = it->second.best_us;
     us[1] = it->second.generic_us;

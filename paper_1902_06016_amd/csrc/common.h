@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <stdexcept>
 #include <map>
 #include <string>
@@ -124,12 +125,17 @@ struct Operator {
 // GEMM autotuner: one choice per product class {element bytes, transA, M tiles, N tiles,
 // floor(log2 K), 16-byte A loads possible}; products of one class behave alike, so shapes that
 // change a little (the reduced model's, round after round) are tuned once.
+// The sigma's fused products are classes of their own: key[1] = one of the TUNE_SIGMA_* kinds
+// below.
 struct TuneChoice {
   int splits = 0;          // 0: generic split-K kernel (heuristic split count); > 0: pipelined
   double best_us = 0.0;    // measured time of the choice
-  double generic_us = 0.0; // measured time of the generic kernel
+  double generic_us = 0.0; // measured time of the generic kernel (or of the unfused route)
   int M = 0, N = 0, K = 0; // the shape it was measured on
+  int tile_m = 0, tile_n = 0;  // segmented-product tile (0: not a segmented-product choice)
 };
+constexpr int64_t TUNE_SIGMA_1H = 20;      // sigma's [W1 ; Vp^T] . X: fused (tile) or unfused
+constexpr int64_t TUNE_SIGMA_2H1P = 21;    // sigma's linear 2h1p products: fused or unfused
 using TuneKey = std::array<int64_t, 6>;
 
 struct TimerSlot {
@@ -158,6 +164,8 @@ struct gfcc_ctx {
   gfcc::TimerSlot timers[3];  // ovvo contraction, whole sigma products, two-term bf16 ovvo
   int tune_mode = 1;        // 0 off, 1 timed, 2 most split variant without timing
   std::map<gfcc::TuneKey, gfcc::TuneChoice> tune;
+  // choices pinned by gfcc_autotune_pin, by kind: {tile rows, tile columns, splits}
+  std::map<int64_t, std::array<int, 3>> tune_pins;
   std::vector<hipEvent_t> event_pool;
 };
 
@@ -209,6 +217,41 @@ bool gemm_pipe(gfcc_ctx* ctx, bool transA, int M, int N, int K, T alpha, const T
 template <typename T>
 void gemm_pipe_split(gfcc_ctx* ctx, bool transA, int M, int N, int K, const T* A, int64_t lda,
                      const T* B, int64_t ldb, T* part, int splits, int kchunk);
+
+// Segmented batched products: C_b = alpha * sum_{s < nseg} A_s,b . B_s,b + beta * C_b for
+// b < batch, with A_s,b row-major [M][K_s] at A[s] + b * sA[s] (row stride lda[s]) and B_s,b
+// row-major [K_s][N] at B[s] + b * sB[s] (row stride ldb[s]); C_b at C + b * sC (row stride
+// ldc), except rows m >= msplit, which go to C2 + b * sC + (m - msplit) * ldc. beta == 0 never
+// reads C. Row and batch strides express the Kronecker-structured 2h1p products of the sigma
+// (a batch over the virtual index whose rows are v rows apart); the segments sum several such
+// products in one pass over the output.
+constexpr int SEG_MAX = 3;
+template <typename T> struct SegSpec {
+  int M = 0, N = 0, batch = 1, nseg = 1;
+  int K[SEG_MAX] = {0, 0, 0};
+  const T* A[SEG_MAX] = {nullptr, nullptr, nullptr};
+  int64_t lda[SEG_MAX] = {0, 0, 0}, sA[SEG_MAX] = {0, 0, 0};
+  const T* B[SEG_MAX] = {nullptr, nullptr, nullptr};
+  int64_t ldb[SEG_MAX] = {0, 0, 0}, sB[SEG_MAX] = {0, 0, 0};
+  T* C = nullptr;
+  T* C2 = nullptr;
+  int64_t ldc = 0, sC = 0;
+  int msplit = 1 << 30;
+  T alpha = T(1), beta = T(0);
+};
+// Runs the product on a given tile (tm x tn, tm in {32, 64, 128}, tn in {64, 128}) and split
+// count (> 1 only for batch 1); the partials live in the context's split-K workspace.
+template <typename T>
+void segmm_run(gfcc_ctx* ctx, const SegSpec<T>& s, int tm, int tn, int splits);
+// The tile and split candidates of a product, in the order the tuner times them.
+template <typename T>
+void segmm_candidates(const SegSpec<T>& s, std::vector<std::array<int, 3>>& out);
+
+// Times each candidate (one warm-up run, then two timed runs, on the context stream) and
+// returns the index of the fastest; us[i] receives candidate i's time in microseconds.
+// Synchronises the stream. Candidates must be complete, idempotent computations.
+int time_candidates(gfcc_ctx* ctx, const std::vector<std::function<void()>>& cands,
+                    std::vector<double>& us);
 
 // A device buffer of at least `bytes` zero bytes, owned by the context (grown on demand).
 const void* zero_row(gfcc_ctx* ctx, size_t bytes);

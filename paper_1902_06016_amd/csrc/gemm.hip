@@ -501,4 +501,302 @@ template void gemm_ovvo<double>(gfcc_ctx*, bool, int, int, int, const double*, c
 template void gemm_ovvo<float>(gfcc_ctx*, bool, int, int, int, const float*, const float*,
                                int64_t, const int*, float*);
 
+
+// ------------------------------------------------------------------ segmented products
+// One workgroup of 4 wavefronts (2 x 2) computes a TBM x TBN tile of C_b (TBM in {32, 64, 128},
+// TBN in {64, 128}); each wavefront holds (TBM/32) x (TBN/32) accumulators of the 16x16x4
+// MFMA. K runs over the concatenated slabs (16 deep) of the segments, register-prefetched one
+// slab ahead into double-buffered LDS; ragged edges are zero-filled on load and masked on
+// store. Split-K (batch 1) gives each blockIdx.z a contiguous run of slabs and writes an
+// [M][N] partial per split.
+namespace {
+
+template <typename T> struct SegArgs {
+  const T* A[SEG_MAX];
+  const T* B[SEG_MAX];
+  int64_t lda[SEG_MAX], sA[SEG_MAX], ldb[SEG_MAX], sB[SEG_MAX];
+  int K[SEG_MAX], ns[SEG_MAX];
+  int nseg, M, N, mtiles, msplit, spz;
+  T* C;
+  T* C2;
+  int64_t ldc, sC, pstride;
+  T alpha, beta;
+};
+
+template <typename T, int TBM, int TBN, bool SPLIT>
+__global__ __launch_bounds__(NT, 2) void segmm_kernel(SegArgs<T> p) {
+  using M4 = Mfma<T>;
+  using C4 = typename M4::C4;
+  constexpr int PAD = M4::PAD;
+  constexpr int RA = TBM / 16;  // A loads per thread and slab: k = tid % 16, rows tid / 16 + 16 r
+  constexpr int RB = TBN / 16;  // B loads: n = tid % TBN, k = tid / TBN + KS r
+  constexpr int KS = NT / TBN;
+  constexpr int IW = TBM / 32, JW = TBN / 32;
+  __shared__ T As[2][BK][TBM + PAD];
+  __shared__ T Bs[2][BK][TBN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int mt = blockIdx.x % p.mtiles, nt = blockIdx.x / p.mtiles;
+  const int m0 = mt * TBM, n0 = nt * TBN;
+  const int64_t bi = blockIdx.y;
+
+  int total = 0;
+  for (int q = 0; q < p.nseg; ++q) total += p.ns[q];
+  int sbeg = 0, send = total;
+  if (SPLIT) {
+    sbeg = blockIdx.z * p.spz;
+    send = min(total, sbeg + p.spz);
+  }
+  const int a_k = tid % BK, a_m = tid / BK;
+  const int b_n = tid % TBN, b_k = tid / TBN;
+  const int Mc = p.M - 1, Nc = p.N - 1;
+
+  T ra[RA], rb[RB];
+  unsigned amask = 0, bmask = 0;
+  auto load_slab = [&](int sl) {
+    int q = 0;
+    while (q + 1 < p.nseg && sl >= p.ns[q]) {
+      sl -= p.ns[q];
+      ++q;
+    }
+    const int k0 = sl * BK;
+    const int K = p.K[q];
+    const int kc = K - 1;
+    const T* __restrict__ A = p.A[q] + bi * p.sA[q];
+    const T* __restrict__ B = p.B[q] + bi * p.sB[q];
+    const int64_t lda = p.lda[q], ldb = p.ldb[q];
+    amask = bmask = 0;
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      const int m = m0 + a_m + 16 * r, k = k0 + a_k;
+      amask |= (m < p.M && k < K) ? (1u << r) : 0u;
+      const int mm = m < Mc ? m : Mc, kk = k < kc ? k : kc;
+      ra[r] = A[(int64_t)mm * lda + kk];
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int k = k0 + b_k + KS * r, n = n0 + b_n;
+      bmask |= (n < p.N && k < K) ? (1u << r) : 0u;
+      const int nn = n < Nc ? n : Nc, kk = k < kc ? k : kc;
+      rb[r] = B[(int64_t)kk * ldb + nn];
+    }
+  };
+  auto store_slab = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < RA; ++r) As[buf][a_k][a_m + 16 * r] = ((amask >> r) & 1u) ? ra[r] : T(0);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) Bs[buf][b_k + KS * r][b_n] = ((bmask >> r) & 1u) ? rb[r] : T(0);
+  };
+
+  C4 acc[IW][JW];
+#pragma unroll
+  for (int i = 0; i < IW; ++i)
+#pragma unroll
+    for (int j = 0; j < JW; ++j) acc[i][j] = C4{0, 0, 0, 0};
+
+  if (sbeg < send) {
+    load_slab(sbeg);
+    store_slab(0);
+    __syncthreads();
+    const int row_l = lane & 15, kq = lane >> 4;
+    int buf = 0;
+    for (int sl = sbeg; sl < send; ++sl) {
+      const bool more = sl + 1 < send;
+      if (more) load_slab(sl + 1);
+#pragma unroll
+      for (int s4 = 0; s4 < BK / 4; ++s4) {
+        T af[IW], bf[JW];
+#pragma unroll
+        for (int i = 0; i < IW; ++i) af[i] = As[buf][s4 * 4 + kq][wm * (TBM / 2) + i * 16 + row_l];
+#pragma unroll
+        for (int j = 0; j < JW; ++j) bf[j] = Bs[buf][s4 * 4 + kq][wn * (TBN / 2) + j * 16 + row_l];
+#pragma unroll
+        for (int i = 0; i < IW; ++i)
+#pragma unroll
+          for (int j = 0; j < JW; ++j) acc[i][j] = M4::op(af[i], bf[j], acc[i][j]);
+      }
+      if (more) store_slab(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
+  const int col_l = lane & 15;
+#pragma unroll
+  for (int i = 0; i < IW; ++i)
+#pragma unroll
+    for (int j = 0; j < JW; ++j) {
+      const int n = n0 + wn * (TBN / 2) + j * 16 + col_l;
+      if (n >= p.N) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + wm * (TBM / 2) + i * 16 + M4::row(lane, q);
+        if (m >= p.M) continue;
+        if (SPLIT) {
+          p.C[(int64_t)blockIdx.z * p.pstride + (int64_t)m * p.N + n] = acc[i][j][q];
+        } else {
+          T* dst = m < p.msplit ? p.C + bi * p.sC + (int64_t)m * p.ldc + n
+                                : p.C2 + bi * p.sC + (int64_t)(m - p.msplit) * p.ldc + n;
+          T val = p.alpha * acc[i][j][q];
+          if (p.beta != T(0)) val += p.beta * *dst;
+          *dst = val;
+        }
+      }
+    }
+}
+
+// C (rows >= msplit: C2) = alpha * sum_z part[z] + beta * C
+template <typename T>
+__global__ void segmm_reduce(const T* __restrict__ part, int splits, int M, int N,
+                             int64_t pstride, T* C, T* C2, int msplit, int64_t ldc, T alpha,
+                             T beta) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)M * N) return;
+  const int m = (int)(idx / N), n = (int)(idx % N);
+  T s = T(0);
+  for (int z = 0; z < splits; ++z) s += part[z * pstride + idx];
+  T* dst = m < msplit ? C + (int64_t)m * ldc + n : C2 + (int64_t)(m - msplit) * ldc + n;
+  T val = alpha * s;
+  if (beta != T(0)) val += beta * *dst;
+  *dst = val;
+}
+
+template <typename T, int TBM, int TBN>
+void segmm_launch(gfcc_ctx* ctx, SegArgs<T> a, int batch, int ntiles, int splits) {
+  dim3 grid((unsigned)(a.mtiles * ntiles), (unsigned)batch, (unsigned)splits);
+  if (splits > 1)
+    hipLaunchKernelGGL((segmm_kernel<T, TBM, TBN, true>), grid, dim3(NT), 0, ctx->stream, a);
+  else
+    hipLaunchKernelGGL((segmm_kernel<T, TBM, TBN, false>), grid, dim3(NT), 0, ctx->stream, a);
+  GFCC_LAUNCH_CHECK();
+}
+
+inline int seg_slabs(const int* K, int nseg) {
+  int t = 0;
+  for (int q = 0; q < nseg; ++q) t += (K[q] + BK - 1) / BK;
+  return t;
+}
+
+}  // namespace
+
+template <typename T>
+void segmm_run(gfcc_ctx* ctx, const SegSpec<T>& s, int tm, int tn, int splits) {
+  if (s.M <= 0 || s.N <= 0 || s.batch <= 0) return;
+  GFCC_REQUIRE(s.nseg >= 1 && s.nseg <= SEG_MAX, GFCC_EINVAL, "segmm: bad segment count");
+  GFCC_REQUIRE(s.batch < 65536, GFCC_EINVAL, "segmm: batch too large");
+  GFCC_REQUIRE(splits == 1 || s.batch == 1, GFCC_EINVAL, "segmm: split-K needs batch 1");
+  SegArgs<T> a{};
+  for (int q = 0; q < SEG_MAX; ++q) {
+    const bool on = q < s.nseg;
+    a.A[q] = on ? s.A[q] : nullptr;
+    a.B[q] = on ? s.B[q] : nullptr;
+    a.lda[q] = on ? s.lda[q] : 0;
+    a.sA[q] = on ? s.sA[q] : 0;
+    a.ldb[q] = on ? s.ldb[q] : 0;
+    a.sB[q] = on ? s.sB[q] : 0;
+    a.K[q] = on ? s.K[q] : 0;
+    a.ns[q] = on ? (s.K[q] + BK - 1) / BK : 0;
+    GFCC_REQUIRE(!on || s.K[q] >= 0, GFCC_EINVAL, "segmm: negative K");
+  }
+  a.nseg = s.nseg;
+  a.M = s.M;
+  a.N = s.N;
+  a.mtiles = (s.M + tm - 1) / tm;
+  const int ntiles = (s.N + tn - 1) / tn;
+  GFCC_REQUIRE((int64_t)a.mtiles * ntiles < (1LL << 31), GFCC_EINVAL, "segmm: too many tiles");
+  a.msplit = s.msplit;
+  a.C = s.C;
+  a.C2 = s.C2 ? s.C2 : s.C;
+  a.ldc = s.ldc;
+  a.sC = s.sC;
+  a.alpha = s.alpha;
+  a.beta = s.beta;
+  const int total = seg_slabs(a.K, a.nseg);
+  T* part = nullptr;
+  int nz = 1;
+  if (splits > 1 && total > 1) {
+    a.spz = (total + splits - 1) / splits;
+    nz = (total + a.spz - 1) / a.spz;
+  } else {
+    a.spz = total;
+  }
+  if (nz > 1) {
+    a.pstride = (int64_t)s.M * s.N;
+    ws_ensure(ctx, ctx->ws_gemm, sizeof(T) * (size_t)a.pstride * nz);
+    part = ctx->ws_gemm.as<T>();
+    a.C = part;
+  }
+#define GFCC_SEG_TILE(BMv, BNv) \
+  if (tm == BMv && tn == BNv) { segmm_launch<T, BMv, BNv>(ctx, a, s.batch, ntiles, nz); } else
+  GFCC_SEG_TILE(32, 64) GFCC_SEG_TILE(32, 128) GFCC_SEG_TILE(64, 64) GFCC_SEG_TILE(64, 128)
+  GFCC_SEG_TILE(128, 64) GFCC_SEG_TILE(128, 128) {
+    throw Error(GFCC_EINVAL, "segmm: unsupported tile");
+  }
+#undef GFCC_SEG_TILE
+  if (nz > 1) {
+    const int64_t slab = (int64_t)s.M * s.N;
+    hipLaunchKernelGGL(segmm_reduce<T>, dim3(blocks_for(slab, 256)), dim3(256), 0, ctx->stream,
+                       part, nz, s.M, s.N, slab, s.C, s.C2 ? s.C2 : s.C, s.msplit, s.ldc,
+                       s.alpha, s.beta);
+    GFCC_LAUNCH_CHECK();
+  }
+}
+
+template <typename T>
+void segmm_candidates(const SegSpec<T>& s, std::vector<std::array<int, 3>>& out) {
+  out.clear();
+  const int total = seg_slabs(s.K, s.nseg);
+  for (int tm : {32, 64, 128}) {
+    // a tile more than twice as tall as the product only adds empty rows
+    if (tm > 32 && tm >= 2 * s.M) continue;
+    for (int tn : {64, 128}) {
+      if (tn > 64 && tn >= 2 * s.N) continue;
+      const int64_t tiles = (int64_t)((s.M + tm - 1) / tm) * ((s.N + tn - 1) / tn) * s.batch;
+      out.push_back({tm, tn, 1});
+      if (s.batch != 1) continue;
+      // split counts that fill one, two and four rounds of 512 workgroups, keeping at least
+      // four slabs of k per split
+      for (int64_t r : {1, 2, 4}) {
+        const int64_t sp = std::min<int64_t>(total / 4, r * 512 / std::max<int64_t>(1, tiles));
+        if (sp < 2) continue;
+        bool dup = false;
+        for (const auto& c : out) dup |= (c[0] == tm && c[1] == tn && c[2] == (int)sp);
+        if (!dup) out.push_back({tm, tn, (int)sp});
+      }
+    }
+  }
+}
+
+int time_candidates(gfcc_ctx* ctx, const std::vector<std::function<void()>>& cands,
+                    std::vector<double>& us) {
+  hipStream_t st = ctx->stream;
+  hipEvent_t e0, e1;
+  GFCC_HIP(hipEventCreate(&e0));
+  GFCC_HIP(hipEventCreate(&e1));
+  us.assign(cands.size(), 0.0);
+  int best = 0;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    cands[i]();
+    GFCC_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < 2; ++r) cands[i]();
+    GFCC_HIP(hipEventRecord(e1, st));
+    GFCC_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    GFCC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    us[i] = ms * 1e3 / 2;
+    if (us[i] < us[best]) best = (int)i;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
+}
+
+template void segmm_run<double>(gfcc_ctx*, const SegSpec<double>&, int, int, int);
+template void segmm_run<float>(gfcc_ctx*, const SegSpec<float>&, int, int, int);
+template void segmm_candidates<double>(const SegSpec<double>&, std::vector<std::array<int, 3>>&);
+template void segmm_candidates<float>(const SegSpec<float>&, std::vector<std::array<int, 3>>&);
+
 }  // namespace gfcc

@@ -10,6 +10,8 @@
 // where r_mj^e is the antisymmetric expansion of the packed 2h1p block, generated inside
 // the ovvo product (gemm_ovvo), and antisym(Z)_(i<j),a = Z[(i,a)][j] - Z[(j,a)][i].
 // The transpose product uses the same pieces with transposed A operands.
+#include <cstdlib>
+
 #include "common.h"
 
 namespace gfcc {
@@ -37,17 +39,11 @@ __global__ __launch_bounds__(256) void antisym_add_kernel(const T* __restrict__ 
   for (int c = threadIdx.x; c < nc; c += blockDim.x) y[c] += zij[c] - zji[c];
 }
 
-// Y1 = S[0:n] and S[0:n] = X1 (the 1h head of the stacked product and its replacement by
-// the 1h block of x), one pass
 template <typename T>
-__global__ void head_swap_kernel(T* __restrict__ S, const T* __restrict__ X1, T* __restrict__ Y1,
-                                 int64_t n) {
+__global__ void copy_kernel(T* __restrict__ dst, const T* __restrict__ src, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const T sv = S[i];
-    Y1[i] = sv;
-    S[i] = X1[i];
-  }
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
 }
 
 template <typename T>
@@ -89,6 +85,78 @@ void woo_product(gfcc_ctx* ctx, bool transW, int64_t P, int64_t N, const T* Woo,
     gemm<T>(ctx, transW, false, (int)P, (int)N, (int)P, T(1), Woo, ldw, X2, N, T(1), Y2, N);
 }
 
+template <typename T>
+void copy_async(gfcc_ctx* ctx, T* dst, const T* src, int64_t n) {
+  hipLaunchKernelGGL(copy_kernel<T>, dim3(grid_for(n)), dim3(256), 0, ctx->stream, dst, src, n);
+  GFCC_LAUNCH_CHECK();
+}
+
+// The tuned route of one of the sigma's linear products: the first call in a class times the
+// unfused route (candidate 0) and every tile and split candidate of the fused segmented
+// product, each a complete computation of the same outputs, and keeps the fastest.
+template <typename T>
+void tuned_route(gfcc_ctx* ctx, int64_t kind, const SegSpec<T>& fused,
+                 const std::function<void()>& unfused) {
+  auto pin = ctx->tune_pins.find(kind);
+  if (pin != ctx->tune_pins.end()) {
+    const auto& c = pin->second;
+    if (c[0] == 0)
+      unfused();
+    else
+      segmm_run<T>(ctx, fused, c[0], c[1], fused.batch == 1 ? c[2] : 1);
+    return;
+  }
+  int64_t K = 0;
+  for (int q = 0; q < fused.nseg; ++q) K += fused.K[q];
+  const TuneKey key{(int64_t)sizeof(T), kind, fused.M, fused.N, K, fused.batch};
+  auto it = ctx->tune.find(key);
+  if (it == ctx->tune.end()) {
+    std::vector<std::array<int, 3>> cand;
+    segmm_candidates(fused, cand);
+    TuneChoice ch;
+    ch.M = fused.M;
+    ch.N = fused.N;
+    ch.K = (int)K;
+    int pick = 0;  // 0: unfused, i > 0: cand[i - 1]
+    if (ctx->tune_mode == 2) {
+      pick = 1;  // untimed: the fused product on its most split candidate
+      for (size_t i = 1; i < cand.size(); ++i)
+        if (cand[i][2] > cand[pick - 1][2]) pick = (int)i + 1;
+    } else if (ctx->tune_mode == 1) {
+      std::vector<std::function<void()>> fns{unfused};
+      for (const auto& c : cand)
+        fns.push_back([&, c] { segmm_run<T>(ctx, fused, c[0], c[1], c[2]); });
+      std::vector<double> us;
+      pick = time_candidates(ctx, fns, us);
+      ch.best_us = us[pick];
+      ch.generic_us = us[0];
+      if (std::getenv("GFCC_TUNE_LOG")) {
+        for (size_t i = 0; i < fns.size(); ++i) {
+          if (i == 0) {
+            std::fprintf(stderr, "[gfcc autotune] sigma kind %lld M=%d N=%d K=%lld batch=%d "
+                         "unfused: %.1f us\n", (long long)kind, fused.M, fused.N, (long long)K,
+                         fused.batch, us[0]);
+          } else {
+            std::fprintf(stderr, "[gfcc autotune] sigma kind %lld tile %dx%d splits=%d: %.1f us\n",
+                         (long long)kind, cand[i - 1][0], cand[i - 1][1], cand[i - 1][2], us[i]);
+          }
+        }
+      }
+    }
+    if (pick > 0) {
+      ch.tile_m = cand[pick - 1][0];
+      ch.tile_n = cand[pick - 1][1];
+      ch.splits = cand[pick - 1][2];
+    }
+    it = ctx->tune.emplace(key, ch).first;
+  }
+  const TuneChoice& ch = it->second;
+  if (ch.tile_m == 0)
+    unfused();
+  else
+    segmm_run<T>(ctx, fused, ch.tile_m, ch.tile_n, ch.splits);
+}
+
 }  // namespace
 
 void ctranspose(gfcc_ctx* ctx, const void* src, int64_t rows, int64_t cols, int64_t lds,
@@ -118,15 +186,61 @@ void sigma_block_f64(gfcc_ctx* ctx, int nc, const double* X, double* Y, bool tra
   hipEvent_t e_all = nullptr, e_ovvo = nullptr;
   timer_begin(ctx, 1, &e_all);
   if (!transpose) {
-    // [sigma_1h ; tau] = [W1 ; 0 | Vp^T] . X, then S = [X_1h ; tau]
-    gemm<double>(ctx, false, false, o + v, nc, (int)D, 1.0, f.W1V.as<double>(), D, X, nc, 0.0,
-                 S, nc);
-    hipLaunchKernelGGL(head_swap_kernel<double>, dim3(grid_for((int64_t)o * nc)), dim3(256), 0,
-                       ctx->stream, S, X1, Y1, (int64_t)o * nc);
-    GFCC_LAUNCH_CHECK();
-    gemm<double>(ctx, false, false, (int)PV, nc, o + v, 1.0, f.W4c.as<double>(), o + v, S, nc,
-                 0.0, Y2, nc);
-    woo_product<double>(ctx, false, P, (int64_t)v * nc, f.Woo.as<double>(), op.ldwoo, X2, Y2);
+    // [sigma_1h ; tau] = [W1 ; 0 | Vp^T] . X: sigma_1h into Y1, tau into S[o:o+v]. Unfused:
+    // the whole product into S, then its 1h rows copied to Y1.
+    double* tau = S + (int64_t)o * nc;
+    SegSpec<double> h;
+    h.M = o + v;
+    h.N = nc;
+    h.K[0] = (int)D;
+    h.A[0] = f.W1V.as<double>();
+    h.lda[0] = D;
+    h.B[0] = X;
+    h.ldb[0] = nc;
+    h.C = Y1;
+    h.C2 = tau;
+    h.ldc = nc;
+    h.msplit = o;
+    tuned_route<double>(ctx, TUNE_SIGMA_1H, h, [&] {
+      gemm<double>(ctx, false, false, o + v, nc, (int)D, 1.0, f.W1V.as<double>(), D, X, nc, 0.0,
+                   S, nc);
+      copy_async<double>(ctx, Y1, S, (int64_t)o * nc);
+    });
+    // sigma_2h1p's linear part, per virtual index a (rows (pair, a) are v rows apart):
+    //   Y2_a = W4c_a[:, :o] . X_1h + W4c_a[:, o:] . tau + Woo . X2_a
+    // Unfused: S[0:o] = X_1h, Y2 = W4c . S, then Y2 += (Woo (x) I_v) . X2.
+    SegSpec<double> g;
+    g.M = (int)P;
+    g.N = nc;
+    g.batch = v;
+    g.nseg = 3;
+    g.K[0] = o;
+    g.A[0] = f.W4c.as<double>();
+    g.lda[0] = (int64_t)v * (o + v);
+    g.sA[0] = o + v;
+    g.B[0] = X1;
+    g.ldb[0] = nc;
+    g.K[1] = v;
+    g.A[1] = f.W4c.as<double>() + o;
+    g.lda[1] = (int64_t)v * (o + v);
+    g.sA[1] = o + v;
+    g.B[1] = tau;
+    g.ldb[1] = nc;
+    g.K[2] = (int)P;
+    g.A[2] = f.Woo.as<double>();
+    g.lda[2] = op.ldwoo;
+    g.B[2] = X2;
+    g.ldb[2] = (int64_t)v * nc;
+    g.sB[2] = nc;
+    g.C = Y2;
+    g.ldc = (int64_t)v * nc;
+    g.sC = nc;
+    tuned_route<double>(ctx, TUNE_SIGMA_2H1P, g, [&] {
+      copy_async<double>(ctx, S, X1, (int64_t)o * nc);
+      gemm<double>(ctx, false, false, (int)PV, nc, o + v, 1.0, f.W4c.as<double>(), o + v, S, nc,
+                   0.0, Y2, nc);
+      woo_product<double>(ctx, false, P, (int64_t)v * nc, f.Woo.as<double>(), op.ldwoo, X2, Y2);
+    });
   } else {
     gemm<double>(ctx, true, false, (int)D, nc, o, 1.0, f.W1.as<double>(), D, X1, nc, 0.0, Y, nc);
     gemm<double>(ctx, true, false, o + v, nc, (int)PV, 1.0, f.W4c.as<double>(), o + v, X2, nc,

@@ -54,6 +54,7 @@ def _load():
                                   vp, vp, vp, vp]),
         "gfcc_autotune": (i32, [vp, i32]),
         "gfcc_autotune_entry": (i32, [vp, i32, vp, vp]),
+        "gfcc_autotune_pin": (i32, [vp, i32, i32, i32, i32]),
         "gfcc_grad_eps": (i32, [vp, i32, vp, i32, vp, vp, vp]),
         "mor_build": (i32, [vp, i32, vp, i32, vp, dbl, dbl, dbl, P(vp)]),
         "mor_build_diag": (i32, [vp, i32, vp, i32, vp, dbl, dbl, dbl, vp]),
@@ -78,6 +79,7 @@ def _load():
 lib = _load()
 SYMBOLS = ("gfcc_dim", "gfcc_create", "gfcc_destroy", "gfcc_last_error", "build_hbar_operands",
            "build_hbar_first_order", "sigma_apply", "gfcc_autotune", "gfcc_autotune_entry",
+           "gfcc_autotune_pin",
            "gfcc_solve", "gfcc_solve_x0", "gfcc_solve_diis", "gfcc_grad_eps", "mor_build",
            "mor_build_diag", "mor_refine", "mor_eval", "mor_eval_noalloc", "mor_lift",
            "mor_info", "mor_destroy", "spectral_function", "spectral_weight", "gfcc_export",
@@ -284,17 +286,23 @@ class Context:
         """enable: False/0 off, True/1 timed, 2 the most split variant of every class untimed."""
         self._check(lib.gfcc_autotune(self.h, int(enable)))
 
+    def autotune_pin(self, kind: int, tile_m: int, tile_n: int, splits: int = 1):
+        """Fix the choice of one of the sigma's fused product kinds (20/21); tile (0, 0) = the
+        unfused route."""
+        self._check(lib.gfcc_autotune_pin(self.h, kind, tile_m, tile_n, splits))
+
     def autotune_entries(self):
-        """The tuner's choices: dicts with the product shape, the split count (0 = generic
-        kernel) and the measured times."""
+        """The tuner's choices: dicts with the product kind (0/1 plain product with transA,
+        20/21 the sigma's fused products), shape, split count (0 = generic kernel), tile
+        (0 x 0: a plain product, or the unfused sigma route) and the measured times."""
         out = []
-        desc = (ctypes.c_int64 * 6)()
+        desc = (ctypes.c_int64 * 8)()
         us = (ctypes.c_double * 2)()
         i = 0
         while lib.gfcc_autotune_entry(self.h, i, desc, us) == GFCC_OK:
-            out.append({"elem_bytes": desc[0], "transA": bool(desc[1]), "M": desc[2],
-                        "N": desc[3], "K": desc[4], "splits": desc[5],
-                        "us": us[0], "generic_us": us[1]})
+            out.append({"elem_bytes": desc[0], "kind": desc[1], "transA": desc[1] == 1,
+                        "M": desc[2], "N": desc[3], "K": desc[4], "splits": desc[5],
+                        "tile": (desc[6], desc[7]), "us": us[0], "generic_us": us[1]})
             i += 1
         return out
 

@@ -35,10 +35,18 @@ def test_sigma_with_and_without_the_tuner(gpu_ctx, transpose):
             ents = gpu_ctx.autotune_entries()
             assert ents, "no product was tuned"
             for e in ents:
-                assert e["elem_bytes"] == 8 and e["K"] * 8 >= 4096 and e["us"] > 0
-                assert e["splits"] == 0 or e["us"] <= e["generic_us"]
+                assert e["elem_bytes"] == 8 and e["us"] > 0
+                if e["kind"] in (0, 1):
+                    assert e["K"] * 8 >= 4096 and e["tile"] == (0, 0)
+                    assert e["splits"] == 0 or e["us"] <= e["generic_us"]
+                else:
+                    # a sigma product: the unfused route or a fused tile no slower than it
+                    assert e["kind"] in (20, 21)
+                    assert e["tile"] == (0, 0) or e["us"] <= e["generic_us"]
             if not transpose:
-                assert any(e["M"] == o + v and e["K"] == D and not e["transA"] for e in ents)
+                assert any(e["kind"] == 20 and e["M"] == o + v and e["K"] == D for e in ents)
+                assert any(e["kind"] == 21 and e["M"] == o * (o - 1) // 2
+                           and e["K"] == o + v + o * (o - 1) // 2 for e in ents)
     assert np.abs(ys[0] - ys[1]).max() <= 1e-13 * scale
     # a fresh tuning may pick another variant; both agree to rounding
     assert np.abs(ys[0] - ys[2]).max() <= 1e-13 * scale
@@ -75,3 +83,36 @@ def test_build_products_in_every_tuner_mode(gpu_ctx):
         scale = np.abs(blocks[0][name]).max()
         assert np.abs(blocks[2][name] - blocks[0][name]).max() <= 1e-13 * max(1.0, scale)
     gpu_ctx.autotune(True)
+
+
+@pytest.mark.parametrize("o,v,nrhs", [(12, 30, 48), (7, 19, 5), (10, 20, 40)])
+def test_every_fused_sigma_variant(gpu_ctx, o, v, nrhs):
+    """The forward sigma with its two fused products pinned to each tile shape and split count
+    (and to the unfused route) matches the oracle: ragged tiles in M (P pairs, o + v rows), in
+    N (2 nrhs columns) and in every K segment (o, v, P)."""
+    print(f"[fused sigma variants o={o} v={v} nrhs={nrhs}]", flush=True)
+    prob = synth.make_problem(o, v, 31)
+    hb = ohbar.build_hbar_from_problem(prob)
+    gpu_ctx.build_from_problem(prob)
+    D = osig.dim(o, v)
+    rng = np.random.default_rng(31)
+    x = rng.standard_normal((nrhs, D)) + 1j * rng.standard_normal((nrhs, D))
+    xt = torch.from_numpy(x).cuda()
+    ref = osig.sigma(hb, x)
+    scale = np.abs(ref).max()
+    variants = [(0, 0, 1)] + [(tm, tn, sp) for tm in (32, 64, 128) for tn in (64, 128)
+                              for sp in (1, 3)]
+    try:
+        for tm, tn, sp in variants:
+            gpu_ctx.autotune(True)
+            gpu_ctx.autotune_pin(20, tm, tn, sp)
+            gpu_ctx.autotune_pin(21, tm, tn, sp)
+            y = gpu_ctx.sigma_apply(xt).cpu().numpy()
+            err = np.abs(y - ref).max()
+            assert err <= 1e-12 * scale, (tm, tn, sp, err / scale)
+        with pytest.raises(gfcc.GfccError):
+            gpu_ctx.autotune_pin(21, 48, 64, 1)
+        with pytest.raises(gfcc.GfccError):
+            gpu_ctx.autotune_pin(5, 32, 64, 1)
+    finally:
+        gpu_ctx.autotune(True)
