@@ -505,9 +505,10 @@ template void gemm_ovvo<float>(gfcc_ctx*, bool, int, int, int, const float*, con
 // ------------------------------------------------------------------ segmented products
 // One workgroup of 4 wavefronts (2 x 2) computes a TBM x TBN tile of C_b (TBM in {32, 64, 128},
 // TBN in {64, 128}); each wavefront holds (TBM/32) x (TBN/32) accumulators of the 16x16x4
-// MFMA. K runs over the concatenated slabs (16 deep) of the segments, register-prefetched one
-// slab ahead into double-buffered LDS; ragged edges are zero-filled on load and masked on
-// store. Split-K (batch 1) gives each blockIdx.z a contiguous run of slabs and writes an
+// MFMA. K runs over the concatenated slabs (16 deep) of the segments, loaded two slabs ahead
+// into two register sets and stored into double-buffered LDS (these products are short in K
+// per workgroup, so their time is mostly load latency); ragged edges are zero-filled on load
+// and masked on store. Split-K (batch 1) gives each blockIdx.z a contiguous run of slabs and writes an
 // [M][N] partial per split.
 namespace {
 
@@ -554,9 +555,10 @@ __global__ __launch_bounds__(NT, 2) void segmm_kernel(SegArgs<T> p) {
   const int b_n = tid % TBN, b_k = tid / TBN;
   const int Mc = p.M - 1, Nc = p.N - 1;
 
-  T ra[RA], rb[RB];
-  unsigned amask = 0, bmask = 0;
-  auto load_slab = [&](int sl) {
+  // two register sets: the loads of slab s + 2 are in flight while slab s is multiplied
+  T ra0[RA], rb0[RB], ra1[RA], rb1[RB];
+  unsigned am0 = 0, bm0 = 0, am1 = 0, bm1 = 0;
+  auto load_slab = [&](int sl, T(&ra)[RA], T(&rb)[RB], unsigned& amask, unsigned& bmask) {
     int q = 0;
     while (q + 1 < p.nseg && sl >= p.ns[q]) {
       sl -= p.ns[q];
@@ -584,7 +586,8 @@ __global__ __launch_bounds__(NT, 2) void segmm_kernel(SegArgs<T> p) {
       rb[r] = B[(int64_t)kk * ldb + nn];
     }
   };
-  auto store_slab = [&](int buf) {
+  auto store_slab = [&](int buf, const T(&ra)[RA], const T(&rb)[RB], unsigned amask,
+                        unsigned bmask) {
 #pragma unroll
     for (int r = 0; r < RA; ++r) As[buf][a_k][a_m + 16 * r] = ((amask >> r) & 1u) ? ra[r] : T(0);
 #pragma unroll
@@ -597,30 +600,53 @@ __global__ __launch_bounds__(NT, 2) void segmm_kernel(SegArgs<T> p) {
 #pragma unroll
     for (int j = 0; j < JW; ++j) acc[i][j] = C4{0, 0, 0, 0};
 
-  if (sbeg < send) {
-    load_slab(sbeg);
-    store_slab(0);
+  const int row_l = lane & 15, kq = lane >> 4;
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int s4 = 0; s4 < BK / 4; ++s4) {
+      T af[IW], bf[JW];
+#pragma unroll
+      for (int i = 0; i < IW; ++i) af[i] = As[buf][s4 * 4 + kq][wm * (TBM / 2) + i * 16 + row_l];
+#pragma unroll
+      for (int j = 0; j < JW; ++j) bf[j] = Bs[buf][s4 * 4 + kq][wn * (TBN / 2) + j * 16 + row_l];
+#pragma unroll
+      for (int i = 0; i < IW; ++i)
+#pragma unroll
+        for (int j = 0; j < JW; ++j) acc[i][j] = M4::op(af[i], bf[j], acc[i][j]);
+    }
+  };
+
+  // the FP64 128 x 128 tile has no registers for a second set: one slab ahead
+  constexpr bool ONE_AHEAD = sizeof(T) == 8 && TBM * TBN >= 128 * 128;
+  if (ONE_AHEAD && sbeg < send) {
+    load_slab(sbeg, ra0, rb0, am0, bm0);
+    store_slab(0, ra0, rb0, am0, bm0);
     __syncthreads();
-    const int row_l = lane & 15, kq = lane >> 4;
     int buf = 0;
     for (int sl = sbeg; sl < send; ++sl) {
       const bool more = sl + 1 < send;
-      if (more) load_slab(sl + 1);
-#pragma unroll
-      for (int s4 = 0; s4 < BK / 4; ++s4) {
-        T af[IW], bf[JW];
-#pragma unroll
-        for (int i = 0; i < IW; ++i) af[i] = As[buf][s4 * 4 + kq][wm * (TBM / 2) + i * 16 + row_l];
-#pragma unroll
-        for (int j = 0; j < JW; ++j) bf[j] = Bs[buf][s4 * 4 + kq][wn * (TBN / 2) + j * 16 + row_l];
-#pragma unroll
-        for (int i = 0; i < IW; ++i)
-#pragma unroll
-          for (int j = 0; j < JW; ++j) acc[i][j] = M4::op(af[i], bf[j], acc[i][j]);
-      }
-      if (more) store_slab(buf ^ 1);
+      if (more) load_slab(sl + 1, ra0, rb0, am0, bm0);
+      compute(buf);
+      if (more) store_slab(buf ^ 1, ra0, rb0, am0, bm0);
       __syncthreads();
       buf ^= 1;
+    }
+  } else if (sbeg < send) {
+    load_slab(sbeg, ra0, rb0, am0, bm0);
+    if (sbeg + 1 < send) load_slab(sbeg + 1, ra1, rb1, am1, bm1);
+    store_slab(0, ra0, rb0, am0, bm0);
+    __syncthreads();
+    for (int sl = sbeg; sl < send; sl += 2) {
+      // LDS buffer 0 holds slab sl, register set 1 slab sl + 1 (when there is one)
+      if (sl + 2 < send) load_slab(sl + 2, ra0, rb0, am0, bm0);
+      compute(0);
+      if (sl + 1 >= send) break;
+      store_slab(1, ra1, rb1, am1, bm1);
+      __syncthreads();
+      if (sl + 3 < send) load_slab(sl + 3, ra1, rb1, am1, bm1);
+      compute(1);
+      if (sl + 2 < send) store_slab(0, ra0, rb0, am0, bm0);
+      __syncthreads();
     }
   }
 

@@ -195,6 +195,230 @@ using Fused = FusedTables<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 
                           21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31>;
 static_assert(FJ == 32, "the launch tables cover NJ = 1 .. 32");
 
+// ---- Arnoldi with delayed reorthogonalisation (restart lengths up to FJ).
+// Step j applies the operator to the pending vector vt_j (orthogonalised once against the
+// final basis Q_0 .. Q_{j-1}, not yet normalised). One sweep over the basis (pass A) gives
+// t = Q^H w and beta = vt_j^H w for w = M(omega) P^{-1} vt_j; one reduction also completes
+// s = Q^H vt_j and alpha = |vt_j|^2, which the previous step's update sweep accumulated.
+// Then rho = sqrt(alpha - |s|^2) is the norm of the reorthogonalised vector, column j-1 of
+// the Hessenberg matrix is c_{j-1} + s with subdiagonal rho, and the second sweep (pass B)
+// writes q_j = (vt_j - Q s) / rho, the next pending vector vt_{j+1} = (w - Q t - g_j q_j) /
+// rho with g_j = (beta - s^H t) / rho, its preconditioned copy, and the dots s, alpha of
+// vt_{j+1}. The first-pass coefficients of column j are c_j = (g - Hbar s) / rho with
+// g = (t, g_j); Hbar s is formed by the next step's reduction. Two sweeps over the basis per
+// step instead of three, one reduction instead of three.
+constexpr int PB = FJ + 1;       // first partial row of pass B (pass A uses rows 0 .. j)
+constexpr int PSTR = PB + FJ + 2;  // partial rows per block
+
+// pass A: partial[blk][jj][r] = sum_d conj(Q_jj[d][r]) w[d][r] (jj < NJ) and row NJ with
+// vt = V_NJ, w = W + z U
+template <int NJ>
+__global__ __launch_bounds__(CW) void dcgs_dots_kernel(const double2* __restrict__ V,
+                                                       int64_t vstride,
+                                                       const double2* __restrict__ Wv,
+                                                       const double2* __restrict__ U,
+                                                       const double2* __restrict__ z, int64_t D,
+                                                       int nb, double2* __restrict__ partial) {
+  const int r = blockIdx.y * CW + threadIdx.x;
+  if (r >= nb) return;
+  const double2 zz = z[r];
+  double2 acc[NJ + 1];
+#pragma unroll
+  for (int jj = 0; jj <= NJ; ++jj) acc[jj] = make_double2(0.0, 0.0);
+  const int64_t rows_per_blk = (D + gridDim.x - 1) / gridDim.x;
+  const int64_t d0 = (int64_t)blockIdx.x * rows_per_blk;
+  const int64_t d1 = min(D, d0 + rows_per_blk);
+  for (int64_t d = d0; d < d1; ++d) {
+    const int64_t idx = d * nb + r;
+    double2 vj[NJ + 1];
+#pragma unroll
+    for (int jj = 0; jj <= NJ; ++jj) vj[jj] = V[(int64_t)jj * vstride + idx];
+    double2 w = Wv[idx];
+    const double2 p = cmul(zz, U[idx]);
+    w.x += p.x;
+    w.y += p.y;
+#pragma unroll
+    for (int jj = 0; jj <= NJ; ++jj) {
+      const double2 q = cconjmul(vj[jj], w);
+      acc[jj].x += q.x;
+      acc[jj].y += q.y;
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj <= NJ; ++jj) partial[((int64_t)blockIdx.x * PSTR + jj) * nb + r] = acc[jj];
+}
+
+// pass B over Q_0 .. Q_{NJ-1} and the pending vector in slot NJ:
+//   q = (vt - sum_i Q_i s_i) qscale          -> V slot NJ
+//   vn = (w - sum_i Q_i t_i - g q) vscale    -> V slot NJ + 1 (not when FINAL)
+//   U = vn / (diag + z); partial rows PB + i = conj(Q_i) vn, PB + NJ = conj(q) vn,
+//   PB + NJ + 1 = |vn|^2
+// s, t: [NJ][nb] (t row NJ holds g). FINAL (end of a cycle) only writes q. Four wavefronts
+// share the coefficients of their 64 RHS in LDS (registers hold the basis rows and the dots)
+// and take every fourth row of the workgroup's range; each writes its own partial row.
+template <int NJ, bool FINAL>
+__global__ __launch_bounds__(256) void dcgs_update_kernel(
+    double2* __restrict__ V, int64_t vstride, const double2* __restrict__ Wv,
+    double2* __restrict__ U, const double2* __restrict__ z, const double* __restrict__ diag,
+    const double2* __restrict__ sc, const double2* __restrict__ tc,
+    const double* __restrict__ qscale, const double* __restrict__ vscale, int64_t D, int nb,
+    double2* __restrict__ partial) {
+  constexpr int NS = NJ > 0 ? NJ : 1;
+  __shared__ double2 s_l[NS][CW];
+  __shared__ double2 t_l[FINAL ? 1 : NS][CW];
+  const int lane = threadIdx.x & (CW - 1), wave = threadIdx.x / CW;
+  const int r = blockIdx.y * CW + lane;
+  const int64_t NB = nb;
+  for (int e = threadIdx.x; e < NJ * CW; e += 256) {
+    const int jj = e / CW, l = e % CW;
+    const int rr = blockIdx.y * CW + l;
+    s_l[jj][l] = rr < nb ? sc[jj * NB + rr] : make_double2(0.0, 0.0);
+    if (!FINAL) t_l[jj][l] = rr < nb ? tc[jj * NB + rr] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  if (r >= nb) return;
+  const double2 gq = FINAL ? make_double2(0.0, 0.0) : tc[(int64_t)NJ * NB + r];
+  const double qs = qscale[r];
+  const double vs = FINAL ? 0.0 : vscale[r];
+  const double2 zz = z[r];
+  constexpr int NA = FINAL ? 1 : NJ + 2;
+  double2 acc[NA];
+#pragma unroll
+  for (int jj = 0; jj < NA; ++jj) acc[jj] = make_double2(0.0, 0.0);
+  const int64_t rows_per_blk = (D + gridDim.x - 1) / gridDim.x;
+  const int64_t d0 = (int64_t)blockIdx.x * rows_per_blk;
+  const int64_t d1 = min(D, d0 + rows_per_blk);
+  for (int64_t d = d0 + wave; d < d1; d += 4) {
+    const int64_t idx = d * nb + r;
+    // an opaque zero keeps the coefficient reads inside the loop (hoisted, they would take
+    // the registers that LDS is there to spare)
+    int opq;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(opq));
+    const int li = lane + opq;
+    double2 vj[NS];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) vj[jj] = V[(int64_t)jj * vstride + idx];
+    double2 q = V[(int64_t)NJ * vstride + idx];
+    double2 w = make_double2(0.0, 0.0);
+    double2 u = make_double2(0.0, 0.0);
+    if (!FINAL) {
+      w = Wv[idx];
+      u = U[idx];
+    }
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+      const double2 a = cmul(vj[jj], s_l[jj][li]);
+      q.x -= a.x;
+      q.y -= a.y;
+    }
+    q.x *= qs;
+    q.y *= qs;
+    V[(int64_t)NJ * vstride + idx] = q;
+    if (FINAL) continue;
+    {
+      const double2 p = cmul(zz, u);
+      w.x += p.x;
+      w.y += p.y;
+    }
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+      const double2 a = cmul(vj[jj], t_l[jj][li]);
+      w.x -= a.x;
+      w.y -= a.y;
+    }
+    {
+      const double2 a = cmul(q, gq);
+      w.x = (w.x - a.x) * vs;
+      w.y = (w.y - a.y) * vs;
+    }
+    V[(int64_t)(NJ + 1) * vstride + idx] = w;
+    U[idx] = cdiv(w, make_double2(diag[d] + zz.x, zz.y));
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+      const double2 a = cconjmul(vj[jj], w);
+      acc[jj].x += a.x;
+      acc[jj].y += a.y;
+    }
+    {
+      const double2 a = cconjmul(q, w);
+      acc[NJ].x += a.x;
+      acc[NJ].y += a.y;
+      acc[NA - 1].x += w.x * w.x + w.y * w.y;
+    }
+  }
+  if (FINAL) return;
+  const int64_t blk = (int64_t)blockIdx.x * 4 + wave;
+#pragma unroll
+  for (int jj = 0; jj < NA; ++jj) partial[(blk * PSTR + PB + jj) * NB + r] = acc[jj];
+}
+
+// The step's reduction, grid (ceil(nb/64), nA + nB + nH), 256 threads:
+//   y < nA:            red[y] = sum_blk partial[blk][y]            (pass A rows)
+//   nA <= y < nA + nB: red[PB + i] = sum_blk partial[blk][PB + i]  (pass B rows, i = y - nA)
+//   y >= nA + nB:      hs[l] = sum_{i = max(l-1, 0)}^{nh_s - 1} Hraw[col i][row l] s_i with
+//                      s = sc (the previous step's s), l = y - nA - nB (one wavefront)
+// The block sums run as in dots_reduce_s.
+__global__ __launch_bounds__(256) void dcgs_reduce_kernel(
+    const double2* __restrict__ partial, int nblk, int nA, int nB, int nh_s, int nb, int m,
+    const double2* __restrict__ Hraw, const double2* __restrict__ sc,
+    double2* __restrict__ red, double2* __restrict__ hs) {
+  __shared__ double2 sum4[4][CW];
+  const int lane = threadIdx.x % CW, w = threadIdx.x / CW;
+  const int r = blockIdx.x * CW + lane;
+  const int y = blockIdx.y;
+  const int64_t NB = nb;
+  if (y >= nA + nB) {
+    if (w != 0 || r >= nb) return;
+    const int l = y - nA - nB;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int i = l > 0 ? l - 1 : 0; i < nh_s; ++i) {
+      const double2 a = cmul(Hraw[((int64_t)i * (m + 1) + l) * NB + r], sc[(int64_t)i * NB + r]);
+      acc.x += a.x;
+      acc.y += a.y;
+    }
+    hs[(int64_t)l * NB + r] = acc;
+    return;
+  }
+  const int row = y < nA ? y : PB + (y - nA);
+  double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
+  if (r < nb) {
+    int b = w;
+    for (; b + 4 < nblk; b += 8) {
+      const double2 x = partial[((int64_t)b * PSTR + row) * NB + r];
+      const double2 x2 = partial[((int64_t)(b + 4) * PSTR + row) * NB + r];
+      s0.x += x.x; s0.y += x.y;
+      s1.x += x2.x; s1.y += x2.y;
+    }
+    for (; b < nblk; b += 4) {
+      const double2 x = partial[((int64_t)b * PSTR + row) * NB + r];
+      s0.x += x.x; s0.y += x.y;
+    }
+  }
+  sum4[w][lane] = make_double2(s0.x + s1.x, s0.y + s1.y);
+  __syncthreads();
+  if (w == 0 && r < nb) {
+    double2 t = sum4[0][lane];
+    for (int q = 1; q < 4; ++q) {
+      t.x += sum4[q][lane].x;
+      t.y += sum4[q][lane].y;
+    }
+    red[(int64_t)row * NB + r] = t;
+  }
+}
+
+typedef void (*DcgsDotsFn)(const double2*, int64_t, const double2*, const double2*,
+                           const double2*, int64_t, int, double2*);
+typedef void (*DcgsUpdateFn)(double2*, int64_t, const double2*, double2*, const double2*,
+                             const double*, const double2*, const double2*, const double*,
+                             const double*, int64_t, int, double2*);
+template <int... I> struct DcgsTables {
+  static constexpr DcgsDotsFn dots[] = {dcgs_dots_kernel<I>...};           // NJ = 0 .. FJ-1
+  static constexpr DcgsUpdateFn update[] = {dcgs_update_kernel<I, false>...};  // NJ = 0 .. FJ-1
+  static constexpr DcgsUpdateFn final_[] = {dcgs_update_kernel<I + 1, true>...};  // 1 .. FJ
+};
+using Dcgs = DcgsTables<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20,
+                        21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31>;
+
 
 // W[d][r] -= sum_{j<=k} V_j[d][r] * h[j][r]
 __global__ void update_kernel(const double2* __restrict__ V, int64_t vstride, int nj,
@@ -320,10 +544,86 @@ struct BlockState {
   double* inv;     // [nb] 1/||w|| for the new basis vector
 };
 
-// One thread per RHS: Hessenberg column k = h1 + h2 (the two Gram-Schmidt passes), the
-// previous Givens rotations, the new one, the residual estimate and the flags. The rotation
-// chain is serial in i; its operands are loaded eight rows at a time ahead of the arithmetic.
-// flag_out (optional, host-visible): one word per 64 RHS, nonzero while any of them is active.
+// Column k of the Hessenberg matrix of one RHS (thread r): entries i <= k from get(i),
+// subdiagonal nrm. Stores the raw column, applies the previous Givens rotations (their
+// operands loaded eight rows at a time ahead of the serial chain), forms rotation k, updates g
+// and the residual estimate, counts the iteration and returns 0 when the RHS continues, 1 when
+// it stops, 2 when the column is singular (the active flag is cleared for 1 and 2; a singular
+// column is excluded from the least-squares problem).
+template <typename Get>
+__device__ __forceinline__ int givens_column(const BlockState& s, int r, int k, int m, int nb,
+                                              int maxit, double nrm, Get get) {
+  const int64_t NB = nb;
+  double2* col = s.H + (int64_t)k * (m + 1) * NB + r;
+  double2* raw = s.Hraw + (int64_t)k * (m + 1) * NB + r;
+  const double2* cs = s.cs + r;
+  const double2* sn = s.sn + r;
+  double2 a = get(0);
+  raw[0] = a;
+  for (int i0 = 0; i0 < k; i0 += 8) {
+    double2 hb[8], cb[8], sb[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      if (i0 + t < k) {
+        hb[t] = get(i0 + t + 1);
+        cb[t] = cs[(int64_t)(i0 + t) * NB];
+        sb[t] = sn[(int64_t)(i0 + t) * NB];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      if (i0 + t < k) {
+        const int i = i0 + t;
+        const double2 b = hb[t];
+        raw[(int64_t)(i + 1) * NB] = b;
+        const double2 t1 = cconjmul(cb[t], a), t2 = cconjmul(sb[t], b);
+        const double2 u1 = cmul(sb[t], a), u2 = cmul(cb[t], b);
+        col[(int64_t)i * NB] = make_double2(t1.x + t2.x, t1.y + t2.y);
+        a = make_double2(u2.x - u1.x, u2.y - u1.y);
+      }
+    }
+  }
+  const double2 b = make_double2(nrm, 0.0);
+  raw[(int64_t)(k + 1) * NB] = b;
+  const double den = hypot(hypot(a.x, a.y), nrm);
+  s.its[r] += 1;
+  s.kend[r] = k + 1;
+  if (den == 0.0) {  // singular least-squares problem
+    col[(int64_t)k * NB] = a;
+    col[(int64_t)(k + 1) * NB] = b;
+    s.brk[r] = 1;
+    s.active[r] = 0;
+    s.kend[r] = k;  // exclude the singular column
+    return 2;
+  }
+  const double2 c = make_double2(a.x / den, a.y / den), sv = make_double2(nrm / den, 0.0);
+  s.cs[(int64_t)k * NB + r] = c;
+  s.sn[(int64_t)k * NB + r] = sv;
+  col[(int64_t)k * NB] = make_double2(den, 0.0);
+  col[(int64_t)(k + 1) * NB] = make_double2(0.0, 0.0);
+  double2* g = s.g + r;
+  const double2 gk = g[(int64_t)k * NB];
+  const double2 ng = cmul(sv, gk);
+  const double2 gk1 = make_double2(-ng.x, -ng.y);
+  g[(int64_t)(k + 1) * NB] = gk1;
+  g[(int64_t)k * NB] = cconjmul(c, gk);
+  const double est = hypot(gk1.x, gk1.y);
+  s.resest[r] = est;
+  const bool stop = est <= s.thresh[r] || nrm == 0.0 || s.its[r] >= maxit || k + 1 == m;
+  if (stop) s.active[r] = 0;
+  return stop ? 1 : 0;
+}
+
+// flag_out (optional, host-visible): one word per 64 RHS, nonzero while any of them is active
+__device__ __forceinline__ void write_flag(int* flag_out, bool act) {
+  if (!flag_out) return;
+  const unsigned long long any = __ballot(act);
+  if (threadIdx.x == 0) flag_out[blockIdx.x] = any != 0ull ? 1 : 0;
+}
+
+// Classical Gram-Schmidt step: column k = h1 + h2 (the two passes), subdiagonal hn; inv = the
+// scale of the new basis vector (also for a RHS that stops here: its residual uses that
+// vector; zero for a singular column and for a RHS that had stopped before).
 __global__ __launch_bounds__(64) void arnoldi_finish_kernel(
     const double2* __restrict__ h1, const double2* __restrict__ h2,
     const double* __restrict__ hn, int k, int m, int nb, int maxit, BlockState s,
@@ -332,83 +632,86 @@ __global__ __launch_bounds__(64) void arnoldi_finish_kernel(
   bool act = false;
   if (r < nb && s.active[r]) {
     const int64_t NB = nb;
-    double2* col = s.H + (int64_t)k * (m + 1) * NB + r;
-    double2* raw = s.Hraw + (int64_t)k * (m + 1) * NB + r;
-    const double2* cs = s.cs + r;
-    const double2* sn = s.sn + r;
     const double nrm = hn[r];
-    double2 a = h1[r];
-    {
-      const double2 t = h2[r];
-      a.x += t.x;
-      a.y += t.y;
-    }
-    raw[0] = a;
-    for (int i0 = 0; i0 < k; i0 += 8) {
-      double2 hb[8], cb[8], sb[8];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        if (i0 + t < k) {
-          const int64_t o = (int64_t)(i0 + t + 1) * NB + r;
-          hb[t] = h1[o];
-          const double2 u = h2[o];
-          hb[t].x += u.x;
-          hb[t].y += u.y;
-          cb[t] = cs[(int64_t)(i0 + t) * NB];
-          sb[t] = sn[(int64_t)(i0 + t) * NB];
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        if (i0 + t < k) {
-          const int i = i0 + t;
-          const double2 b = hb[t];
-          raw[(int64_t)(i + 1) * NB] = b;
-          const double2 t1 = cconjmul(cb[t], a), t2 = cconjmul(sb[t], b);
-          const double2 u1 = cmul(sb[t], a), u2 = cmul(cb[t], b);
-          col[(int64_t)i * NB] = make_double2(t1.x + t2.x, t1.y + t2.y);
-          a = make_double2(u2.x - u1.x, u2.y - u1.y);
-        }
-      }
-    }
-    const double2 b = make_double2(nrm, 0.0);
-    raw[(int64_t)(k + 1) * NB] = b;
-    const double den = hypot(hypot(a.x, a.y), nrm);
-    s.its[r] += 1;
-    s.kend[r] = k + 1;
-    if (den == 0.0) {  // singular least-squares problem
-      col[(int64_t)k * NB] = a;
-      col[(int64_t)(k + 1) * NB] = b;
-      s.brk[r] = 1;
-      s.active[r] = 0;
-      s.inv[r] = 0.0;
-      s.kend[r] = k;  // exclude the singular column
-    } else {
-      const double2 c = make_double2(a.x / den, a.y / den), sv = make_double2(nrm / den, 0.0);
-      s.cs[(int64_t)k * NB + r] = c;
-      s.sn[(int64_t)k * NB + r] = sv;
-      col[(int64_t)k * NB] = make_double2(den, 0.0);
-      col[(int64_t)(k + 1) * NB] = make_double2(0.0, 0.0);
-      double2* g = s.g + r;
-      const double2 gk = g[(int64_t)k * NB];
-      const double2 ng = cmul(sv, gk);
-      const double2 gk1 = make_double2(-ng.x, -ng.y);
-      g[(int64_t)(k + 1) * NB] = gk1;
-      g[(int64_t)k * NB] = cconjmul(c, gk);
-      const double est = hypot(gk1.x, gk1.y);
-      s.resest[r] = est;
-      const bool stop = est <= s.thresh[r] || nrm == 0.0 || s.its[r] >= maxit || k + 1 == m;
-      s.inv[r] = (nrm > 0.0) ? 1.0 / nrm : 0.0;
-      if (stop) s.active[r] = 0;
-      act = !stop;
-    }
+    const int res = givens_column(s, r, k, m, nb, maxit, nrm, [&](int i) {
+      const double2 x = h1[(int64_t)i * NB + r], y = h2[(int64_t)i * NB + r];
+      return make_double2(x.x + y.x, x.y + y.y);
+    });
+    s.inv[r] = (res != 2 && nrm > 0.0) ? 1.0 / nrm : 0.0;
+    act = res == 0;
   } else if (r < nb) {
     s.inv[r] = 0.0;
   }
-  if (flag_out) {
-    const unsigned long long any = __ballot(act);
-    if (threadIdx.x == 0) flag_out[blockIdx.x] = any != 0ull ? 1 : 0;
+  write_flag(flag_out, act);
+}
+
+// Delayed-reorthogonalisation step j (see dcgs_dots_kernel), one thread per RHS. For j >= 1:
+// rho = sqrt(alpha - |s|^2) and column j-1 = (g_prev - Hbar s_prev) / rho_prev + s with
+// subdiagonal rho (g_prev in tc, 1/rho_prev in vscale, Hbar s_prev in hs for j >= 2). A RHS
+// that continues gets the pass-B coefficients s (sc), t and g_j (tc), qscale = vscale =
+// 1/rho; one that stops here only has its pending vector finalised (vscale = 0); final
+// (end of the cycle) forms no new coefficients.
+__global__ __launch_bounds__(64) void dcgs_finish_kernel(
+    int j, int m, int nb, int maxit, int final_, BlockState s, const double2* __restrict__ red,
+    const double2* __restrict__ hs, double2* __restrict__ sc, double2* __restrict__ tc,
+    double* __restrict__ qscale, double* __restrict__ vscale, int* __restrict__ flag_out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  bool act = false;
+  if (r < nb) {
+    const int64_t NB = nb;
+    if (!s.active[r]) {
+      qscale[r] = 0.0;
+      vscale[r] = 0.0;
+    } else {
+      double rho = 1.0;
+      bool cont = true;
+      if (j > 0) {
+        double ss = 0.0;
+        for (int i = 0; i < j; ++i) {
+          const double2 si = red[(int64_t)(PB + i) * NB + r];
+          ss += si.x * si.x + si.y * si.y;
+        }
+        const double rho2 = red[(int64_t)(PB + j) * NB + r].x - ss;
+        rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
+        const double ip = vscale[r];
+        const bool lag = j >= 2;
+        const int res = givens_column(s, r, j - 1, m, nb, maxit, rho, [&](int i) {
+          double2 g = tc[(int64_t)i * NB + r];
+          if (lag) {
+            const double2 h = hs[(int64_t)i * NB + r];
+            g.x -= h.x;
+            g.y -= h.y;
+          }
+          const double2 si = red[(int64_t)(PB + i) * NB + r];
+          return make_double2(g.x * ip + si.x, g.y * ip + si.y);
+        });
+        cont = res == 0;
+      }
+      if (cont && !final_) {
+        double2 st = make_double2(0.0, 0.0);
+        for (int i = 0; i < j; ++i) {
+          const double2 si = red[(int64_t)(PB + i) * NB + r];
+          const double2 ti = red[(int64_t)i * NB + r];
+          const double2 a = cconjmul(si, ti);
+          st.x += a.x;
+          st.y += a.y;
+          sc[(int64_t)i * NB + r] = si;
+          tc[(int64_t)i * NB + r] = ti;
+        }
+        const double2 beta = red[(int64_t)j * NB + r];
+        const double ir = 1.0 / rho;
+        tc[(int64_t)j * NB + r] = make_double2((beta.x - st.x) * ir, (beta.y - st.y) * ir);
+        qscale[r] = ir;
+        vscale[r] = ir;
+        act = true;
+      } else {
+        for (int i = 0; i < j; ++i) sc[(int64_t)i * NB + r] = red[(int64_t)(PB + i) * NB + r];
+        qscale[r] = rho > 0.0 ? 1.0 / rho : 0.0;
+        vscale[r] = 0.0;
+      }
+    }
   }
+  write_flag(flag_out, act);
 }
 
 // y = H(0:kend,0:kend)^{-1} g(0:kend), written to yout[j][r] (zero beyond kend)
@@ -612,6 +915,9 @@ struct GmresBlock {
   // work arrays live in the context (ws_solve, ws_solve_f32), so that consecutive solves
   // reuse them instead of allocating and freeing the Krylov basis every call
   double2 *V, *W, *U, *X, *B, *R, *Hh, *Hh2, *Y, *Cc, *z;
+  // delayed-reorthogonalisation state: reduced dots, Hbar s, pass-B coefficients and scales
+  double2 *red = nullptr, *hsb = nullptr, *scb = nullptr, *tcb = nullptr;
+  double *qsc = nullptr, *vsc = nullptr;
   double *nrm, *part_n;
   double2* part_h;
   int *used, *prow;
@@ -642,7 +948,10 @@ struct GmresBlock {
     precision = prec;
     transpose = tr;
     const int64_t vec = D * nb;
+    // a multiple of 4: the delayed-reorthogonalisation update runs nblk_rows / 4 workgroups
+    // of four wavefronts, one partial row per wavefront
     nblk_rows = (int)std::min<int64_t>(1024, std::max<int64_t>(1, vec / 4096));
+    nblk_rows = (nblk_rows + 3) / 4 * 4;
     nbrows_y = (nb + CW - 1) / CW;
     int64_t bytes = 0;
     auto add = [&](int64_t n, int64_t sz) { bytes += ((n * sz + 255) / 256) * 256; };
@@ -654,7 +963,10 @@ struct GmresBlock {
     add(nb, 16);                                              // z
     add(nb, 8);                                               // nrm
     add((int64_t)nblk_rows * nb, 8);                          // part_n
-    add((int64_t)nblk_rows * FJ * nb, 16);                    // part_h
+    add((int64_t)nblk_rows * PSTR * nb, 16);                  // part_h
+    add((int64_t)PSTR * nb, 16); add((int64_t)(FJ + 1) * nb, 16);    // red hsb
+    add((int64_t)(FJ + 1) * nb, 16); add((int64_t)(FJ + 2) * nb, 16);  // scb tcb
+    add(nb, 8); add(nb, 8);                                   // qsc vsc
     add(nb, 4); add(nb, 4);                                   // used prow
     add((int64_t)nb * m * (m + 1), 16);                       // H
     add((int64_t)nb * m * (m + 1), 16);                       // Hraw
@@ -678,7 +990,13 @@ struct GmresBlock {
     z = carve<double2>(cur, nb);
     nrm = carve<double>(cur, nb);
     part_n = carve<double>(cur, (int64_t)nblk_rows * nb);
-    part_h = carve<double2>(cur, (int64_t)nblk_rows * FJ * nb);
+    part_h = carve<double2>(cur, (int64_t)nblk_rows * PSTR * nb);
+    red = carve<double2>(cur, (int64_t)PSTR * nb);
+    hsb = carve<double2>(cur, (int64_t)(FJ + 1) * nb);
+    scb = carve<double2>(cur, (int64_t)(FJ + 1) * nb);
+    tcb = carve<double2>(cur, (int64_t)(FJ + 2) * nb);
+    qsc = carve<double>(cur, nb);
+    vsc = carve<double>(cur, nb);
     used = carve<int>(cur, nb);
     prow = carve<int>(cur, nb);
     s.H = carve<double2>(cur, (int64_t)nb * m * (m + 1));
@@ -763,6 +1081,13 @@ struct GmresBlock {
   void reduce_dots(int nj, double2* h) {
     hipLaunchKernelGGL(dots_reduce_s<FJ>, dim3(nbrows_y, nj), dim3(256), 0, st(), part_h, nblk_rows, 0,
                        nj, nb, h);
+    GFCC_LAUNCH_CHECK();
+  }
+  // the delayed-reorthogonalisation reduction: nA pass-A rows, nB pass-B rows, nH rows of
+  // Hbar s over the previous step's nh_s coefficients
+  void dcgs_reduce(int nA, int nB, int nH, int nh_s) {
+    hipLaunchKernelGGL(dcgs_reduce_kernel, dim3(nbrows_y, nA + nB + nH), dim3(256), 0, st(),
+                       part_h, nblk_rows, nA, nB, nh_s, nb, m, s.Hraw, scb, red, hsb);
     GFCC_LAUNCH_CHECK();
   }
   void reduce_norms(double* out) {
@@ -905,7 +1230,67 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
     GFCC_LAUNCH_CHECK();
     int ksteps = 0;  // Arnoldi steps taken in this cycle (basis vectors that y can weight)
     const dim3 rgrid(gb.nblk_rows, gb.nbrows_y);
-    for (int k = 0; k < m; ++k) {
+    const dim3 ugrid(gb.nblk_rows / 4, gb.nbrows_y);
+    // flags written by the finishing kernel of step kk: is any RHS still active?
+    auto any_active = [&](int kk) {
+      GFCC_HIP(hipEventSynchronize(gb.flag_ev[kk & 1]));
+      const volatile int* f = gb.hflags + (size_t)(kk & 1) * gb.nbrows_y;
+      int any = 0;
+      for (int b = 0; b < gb.nbrows_y; ++b) any |= f[b];
+      return any != 0;
+    };
+    const bool delayed = m <= FJ;
+    if (delayed) {
+      // Arnoldi with delayed reorthogonalisation: step k finalises column k - 1 and basis
+      // vector k; the end of the cycle finalises column m - 1 and vector m
+      bool stopped = false;
+      for (int k = 0; k < m; ++k) {
+        if (k == 0 && unit_start) {
+          unit_sigma(ctx, gb.prow, gb.z, nb, gb.W);
+        } else {
+          gb.apply_M(gb.U, gb.W, false, false);
+        }
+        hipLaunchKernelGGL(Dcgs::dots[k], rgrid, dim3(CW), 0, st, gb.V, D * nb, gb.W, gb.U, gb.z,
+                           D, nb, gb.part_h);
+        GFCC_LAUNCH_CHECK();
+        gb.dcgs_reduce(k + 1, k >= 1 ? k + 1 : 0, k >= 2 ? k : 0, k - 1);
+        int* fslot = gb.dflags + (size_t)(k & 1) * gb.nbrows_y;
+        hipLaunchKernelGGL(dcgs_finish_kernel, dim3(gb.nbrows_y), dim3(CW), 0, st, k, m, nb,
+                           maxit, 0, gb.s, gb.red, gb.hsb, gb.scb, gb.tcb, gb.qsc, gb.vsc, fslot);
+        GFCC_LAUNCH_CHECK();
+        hipLaunchKernelGGL(Dcgs::update[k], ugrid, dim3(256), 0, st, gb.V, D * nb, gb.W, gb.U,
+                           gb.z, ctx->op.diag.as<double>(), gb.scb, gb.tcb, gb.qsc, gb.vsc, D,
+                           nb, gb.part_h);
+        GFCC_LAUNCH_CHECK();
+        GFCC_HIP(hipEventRecord(gb.flag_ev[k & 1], st));
+        if (late) {
+          // step k is queued before the flags of step k - 1 are read; when step k - 1 has
+          // stopped every RHS (its columns reach k - 2), step k met only inactive ones
+          if (k > 0 && !any_active(k - 1)) {
+            ksteps = k - 1;
+            stopped = true;
+            break;
+          }
+        } else if (!any_active(k)) {
+          ksteps = k;
+          stopped = true;
+          break;
+        }
+      }
+      if (!stopped) {
+        gb.dcgs_reduce(0, m + 1, m >= 2 ? m : 0, m - 1);
+        hipLaunchKernelGGL(dcgs_finish_kernel, dim3(gb.nbrows_y), dim3(CW), 0, st, m, m, nb,
+                           maxit, 1, gb.s, gb.red, gb.hsb, gb.scb, gb.tcb, gb.qsc, gb.vsc,
+                           (int*)nullptr);
+        GFCC_LAUNCH_CHECK();
+        hipLaunchKernelGGL(Dcgs::final_[m - 1], ugrid, dim3(256), 0, st, gb.V, D * nb, gb.W,
+                           gb.U, gb.z, ctx->op.diag.as<double>(), gb.scb, gb.tcb, gb.qsc, gb.vsc,
+                           D, nb, gb.part_h);
+        GFCC_LAUNCH_CHECK();
+        ksteps = m;
+      }
+    }
+    for (int k = 0; k < m && !delayed; ++k) {
       const int nj = k + 1;
       if (nj <= FJ) {
         // W = sigma(U); the shift, both Gram-Schmidt passes (CGS2) and the norm in three
@@ -955,13 +1340,7 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
         // inactive ones (their next basis vectors and inputs are zero, their state is left
         // alone) and does not count.
         GFCC_HIP(hipEventRecord(gb.flag_ev[k & 1], st));
-        if (k > 0) {
-          GFCC_HIP(hipEventSynchronize(gb.flag_ev[(k - 1) & 1]));
-          const volatile int* f = gb.hflags + (size_t)((k - 1) & 1) * gb.nbrows_y;
-          int any = 0;
-          for (int b = 0; b < gb.nbrows_y; ++b) any |= f[b];
-          if (!any) break;
-        }
+        if (k > 0 && !any_active(k - 1)) break;
         ksteps = k + 1;
         continue;
       }
