@@ -380,21 +380,24 @@ __global__ __launch_bounds__(256) void dcgs_reduce_kernel(
     return;
   }
   const int row = y < nA ? y : PB + (y - nA);
-  double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
+  // wavefront w sums blocks w, w + 4, ...: eight loads in flight, then a fixed-order sum
+  double2 sacc = make_double2(0.0, 0.0);
   if (r < nb) {
-    int b = w;
-    for (; b + 4 < nblk; b += 8) {
-      const double2 x = partial[((int64_t)b * PSTR + row) * NB + r];
-      const double2 x2 = partial[((int64_t)(b + 4) * PSTR + row) * NB + r];
-      s0.x += x.x; s0.y += x.y;
-      s1.x += x2.x; s1.y += x2.y;
-    }
-    for (; b < nblk; b += 4) {
-      const double2 x = partial[((int64_t)b * PSTR + row) * NB + r];
-      s0.x += x.x; s0.y += x.y;
+    for (int b0 = w; b0 < nblk; b0 += 32) {
+      double2 x[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int b = b0 + 4 * t;
+        x[t] = b < nblk ? partial[((int64_t)b * PSTR + row) * NB + r] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        sacc.x += x[t].x;
+        sacc.y += x[t].y;
+      }
     }
   }
-  sum4[w][lane] = make_double2(s0.x + s1.x, s0.y + s1.y);
+  sum4[w][lane] = sacc;
   __syncthreads();
   if (w == 0 && r < nb) {
     double2 t = sum4[0][lane];
@@ -647,14 +650,18 @@ __global__ __launch_bounds__(64) void arnoldi_finish_kernel(
 
 // Delayed-reorthogonalisation step j (see dcgs_dots_kernel), one thread per RHS. For j >= 1:
 // rho = sqrt(alpha - |s|^2) and column j-1 = (g_prev - Hbar s_prev) / rho_prev + s with
-// subdiagonal rho (g_prev in tc, 1/rho_prev in vscale, Hbar s_prev in hs for j >= 2). A RHS
-// that continues gets the pass-B coefficients s (sc), t and g_j (tc), qscale = vscale =
-// 1/rho; one that stops here only has its pending vector finalised (vscale = 0); final
-// (end of the cycle) forms no new coefficients.
+// subdiagonal rho (g_prev in tc, 1/rho_prev in vscale, Hbar s_prev in hs for j >= 2); the
+// column is stored raw and rotated, rotation j-1 and the residual estimate formed as in
+// givens_column. A RHS that continues gets the pass-B coefficients s (sc), t and g_j (tc),
+// qscale = vscale = 1/rho; one that stops here only has its pending vector finalised
+// (vscale = 0); final (end of the cycle) forms no new coefficients. Every per-row quantity
+// (the column entry, its rotation, |s|^2, s^H t and the new coefficients) comes from one pass
+// whose loads are issued a few rows at a time.
 __global__ __launch_bounds__(64) void dcgs_finish_kernel(
     int j, int m, int nb, int maxit, int final_, BlockState s, const double2* __restrict__ red,
     const double2* __restrict__ hs, double2* __restrict__ sc, double2* __restrict__ tc,
     double* __restrict__ qscale, double* __restrict__ vscale, int* __restrict__ flag_out) {
+  constexpr int FB = 8;  // rows per batch of loads
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   bool act = false;
   if (r < nb) {
@@ -662,50 +669,103 @@ __global__ __launch_bounds__(64) void dcgs_finish_kernel(
     if (!s.active[r]) {
       qscale[r] = 0.0;
       vscale[r] = 0.0;
+    } else if (j == 0) {  // the pending vector is the normalised start vector: no column yet
+      tc[r] = red[r];
+      qscale[r] = 1.0;
+      vscale[r] = 1.0;
+      act = true;
     } else {
-      double rho = 1.0;
-      bool cont = true;
-      if (j > 0) {
-        double ss = 0.0;
-        for (int i = 0; i < j; ++i) {
-          const double2 si = red[(int64_t)(PB + i) * NB + r];
-          ss += si.x * si.x + si.y * si.y;
+      const int k = j - 1;
+      const double ip = vscale[r];
+      const bool lag = j >= 2;
+      const double alpha = red[(int64_t)(PB + j) * NB + r].x;
+      const double2 beta = red[(int64_t)j * NB + r];
+      double2* col = s.H + (int64_t)k * (m + 1) * NB + r;
+      double2* raw = s.Hraw + (int64_t)k * (m + 1) * NB + r;
+      double ss = 0.0;
+      double2 st = make_double2(0.0, 0.0);
+      double2 a = make_double2(0.0, 0.0);
+      for (int i0 = 0; i0 < j; i0 += FB) {
+        double2 sb[FB], tb[FB], gb[FB], hb[FB], cb[FB], qb[FB];
+#pragma unroll
+        for (int t = 0; t < FB; ++t) {
+          // unconditional loads at clamped rows (every buffer has them), values selected after
+          const int i = i0 + t;
+          const int ic = i < j ? i : j - 1, ir = ic > 0 ? ic - 1 : 0;
+          const bool on = i < j, rot = on && i >= 1;
+          const double2 zero = make_double2(0.0, 0.0);
+          const double2 s_ = red[(int64_t)(PB + ic) * NB + r], t_ = red[(int64_t)ic * NB + r];
+          const double2 g_ = tc[(int64_t)ic * NB + r], h_ = hs[(int64_t)ic * NB + r];
+          const double2 c_ = s.cs[(int64_t)ir * NB + r], q_ = s.sn[(int64_t)ir * NB + r];
+          sb[t] = on ? s_ : zero;
+          tb[t] = on ? t_ : zero;
+          gb[t] = on ? g_ : zero;
+          hb[t] = on && lag ? h_ : zero;
+          cb[t] = rot ? c_ : zero;
+          qb[t] = rot ? q_ : zero;
         }
-        const double rho2 = red[(int64_t)(PB + j) * NB + r].x - ss;
-        rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
-        const double ip = vscale[r];
-        const bool lag = j >= 2;
-        const int res = givens_column(s, r, j - 1, m, nb, maxit, rho, [&](int i) {
-          double2 g = tc[(int64_t)i * NB + r];
-          if (lag) {
-            const double2 h = hs[(int64_t)i * NB + r];
-            g.x -= h.x;
-            g.y -= h.y;
+#pragma unroll
+        for (int t = 0; t < FB; ++t) {
+          const int i = i0 + t;
+          if (i >= j) continue;
+          ss += sb[t].x * sb[t].x + sb[t].y * sb[t].y;
+          const double2 p = cconjmul(sb[t], tb[t]);
+          st.x += p.x;
+          st.y += p.y;
+          const double2 ci = make_double2((gb[t].x - hb[t].x) * ip + sb[t].x,
+                                          (gb[t].y - hb[t].y) * ip + sb[t].y);
+          raw[(int64_t)i * NB] = ci;
+          sc[(int64_t)i * NB + r] = sb[t];
+          tc[(int64_t)i * NB + r] = tb[t];
+          if (i == 0) {
+            a = ci;
+          } else {  // rotation i-1 on the entries (i-1, i)
+            const double2 t1 = cconjmul(cb[t], a), t2 = cconjmul(qb[t], ci);
+            const double2 u1 = cmul(qb[t], a), u2 = cmul(cb[t], ci);
+            col[(int64_t)(i - 1) * NB] = make_double2(t1.x + t2.x, t1.y + t2.y);
+            a = make_double2(u2.x - u1.x, u2.y - u1.y);
           }
-          const double2 si = red[(int64_t)(PB + i) * NB + r];
-          return make_double2(g.x * ip + si.x, g.y * ip + si.y);
-        });
-        cont = res == 0;
+        }
+      }
+      const double rho2 = alpha - ss;
+      const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
+      const double2 b = make_double2(rho, 0.0);
+      raw[(int64_t)j * NB] = b;
+      const double den = hypot(hypot(a.x, a.y), rho);
+      s.its[r] += 1;
+      s.kend[r] = j;
+      bool cont = false;
+      if (den == 0.0) {  // singular least-squares problem: the column is excluded
+        col[(int64_t)k * NB] = a;
+        col[(int64_t)j * NB] = b;
+        s.brk[r] = 1;
+        s.active[r] = 0;
+        s.kend[r] = k;
+      } else {
+        const double2 c = make_double2(a.x / den, a.y / den), sv = make_double2(rho / den, 0.0);
+        s.cs[(int64_t)k * NB + r] = c;
+        s.sn[(int64_t)k * NB + r] = sv;
+        col[(int64_t)k * NB] = make_double2(den, 0.0);
+        col[(int64_t)j * NB] = make_double2(0.0, 0.0);
+        double2* g = s.g + r;
+        const double2 gk = g[(int64_t)k * NB];
+        const double2 ng = cmul(sv, gk);
+        const double2 gk1 = make_double2(-ng.x, -ng.y);
+        g[(int64_t)j * NB] = gk1;
+        g[(int64_t)k * NB] = cconjmul(c, gk);
+        const double est = hypot(gk1.x, gk1.y);
+        s.resest[r] = est;
+        const bool stop = est <= s.thresh[r] || rho == 0.0 || s.its[r] >= maxit || j == m;
+        if (stop) s.active[r] = 0;
+        cont = !stop;
       }
       if (cont && !final_) {
-        double2 st = make_double2(0.0, 0.0);
-        for (int i = 0; i < j; ++i) {
-          const double2 si = red[(int64_t)(PB + i) * NB + r];
-          const double2 ti = red[(int64_t)i * NB + r];
-          const double2 a = cconjmul(si, ti);
-          st.x += a.x;
-          st.y += a.y;
-          sc[(int64_t)i * NB + r] = si;
-          tc[(int64_t)i * NB + r] = ti;
-        }
-        const double2 beta = red[(int64_t)j * NB + r];
         const double ir = 1.0 / rho;
         tc[(int64_t)j * NB + r] = make_double2((beta.x - st.x) * ir, (beta.y - st.y) * ir);
         qscale[r] = ir;
         vscale[r] = ir;
         act = true;
       } else {
-        for (int i = 0; i < j; ++i) sc[(int64_t)i * NB + r] = red[(int64_t)(PB + i) * NB + r];
         qscale[r] = rho > 0.0 ? 1.0 / rho : 0.0;
         vscale[r] = 0.0;
       }
@@ -733,6 +793,70 @@ __global__ void ysolve_kernel(int m, int nb, BlockState s, const int* __restrict
     }
     yout[(int64_t)i * NB + r] = cdiv(acc, H[((int64_t)i * (m + 1) + i) * NB]);
   }
+}
+
+// The same back substitution for m <= 32, 32 lanes per RHS (two per wavefront): lane l holds
+// row l of the rotated (upper triangular) H, loaded at once, and g_l; step i (from kend - 1
+// down) takes y_i from lane i and updates the rows above it.
+__global__ __launch_bounds__(64) void ysolve32_kernel(int m, int nb, BlockState s,
+                                                      const int* __restrict__ used,
+                                                      double2* __restrict__ yout) {
+  const int half = threadIdx.x >> 5, l = threadIdx.x & 31;
+  const int r = blockIdx.x * 2 + half;
+  const bool ok = r < nb;
+  const int ke = ok && used[r] ? s.kend[r] : 0;
+  const int64_t NB = nb;
+  double2 row[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i)
+    row[i] = (i < ke && l <= i) ? s.H[((int64_t)i * (m + 1) + l) * NB + r] : make_double2(0.0, 0.0);
+  double2 g = l < ke ? s.g[(int64_t)l * NB + r] : make_double2(0.0, 0.0);
+  double2 y = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int i = 31; i >= 0; --i) {
+    const double2 mine = l == i && i < ke ? cdiv(g, row[i]) : make_double2(0.0, 0.0);
+    const double2 yi = make_double2(__shfl(mine.x, half * 32 + i), __shfl(mine.y, half * 32 + i));
+    if (i < ke) {
+      if (l == i) y = yi;
+      if (l < i) {
+        const double2 a = cmul(row[i], yi);
+        g.x -= a.x;
+        g.y -= a.y;
+      }
+    }
+  }
+  if (ok && l < m) yout[(int64_t)l * NB + r] = y;
+}
+
+// Residual coefficients for m <= 32, one wavefront per RHS, lane i = row i (i <= m): the
+// row's Hessenberg entries and the y_j it needs are loaded at once.
+__global__ __launch_bounds__(64) void rescoef64_kernel(int m, int nb, BlockState s,
+                                                       const int* __restrict__ used,
+                                                       const double2* __restrict__ y,
+                                                       double2* __restrict__ c) {
+  const int r = blockIdx.x, i = threadIdx.x;
+  if (i > m) return;
+  const int ke = used[r] ? s.kend[r] : -1;
+  const int64_t NB = nb;
+  double2 acc = make_double2(i == 0 && ke >= 0 ? s.beta[r] : 0.0, 0.0);
+  if (i <= ke) {
+    double2 hv[32], yv[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      const bool on = j < ke && j >= i - 1;  // H is upper Hessenberg
+      hv[j] = on ? s.Hraw[((int64_t)j * (m + 1) + i) * NB + r] : make_double2(0.0, 0.0);
+      yv[j] = on ? y[(int64_t)j * NB + r] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      const double2 a = cmul(hv[j], yv[j]);
+      acc.x -= a.x;
+      acc.y -= a.y;
+    }
+  } else {
+    acc = make_double2(0.0, 0.0);
+  }
+  c[(int64_t)i * NB + r] = acc;
 }
 
 // X[d][r] += (sum_j V_j[d][r] y[j][r]) / (diag[d] + z[r])
@@ -1353,13 +1477,23 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
     }
     // ---- solution update x += P^{-1} V y (y is zero beyond each right-hand side's kend,
     // and kend <= ksteps)
-    hipLaunchKernelGGL(ysolve_kernel, dim3(blocks_for(nb, 64)), dim3(64), 0, st, m, nb, gb.s,
-                       gb.used, gb.Y);
+    if (m <= 32) {
+      hipLaunchKernelGGL(ysolve32_kernel, dim3((nb + 1) / 2), dim3(64), 0, st, m, nb, gb.s,
+                         gb.used, gb.Y);
+    } else {
+      hipLaunchKernelGGL(ysolve_kernel, dim3(blocks_for(nb, 64)), dim3(64), 0, st, m, nb, gb.s,
+                         gb.used, gb.Y);
+    }
     GFCC_LAUNCH_CHECK();
     if (!mixed) {
       // FP64: the update and the residual of the updated X (Arnoldi relation) in one pass
-      hipLaunchKernelGGL(rescoef_kernel, dim3(blocks_for(nb, 64)), dim3(64), 0, st, m, nb, gb.s,
-                         gb.used, gb.Y, gb.Cc);
+      if (m <= 32) {
+        hipLaunchKernelGGL(rescoef64_kernel, dim3(nb), dim3(64), 0, st, m, nb, gb.s, gb.used,
+                           gb.Y, gb.Cc);
+      } else {
+        hipLaunchKernelGGL(rescoef_kernel, dim3(blocks_for(nb, 64)), dim3(64), 0, st, m, nb, gb.s,
+                           gb.used, gb.Y, gb.Cc);
+      }
       GFCC_LAUNCH_CHECK();
       hipLaunchKernelGGL(xupdate_res_kernel, dim3(gridn(D * nb)), dim3(256), 0, st, gb.V, D * nb,
                          ksteps, gb.Y, gb.Cc, gb.used, ctx->op.diag.as<double>(), gb.z, D, nb,
