@@ -648,126 +648,153 @@ __global__ __launch_bounds__(64) void arnoldi_finish_kernel(
   write_flag(flag_out, act);
 }
 
-// Delayed-reorthogonalisation step j (see dcgs_dots_kernel), one thread per RHS. For j >= 1:
-// rho = sqrt(alpha - |s|^2) and column j-1 = (g_prev - Hbar s_prev) / rho_prev + s with
-// subdiagonal rho (g_prev in tc, 1/rho_prev in vscale, Hbar s_prev in hs for j >= 2); the
-// column is stored raw and rotated, rotation j-1 and the residual estimate formed as in
-// givens_column. A RHS that continues gets the pass-B coefficients s (sc), t and g_j (tc),
-// qscale = vscale = 1/rho; one that stops here only has its pending vector finalised
-// (vscale = 0); final (end of the cycle) forms no new coefficients. Every per-row quantity
-// (the column entry, its rotation, |s|^2, s^H t and the new coefficients) comes from one pass
+// Delayed-reorthogonalisation step j (see dcgs_dots_kernel), one thread per RHS, in two parts.
+// Column part (j >= 1): rho = sqrt(alpha - |s|^2) and column j-1 = (g_prev - Hbar s_prev) /
+// rho_prev + s with subdiagonal rho (g_prev in tc, 1/rho_prev in vscale, Hbar s_prev in hs for
+// j >= 2), stored raw and rotated; rotation j-1 and the residual estimate as in givens_column;
+// s goes to sc and 1/rho to qscale (the pending vector is finalised with them). Coefficient
+// part, for a RHS that continues: t and g_j = (beta - s^H t) / rho to tc, vscale = 1/rho; a RHS
+// that stopped gets vscale = 0. mode 0 runs both parts (s, alpha, t and beta all reduced), mode
+// 1 the column part only (also the end of a cycle), mode 2 the coefficient part only (after
+// mode 1 and the operator product of the step). Every per-row quantity comes from one pass
 // whose loads are issued a few rows at a time.
 __global__ __launch_bounds__(64) void dcgs_finish_kernel(
-    int j, int m, int nb, int maxit, int final_, BlockState s, const double2* __restrict__ red,
+    int j, int m, int nb, int maxit, int mode, BlockState s, const double2* __restrict__ red,
     const double2* __restrict__ hs, double2* __restrict__ sc, double2* __restrict__ tc,
     double* __restrict__ qscale, double* __restrict__ vscale, int* __restrict__ flag_out) {
   constexpr int FB = 8;  // rows per batch of loads
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool colpart = mode != 2, coefpart = mode != 1;
   bool act = false;
   if (r < nb) {
     const int64_t NB = nb;
-    if (!s.active[r]) {
-      qscale[r] = 0.0;
-      vscale[r] = 0.0;
-    } else if (j == 0) {  // the pending vector is the normalised start vector: no column yet
-      tc[r] = red[r];
-      qscale[r] = 1.0;
-      vscale[r] = 1.0;
-      act = true;
-    } else {
-      const int k = j - 1;
-      const double ip = vscale[r];
-      const bool lag = j >= 2;
-      const double alpha = red[(int64_t)(PB + j) * NB + r].x;
-      const double2 beta = red[(int64_t)j * NB + r];
-      double2* col = s.H + (int64_t)k * (m + 1) * NB + r;
-      double2* raw = s.Hraw + (int64_t)k * (m + 1) * NB + r;
-      double ss = 0.0;
-      double2 st = make_double2(0.0, 0.0);
-      double2 a = make_double2(0.0, 0.0);
-      for (int i0 = 0; i0 < j; i0 += FB) {
-        double2 sb[FB], tb[FB], gb[FB], hb[FB], cb[FB], qb[FB];
+    const double2 zero = make_double2(0.0, 0.0);
+    bool live = s.active[r] != 0;
+    double2 st = zero;  // s^H t (merged mode: accumulated with the column)
+    if (colpart) {
+      if (!live) {
+        qscale[r] = 0.0;
+      } else if (j == 0) {  // the pending vector is the normalised start vector: no column yet
+        qscale[r] = 1.0;
+      } else {
+        const int k = j - 1;
+        const double ip = vscale[r];
+        const bool lag = j >= 2;
+        const double alpha = red[(int64_t)(PB + j) * NB + r].x;
+        double2* col = s.H + (int64_t)k * (m + 1) * NB + r;
+        double2* raw = s.Hraw + (int64_t)k * (m + 1) * NB + r;
+        double ss = 0.0;
+        double2 a = zero;
+        for (int i0 = 0; i0 < j; i0 += FB) {
+          double2 sb[FB], tb[FB], gb[FB], hb[FB], cb[FB], qb[FB];
 #pragma unroll
-        for (int t = 0; t < FB; ++t) {
-          // unconditional loads at clamped rows (every buffer has them), values selected after
-          const int i = i0 + t;
-          const int ic = i < j ? i : j - 1, ir = ic > 0 ? ic - 1 : 0;
-          const bool on = i < j, rot = on && i >= 1;
-          const double2 zero = make_double2(0.0, 0.0);
-          const double2 s_ = red[(int64_t)(PB + ic) * NB + r], t_ = red[(int64_t)ic * NB + r];
-          const double2 g_ = tc[(int64_t)ic * NB + r], h_ = hs[(int64_t)ic * NB + r];
-          const double2 c_ = s.cs[(int64_t)ir * NB + r], q_ = s.sn[(int64_t)ir * NB + r];
-          sb[t] = on ? s_ : zero;
-          tb[t] = on ? t_ : zero;
-          gb[t] = on ? g_ : zero;
-          hb[t] = on && lag ? h_ : zero;
-          cb[t] = rot ? c_ : zero;
-          qb[t] = rot ? q_ : zero;
-        }
+          for (int t = 0; t < FB; ++t) {
+            // unconditional loads at clamped rows (every buffer has them), values selected
+            const int i = i0 + t;
+            const int ic = i < j ? i : j - 1, ir = ic > 0 ? ic - 1 : 0;
+            const bool on = i < j, rot = on && i >= 1;
+            const double2 s_ = red[(int64_t)(PB + ic) * NB + r], t_ = red[(int64_t)ic * NB + r];
+            const double2 g_ = tc[(int64_t)ic * NB + r], h_ = hs[(int64_t)ic * NB + r];
+            const double2 c_ = s.cs[(int64_t)ir * NB + r], q_ = s.sn[(int64_t)ir * NB + r];
+            sb[t] = on ? s_ : zero;
+            tb[t] = on && coefpart ? t_ : zero;
+            gb[t] = on ? g_ : zero;
+            hb[t] = on && lag ? h_ : zero;
+            cb[t] = rot ? c_ : zero;
+            qb[t] = rot ? q_ : zero;
+          }
 #pragma unroll
-        for (int t = 0; t < FB; ++t) {
-          const int i = i0 + t;
-          if (i >= j) continue;
-          ss += sb[t].x * sb[t].x + sb[t].y * sb[t].y;
-          const double2 p = cconjmul(sb[t], tb[t]);
-          st.x += p.x;
-          st.y += p.y;
-          const double2 ci = make_double2((gb[t].x - hb[t].x) * ip + sb[t].x,
-                                          (gb[t].y - hb[t].y) * ip + sb[t].y);
-          raw[(int64_t)i * NB] = ci;
-          sc[(int64_t)i * NB + r] = sb[t];
-          tc[(int64_t)i * NB + r] = tb[t];
-          if (i == 0) {
-            a = ci;
-          } else {  // rotation i-1 on the entries (i-1, i)
-            const double2 t1 = cconjmul(cb[t], a), t2 = cconjmul(qb[t], ci);
-            const double2 u1 = cmul(qb[t], a), u2 = cmul(cb[t], ci);
-            col[(int64_t)(i - 1) * NB] = make_double2(t1.x + t2.x, t1.y + t2.y);
-            a = make_double2(u2.x - u1.x, u2.y - u1.y);
+          for (int t = 0; t < FB; ++t) {
+            const int i = i0 + t;
+            if (i >= j) continue;
+            ss += sb[t].x * sb[t].x + sb[t].y * sb[t].y;
+            const double2 ci = make_double2((gb[t].x - hb[t].x) * ip + sb[t].x,
+                                            (gb[t].y - hb[t].y) * ip + sb[t].y);
+            raw[(int64_t)i * NB] = ci;
+            sc[(int64_t)i * NB + r] = sb[t];
+            if (coefpart) {
+              const double2 p = cconjmul(sb[t], tb[t]);
+              st.x += p.x;
+              st.y += p.y;
+              tc[(int64_t)i * NB + r] = tb[t];
+            }
+            if (i == 0) {
+              a = ci;
+            } else {  // rotation i-1 on the entries (i-1, i)
+              const double2 t1 = cconjmul(cb[t], a), t2 = cconjmul(qb[t], ci);
+              const double2 u1 = cmul(qb[t], a), u2 = cmul(cb[t], ci);
+              col[(int64_t)(i - 1) * NB] = make_double2(t1.x + t2.x, t1.y + t2.y);
+              a = make_double2(u2.x - u1.x, u2.y - u1.y);
+            }
           }
         }
+        const double rho2 = alpha - ss;
+        const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
+        const double2 b = make_double2(rho, 0.0);
+        raw[(int64_t)j * NB] = b;
+        const double den = hypot(hypot(a.x, a.y), rho);
+        s.its[r] += 1;
+        s.kend[r] = j;
+        if (den == 0.0) {  // singular least-squares problem: the column is excluded
+          col[(int64_t)k * NB] = a;
+          col[(int64_t)j * NB] = b;
+          s.brk[r] = 1;
+          s.active[r] = 0;
+          s.kend[r] = k;
+          live = false;
+        } else {
+          const double2 c = make_double2(a.x / den, a.y / den), sv = make_double2(rho / den, 0.0);
+          s.cs[(int64_t)k * NB + r] = c;
+          s.sn[(int64_t)k * NB + r] = sv;
+          col[(int64_t)k * NB] = make_double2(den, 0.0);
+          col[(int64_t)j * NB] = zero;
+          double2* g = s.g + r;
+          const double2 gk = g[(int64_t)k * NB];
+          const double2 ng = cmul(sv, gk);
+          const double2 gk1 = make_double2(-ng.x, -ng.y);
+          g[(int64_t)j * NB] = gk1;
+          g[(int64_t)k * NB] = cconjmul(c, gk);
+          const double est = hypot(gk1.x, gk1.y);
+          s.resest[r] = est;
+          const bool stop = est <= s.thresh[r] || rho == 0.0 || s.its[r] >= maxit || j == m;
+          if (stop) s.active[r] = 0;
+          live = !stop;
+        }
+        qscale[r] = rho > 0.0 ? 1.0 / rho : 0.0;
       }
-      const double rho2 = alpha - ss;
-      const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
-      const double2 b = make_double2(rho, 0.0);
-      raw[(int64_t)j * NB] = b;
-      const double den = hypot(hypot(a.x, a.y), rho);
-      s.its[r] += 1;
-      s.kend[r] = j;
-      bool cont = false;
-      if (den == 0.0) {  // singular least-squares problem: the column is excluded
-        col[(int64_t)k * NB] = a;
-        col[(int64_t)j * NB] = b;
-        s.brk[r] = 1;
-        s.active[r] = 0;
-        s.kend[r] = k;
+      if (!coefpart) act = live;
+    }
+    if (coefpart) {
+      if (!live) {
+        vscale[r] = 0.0;
       } else {
-        const double2 c = make_double2(a.x / den, a.y / den), sv = make_double2(rho / den, 0.0);
-        s.cs[(int64_t)k * NB + r] = c;
-        s.sn[(int64_t)k * NB + r] = sv;
-        col[(int64_t)k * NB] = make_double2(den, 0.0);
-        col[(int64_t)j * NB] = make_double2(0.0, 0.0);
-        double2* g = s.g + r;
-        const double2 gk = g[(int64_t)k * NB];
-        const double2 ng = cmul(sv, gk);
-        const double2 gk1 = make_double2(-ng.x, -ng.y);
-        g[(int64_t)j * NB] = gk1;
-        g[(int64_t)k * NB] = cconjmul(c, gk);
-        const double est = hypot(gk1.x, gk1.y);
-        s.resest[r] = est;
-        const bool stop = est <= s.thresh[r] || rho == 0.0 || s.its[r] >= maxit || j == m;
-        if (stop) s.active[r] = 0;
-        cont = !stop;
-      }
-      if (cont && !final_) {
-        const double ir = 1.0 / rho;
+        const double ir = qscale[r];
+        if (!colpart) {  // s from sc (column part of this step), t from the reduction
+          for (int i0 = 0; i0 < j; i0 += FB) {
+            double2 sb[FB], tb[FB];
+#pragma unroll
+            for (int t = 0; t < FB; ++t) {
+              const int i = i0 + t;
+              const int ic = i < j ? i : j - 1;
+              const double2 s_ = sc[(int64_t)ic * NB + r], t_ = red[(int64_t)ic * NB + r];
+              sb[t] = i < j ? s_ : zero;
+              tb[t] = i < j ? t_ : zero;
+            }
+#pragma unroll
+            for (int t = 0; t < FB; ++t) {
+              const int i = i0 + t;
+              if (i >= j) continue;
+              const double2 p = cconjmul(sb[t], tb[t]);
+              st.x += p.x;
+              st.y += p.y;
+              tc[(int64_t)i * NB + r] = tb[t];
+            }
+          }
+        }
+        const double2 beta = red[(int64_t)j * NB + r];
         tc[(int64_t)j * NB + r] = make_double2((beta.x - st.x) * ir, (beta.y - st.y) * ir);
-        qscale[r] = ir;
         vscale[r] = ir;
         act = true;
-      } else {
-        qscale[r] = rho > 0.0 ? 1.0 / rho : 0.0;
-        vscale[r] = 0.0;
       }
     }
   }
@@ -1368,7 +1395,34 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
       // Arnoldi with delayed reorthogonalisation: step k finalises column k - 1 and basis
       // vector k; the end of the cycle finalises column m - 1 and vector m
       bool stopped = false;
+      auto finish = [&](int j, int mode, int* fslot) {
+        hipLaunchKernelGGL(dcgs_finish_kernel, dim3(gb.nbrows_y), dim3(CW), 0, st, j, m, nb,
+                           maxit, mode, gb.s, gb.red, gb.hsb, gb.scb, gb.tcb, gb.qsc, gb.vsc,
+                           fslot);
+        GFCC_LAUNCH_CHECK();
+      };
+      auto final_vector = [&](int j) {  // q_j = (vt_j - Q s) / rho, no new pending vector
+        hipLaunchKernelGGL(Dcgs::final_[j - 1], ugrid, dim3(256), 0, st, gb.V, D * nb, gb.W,
+                           gb.U, gb.z, ctx->op.diag.as<double>(), gb.scb, gb.tcb, gb.qsc,
+                           gb.vsc, D, nb, gb.part_h);
+        GFCC_LAUNCH_CHECK();
+      };
       for (int k = 0; k < m; ++k) {
+        int* fslot = gb.dflags + (size_t)(k & 1) * gb.nbrows_y;
+        if (!late && k > 0) {
+          // large blocks: column k - 1 is finalised before the operator product of step k,
+          // so a block whose right-hand sides have all stopped ends the cycle with one sweep
+          // over the basis instead of another product
+          gb.dcgs_reduce(0, k + 1, k >= 2 ? k : 0, k - 1);
+          finish(k, 1, fslot);
+          GFCC_HIP(hipEventRecord(gb.flag_ev[k & 1], st));
+          if (!any_active(k)) {
+            final_vector(k);
+            ksteps = k;
+            stopped = true;
+            break;
+          }
+        }
         if (k == 0 && unit_start) {
           unit_sigma(ctx, gb.prow, gb.z, nb, gb.W);
         } else {
@@ -1377,40 +1431,32 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
         hipLaunchKernelGGL(Dcgs::dots[k], rgrid, dim3(CW), 0, st, gb.V, D * nb, gb.W, gb.U, gb.z,
                            D, nb, gb.part_h);
         GFCC_LAUNCH_CHECK();
-        gb.dcgs_reduce(k + 1, k >= 1 ? k + 1 : 0, k >= 2 ? k : 0, k - 1);
-        int* fslot = gb.dflags + (size_t)(k & 1) * gb.nbrows_y;
-        hipLaunchKernelGGL(dcgs_finish_kernel, dim3(gb.nbrows_y), dim3(CW), 0, st, k, m, nb,
-                           maxit, 0, gb.s, gb.red, gb.hsb, gb.scb, gb.tcb, gb.qsc, gb.vsc, fslot);
-        GFCC_LAUNCH_CHECK();
+        if (late) {
+          gb.dcgs_reduce(k + 1, k >= 1 ? k + 1 : 0, k >= 2 ? k : 0, k - 1);
+          finish(k, 0, fslot);
+        } else {
+          gb.dcgs_reduce(k + 1, 0, 0, 0);
+          finish(k, k == 0 ? 0 : 2, nullptr);
+        }
         hipLaunchKernelGGL(Dcgs::update[k], ugrid, dim3(256), 0, st, gb.V, D * nb, gb.W, gb.U,
                            gb.z, ctx->op.diag.as<double>(), gb.scb, gb.tcb, gb.qsc, gb.vsc, D,
                            nb, gb.part_h);
         GFCC_LAUNCH_CHECK();
-        GFCC_HIP(hipEventRecord(gb.flag_ev[k & 1], st));
         if (late) {
           // step k is queued before the flags of step k - 1 are read; when step k - 1 has
           // stopped every RHS (its columns reach k - 2), step k met only inactive ones
+          GFCC_HIP(hipEventRecord(gb.flag_ev[k & 1], st));
           if (k > 0 && !any_active(k - 1)) {
             ksteps = k - 1;
             stopped = true;
             break;
           }
-        } else if (!any_active(k)) {
-          ksteps = k;
-          stopped = true;
-          break;
         }
       }
-      if (!stopped) {
+      if (!stopped) {  // the end of the cycle: column m - 1 and basis vector m
         gb.dcgs_reduce(0, m + 1, m >= 2 ? m : 0, m - 1);
-        hipLaunchKernelGGL(dcgs_finish_kernel, dim3(gb.nbrows_y), dim3(CW), 0, st, m, m, nb,
-                           maxit, 1, gb.s, gb.red, gb.hsb, gb.scb, gb.tcb, gb.qsc, gb.vsc,
-                           (int*)nullptr);
-        GFCC_LAUNCH_CHECK();
-        hipLaunchKernelGGL(Dcgs::final_[m - 1], ugrid, dim3(256), 0, st, gb.V, D * nb, gb.W,
-                           gb.U, gb.z, ctx->op.diag.as<double>(), gb.scb, gb.tcb, gb.qsc, gb.vsc,
-                           D, nb, gb.part_h);
-        GFCC_LAUNCH_CHECK();
+        finish(m, 1, nullptr);
+        final_vector(m);
         ksteps = m;
       }
     }
