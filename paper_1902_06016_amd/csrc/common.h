@@ -238,6 +238,11 @@ template <typename T> struct SegSpec {
   int64_t ldc = 0, sC = 0;
   int msplit = 1 << 30;
   T alpha = T(1), beta = T(0);
+  // Optional epilogue term (batch 1 per virtual index a, rows = pairs i < j, columns c): adds
+  // Z[(i v + a)][j nc + c] - Z[(j v + a)][i nc + c], the antisymmetrised ovvo contraction of
+  // the sigma (Z as written by gemm_ovvo, o v rows of o nc).
+  const T* Zas = nullptr;
+  int as_o = 0, as_v = 0, as_nc = 0;
 };
 // Runs the product on a given tile (tm x tn, tm in {32, 64, 128}, tn in {64, 128}) and split
 // count (> 1 only for batch 1); the partials live in the context's split-K workspace.

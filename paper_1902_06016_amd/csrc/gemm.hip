@@ -522,9 +522,23 @@ template <typename T> struct SegArgs {
   T* C2;
   int64_t ldc, sC, pstride;
   T alpha, beta;
+  const T* Zas;  // antisymmetrised ovvo term of the epilogue (null: none)
+  int as_o, as_v, as_nc;
 };
 
-template <typename T, int TBM, int TBN, bool SPLIT>
+// (i, j) of pair p = i o - i (i + 1) / 2 + (j - i - 1), i < j < o: the root of the quadratic in
+// double, then an exact integer correction
+__device__ __forceinline__ void pair_ij(int p, int o, int& i, int& j) {
+  const double b = 2.0 * o - 1.0;
+  int ii = (int)floor((b - sqrt(b * b - 8.0 * p)) * 0.5);
+  ii = max(0, min(ii, o - 2));
+  while (ii > 0 && ii * o - (ii * (ii + 1) >> 1) > p) --ii;
+  while (ii + 1 <= o - 2 && (ii + 1) * o - ((ii + 1) * (ii + 2) >> 1) <= p) ++ii;
+  i = ii;
+  j = p - (ii * o - (ii * (ii + 1) >> 1)) + ii + 1;
+}
+
+template <typename T, int TBM, int TBN, bool SPLIT, bool AS>
 __global__ __launch_bounds__(NT, 2) void segmm_kernel(SegArgs<T> p) {
   using M4 = Mfma<T>;
   using C4 = typename M4::C4;
@@ -600,6 +614,31 @@ __global__ __launch_bounds__(NT, 2) void segmm_kernel(SegArgs<T> p) {
 #pragma unroll
     for (int j = 0; j < JW; ++j) acc[i][j] = C4{0, 0, 0, 0};
 
+  // AS: the epilogue's antisymmetric term; small tiles load it before the k loop so that its
+  // latency hides behind the slabs (rows and columns clamped into range; out-of-range entries
+  // are not stored), larger ones in the epilogue
+  constexpr bool PREZ = AS && IW * JW <= 4;
+  C4 zdiff[PREZ ? IW : 1][PREZ ? JW : 1];
+  auto zterm = [&](int m, int n) {
+    const int64_t ldz = (int64_t)p.as_o * p.as_nc;
+    int pi, pj;
+    pair_ij(m, p.as_o, pi, pj);
+    return p.Zas[((int64_t)pi * p.as_v + bi) * ldz + (int64_t)pj * p.as_nc + n] -
+           p.Zas[((int64_t)pj * p.as_v + bi) * ldz + (int64_t)pi * p.as_nc + n];
+  };
+  if (PREZ) {
+#pragma unroll
+    for (int i = 0; i < IW; ++i)
+#pragma unroll
+      for (int j = 0; j < JW; ++j) {
+        const int n = min(n0 + wn * (TBN / 2) + j * 16 + (lane & 15), Nc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          zdiff[PREZ ? i : 0][PREZ ? j : 0][q] =
+              zterm(min(m0 + wm * (TBM / 2) + i * 16 + M4::row(lane, q), Mc), n);
+      }
+  }
+
   const int row_l = lane & 15, kq = lane >> 4;
   auto compute = [&](int buf) {
 #pragma unroll
@@ -668,6 +707,8 @@ __global__ __launch_bounds__(NT, 2) void segmm_kernel(SegArgs<T> p) {
                                 : p.C2 + bi * p.sC + (int64_t)(m - p.msplit) * p.ldc + n;
           T val = p.alpha * acc[i][j][q];
           if (p.beta != T(0)) val += p.beta * *dst;
+          if (PREZ) val += zdiff[PREZ ? i : 0][PREZ ? j : 0][q];
+          else if (AS) val += zterm(m, n);
           *dst = val;
         }
       }
@@ -694,9 +735,11 @@ template <typename T, int TBM, int TBN>
 void segmm_launch(gfcc_ctx* ctx, SegArgs<T> a, int batch, int ntiles, int splits) {
   dim3 grid((unsigned)(a.mtiles * ntiles), (unsigned)batch, (unsigned)splits);
   if (splits > 1)
-    hipLaunchKernelGGL((segmm_kernel<T, TBM, TBN, true>), grid, dim3(NT), 0, ctx->stream, a);
+    hipLaunchKernelGGL((segmm_kernel<T, TBM, TBN, true, false>), grid, dim3(NT), 0, ctx->stream, a);
+  else if (a.Zas)
+    hipLaunchKernelGGL((segmm_kernel<T, TBM, TBN, false, true>), grid, dim3(NT), 0, ctx->stream, a);
   else
-    hipLaunchKernelGGL((segmm_kernel<T, TBM, TBN, false>), grid, dim3(NT), 0, ctx->stream, a);
+    hipLaunchKernelGGL((segmm_kernel<T, TBM, TBN, false, false>), grid, dim3(NT), 0, ctx->stream, a);
   GFCC_LAUNCH_CHECK();
 }
 
@@ -740,6 +783,11 @@ void segmm_run(gfcc_ctx* ctx, const SegSpec<T>& s, int tm, int tn, int splits) {
   a.sC = s.sC;
   a.alpha = s.alpha;
   a.beta = s.beta;
+  a.Zas = s.Zas;
+  a.as_o = s.as_o;
+  a.as_v = s.as_v;
+  a.as_nc = s.as_nc;
+  GFCC_REQUIRE(!s.Zas || splits == 1, GFCC_EINVAL, "segmm: the antisymmetric term needs no split");
   const int total = seg_slabs(a.K, a.nseg);
   T* part = nullptr;
   int nz = 1;
@@ -782,7 +830,7 @@ void segmm_candidates(const SegSpec<T>& s, std::vector<std::array<int, 3>>& out)
       if (tn > 64 && tn >= 2 * s.N) continue;
       const int64_t tiles = (int64_t)((s.M + tm - 1) / tm) * ((s.N + tn - 1) / tn) * s.batch;
       out.push_back({tm, tn, 1});
-      if (s.batch != 1) continue;
+      if (s.batch != 1 || s.Zas) continue;
       // split counts that fill one, two and four rounds of 512 workgroups, keeping at least
       // four slabs of k per split
       for (int64_t r : {1, 2, 4}) {

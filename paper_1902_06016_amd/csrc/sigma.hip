@@ -94,17 +94,19 @@ void copy_async(gfcc_ctx* ctx, T* dst, const T* src, int64_t n) {
 // The tuned route of one of the sigma's linear products: the first call in a class times the
 // unfused route (candidate 0) and every tile and split candidate of the fused segmented
 // product, each a complete computation of the same outputs, and keeps the fastest.
+// Returns true when the fused product ran (false: the unfused route).
 template <typename T>
-void tuned_route(gfcc_ctx* ctx, int64_t kind, const SegSpec<T>& fused,
+bool tuned_route(gfcc_ctx* ctx, int64_t kind, const SegSpec<T>& fused,
                  const std::function<void()>& unfused) {
   auto pin = ctx->tune_pins.find(kind);
   if (pin != ctx->tune_pins.end()) {
     const auto& c = pin->second;
-    if (c[0] == 0)
+    if (c[0] == 0) {
       unfused();
-    else
-      segmm_run<T>(ctx, fused, c[0], c[1], fused.batch == 1 ? c[2] : 1);
-    return;
+      return false;
+    }
+    segmm_run<T>(ctx, fused, c[0], c[1], fused.batch == 1 && !fused.Zas ? c[2] : 1);
+    return true;
   }
   int64_t K = 0;
   for (int q = 0; q < fused.nseg; ++q) K += fused.K[q];
@@ -151,10 +153,12 @@ void tuned_route(gfcc_ctx* ctx, int64_t kind, const SegSpec<T>& fused,
     it = ctx->tune.emplace(key, ch).first;
   }
   const TuneChoice& ch = it->second;
-  if (ch.tile_m == 0)
+  if (ch.tile_m == 0) {
     unfused();
-  else
-    segmm_run<T>(ctx, fused, ch.tile_m, ch.tile_n, ch.splits);
+    return false;
+  }
+  segmm_run<T>(ctx, fused, ch.tile_m, ch.tile_n, ch.splits);
+  return true;
 }
 
 }  // namespace
@@ -185,6 +189,14 @@ void sigma_block_f64(gfcc_ctx* ctx, int nc, const double* X, double* Y, bool tra
   double* Z = ctx->ws_b.as<double>();
   hipEvent_t e_all = nullptr, e_ovvo = nullptr;
   timer_begin(ctx, 1, &e_all);
+  // Z = Weff . r (the ovvo contraction), then the linear products; the fused 2h1p product adds
+  // antisym(Z) in its epilogue, the other routes with antisym_add_kernel
+  timer_begin(ctx, 0, &e_ovvo);
+  gemm_ovvo<double>(ctx, transpose, o, v, nc, f.Weff.as<double>(), X2, nc,
+                    op.pairlut.as<int>(), Z);
+  timer_end(ctx, 0, e_ovvo);
+  GFCC_REQUIRE(PV < (1LL << 31), GFCC_EINVAL, "sigma: too many 2h1p rows");
+  bool antisym_done = false;
   if (!transpose) {
     // [sigma_1h ; tau] = [W1 ; 0 | Vp^T] . X: sigma_1h into Y1, tau into S[o:o+v]. Unfused:
     // the whole product into S, then its 1h rows copied to Y1.
@@ -235,11 +247,20 @@ void sigma_block_f64(gfcc_ctx* ctx, int nc, const double* X, double* Y, bool tra
     g.C = Y2;
     g.ldc = (int64_t)v * nc;
     g.sC = nc;
+    g.Zas = Z;
+    g.as_o = o;
+    g.as_v = v;
+    g.as_nc = nc;
+    // both routes add antisym(Z): the fused one in its epilogue, the unfused one last
+    antisym_done = true;
     tuned_route<double>(ctx, TUNE_SIGMA_2H1P, g, [&] {
       copy_async<double>(ctx, S, X1, (int64_t)o * nc);
       gemm<double>(ctx, false, false, (int)PV, nc, o + v, 1.0, f.W4c.as<double>(), o + v, S, nc,
                    0.0, Y2, nc);
       woo_product<double>(ctx, false, P, (int64_t)v * nc, f.Woo.as<double>(), op.ldwoo, X2, Y2);
+      hipLaunchKernelGGL(antisym_add_kernel<double>, dim3((unsigned)PV), dim3(256), 0,
+                         ctx->stream, Z, o, v, nc, Y2);
+      GFCC_LAUNCH_CHECK();
     });
   } else {
     gemm<double>(ctx, true, false, (int)D, nc, o, 1.0, f.W1.as<double>(), D, X1, nc, 0.0, Y, nc);
@@ -252,14 +273,11 @@ void sigma_block_f64(gfcc_ctx* ctx, int nc, const double* X, double* Y, bool tra
                  S + (int64_t)o * nc, nc, 1.0, Y2, nc);
     woo_product<double>(ctx, true, P, (int64_t)v * nc, f.Woo.as<double>(), op.ldwoo, X2, Y2);
   }
-  timer_begin(ctx, 0, &e_ovvo);
-  gemm_ovvo<double>(ctx, transpose, o, v, nc, f.Weff.as<double>(), X2, nc,
-                    op.pairlut.as<int>(), Z);
-  timer_end(ctx, 0, e_ovvo);
-  GFCC_REQUIRE(PV < (1LL << 31), GFCC_EINVAL, "sigma: too many 2h1p rows");
-  hipLaunchKernelGGL(antisym_add_kernel<double>, dim3((unsigned)PV), dim3(256), 0,
-                     ctx->stream, Z, o, v, nc, Y2);
-  GFCC_LAUNCH_CHECK();
+  if (!antisym_done) {
+    hipLaunchKernelGGL(antisym_add_kernel<double>, dim3((unsigned)PV), dim3(256), 0,
+                       ctx->stream, Z, o, v, nc, Y2);
+    GFCC_LAUNCH_CHECK();
+  }
   timer_end(ctx, 1, e_all);
 }
 
