@@ -99,7 +99,7 @@ __host__ __device__ inline int64_t pair_of(int i, int j, int o) {
 template <typename T> struct OpPieces {
   DevBuf W1, W4c, Woo, Vp, Weff;
   DevBuf W1V;              // [W1 ; 0 | Vp^T] (FP64): sigma_1h and tau in one product
-  DevBuf W4, T2p;          // split form of W4c (mixed precision: T2p may be bf16)
+  DevBuf W4;               // the first o columns of W4c (mixed precision)
 };
 
 struct Operator {
@@ -110,8 +110,9 @@ struct Operator {
   int keep = 0;
   OpPieces<double> f64;
   OpPieces<float> f32;
-  DevBuf Vp_bf16, T2p_bf16;     // bf16 three-body operands (mixed precision): high parts
-  DevBuf Vp_bf16_lo, T2p_bf16_lo;  // and the bf16 remainders (x = hi + lo)
+  // bf16 pairs (x = hi + lo) of the three-body operands (mixed precision), padded row layout
+  // of pairs_gemm: Vp^T [v][(ij)a] and -t2 [(ij)a][d]
+  DevBuf VpT_bf16, VpT_bf16_lo, T2p_bf16, T2p_bf16_lo;
   DevBuf Weff_bf16, Weff_bf16_lo;  // Weff as bf16 pairs [o v][ldweff_bf] (pairs_split_rows)
   int64_t ldweff_bf = 0;
   DevBuf WeffT, W1T, W4cT, WooT, VpT;  // transposed copies (adjoint)
@@ -252,7 +253,8 @@ void segmm_run(gfcc_ctx* ctx, const SegSpec<T>& s, int tm, int tn, int splits);
 template <typename T>
 void segmm_candidates(const SegSpec<T>& s, std::vector<std::array<int, 3>>& out);
 
-// Times each candidate (one warm-up run, then two timed runs, on the context stream) and
+// Times each candidate (one warm-up run, then two timed runs, on the context stream; a
+// candidate whose warm-up run took more than twice the best time so far is not run again) and
 // returns the index of the fastest; us[i] receives candidate i's time in microseconds.
 // Synchronises the stream. Candidates must be complete, idempotent computations.
 int time_candidates(gfcc_ctx* ctx, const std::vector<std::function<void()>>& cands,
@@ -261,10 +263,16 @@ int time_candidates(gfcc_ctx* ctx, const std::vector<std::function<void()>>& can
 // A device buffer of at least `bytes` zero bytes, owned by the context (grown on demand).
 const void* zero_row(gfcc_ctx* ctx, size_t bytes);
 
-// bf16 x bf16 -> fp32 GEMM (three-body term of the mixed-precision sigma).
-void gemm_bf16(gfcc_ctx* ctx, bool transA, int M, int N, int K, float alpha,
-               const __hip_bfloat16* A, int64_t lda, const __hip_bfloat16* B, int64_t ldb,
-               float beta, float* C, int64_t ldc);
+// Two-term bf16 products (ovvo_bf3.hip): C[M][N] (+)= A B with A held as bf16 pairs (hi, lo)
+// in the padded row layout [pairs_pad_rows(M)][pairs_pad_k(K)] written by pairs_split_general
+// (A[r][k] = S[r rs + k cs]), and B FP32 [K][N] (row stride ldb) split into pairs on the way;
+// every block takes hi.hi + hi.lo + lo.hi with FP32 accumulation.
+int64_t pairs_pad_rows(int64_t M);
+int64_t pairs_pad_k(int64_t K);
+void pairs_split_general(gfcc_ctx* ctx, const double* S, int64_t rs, int64_t cs, int64_t M,
+                         int64_t K, void* hi, void* lo);
+void pairs_gemm(gfcc_ctx* ctx, const void* Ah, const void* Al, int M, int K, const float* B,
+                int64_t ldb, int N, float* C, int64_t ldc, bool accumulate);
 
 // ------------------------------------------------------------------- tensor utilities
 // dst[i0][i1][i2][i3] (contiguous, dims d[]) = alpha * src[i0*s0 + i1*s1 + i2*s2 + i3*s3]
@@ -274,14 +282,7 @@ void permute4(gfcc_ctx* ctx, const double* src, const int64_t d[4], const int64_
 void fill(gfcc_ctx* ctx, double* p, int64_t n, double val);
 void fill_f(gfcc_ctx* ctx, float* p, int64_t n, float val);
 void cast_f64_f32(gfcc_ctx* ctx, const double* s, float* d, int64_t n);
-void cast_f64_bf16(gfcc_ctx* ctx, const double* s, __hip_bfloat16* d, int64_t n);
 void cast_f32_f64(gfcc_ctx* ctx, const float* s, double* d, int64_t n);
-void cast_f32_bf16(gfcc_ctx* ctx, const float* s, __hip_bfloat16* d, int64_t n);
-// x = hi + lo in bf16 (hi = bf16(x), lo = bf16(x - hi)): about 16 significant bits
-// hi/lo pairs of a [rows][cols] matrix into rows of ld >= cols, zero-filled up to total
-// elements (total >= rows * ld)
-void split_pad_f64_bf16(gfcc_ctx* ctx, const double* s, int64_t rows, int64_t cols,
-                        __hip_bfloat16* hi, __hip_bfloat16* lo, int64_t ld, int64_t total);
 // ovvo contraction with two-term bf16 operands (FP32 X2 and Z; W as pairs from
 // pairs_split_rows); false when nc is not a multiple of 128 (the caller then uses the FP32
 // kernel)
@@ -294,10 +295,6 @@ int64_t pairs_ldk(int o, int v);
 int64_t pairs_rows(int o, int v);
 // those pairs from the FP64 matrix S [o v][o v]: hi and lo are [pairs_rows][pairs_ldk] bf16
 void pairs_split_rows(gfcc_ctx* ctx, const double* S, int o, int v, void* hi, void* lo);
-void split_f64_bf16(gfcc_ctx* ctx, const double* s, __hip_bfloat16* hi, __hip_bfloat16* lo,
-                    int64_t n);
-void split_f32_bf16(gfcc_ctx* ctx, const float* s, __hip_bfloat16* hi, __hip_bfloat16* lo,
-                    int64_t n);
 void transpose2d(gfcc_ctx* ctx, const double* src, int64_t rows, int64_t cols, double* dst);
 // complex128 transpose: dst[c*ldd + r] = src[r*lds + c] for r < rows, c < cols
 void ctranspose(gfcc_ctx* ctx, const void* src, int64_t rows, int64_t cols, int64_t lds,

@@ -852,15 +852,23 @@ int time_candidates(gfcc_ctx* ctx, const std::vector<std::function<void()>>& can
   GFCC_HIP(hipEventCreate(&e1));
   us.assign(cands.size(), 0.0);
   int best = 0;
-  for (size_t i = 0; i < cands.size(); ++i) {
-    cands[i]();
+  auto timed = [&](const std::function<void()>& f, int reps) {
     GFCC_HIP(hipEventRecord(e0, st));
-    for (int r = 0; r < 2; ++r) cands[i]();
+    for (int r = 0; r < reps; ++r) f();
     GFCC_HIP(hipEventRecord(e1, st));
     GFCC_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
     GFCC_HIP(hipEventElapsedTime(&ms, e0, e1));
-    us[i] = ms * 1e3 / 2;
+    return ms * 1e3 / reps;
+  };
+  for (size_t i = 0; i < cands.size(); ++i) {
+    // the first run warms up; a candidate already twice as slow as the best is not run again
+    const double warm = timed(cands[i], 1);
+    if (i > 0 && warm > 2.0 * us[best]) {
+      us[i] = warm;
+      continue;
+    }
+    us[i] = timed(cands[i], 2);
     if (us[i] < us[best]) best = (int)i;
   }
   (void)hipEventDestroy(e0);

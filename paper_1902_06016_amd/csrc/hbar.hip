@@ -263,17 +263,17 @@ namespace {
 // hipMalloc or hipFree (each of which waits for the device). Buffers not taken are freed at
 // the end of the build.
 void collect(OpPieces<double>& f, std::vector<DevBuf>& out) {
-  for (DevBuf* b : {&f.W1, &f.W4c, &f.Woo, &f.Vp, &f.Weff, &f.W1V, &f.W4, &f.T2p})
+  for (DevBuf* b : {&f.W1, &f.W4c, &f.Woo, &f.Vp, &f.Weff, &f.W1V, &f.W4})
     if (b->p) out.push_back(std::move(*b));
 }
 void collect(OpPieces<float>& f, std::vector<DevBuf>& out) {
-  for (DevBuf* b : {&f.W1, &f.W4c, &f.Woo, &f.Vp, &f.Weff, &f.W1V, &f.W4, &f.T2p})
+  for (DevBuf* b : {&f.W1, &f.W4c, &f.Woo, &f.Vp, &f.Weff, &f.W1V, &f.W4})
     if (b->p) out.push_back(std::move(*b));
 }
 void collect(Operator& op, std::vector<DevBuf>& out) {
   collect(op.f64, out);
   collect(op.f32, out);
-  for (DevBuf* b : {&op.Vp_bf16, &op.T2p_bf16, &op.Vp_bf16_lo, &op.T2p_bf16_lo, &op.Weff_bf16,
+  for (DevBuf* b : {&op.VpT_bf16, &op.T2p_bf16, &op.VpT_bf16_lo, &op.T2p_bf16_lo, &op.Weff_bf16,
                     &op.Weff_bf16_lo, &op.WeffT, &op.W1T, &op.W4cT, &op.WooT, &op.VpT, &op.diag, &op.Crows, &op.pairlut, &op.Foo, &op.Fov, &op.Fvv, &op.Woooo,
                     &op.Wooov, &op.Wovvo, &op.Wovoo})
     if (b->p) out.push_back(std::move(*b));
@@ -525,11 +525,14 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
       bb.take(op.Weff_bf16, (size_t)nwb * sizeof(__hip_bfloat16));
       bb.take(op.Weff_bf16_lo, (size_t)nwb * sizeof(__hip_bfloat16));
       pairs_split_rows(ctx, Weff, o, v, op.Weff_bf16.p, op.Weff_bf16_lo.p);
-      // bf16 three-body operands: Vp and -t2 packed as [(ij)a][d]
-      bb.take(op.Vp_bf16, (size_t)PV * V * sizeof(__hip_bfloat16));
-      bb.take(op.Vp_bf16_lo, (size_t)PV * V * sizeof(__hip_bfloat16));
-      split_f64_bf16(ctx, Vp, op.Vp_bf16.as<__hip_bfloat16>(),
-                     op.Vp_bf16_lo.as<__hip_bfloat16>(), PV * V);
+      // bf16 three-body operands in the pair GEMM's layout: Vp^T [v][(ij)a] and -t2
+      // [(ij)a][d]
+      {
+        const size_t nvt = (size_t)(pairs_pad_rows(V) * pairs_pad_k(PV));
+        bb.take(op.VpT_bf16, nvt * sizeof(__hip_bfloat16));
+        bb.take(op.VpT_bf16_lo, nvt * sizeof(__hip_bfloat16));
+        pairs_split_general(ctx, Vp, 1, V, V, PV, op.VpT_bf16.p, op.VpT_bf16_lo.p);
+      }
       WorkBuf bt(bb);
       double* t2p = BW(bt, PV * V);
       // -t2 packed rows = columns o.. of W4c
@@ -538,10 +541,12 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
         int64_t s4[4] = {0, 0, O + V, 1};
         permute4(ctx, W4c + o, d4, s4, t2p, 1.0, 0.0);
       }
-      bb.take(op.T2p_bf16, (size_t)PV * V * sizeof(__hip_bfloat16));
-      bb.take(op.T2p_bf16_lo, (size_t)PV * V * sizeof(__hip_bfloat16));
-      split_f64_bf16(ctx, t2p, op.T2p_bf16.as<__hip_bfloat16>(),
-                     op.T2p_bf16_lo.as<__hip_bfloat16>(), PV * V);
+      {
+        const size_t nt2 = (size_t)(pairs_pad_rows(PV) * pairs_pad_k(V));
+        bb.take(op.T2p_bf16, nt2 * sizeof(__hip_bfloat16));
+        bb.take(op.T2p_bf16_lo, nt2 * sizeof(__hip_bfloat16));
+        pairs_split_general(ctx, t2p, V, 1, PV, V, op.T2p_bf16.p, op.T2p_bf16_lo.p);
+      }
       // FP32 W4 = first o columns of W4c (the three-body columns go through bf16)
       {
         WorkBuf bw(bb);

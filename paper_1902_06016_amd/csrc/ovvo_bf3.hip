@@ -256,6 +256,68 @@ __global__ void pairs_expand_kernel(const float* __restrict__ X2, int64_t ldx, i
   }
 }
 
+// A plain FP32 operand B[K][N] (row stride ldb) as chunked pairs [K8][ldb8]: chunk (g, n) holds
+// k = 8g .. 8g + 7 of column n, zeros for k >= K and n >= N
+__global__ void pairs_chunk_kernel(const float* __restrict__ B, int64_t ldb, int K, int N,
+                                   int K8, int64_t ldb8, u4* __restrict__ Bh,
+                                   u4* __restrict__ Bl) {
+  const int64_t total = (int64_t)K8 * ldb8;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int g = (int)(idx / ldb8);
+    const int64_t n = idx - (int64_t)g * ldb8;
+    float x[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = 8 * g + t;
+      x[t] = (k < K && n < N) ? B[(int64_t)k * ldb + n] : 0.0f;
+    }
+    u4 h, l;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const f2 xv = {x[2 * u], x[2 * u + 1]};
+      const b2 hv = __builtin_convertvector(xv, b2);
+      const f2 hf = __builtin_convertvector(hv, f2);
+      const f2 rem = {xv[0] - hf[0], xv[1] - hf[1]};
+      h[u] = __builtin_bit_cast(unsigned, hv);
+      l[u] = __builtin_bit_cast(unsigned, __builtin_convertvector(rem, b2));
+    }
+    Bh[idx] = h;
+    Bl[idx] = l;
+  }
+}
+
+// A[r][k] = S[r rs + k cs] as bf16 pairs [Mpad][ldk] (zeros for r >= M or k >= K)
+__global__ void pairs_split_general_kernel(const double* __restrict__ S, int64_t rs, int64_t cs,
+                                           int64_t M, int64_t K, int64_t Mpad, int64_t ldk,
+                                           __hip_bfloat16* __restrict__ hi,
+                                           __hip_bfloat16* __restrict__ lo) {
+  const int64_t total = Mpad * ldk;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / ldk, k = i - r * ldk;
+    const double x = (r < M && k < K) ? S[r * rs + k * cs] : 0.0;
+    const __hip_bfloat16 h = __float2bfloat16((float)x);
+    hi[i] = h;
+    lo[i] = __float2bfloat16((float)(x - (double)__bfloat162float(h)));
+  }
+}
+
+// C[m][n] (+)= sum_z part[z][m][n]
+__global__ void pairs_reduce_kernel(const float* __restrict__ part, int nz, int M, int N,
+                                    int64_t pstride, float* __restrict__ C, int64_t ldc,
+                                    int accumulate) {
+  const int64_t total = (int64_t)M * N;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int m = (int)(i / N), n = (int)(i - (int64_t)m * N);
+    float acc = 0.0f;
+    for (int z = 0; z < nz; ++z) acc += part[z * pstride + i];
+    float* cp = C + (int64_t)m * ldc + n;
+    *cp = accumulate ? *cp + acc : acc;
+  }
+}
+
 // W[r][k'] pairs from the FP64 ovvo matrix S[r][(m, e)] (ld o v) for rows r < Mpad: k' =
 // m vp + e, zero for e >= v, m >= o or r >= M; hi = bf16(x), lo = bf16(x - hi)
 __global__ void pairs_split_rows_kernel(const double* __restrict__ S, int64_t M, int64_t Mpad,
@@ -289,12 +351,16 @@ struct Pair8Args {
   const u4* A;     // W pairs: high parts at A, remainders at A + a_lo (chunks, [Mpad][ldk8])
   int64_t a_lo;
   int64_t ldk8;
-  const u4* B;     // expanded operand: high parts at B, remainders at B + b_lo ([K8][N])
+  const u4* B;     // expanded operand: high parts at B, remainders at B + b_lo ([K8][ldb8])
   int64_t b_lo;
-  float* C;
-  int M, N, K8;
+  int64_t ldb8;    // chunk-row stride of B (a multiple of 256 columns)
+  float* C;        // C (+)= A B, row stride ldc; split z writes C + z pstride
+  int64_t ldc, pstride;
+  int M, N, K8;    // N: columns stored (B's columns past N are zero)
   int mtiles, ntiles;
-  int nc, vc;
+  int nc, vc;      // zero-segment skip of the ovvo operand (vc = 0: none)
+  int nsplit, spz; // split-K: nsplit ranges of spz slabs
+  int accumulate;  // add to C instead of storing
 };
 
 // One direct load: 16 bytes per lane from gsrc to LDS at lds_off + 16 x lane. Written as
@@ -319,15 +385,20 @@ __global__ __launch_bounds__(512, 1) void pairs_gemm8_kernel(Pair8Args p) {
   const int wm = wave >> 1, wn = wave & 1;
   constexpr int GM = 8;
   const int ntot = p.mtiles * p.ntiles;
-  const int T8 = (ntot + 7) / 8;
-  const int L = (int)(blockIdx.x & 7) * T8 + (int)(blockIdx.x >> 3);
-  if (L >= ntot) return;
+  const int nwork = ntot * p.nsplit;  // (split, tile) pairs, tile-fastest
+  const int T8 = (nwork + 7) / 8;
+  const int Lw = (int)(blockIdx.x & 7) * T8 + (int)(blockIdx.x >> 3);
+  if (Lw >= nwork) return;
+  const int z = Lw / ntot;
+  const int L = Lw - z * ntot;
   const int grp = L / (GM * p.ntiles);
   const int rows = min(GM, p.mtiles - grp * GM);
   const int idx = L - grp * GM * p.ntiles;
   const int mt = grp * GM + idx % rows, nt = idx / rows;
   const int m0 = mt * BM, n0 = nt * BN;
-  const int nslab = p.K8 / SLAB8;
+  // this workgroup's slabs: [sbeg, nslab)
+  const int sbeg = z * p.spz;
+  const int nslab = min(p.K8 / SLAB8, sbeg + p.spz);
   const int j = n0 / p.nc;
   const int zlo = (j * p.vc + SLAB8 - 1) / SLAB8, zhi = ((j + 1) * p.vc) / SLAB8;
   auto skip = [&](int s) { return (s >= zlo && s < zhi) ? zhi : s; };
@@ -340,9 +411,9 @@ __global__ __launch_bounds__(512, 1) void pairs_gemm8_kernel(Pair8Args p) {
   const int c = (lane & 7) ^ ((lane >> 3) & 7);
   const u4* sa = p.A + (c >= 4 ? p.a_lo : 0) + (int64_t)(m0 + 32 * wave + (lane >> 3)) * p.ldk8 +
                  (c & 3);
-  const u4* sb = p.B + (c >= 4 ? p.b_lo : 0) + (int64_t)(c & 3) * p.N + n0 + 32 * wave +
+  const u4* sb = p.B + (c >= 4 ? p.b_lo : 0) + (int64_t)(c & 3) * p.ldb8 + n0 + 32 * wave +
                  (lane >> 3);
-  const int64_t astep_t = 8 * p.ldk8, bstep_s = (int64_t)SLAB8 * p.N;
+  const int64_t astep_t = 8 * p.ldk8, bstep_s = (int64_t)SLAB8 * p.ldb8;
   auto issue = [&](auto BUFC, int s) {
     constexpr int b = decltype(BUFC)::value;
     u4(*As)[8] = b ? As1 : As0;
@@ -392,7 +463,7 @@ __global__ __launch_bounds__(512, 1) void pairs_gemm8_kernel(Pair8Args p) {
   // buffer of this slab takes the direct loads of the slab after next, and the third pass
   // runs while the first fragments of the next slab are read, so no pass starts on an empty
   // pipe.
-  int s = skip(0);
+  int s = skip(sbeg);
   int s1 = skip(s + 1);
   issue(IC<0>{}, s);
   __builtin_amdgcn_s_waitcnt(0);
@@ -439,7 +510,10 @@ __global__ __launch_bounds__(512, 1) void pairs_gemm8_kernel(Pair8Args p) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int row = m0 + wm * 64 + i * 16 + 4 * kq + e;
-        if (row < p.M) p.C[(int64_t)row * p.N + col] = acc[i][q][e];
+        if (row < p.M && col < p.N) {
+          float* cp = p.C + (int64_t)z * p.pstride + (int64_t)row * p.ldc + col;
+          *cp = p.accumulate ? *cp + acc[i][q][e] : acc[i][q][e];
+        }
       }
     }
 }
@@ -466,6 +540,85 @@ void pairs_split_rows(gfcc_ctx* ctx, const double* S, int o, int v, void* hi, vo
                      ctx->stream, S, M, Mpad, o, v, vp, ldk, static_cast<__hip_bfloat16*>(hi),
                      static_cast<__hip_bfloat16*>(lo));
   GFCC_LAUNCH_CHECK();
+}
+
+int64_t pairs_pad_rows(int64_t M) { return (M + 255) / 256 * 256; }
+int64_t pairs_pad_k(int64_t K) { return (K + 8 * SLAB8 - 1) / (8 * SLAB8) * (8 * SLAB8); }
+
+void pairs_split_general(gfcc_ctx* ctx, const double* S, int64_t rs, int64_t cs, int64_t M,
+                         int64_t K, void* hi, void* lo) {
+  const int64_t Mpad = pairs_pad_rows(M), ldk = pairs_pad_k(K);
+  hipLaunchKernelGGL(pairs_split_general_kernel, dim3(grid_cap(Mpad * ldk)), dim3(256), 0,
+                     ctx->stream, S, rs, cs, M, K, Mpad, ldk, static_cast<__hip_bfloat16*>(hi),
+                     static_cast<__hip_bfloat16*>(lo));
+  GFCC_LAUNCH_CHECK();
+}
+
+void pairs_gemm(gfcc_ctx* ctx, const void* Ah, const void* Al, int M, int K, const float* B,
+                int64_t ldb, int N, float* C, int64_t ldc, bool accumulate) {
+  if (M <= 0 || N <= 0) return;
+  GFCC_REQUIRE(K >= 0 && ldb >= N && ldc >= N, GFCC_EINVAL, "pairs_gemm: bad shape");
+  GFCC_REQUIRE(reinterpret_cast<uintptr_t>(Ah) % 16 == 0 && reinterpret_cast<uintptr_t>(Al) % 16 == 0,
+               GFCC_EINVAL, "pairs_gemm: operand pairs not 16-byte aligned");
+  const int64_t Mpad = pairs_pad_rows(M), ldk = pairs_pad_k(K), K8 = ldk / 8;
+  const int64_t ldb8 = ((int64_t)N + 255) / 256 * 256;
+  GFCC_REQUIRE(K8 * ldb8 < (1LL << 40) && Mpad < (1LL << 31), GFCC_EINVAL,
+               "pairs_gemm: operand too large");
+  // B as chunked pairs in the pair workspace
+  const size_t bbytes = sizeof(u4) * (size_t)(K8 * ldb8);
+  ws_ensure(ctx, ctx->ws_pairs, 2 * bbytes);
+  u4* Bh = ctx->ws_pairs.as<u4>();
+  u4* Bl = reinterpret_cast<u4*>(ctx->ws_pairs.as<char>() + bbytes);
+  hipLaunchKernelGGL(pairs_chunk_kernel, dim3(grid_cap(K8 * ldb8)), dim3(256), 0, ctx->stream,
+                     B, ldb, K, N, (int)K8, ldb8, Bh, Bl);
+  GFCC_LAUNCH_CHECK();
+  Pair8Args q{};
+  q.A = static_cast<const u4*>(Ah);
+  q.a_lo = (reinterpret_cast<intptr_t>(Al) - reinterpret_cast<intptr_t>(Ah)) / (intptr_t)sizeof(u4);
+  q.ldk8 = K8;
+  q.B = Bh;
+  q.b_lo = K8 * ldb8;
+  q.ldb8 = ldb8;
+  q.M = M;
+  q.N = N;
+  q.K8 = (int)K8;
+  q.mtiles = (int)(Mpad / 256);
+  q.ntiles = (int)(ldb8 / 256);
+  q.nc = (int)ldb8;  // one column block: no zero segment
+  q.vc = 0;
+  const int nslab = (int)(K8 / SLAB8);
+  const int64_t tiles = (int64_t)q.mtiles * q.ntiles;
+  // split-K when the tiles cannot fill the GPU's 256 CUs (one workgroup each): about 1024
+  // (split, tile) pairs, each at least 8 slabs deep
+  int nz = 1;
+  if (tiles < 512 && nslab >= 16)
+    nz = (int)std::min<int64_t>(nslab / 8, (1024 + tiles - 1) / tiles);
+  q.spz = (nslab + nz - 1) / nz;
+  nz = (nslab + q.spz - 1) / q.spz;
+  q.nsplit = nz;
+  float* part = nullptr;
+  if (nz > 1) {
+    q.pstride = (int64_t)M * N;
+    ws_ensure(ctx, ctx->ws_gemm, sizeof(float) * (size_t)q.pstride * nz);
+    part = ctx->ws_gemm.as<float>();
+    q.C = part;
+    q.ldc = N;
+    q.accumulate = 0;
+  } else {
+    q.C = C;
+    q.ldc = ldc;
+    q.accumulate = accumulate ? 1 : 0;
+  }
+  const int64_t work = tiles * nz;
+  GFCC_REQUIRE(work < (1LL << 31) - 8, GFCC_EINVAL, "pairs_gemm: too many tiles");
+  hipLaunchKernelGGL(pairs_gemm8_kernel, dim3((unsigned)((work + 7) / 8 * 8)), dim3(512), 0,
+                     ctx->stream, q);
+  GFCC_LAUNCH_CHECK();
+  if (nz > 1) {
+    hipLaunchKernelGGL(pairs_reduce_kernel, dim3(grid_cap((int64_t)M * N)), dim3(256), 0,
+                       ctx->stream, part, nz, M, N, q.pstride, C, ldc, accumulate ? 1 : 0);
+    GFCC_LAUNCH_CHECK();
+  }
 }
 
 bool ovvo_bf3(gfcc_ctx* ctx, int o, int v, int nc, const void* Wh, const void* Wl,
@@ -495,7 +648,9 @@ bool ovvo_bf3(gfcc_ctx* ctx, int o, int v, int nc, const void* Wh, const void* W
     q.ldk8 = K8;
     q.B = Bh;
     q.b_lo = K8 * N;
+    q.ldb8 = N;
     q.C = Z;
+    q.ldc = N;
     q.M = (int)OV;
     q.N = (int)N;
     q.K8 = (int)K8;
@@ -503,6 +658,8 @@ bool ovvo_bf3(gfcc_ctx* ctx, int o, int v, int nc, const void* Wh, const void* W
     q.ntiles = (int)(N / 256);
     q.nc = nc;
     q.vc = vp / 8;
+    q.nsplit = 1;
+    q.spz = (int)(K8 / SLAB8);
     const int64_t tiles = (int64_t)q.mtiles * q.ntiles;
     if (tiles >= (1LL << 31) - 8) return false;
     hipLaunchKernelGGL(pairs_gemm8_kernel, dim3((unsigned)((tiles + 7) / 8 * 8)), dim3(512), 0,

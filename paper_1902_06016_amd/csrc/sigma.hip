@@ -308,34 +308,17 @@ void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, int precis
     gemm<float>(ctx, false, false, (int)PV, nc, o + v, 1.0f, f.W4c.as<float>(), o + v, S, nc,
                 0.0f, Y2, nc);
   } else {
-    // three-body term on bf16 matrix cores: tau = Vp^T X2, Y2 = W4 X1 + (-t2) tau. Both
-    // operands of each product are held as hi + lo bf16 pairs and the product is formed as
-    // hi.hi + hi.lo + lo.hi with FP32 accumulation (the lo.lo term is below the FP32 sum's
-    // rounding), so the term carries about 16 significant bits instead of bf16's 8, which
-    // keeps the refinement's contraction per cycle at the FP32 path's level
-    const size_t xb = sizeof(__hip_bfloat16) * (size_t)PV * nc;
-    const size_t tb = sizeof(__hip_bfloat16) * (size_t)v * nc;
-    ws_ensure(ctx, ctx->ws_c, 2 * xb);
-    ws_ensure(ctx, ctx->ws_d, sizeof(float) * (size_t)v * nc + 2 * tb);
-    __hip_bfloat16* Xh = ctx->ws_c.as<__hip_bfloat16>();
-    __hip_bfloat16* Xl = reinterpret_cast<__hip_bfloat16*>(ctx->ws_c.as<char>() + xb);
-    float* tau = reinterpret_cast<float*>(ctx->ws_d.as<char>());
-    __hip_bfloat16* th =
-        reinterpret_cast<__hip_bfloat16*>(ctx->ws_d.as<char>() + sizeof(float) * (size_t)v * nc);
-    __hip_bfloat16* tl = reinterpret_cast<__hip_bfloat16*>(reinterpret_cast<char*>(th) + tb);
-    const __hip_bfloat16* Vh = op.Vp_bf16.as<__hip_bfloat16>();
-    const __hip_bfloat16* Vl = op.Vp_bf16_lo.as<__hip_bfloat16>();
-    const __hip_bfloat16* Th = op.T2p_bf16.as<__hip_bfloat16>();
-    const __hip_bfloat16* Tl = op.T2p_bf16_lo.as<__hip_bfloat16>();
-    split_f32_bf16(ctx, X2, Xh, Xl, PV * nc);
-    gemm_bf16(ctx, true, v, nc, (int)PV, 1.0f, Vh, v, Xh, nc, 0.0f, tau, nc);
-    gemm_bf16(ctx, true, v, nc, (int)PV, 1.0f, Vh, v, Xl, nc, 1.0f, tau, nc);
-    gemm_bf16(ctx, true, v, nc, (int)PV, 1.0f, Vl, v, Xh, nc, 1.0f, tau, nc);
-    split_f32_bf16(ctx, tau, th, tl, (int64_t)v * nc);
+    // three-body term on bf16 matrix cores: tau = Vp^T X2, then Y2 = W4 X1 + (-t2) tau. Both
+    // operands of each product are held as hi + lo bf16 pairs (the operator's split once at
+    // build time, the vector's on the way into the product) and every block is formed as
+    // hi.hi + hi.lo + lo.hi with FP32 accumulation, one launch per product (the lo.lo term is
+    // below the FP32 sum's rounding), so the term carries about 16 significant bits instead of
+    // bf16's 8, which keeps the refinement's contraction per cycle at the FP32 path's level
+    ws_ensure(ctx, ctx->ws_d, sizeof(float) * (size_t)v * nc);
+    float* tau = ctx->ws_d.as<float>();
+    pairs_gemm(ctx, op.VpT_bf16.p, op.VpT_bf16_lo.p, v, (int)PV, X2, nc, nc, tau, nc, false);
     gemm<float>(ctx, false, false, (int)PV, nc, o, 1.0f, f.W4.as<float>(), o, X1, nc, 0.0f, Y2, nc);
-    gemm_bf16(ctx, false, (int)PV, nc, v, 1.0f, Th, v, th, nc, 1.0f, Y2, nc);
-    gemm_bf16(ctx, false, (int)PV, nc, v, 1.0f, Th, v, tl, nc, 1.0f, Y2, nc);
-    gemm_bf16(ctx, false, (int)PV, nc, v, 1.0f, Tl, v, th, nc, 1.0f, Y2, nc);
+    pairs_gemm(ctx, op.T2p_bf16.p, op.T2p_bf16_lo.p, (int)PV, v, tau, nc, nc, Y2, nc, true);
   }
   woo_product<float>(ctx, false, P, (int64_t)v * nc, f.Woo.as<float>(), op.ldwoo, X2, Y2);
   timer_begin(ctx, 0, &e_ovvo);

@@ -49,52 +49,6 @@ __global__ void cast_f32_f64_kernel(const float* __restrict__ s, double* __restr
     d[i] = (double)s[i];
 }
 
-__global__ void cast_f32_bf16_kernel(const float* __restrict__ s, __hip_bfloat16* __restrict__ d,
-                                     int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    d[i] = __float2bfloat16(s[i]);
-}
-
-// x = hi + lo with hi = bf16(x) and lo = bf16(x - hi): a two-term bf16 representation with
-// about 16 significant bits
-__global__ void split_f64_bf16_kernel(const double* __restrict__ s, __hip_bfloat16* __restrict__ hi,
-                                      __hip_bfloat16* __restrict__ lo, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const double x = s[i];
-    const __hip_bfloat16 h = __float2bfloat16((float)x);
-    hi[i] = h;
-    lo[i] = __float2bfloat16((float)(x - (double)__bfloat162float(h)));
-  }
-}
-
-__global__ void split_pad_f64_bf16_kernel(const double* __restrict__ s, int64_t rows,
-                                          int64_t cols, __hip_bfloat16* __restrict__ hi,
-                                          __hip_bfloat16* __restrict__ lo, int64_t ld,
-                                          int64_t total) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / ld, c = i - r * ld;
-    double x = 0.0;
-    if (r < rows && c < cols) x = s[r * cols + c];
-    const __hip_bfloat16 h = __float2bfloat16((float)x);
-    hi[i] = h;
-    lo[i] = __float2bfloat16((float)(x - (double)__bfloat162float(h)));
-  }
-}
-
-__global__ void split_f32_bf16_kernel(const float* __restrict__ s, __hip_bfloat16* __restrict__ hi,
-                                      __hip_bfloat16* __restrict__ lo, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const float x = s[i];
-    const __hip_bfloat16 h = __float2bfloat16(x);
-    hi[i] = h;
-    lo[i] = __float2bfloat16(x - __bfloat162float(h));
-  }
-}
-
 __global__ void transpose_kernel(const double* __restrict__ src, int64_t rows, int64_t cols,
                                  double* __restrict__ dst) {
   __shared__ double tile[32][33];
@@ -186,46 +140,9 @@ void cast_f64_f32(gfcc_ctx* ctx, const double* s, float* d, int64_t n) {
   GFCC_LAUNCH_CHECK();
 }
 
-void cast_f64_bf16(gfcc_ctx* ctx, const double* s, __hip_bfloat16* d, int64_t n) {
-  if (n == 0) return;
-  hipLaunchKernelGGL(cast_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, ctx->stream, s, d, n);
-  GFCC_LAUNCH_CHECK();
-}
-
 void cast_f32_f64(gfcc_ctx* ctx, const float* s, double* d, int64_t n) {
   if (n == 0) return;
   hipLaunchKernelGGL(cast_f32_f64_kernel, dim3(grid_for(n)), dim3(256), 0, ctx->stream, s, d, n);
-  GFCC_LAUNCH_CHECK();
-}
-
-void cast_f32_bf16(gfcc_ctx* ctx, const float* s, __hip_bfloat16* d, int64_t n) {
-  if (n == 0) return;
-  hipLaunchKernelGGL(cast_f32_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, ctx->stream, s, d, n);
-  GFCC_LAUNCH_CHECK();
-}
-
-void split_f64_bf16(gfcc_ctx* ctx, const double* s, __hip_bfloat16* hi, __hip_bfloat16* lo,
-                    int64_t n) {
-  if (n == 0) return;
-  hipLaunchKernelGGL(split_f64_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, ctx->stream, s, hi,
-                     lo, n);
-  GFCC_LAUNCH_CHECK();
-}
-
-void split_pad_f64_bf16(gfcc_ctx* ctx, const double* s, int64_t rows, int64_t cols,
-                        __hip_bfloat16* hi, __hip_bfloat16* lo, int64_t ld, int64_t total) {
-  GFCC_REQUIRE(ld >= cols && total >= rows * ld, GFCC_EINVAL, "split_pad: bad layout");
-  if (total == 0) return;
-  hipLaunchKernelGGL(split_pad_f64_bf16_kernel, dim3(grid_for(total)), dim3(256), 0, ctx->stream,
-                     s, rows, cols, hi, lo, ld, total);
-  GFCC_LAUNCH_CHECK();
-}
-
-void split_f32_bf16(gfcc_ctx* ctx, const float* s, __hip_bfloat16* hi, __hip_bfloat16* lo,
-                    int64_t n) {
-  if (n == 0) return;
-  hipLaunchKernelGGL(split_f32_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, ctx->stream, s, hi,
-                     lo, n);
   GFCC_LAUNCH_CHECK();
 }
 
