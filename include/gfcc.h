@@ -174,6 +174,17 @@ gfcc_status gfcc_autotune_entry(const gfcc_ctx* ctx, int index, int64_t* desc, d
 gfcc_status gfcc_autotune_pin(gfcc_ctx* ctx, int kind, int tile_m, int tile_n, int splits);
 
 /*
+ * gfcc_graphs -- capture the Arnoldi steps of small GMRES blocks (those whose convergence flags
+ * are read one step late: sigma work per step below about 0.3 ms) as HIP graphs (1, the
+ * default) or launch them kernel by kernel (0). The first time a step shape is met on ctx it
+ * runs eagerly, the second time it is captured, after that its graph is launched; graphs are
+ * kept by the context and dropped whenever a workspace grows, the operator is rebuilt or the
+ * tuner changes. No capture while a gfcc_timer records. Results are bitwise identical either
+ * way. EINVAL for another value of enable.
+ */
+gfcc_status gfcc_graphs(gfcc_ctx* ctx, int enable);
+
+/*
  * gfcc_solve -- solve Eq. xplin at every (omega_w, p_k) and form G (Eq. gfcclineqn).
  *
  * omega [nw] (host), p [np] (host; occupied orbitals 0 <= p < o, distinct), eta >= 0 (the

@@ -127,6 +127,9 @@ gfcc_status gfcc_destroy(gfcc_ctx* ctx) {
       (void)hipEventDestroy(pr.second);
     }
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  for (auto& kv : ctx->step_graphs) (void)hipGraphExecDestroy(kv.second);
+  if (ctx->hflags) (void)hipHostFree(ctx->hflags);
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   delete ctx;
   return GFCC_OK;
 }
@@ -190,6 +193,14 @@ gfcc_status gfcc_autotune(gfcc_ctx* ctx, int enable) {
   ctx->tune_mode = enable;
   ctx->tune.clear();
   ctx->tune_pins.clear();
+  gfcc::drop_step_graphs(ctx);
+  return GFCC_OK;
+}
+
+gfcc_status gfcc_graphs(gfcc_ctx* ctx, int enable) {
+  if (!ctx || enable < 0 || enable > 1) return GFCC_EINVAL;
+  ctx->graphs = enable != 0;
+  gfcc::drop_step_graphs(ctx);
   return GFCC_OK;
 }
 
@@ -201,6 +212,7 @@ gfcc_status gfcc_autotune_pin(gfcc_ctx* ctx, int kind, int tile_m, int tile_n, i
                    (tile_n != 64 && tile_n != 128) || splits < 1))
     return GFCC_EINVAL;
   ctx->tune_pins[kind] = {tile_m, tile_n, unfused ? 0 : splits};
+  gfcc::drop_step_graphs(ctx);
   return GFCC_OK;
 }
 

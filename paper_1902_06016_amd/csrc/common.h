@@ -168,16 +168,41 @@ struct gfcc_ctx {
   // choices pinned by gfcc_autotune_pin, by kind: {tile rows, tile columns, splits}
   std::map<int64_t, std::array<int, 3>> tune_pins;
   std::vector<hipEvent_t> event_pool;
+  // Captured Arnoldi steps of small GMRES blocks (solve.hip), keyed by the step's shape; they
+  // bake in kernel arguments (workspace and operator addresses, tuner choices), so every
+  // workspace growth, operator build and tuner change bumps the generation and drops them.
+  uint64_t generation = 0;
+  bool graphs = true;
+  hipStream_t capture_stream = nullptr;  // the steps are captured here, launched on `stream`
+  // host-visible convergence flags of the GMRES blocks (pinned, mapped; hflags_n words per slot)
+  int* hflags = nullptr;
+  int* dflags = nullptr;
+  int hflags_n = 0;
+  std::map<std::array<int64_t, 8>, hipGraphExec_t> step_graphs;
+  std::map<std::array<int64_t, 8>, int> step_seen;
 };
 
 namespace gfcc {
 
 // Grow a context-owned scratch buffer. Work already queued on the context stream may still
 // read the old allocation, so the stream is drained before it is released.
+// Drops the captured Arnoldi steps (their baked-in addresses or choices may be stale), after
+// the stream has run every launch of them.
+inline void drop_step_graphs(gfcc_ctx* ctx) {
+  ++ctx->generation;
+  if (!ctx->step_graphs.empty()) {
+    GFCC_HIP(hipStreamSynchronize(ctx->stream));
+    for (auto& kv : ctx->step_graphs) (void)hipGraphExecDestroy(kv.second);
+    ctx->step_graphs.clear();
+  }
+  ctx->step_seen.clear();
+}
+
 inline void ws_ensure(gfcc_ctx* ctx, DevBuf& b, size_t n) {
   if (n <= b.bytes) return;
   GFCC_HIP(hipStreamSynchronize(ctx->stream));
   b.alloc(n);
+  drop_step_graphs(ctx);
 }
 
 // ------------------------------------------------------------------------------ GEMM

@@ -317,6 +317,7 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
                     const double* ovvv, int keep) {
   Operator& op = ctx->op;
   op.built = false;
+  drop_step_graphs(ctx);
   BuildBuffers bb;
   bb.avail = std::move(ctx->build_pool);
   ctx->build_pool.clear();

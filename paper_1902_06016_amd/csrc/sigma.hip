@@ -301,8 +301,7 @@ void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, int precis
   timer_begin(ctx, 1, &e_all);
   gemm<float>(ctx, false, false, o, nc, (int)D, 1.0f, f.W1.as<float>(), D, X, nc, 0.0f, Y1, nc);
   if (precision != GFCC_FP32_BF16_3BODY) {
-    GFCC_HIP(hipMemcpyAsync(S, X1, sizeof(float) * (size_t)o * nc, hipMemcpyDeviceToDevice,
-                            ctx->stream));
+    copy_async<float>(ctx, S, X1, (int64_t)o * nc);
     gemm<float>(ctx, true, false, v, nc, (int)PV, 1.0f, f.Vp.as<float>(), v, X2, nc, 0.0f,
                 S + (int64_t)o * nc, nc);
     gemm<float>(ctx, false, false, (int)PV, nc, o + v, 1.0f, f.W4c.as<float>(), o + v, S, nc,

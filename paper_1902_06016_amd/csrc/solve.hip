@@ -1075,18 +1075,17 @@ struct GmresBlock {
   float *Uf = nullptr, *Sf = nullptr;
   BlockState s;
   int nblk_rows = 1, nbrows_y = 1;
-  // convergence flags written by arnoldi_finish_kernel straight into host-visible memory (one
-  // word per 64 RHS, two slots by step parity), for the one-step-late check of small blocks
+  // convergence flags written by the finishing kernels straight into host-visible memory (one
+  // word per 64 RHS, two slots by step parity; owned by the context, so that captured steps
+  // stay valid from solve to solve)
   int* hflags = nullptr;
   int* dflags = nullptr;  // the same memory as the kernel sees it
-  int hflags_nb = 0;
   hipEvent_t flag_ev[2] = {nullptr, nullptr};
 
   GmresBlock() = default;
   GmresBlock(const GmresBlock&) = delete;
   GmresBlock& operator=(const GmresBlock&) = delete;
   ~GmresBlock() {
-    if (hflags) (void)hipHostFree(hflags);
     for (hipEvent_t e : flag_ev)
       if (e) (void)hipEventDestroy(e);
   }
@@ -1168,15 +1167,19 @@ struct GmresBlock {
       Uf = ctx->ws_solve_f32.as<float>();
       Sf = Uf + vec * 2;
     }
-    if (nb > hflags_nb) {
-      if (hflags) GFCC_HIP(hipHostFree(hflags));
-      hflags = nullptr;
-      hflags_nb = 0;
-      GFCC_HIP(hipHostMalloc(reinterpret_cast<void**>(&hflags), sizeof(int) * 2 * (size_t)nb,
+    if (nb > ctx->hflags_n) {
+      drop_step_graphs(ctx);
+      if (ctx->hflags) GFCC_HIP(hipHostFree(ctx->hflags));
+      ctx->hflags = nullptr;
+      ctx->dflags = nullptr;
+      ctx->hflags_n = 0;
+      GFCC_HIP(hipHostMalloc(reinterpret_cast<void**>(&ctx->hflags), sizeof(int) * 2 * (size_t)nb,
                              hipHostMallocMapped | hipHostMallocCoherent));
-      GFCC_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&dflags), hflags, 0));
-      hflags_nb = nb;
+      GFCC_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&ctx->dflags), ctx->hflags, 0));
+      ctx->hflags_n = nb;
     }
+    hflags = ctx->hflags;
+    dflags = ctx->dflags;
     for (hipEvent_t& e : flag_ev)
       if (!e) GFCC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
@@ -1407,9 +1410,88 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
                            gb.vsc, D, nb, gb.part_h);
         GFCC_LAUNCH_CHECK();
       };
-      for (int k = 0; k < m; ++k) {
+      // one step of a small block (flags read one step late): the operator product, pass A,
+      // the reduction, the finishing kernel and pass B
+      auto late_step = [&](int k) {
         int* fslot = gb.dflags + (size_t)(k & 1) * gb.nbrows_y;
-        if (!late && k > 0) {
+        if (k == 0 && unit_start) {
+          unit_sigma(ctx, gb.prow, gb.z, nb, gb.W);
+        } else {
+          gb.apply_M(gb.U, gb.W, false, false);
+        }
+        hipLaunchKernelGGL(Dcgs::dots[k], rgrid, dim3(CW), 0, st, gb.V, D * nb, gb.W, gb.U, gb.z,
+                           D, nb, gb.part_h);
+        GFCC_LAUNCH_CHECK();
+        gb.dcgs_reduce(k + 1, k >= 1 ? k + 1 : 0, k >= 2 ? k : 0, k - 1);
+        finish(k, 0, fslot);
+        hipLaunchKernelGGL(Dcgs::update[k], ugrid, dim3(256), 0, st, gb.V, D * nb, gb.W, gb.U,
+                           gb.z, ctx->op.diag.as<double>(), gb.scb, gb.tcb, gb.qsc, gb.vsc, D,
+                           nb, gb.part_h);
+        GFCC_LAUNCH_CHECK();
+      };
+      // The same step as a HIP graph, one per step shape, kept by the context: the first
+      // sighting of a shape runs eagerly (it tunes products and sizes workspaces), the second
+      // captures and launches, later ones launch. Not while a timer records launches (its
+      // host-side bookkeeping runs per call).
+      bool timing = false;
+      for (const auto& t : ctx->timers) timing |= t.enabled;
+      auto run_late_step = [&](int k) {
+        if (!ctx->graphs || timing) {
+          late_step(k);
+          return;
+        }
+        const std::array<int64_t, 8> key{(int64_t)ctx->generation, nb, m, k,
+                                         (k == 0 && unit_start) ? 1 : 0, gb.precision,
+                                         gb.transpose ? 1 : 0, maxit};
+        auto it = ctx->step_graphs.find(key);
+        if (it != ctx->step_graphs.end()) {
+          GFCC_HIP(hipGraphLaunch(it->second, st));
+          return;
+        }
+        if (ctx->step_seen[key]++ == 0) {
+          late_step(k);
+          return;
+        }
+        // captured on a stream of the context's own (the library's stream may be the null
+        // stream, on which capture is not permitted), launched on the library's stream
+        if (!ctx->capture_stream)
+          GFCC_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+        const hipStream_t home = st;
+        hipGraph_t g = nullptr;
+        GFCC_HIP(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+        ctx->stream = st = ctx->capture_stream;
+        try {
+          late_step(k);
+        } catch (...) {
+          ctx->stream = st = home;
+          if (hipStreamEndCapture(ctx->capture_stream, &g) == hipSuccess && g)
+            (void)hipGraphDestroy(g);
+          throw;
+        }
+        ctx->stream = st = home;
+        GFCC_HIP(hipStreamEndCapture(ctx->capture_stream, &g));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        GFCC_HIP(e);
+        ctx->step_graphs[key] = ex;
+        GFCC_HIP(hipGraphLaunch(ex, st));
+      };
+      for (int k = 0; k < m; ++k) {
+        if (late) {
+          // step k is queued before the flags of step k - 1 are read; when step k - 1 has
+          // stopped every RHS (its columns reach k - 2), step k met only inactive ones
+          run_late_step(k);
+          GFCC_HIP(hipEventRecord(gb.flag_ev[k & 1], st));
+          if (k > 0 && !any_active(k - 1)) {
+            ksteps = k - 1;
+            stopped = true;
+            break;
+          }
+          continue;
+        }
+        int* fslot = gb.dflags + (size_t)(k & 1) * gb.nbrows_y;
+        if (k > 0) {
           // large blocks: column k - 1 is finalised before the operator product of step k,
           // so a block whose right-hand sides have all stopped ends the cycle with one sweep
           // over the basis instead of another product
@@ -1431,27 +1513,12 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
         hipLaunchKernelGGL(Dcgs::dots[k], rgrid, dim3(CW), 0, st, gb.V, D * nb, gb.W, gb.U, gb.z,
                            D, nb, gb.part_h);
         GFCC_LAUNCH_CHECK();
-        if (late) {
-          gb.dcgs_reduce(k + 1, k >= 1 ? k + 1 : 0, k >= 2 ? k : 0, k - 1);
-          finish(k, 0, fslot);
-        } else {
-          gb.dcgs_reduce(k + 1, 0, 0, 0);
-          finish(k, k == 0 ? 0 : 2, nullptr);
-        }
+        gb.dcgs_reduce(k + 1, 0, 0, 0);
+        finish(k, k == 0 ? 0 : 2, nullptr);
         hipLaunchKernelGGL(Dcgs::update[k], ugrid, dim3(256), 0, st, gb.V, D * nb, gb.W, gb.U,
                            gb.z, ctx->op.diag.as<double>(), gb.scb, gb.tcb, gb.qsc, gb.vsc, D,
                            nb, gb.part_h);
         GFCC_LAUNCH_CHECK();
-        if (late) {
-          // step k is queued before the flags of step k - 1 are read; when step k - 1 has
-          // stopped every RHS (its columns reach k - 2), step k met only inactive ones
-          GFCC_HIP(hipEventRecord(gb.flag_ev[k & 1], st));
-          if (k > 0 && !any_active(k - 1)) {
-            ksteps = k - 1;
-            stopped = true;
-            break;
-          }
-        }
       }
       if (!stopped) {  // the end of the cycle: column m - 1 and basis vector m
         gb.dcgs_reduce(0, m + 1, m >= 2 ? m : 0, m - 1);

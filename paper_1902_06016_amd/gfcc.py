@@ -55,6 +55,7 @@ def _load():
         "gfcc_autotune": (i32, [vp, i32]),
         "gfcc_autotune_entry": (i32, [vp, i32, vp, vp]),
         "gfcc_autotune_pin": (i32, [vp, i32, i32, i32, i32]),
+        "gfcc_graphs": (i32, [vp, i32]),
         "gfcc_grad_eps": (i32, [vp, i32, vp, i32, vp, vp, vp]),
         "mor_build": (i32, [vp, i32, vp, i32, vp, dbl, dbl, dbl, P(vp)]),
         "mor_build_diag": (i32, [vp, i32, vp, i32, vp, dbl, dbl, dbl, vp]),
@@ -79,7 +80,7 @@ def _load():
 lib = _load()
 SYMBOLS = ("gfcc_dim", "gfcc_create", "gfcc_destroy", "gfcc_last_error", "build_hbar_operands",
            "build_hbar_first_order", "sigma_apply", "gfcc_autotune", "gfcc_autotune_entry",
-           "gfcc_autotune_pin",
+           "gfcc_autotune_pin", "gfcc_graphs",
            "gfcc_solve", "gfcc_solve_x0", "gfcc_solve_diis", "gfcc_grad_eps", "mor_build",
            "mor_build_diag", "mor_refine", "mor_eval", "mor_eval_noalloc", "mor_lift",
            "mor_info", "mor_destroy", "spectral_function", "spectral_weight", "gfcc_export",
@@ -285,6 +286,10 @@ class Context:
     def autotune(self, enable=True):
         """enable: False/0 off, True/1 timed, 2 the most split variant of every class untimed."""
         self._check(lib.gfcc_autotune(self.h, int(enable)))
+
+    def graphs(self, enable: bool = True):
+        """Capture the Arnoldi steps of small blocks as HIP graphs (gfcc_graphs)."""
+        self._check(lib.gfcc_graphs(self.h, int(enable)))
 
     def autotune_pin(self, kind: int, tile_m: int, tile_n: int, splits: int = 1):
         """Fix the choice of one of the sigma's fused product kinds (20/21); tile (0, 0) = the
