@@ -173,13 +173,14 @@ struct gfcc_ctx {
   // workspace growth, operator build and tuner change bumps the generation and drops them.
   uint64_t generation = 0;
   bool graphs = true;
+  std::vector<const void*> op_addresses;  // of the operator the captured steps were made for
   hipStream_t capture_stream = nullptr;  // the steps are captured here, launched on `stream`
   // host-visible convergence flags of the GMRES blocks (pinned, mapped; hflags_n words per slot)
   int* hflags = nullptr;
   int* dflags = nullptr;
   int hflags_n = 0;
-  std::map<std::array<int64_t, 8>, hipGraphExec_t> step_graphs;
-  std::map<std::array<int64_t, 8>, int> step_seen;
+  std::map<std::array<int64_t, 10>, hipGraphExec_t> step_graphs;
+  std::map<std::array<int64_t, 10>, int> step_seen;
 };
 
 namespace gfcc {

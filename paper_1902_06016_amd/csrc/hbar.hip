@@ -279,6 +279,20 @@ void collect(Operator& op, std::vector<DevBuf>& out) {
     if (b->p) out.push_back(std::move(*b));
 }
 
+// The device addresses of every operator piece, in a fixed order: captured solver steps bake
+// them in, so they stay valid across a rebuild that hands back the same addresses.
+std::vector<const void*> operator_addresses(const Operator& op) {
+  std::vector<const void*> a;
+  for (const DevBuf* b : {&op.f64.W1, &op.f64.W4c, &op.f64.Woo, &op.f64.Vp, &op.f64.Weff,
+                          &op.f64.W1V, &op.f64.W4, &op.f32.W1, &op.f32.W4c, &op.f32.Woo,
+                          &op.f32.Vp, &op.f32.Weff, &op.f32.W1V, &op.f32.W4, &op.VpT_bf16,
+                          &op.T2p_bf16, &op.VpT_bf16_lo, &op.T2p_bf16_lo, &op.Weff_bf16,
+                          &op.Weff_bf16_lo, &op.WeffT, &op.W1T, &op.W4cT, &op.WooT, &op.VpT,
+                          &op.diag, &op.Crows, &op.pairlut})
+    a.push_back(b->p);
+  return a;
+}
+
 struct BuildBuffers {
   std::vector<DevBuf> avail;       // reusable buffers (freed when the build ends)
   std::vector<DevBuf>* keep_pool;  // receives the current operator build's work arrays
@@ -317,7 +331,6 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
                     const double* ovvv, int keep) {
   Operator& op = ctx->op;
   op.built = false;
-  drop_step_graphs(ctx);
   BuildBuffers bb;
   bb.avail = std::move(ctx->build_pool);
   ctx->build_pool.clear();
@@ -561,6 +574,13 @@ void build_operator(gfcc_ctx* ctx, int o, int v, const double* eps, const double
   }
   GFCC_HIP(hipStreamSynchronize(st));
   op.built = true;
+  // captured solver steps survive a rebuild only where every operator piece kept its address
+  // (and its shape: the step shapes carry o and v through D)
+  std::vector<const void*> addr = operator_addresses(op);
+  if (addr != ctx->op_addresses) {
+    drop_step_graphs(ctx);
+    ctx->op_addresses = std::move(addr);
+  }
   size_t pooled = 0;
   for (const DevBuf& b : ctx->build_pool) pooled += b.bytes;
   if (pooled > BUILD_POOL_MAX) ctx->build_pool.clear();

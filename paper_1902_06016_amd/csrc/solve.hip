@@ -1440,9 +1440,9 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
           late_step(k);
           return;
         }
-        const std::array<int64_t, 8> key{(int64_t)ctx->generation, nb, m, k,
-                                         (k == 0 && unit_start) ? 1 : 0, gb.precision,
-                                         gb.transpose ? 1 : 0, maxit};
+        const std::array<int64_t, 10> key{(int64_t)ctx->generation, ctx->op.o, ctx->op.v, nb, m,
+                                          k, (k == 0 && unit_start) ? 1 : 0, gb.precision,
+                                          gb.transpose ? 1 : 0, maxit};
         auto it = ctx->step_graphs.find(key);
         if (it != ctx->step_graphs.end()) {
           GFCC_HIP(hipGraphLaunch(it->second, st));

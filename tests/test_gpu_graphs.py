@@ -45,6 +45,16 @@ def test_replayed_steps_match_eager_steps(gpu_ctx, transpose):
         # another maxit is another step shape (its stopping test differs)
         r = gpu_ctx.gfcc_solve(om, ps, 0.01, maxit=400, **kw)
         assert np.array_equal(r.G.cpu().numpy(), G0)
+        # a rebuild of the same shape from other inputs keeps the operator's addresses, so the
+        # captured steps stay in use; they must read the new operator
+        prob2 = synth.make_problem(o, v, 3)
+        gpu_ctx.build_from_problem(prob2, keep=keep)
+        r2 = [gpu_ctx.gfcc_solve(om, ps, 0.01, **kw).G.cpu().numpy() for _ in range(2)]
+        gpu_ctx.graphs(False)
+        e2 = gpu_ctx.gfcc_solve(om, ps, 0.01, **kw).G.cpu().numpy()
+        assert not np.array_equal(e2, G0)
+        assert np.array_equal(r2[0], e2) and np.array_equal(r2[1], e2)
+        gpu_ctx.build_from_problem(prob, keep=keep)
     finally:
         gpu_ctx.graphs(True)
     if transpose:
