@@ -142,11 +142,15 @@ gfcc_status sigma_apply(gfcc_ctx* ctx, int nrhs, const void* x, void* y, int tra
  * products ([W1 ; 0 | Vp^T] . x, and the 2h1p products W4c . [x_1h ; tau] + (Woo (x) I_v) .
  * x_2h1p summed in one pass as a product batched over the virtual index) are timed as their
  * unfused route and as a segmented product on every candidate tile (32, 64 or 128 rows by 64
- * or 128 columns) and split count. Off: the generic kernel with its heuristic split count for
- * the first kind, the plain pipelined kernel for the second, the unfused route for the sigma's
- * products. enable = 2 skips the timing and takes the most split candidate of every class
- * (the fused segmented product for the sigma's), so that tests reach the split-K and fused
- * paths. Results agree to rounding in every mode. EINVAL for another value of enable.
+ * or 128 columns) and split count. Small row-major products (fewer than 64 tiles of 128 x 128
+ * and K >= 128, chiefly the operator build's at small shapes; a transposed B is transposed
+ * first) are timed, into a scratch output, as their route above and as a segmented product on
+ * every candidate tile and split count. Off: the generic kernel with its heuristic split count
+ * for the first kind, the plain pipelined kernel for the second, the unfused route for the
+ * sigma's products, the route above for small products. enable = 2 skips the timing and takes
+ * the most split candidate of every class (the fused segmented product for the sigma's and the
+ * small products), so that tests reach the split-K and segmented paths. Results agree to
+ * rounding in every mode. EINVAL for another value of enable.
  */
 gfcc_status gfcc_autotune(gfcc_ctx* ctx, int enable);
 
@@ -154,12 +158,14 @@ gfcc_status gfcc_autotune(gfcc_ctx* ctx, int enable);
  * gfcc_autotune_entry -- the tuner's choice number `index` (0-based, ordered by class):
  * desc[8] (host) receives {element bytes, kind, M, N, K, splits, tile rows, tile columns}.
  * kind: 0 or 1 a plain product (transA); 20 the sigma's [W1 ; 0 | Vp^T] . x; 21 the sigma's
- * linear 2h1p products. M, N, K: the shape it was measured on (for kind 21 the fused
+ * linear 2h1p products; 22 a small product. M, N, K: the shape it was measured on (for kind 21 the fused
  * product's: M = P pairs, N = columns, K = o + v + P, batched over the v virtual orbitals). splits: 0 for the generic kernel and,
  * for plain products of 256 tiles or more, 1 for the plain pipelined kernel. The tile is 0 x 0
- * for a plain product and for a sigma product that runs unfused. us[2] (host, may be NULL):
+ * for a plain product, for a sigma product that runs unfused and for a small product that
+ * keeps its route. us[2] (host, may be NULL):
  * the measured time of the choice and of the reference variant (the generic kernel, the plain
- * pipelined kernel for products of 256 tiles or more, the unfused route of a sigma product) in
+ * pipelined kernel for products of 256 tiles or more, the unfused route of a sigma product,
+ * the route of a small product when it is not segmented) in
  * microseconds. EINVAL past the last entry.
  */
 gfcc_status gfcc_autotune_entry(const gfcc_ctx* ctx, int index, int64_t* desc, double* us);
@@ -183,6 +189,17 @@ gfcc_status gfcc_autotune_pin(gfcc_ctx* ctx, int kind, int tile_m, int tile_n, i
  * way. EINVAL for another value of enable.
  */
 gfcc_status gfcc_graphs(gfcc_ctx* ctx, int enable);
+
+/*
+ * gfcc_compact -- restart compaction of GMRES blocks (1, the default) or none (0). At an FP64
+ * restart where the right-hand sides that go on fill at most half the block's columns (counted
+ * in groups of 64), they go on in a block of only their columns, whose work arrays take part
+ * of the Krylov basis of the block they came from; its cycles start from their iterates with
+ * the explicit FP64 residual, as the restart would. Results agree with the uncompacted solve
+ * to rounding (the products of a narrower block may sum in another order); iteration counts
+ * and residuals are reported per right-hand side as before. EINVAL for another value.
+ */
+gfcc_status gfcc_compact(gfcc_ctx* ctx, int enable);
 
 /*
  * gfcc_solve -- solve Eq. xplin at every (omega_w, p_k) and form G (Eq. gfcclineqn).

@@ -204,6 +204,12 @@ gfcc_status gfcc_graphs(gfcc_ctx* ctx, int enable) {
   return GFCC_OK;
 }
 
+gfcc_status gfcc_compact(gfcc_ctx* ctx, int enable) {
+  if (!ctx || enable < 0 || enable > 1) return GFCC_EINVAL;
+  ctx->compact = enable != 0;
+  return GFCC_OK;
+}
+
 gfcc_status gfcc_autotune_pin(gfcc_ctx* ctx, int kind, int tile_m, int tile_n, int splits) {
   if (!ctx) return GFCC_EINVAL;
   if (kind != gfcc::TUNE_SIGMA_1H && kind != gfcc::TUNE_SIGMA_2H1P) return GFCC_EINVAL;

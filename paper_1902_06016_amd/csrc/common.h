@@ -137,6 +137,7 @@ struct TuneChoice {
 };
 constexpr int64_t TUNE_SIGMA_1H = 20;      // sigma's [W1 ; Vp^T] . X: fused (tile) or unfused
 constexpr int64_t TUNE_SIGMA_2H1P = 21;    // sigma's linear 2h1p products: fused or unfused
+constexpr int64_t TUNE_SMALL = 22;         // small products: segmented tile and split, or generic
 using TuneKey = std::array<int64_t, 6>;
 
 struct TimerSlot {
@@ -173,6 +174,7 @@ struct gfcc_ctx {
   // workspace growth, operator build and tuner change bumps the generation and drops them.
   uint64_t generation = 0;
   bool graphs = true;
+  bool compact = true;  // GMRES restarts continue the active right-hand sides in a compacted block
   std::vector<const void*> op_addresses;  // of the operator the captured steps were made for
   hipStream_t capture_stream = nullptr;  // the steps are captured here, launched on `stream`
   // host-visible convergence flags of the GMRES blocks (pinned, mapped; hflags_n words per slot)
@@ -279,8 +281,9 @@ void segmm_run(gfcc_ctx* ctx, const SegSpec<T>& s, int tm, int tn, int splits);
 template <typename T>
 void segmm_candidates(const SegSpec<T>& s, std::vector<std::array<int, 3>>& out);
 
-// Times each candidate (one warm-up run, then two timed runs, on the context stream; a
-// candidate whose warm-up run took more than twice the best time so far is not run again) and
+// Times each candidate (an untimed run, a timed warm-up run, then two timed runs, on the context
+// stream; a candidate whose warm-up run took more than twice the best time so far is not run
+// again) and
 // returns the index of the fastest; us[i] receives candidate i's time in microseconds.
 // Synchronises the stream. Candidates must be complete, idempotent computations.
 int time_candidates(gfcc_ctx* ctx, const std::vector<std::function<void()>>& cands,

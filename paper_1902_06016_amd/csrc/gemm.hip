@@ -439,20 +439,124 @@ const TuneChoice& tune_choice(gfcc_ctx* ctx, bool transA, int M, int N, int K, c
 
 }  // namespace
 
+// Products whose 128 x 128 tiles number under 64 while K is at least 128 (the small build
+// products: one to four workgroups on the 128 x 128 kernels, each walking all of K)
+inline bool small_product(int M, int N, int K) {
+  const int64_t tiles = (int64_t)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  return tiles < 64 && K >= 128;
+}
+
+template <typename T>
+void gemm_route(gfcc_ctx* ctx, bool transA, bool transB, int M, int N, int K, T alpha,
+                const T* A, int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc,
+                int batch, int64_t sA, int64_t sB, int64_t sC);
+
+// A small row-major product (see small_product): the first call in a class times the generic
+// route and every tile and split candidate of the segmented kernel, all into a scratch output
+// with beta = 0 (so that a product that accumulates into C is not run more than once on it),
+// and keeps the fastest; class = element bytes, TUNE_SMALL, the counts of 32-row and 64-column
+// tiles, floor(log2 K).
+template <typename T>
+void gemm_small(gfcc_ctx* ctx, int M, int N, int K, T alpha, const T* A, int64_t lda,
+                const T* B, int64_t ldb, T beta, T* C, int64_t ldc) {
+  SegSpec<T> s;
+  s.M = M;
+  s.N = N;
+  s.K[0] = K;
+  s.A[0] = A;
+  s.lda[0] = lda;
+  s.B[0] = B;
+  s.ldb[0] = ldb;
+  s.C = C;
+  s.ldc = ldc;
+  s.alpha = alpha;
+  s.beta = beta;
+  int64_t kb = 0;
+  while ((int64_t(1) << (kb + 1)) <= K) ++kb;
+  const TuneKey key{(int64_t)sizeof(T), TUNE_SMALL, (M + 31) / 32, (N + 63) / 64, kb, 0};
+  auto it = ctx->tune.find(key);
+  if (it == ctx->tune.end()) {
+    std::vector<std::array<int, 3>> cand;
+    segmm_candidates(s, cand);
+    TuneChoice ch;
+    ch.M = M;
+    ch.N = N;
+    ch.K = K;
+    int pick = 0;  // 0: generic route, i > 0: cand[i - 1]
+    if (ctx->tune_mode == 2) {
+      pick = 1;  // untimed: the segmented product on its most split candidate
+      for (size_t i = 1; i < cand.size(); ++i)
+        if (cand[i][2] > cand[pick - 1][2]) pick = (int)i + 1;
+    } else if (ctx->tune_mode == 1) {
+      DevBuf scratch;
+      scratch.alloc(sizeof(T) * (size_t)M * N);
+      SegSpec<T> t = s;
+      t.C = scratch.as<T>();
+      t.ldc = N;
+      t.beta = T(0);
+      std::vector<std::function<void()>> fns{[&] {
+        gemm_route<T>(ctx, false, false, M, N, K, alpha, A, lda, B, ldb, T(0), t.C, N, 1, 0, 0,
+                      0);
+      }};
+      for (const auto& c : cand)
+        fns.push_back([&, c] { segmm_run<T>(ctx, t, c[0], c[1], c[2]); });
+      std::vector<double> us;
+      pick = time_candidates(ctx, fns, us);
+      ch.best_us = us[pick];
+      ch.generic_us = us[0];
+      if (std::getenv("GFCC_TUNE_LOG")) {
+        for (size_t i = 0; i < fns.size(); ++i)
+          std::fprintf(stderr, "[gfcc autotune] small M=%d N=%d K=%d %s %dx%d splits=%d: %.1f us\n",
+                       M, N, K, i == 0 ? "generic" : "tile", i ? cand[i - 1][0] : 0,
+                       i ? cand[i - 1][1] : 0, i ? cand[i - 1][2] : 0, us[i]);
+      }
+    }
+    if (pick > 0) {
+      ch.tile_m = cand[pick - 1][0];
+      ch.tile_n = cand[pick - 1][1];
+      ch.splits = cand[pick - 1][2];
+    }
+    it = ctx->tune.emplace(key, ch).first;
+  }
+  const TuneChoice& ch = it->second;
+  if (ch.tile_m == 0) {
+    gemm_route<T>(ctx, false, false, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 1, 0, 0, 0);
+    return;
+  }
+  segmm_run<T>(ctx, s, ch.tile_m, ch.tile_n, ch.splits);
+}
+
 template <typename T>
 void gemm(gfcc_ctx* ctx, bool transA, bool transB, int M, int N, int K, T alpha, const T* A,
           int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc, int batch,
           int64_t sA, int64_t sB, int64_t sC) {
-  // a large transposed B ([N][K], contiguous; the operator build's l2 t2^T and oovv tau^T) is
-  // transposed once into the context's transpose workspace so that the product takes the
-  // row-major paths below (stream order protects the workspace until the product has read it)
-  if (transB && batch == 1 && sizeof(T) == 8 && ldb == K && (int64_t)K * N >= (1 << 20) &&
+  // a large transposed B ([N][K], contiguous; the operator build's l2 t2^T and oovv tau^T), or
+  // that of a small product, is transposed once into the context's transpose workspace so that
+  // the product takes the row-major paths below (stream order protects the workspace until the
+  // product has read it)
+  if (transB && batch == 1 && sizeof(T) == 8 && ldb == K &&
+      ((int64_t)K * N >= (1 << 20) || (!transA && M > 0 && N > 0 && small_product(M, N, K))) &&
       N < 65536 * 32) {
     ws_ensure(ctx, ctx->ws_trans, sizeof(T) * (size_t)K * N);
     transpose2d(ctx, reinterpret_cast<const double*>(B), N, K, ctx->ws_trans.as<double>());
     gemm<T>(ctx, transA, false, M, N, K, alpha, A, lda, ctx->ws_trans.as<T>(), N, beta, C, ldc);
     return;
   }
+  if (!transA && !transB && batch == 1 && M > 0 && N > 0 && small_product(M, N, K) &&
+      ctx->tune_mode != 0) {
+    gemm_small<T>(ctx, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    return;
+  }
+  gemm_route<T>(ctx, transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, batch, sA, sB,
+                sC);
+}
+
+// the routes of a product that is not small (or whose small-product tuning chose the generic
+// route)
+template <typename T>
+void gemm_route(gfcc_ctx* ctx, bool transA, bool transB, int M, int N, int K, T alpha,
+                const T* A, int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc,
+                int batch, int64_t sA, int64_t sB, int64_t sC) {
   // mid-size products with a long K: plain pipelined kernel or split-K, as tuned
   if (!transB && batch == 1 && M > 0 && N > 0 && tunable_mid(M, N, K, sizeof(T))) {
     const TuneChoice& ch = tune_choice<T>(ctx, transA, M, N, K, A, lda, B, ldb, true);
@@ -862,7 +966,10 @@ int time_candidates(gfcc_ctx* ctx, const std::vector<std::function<void()>>& can
     return ms * 1e3 / reps;
   };
   for (size_t i = 0; i < cands.size(); ++i) {
-    // the first run warms up; a candidate already twice as slow as the best is not run again
+    // an untimed first run takes any workspace growth (an allocation would otherwise count
+    // against the candidate); a candidate whose next run is already twice as slow as the best
+    // is not run again
+    cands[i]();
     const double warm = timed(cands[i], 1);
     if (i > 0 && warm > 2.0 * us[best]) {
       us[i] = warm;

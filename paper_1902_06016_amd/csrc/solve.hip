@@ -210,25 +210,58 @@ static_assert(FJ == 32, "the launch tables cover NJ = 1 .. 32");
 constexpr int PB = FJ + 1;       // first partial row of pass B (pass A uses rows 0 .. j)
 constexpr int PSTR = PB + FJ + 2;  // partial rows per block
 
+// The four wavefronts of a sweep workgroup take every fourth row of its range; their partial
+// sums are added in LDS, in a fixed order, C rows at a time (buf holds 4 C rows of CW values),
+// and the workgroup writes one partial row per sum: dst[c][r] for c < NA. Every thread of the
+// workgroup calls this (it holds barriers); lanes past nb carry zero sums and store nothing.
+template <int NA, int C>
+__device__ __forceinline__ void combine_partials(const double2 (&acc)[NA], double2 (*buf)[CW],
+                                                 double2* __restrict__ dst, int64_t NB, int nb) {
+  const int lane = threadIdx.x & (CW - 1), wave = threadIdx.x / CW;
+  const int r0 = blockIdx.y * CW;
+#pragma unroll
+  for (int c0 = 0; c0 < NA; c0 += C) {
+    __syncthreads();  // the buffer's previous contents have been read
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      if (c0 + c < NA) buf[wave * C + c][lane] = acc[c0 + c];
+    __syncthreads();
+    for (int e = threadIdx.x; e < C * CW; e += 256) {
+      const int c = e / CW, l = e % CW;
+      if (c0 + c >= NA || r0 + l >= nb) continue;
+      double2 t = buf[c][l];
+#pragma unroll
+      for (int q = 1; q < 4; ++q) {
+        t.x += buf[q * C + c][l].x;
+        t.y += buf[q * C + c][l].y;
+      }
+      dst[(int64_t)(c0 + c) * NB + r0 + l] = t;
+    }
+  }
+}
+
 // pass A: partial[blk][jj][r] = sum_d conj(Q_jj[d][r]) w[d][r] (jj < NJ) and row NJ with
-// vt = V_NJ, w = W + z U
+// vt = V_NJ, w = W + z U; one workgroup of four wavefronts per block of rows
 template <int NJ>
-__global__ __launch_bounds__(CW) void dcgs_dots_kernel(const double2* __restrict__ V,
-                                                       int64_t vstride,
-                                                       const double2* __restrict__ Wv,
-                                                       const double2* __restrict__ U,
-                                                       const double2* __restrict__ z, int64_t D,
-                                                       int nb, double2* __restrict__ partial) {
-  const int r = blockIdx.y * CW + threadIdx.x;
-  if (r >= nb) return;
-  const double2 zz = z[r];
+__global__ __launch_bounds__(256) void dcgs_dots_kernel(const double2* __restrict__ V,
+                                                        int64_t vstride,
+                                                        const double2* __restrict__ Wv,
+                                                        const double2* __restrict__ U,
+                                                        const double2* __restrict__ z, int64_t D,
+                                                        int nb, double2* __restrict__ partial) {
+  constexpr int C = 8;
+  __shared__ double2 buf[4 * C][CW];
+  const int lane = threadIdx.x & (CW - 1), wave = threadIdx.x / CW;
+  const int r = blockIdx.y * CW + lane;
+  const bool live = r < nb;
+  const double2 zz = live ? z[r] : make_double2(0.0, 0.0);
   double2 acc[NJ + 1];
 #pragma unroll
   for (int jj = 0; jj <= NJ; ++jj) acc[jj] = make_double2(0.0, 0.0);
   const int64_t rows_per_blk = (D + gridDim.x - 1) / gridDim.x;
   const int64_t d0 = (int64_t)blockIdx.x * rows_per_blk;
-  const int64_t d1 = min(D, d0 + rows_per_blk);
-  for (int64_t d = d0; d < d1; ++d) {
+  const int64_t d1 = live ? min(D, d0 + rows_per_blk) : d0;
+  for (int64_t d = d0 + wave; d < d1; d += 4) {
     const int64_t idx = d * nb + r;
     double2 vj[NJ + 1];
 #pragma unroll
@@ -244,8 +277,7 @@ __global__ __launch_bounds__(CW) void dcgs_dots_kernel(const double2* __restrict
       acc[jj].y += q.y;
     }
   }
-#pragma unroll
-  for (int jj = 0; jj <= NJ; ++jj) partial[((int64_t)blockIdx.x * PSTR + jj) * nb + r] = acc[jj];
+  combine_partials<NJ + 1, C>(acc, buf, partial + (int64_t)blockIdx.x * PSTR * nb, nb, nb);
 }
 
 // pass B over Q_0 .. Q_{NJ-1} and the pending vector in slot NJ:
@@ -255,7 +287,8 @@ __global__ __launch_bounds__(CW) void dcgs_dots_kernel(const double2* __restrict
 //   PB + NJ + 1 = |vn|^2
 // s, t: [NJ][nb] (t row NJ holds g). FINAL (end of a cycle) only writes q. Four wavefronts
 // share the coefficients of their 64 RHS in LDS (registers hold the basis rows and the dots)
-// and take every fourth row of the workgroup's range; each writes its own partial row.
+// and take every fourth row of the workgroup's range; the workgroup writes one partial row per
+// sum (combine_partials).
 template <int NJ, bool FINAL>
 __global__ __launch_bounds__(256) void dcgs_update_kernel(
     double2* __restrict__ V, int64_t vstride, const double2* __restrict__ Wv,
@@ -264,8 +297,14 @@ __global__ __launch_bounds__(256) void dcgs_update_kernel(
     const double* __restrict__ qscale, const double* __restrict__ vscale, int64_t D, int nb,
     double2* __restrict__ partial) {
   constexpr int NS = NJ > 0 ? NJ : 1;
-  __shared__ double2 s_l[NS][CW];
-  __shared__ double2 t_l[FINAL ? 1 : NS][CW];
+  // the coefficients s (rows 0 .. NS-1) and t (rows NS ..) of the workgroup's 64 RHS; after the
+  // sweep the same buffer adds the four wavefronts' partial sums, C rows at a time
+  constexpr int NL = FINAL ? NS : 2 * NS;
+  constexpr int NBUF = NL > 16 ? NL : 16;
+  constexpr int C = NBUF / 4;
+  __shared__ double2 buf[NBUF][CW];
+  double2 (*s_l)[CW] = buf;
+  double2 (*t_l)[CW] = buf + NS;
   const int lane = threadIdx.x & (CW - 1), wave = threadIdx.x / CW;
   const int r = blockIdx.y * CW + lane;
   const int64_t NB = nb;
@@ -276,18 +315,19 @@ __global__ __launch_bounds__(256) void dcgs_update_kernel(
     if (!FINAL) t_l[jj][l] = rr < nb ? tc[jj * NB + rr] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  if (r >= nb) return;
-  const double2 gq = FINAL ? make_double2(0.0, 0.0) : tc[(int64_t)NJ * NB + r];
-  const double qs = qscale[r];
-  const double vs = FINAL ? 0.0 : vscale[r];
-  const double2 zz = z[r];
+  const bool live = r < nb;
+  if (FINAL && !live) return;  // the final sweep has no barrier after this point
+  const double2 gq = (FINAL || !live) ? make_double2(0.0, 0.0) : tc[(int64_t)NJ * NB + r];
+  const double qs = live ? qscale[r] : 0.0;
+  const double vs = (FINAL || !live) ? 0.0 : vscale[r];
+  const double2 zz = live ? z[r] : make_double2(0.0, 0.0);
   constexpr int NA = FINAL ? 1 : NJ + 2;
   double2 acc[NA];
 #pragma unroll
   for (int jj = 0; jj < NA; ++jj) acc[jj] = make_double2(0.0, 0.0);
   const int64_t rows_per_blk = (D + gridDim.x - 1) / gridDim.x;
   const int64_t d0 = (int64_t)blockIdx.x * rows_per_blk;
-  const int64_t d1 = min(D, d0 + rows_per_blk);
+  const int64_t d1 = live ? min(D, d0 + rows_per_blk) : d0;
   for (int64_t d = d0 + wave; d < d1; d += 4) {
     const int64_t idx = d * nb + r;
     // an opaque zero keeps the coefficient reads inside the loop (hoisted, they would take
@@ -347,9 +387,7 @@ __global__ __launch_bounds__(256) void dcgs_update_kernel(
     }
   }
   if (FINAL) return;
-  const int64_t blk = (int64_t)blockIdx.x * 4 + wave;
-#pragma unroll
-  for (int jj = 0; jj < NA; ++jj) partial[(blk * PSTR + PB + jj) * NB + r] = acc[jj];
+  combine_partials<NA, C>(acc, buf, partial + ((int64_t)blockIdx.x * PSTR + PB) * NB, NB, nb);
 }
 
 // The step's reduction, grid (ceil(nb/64), nA + nB + nH), 256 threads:
@@ -1006,6 +1044,31 @@ __global__ void rhs_kernel(const int* __restrict__ prow, const double* __restric
   }
 }
 
+// Column compaction of a block ([D][ns] -> [D][nd]): dst[d][j] = src[d][map[j]] (zero where
+// map[j] < 0), and back: dst[d][map[j]] = src[d][j] where map[j] >= 0
+__global__ void pick_cols_kernel(const double2* __restrict__ src, int ns,
+                                 const int* __restrict__ map, int nd, int64_t D,
+                                 double2* __restrict__ dst) {
+  const int64_t n = D * nd;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t d = i / nd;
+    const int c = map[i % nd];
+    dst[i] = c >= 0 ? src[d * ns + c] : make_double2(0.0, 0.0);
+  }
+}
+__global__ void put_cols_kernel(const double2* __restrict__ src, int nd,
+                                const int* __restrict__ map, int ns, int64_t D,
+                                double2* __restrict__ dst) {
+  const int64_t n = D * nd;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t d = i / nd;
+    const int c = map[i % nd];
+    if (c >= 0) dst[d * ns + c] = src[i];
+  }
+}
+
 // Gq[k][r] = sum_d Crows[q_k][d] X[d][r]  computed by gemm; here the transpose variant:
 // Gq[k][r] = X[q_k][r]
 __global__ void gather_rows_kernel(const double2* __restrict__ X, const int* __restrict__ q, int nq,
@@ -1090,19 +1153,16 @@ struct GmresBlock {
       if (e) (void)hipEventDestroy(e);
   }
 
-  void setup(gfcc_ctx* c, int nb_, int m_, int prec, bool tr) {
-    ctx = c;
-    D = ctx->op.D;
-    nb = nb_;
-    m = m_;
-    precision = prec;
-    transpose = tr;
+  // a multiple of 4: the delayed-reorthogonalisation sweeps run row_blocks / 4 workgroups of
+  // four wavefronts, one partial row per workgroup and sum
+  static int row_blocks(int64_t D, int nb) {
+    const int n = (int)std::min<int64_t>(1024, std::max<int64_t>(1, D * nb / 4096));
+    return (n + 3) / 4 * 4;
+  }
+  // bytes of the work arrays of a block (each array 256-byte aligned)
+  static int64_t bytes_for(int64_t D, int nb, int m) {
     const int64_t vec = D * nb;
-    // a multiple of 4: the delayed-reorthogonalisation update runs nblk_rows / 4 workgroups
-    // of four wavefronts, one partial row per wavefront
-    nblk_rows = (int)std::min<int64_t>(1024, std::max<int64_t>(1, vec / 4096));
-    nblk_rows = (nblk_rows + 3) / 4 * 4;
-    nbrows_y = (nb + CW - 1) / CW;
+    const int nblk = row_blocks(D, nb);
     int64_t bytes = 0;
     auto add = [&](int64_t n, int64_t sz) { bytes += ((n * sz + 255) / 256) * 256; };
     add(vec * (m + 1), 16);                                   // V
@@ -1112,8 +1172,8 @@ struct GmresBlock {
     add((int64_t)(m + 1) * nb, 16);                           // Cc
     add(nb, 16);                                              // z
     add(nb, 8);                                               // nrm
-    add((int64_t)nblk_rows * nb, 8);                          // part_n
-    add((int64_t)nblk_rows * PSTR * nb, 16);                  // part_h
+    add((int64_t)nblk * nb, 8);                               // part_n
+    add((int64_t)nblk * PSTR * nb, 16);                       // part_h
     add((int64_t)PSTR * nb, 16); add((int64_t)(FJ + 1) * nb, 16);    // red hsb
     add((int64_t)(FJ + 1) * nb, 16); add((int64_t)(FJ + 2) * nb, 16);  // scb tcb
     add(nb, 8); add(nb, 8);                                   // qsc vsc
@@ -1125,8 +1185,28 @@ struct GmresBlock {
     add((int64_t)nb * (m + 1), 16);                           // g
     for (int i = 0; i < 4; ++i) add(nb, 4);
     for (int i = 0; i < 3; ++i) add(nb, 8);
-    ws_ensure(ctx, ctx->ws_solve, (size_t)bytes);
-    char* cur = ctx->ws_solve.as<char>();
+    return bytes;
+  }
+
+  // Work arrays carved from the context's solver workspace (base null), or from base, which
+  // must hold bytes_for(D, nb_, m_) bytes: a compacted block of the right-hand sides a restart
+  // leaves active lives in the Krylov basis of the block it came from.
+  void setup(gfcc_ctx* c, int nb_, int m_, int prec, bool tr, char* base = nullptr) {
+    ctx = c;
+    D = ctx->op.D;
+    nb = nb_;
+    m = m_;
+    precision = prec;
+    transpose = tr;
+    const int64_t vec = D * nb;
+    nblk_rows = row_blocks(D, nb);
+    nbrows_y = (nb + CW - 1) / CW;
+    const int64_t bytes = bytes_for(D, nb, m);
+    if (!base) {
+      ws_ensure(ctx, ctx->ws_solve, (size_t)bytes);
+      base = ctx->ws_solve.as<char>();
+    }
+    char* cur = base;
     V = carve<double2>(cur, vec * (m + 1));
     W = carve<double2>(cur, vec);
     U = carve<double2>(cur, vec);
@@ -1241,7 +1321,7 @@ struct GmresBlock {
   // Hbar s over the previous step's nh_s coefficients
   void dcgs_reduce(int nA, int nB, int nH, int nh_s) {
     hipLaunchKernelGGL(dcgs_reduce_kernel, dim3(nbrows_y, nA + nB + nH), dim3(256), 0, st(),
-                       part_h, nblk_rows, nA, nB, nh_s, nb, m, s.Hraw, scb, red, hsb);
+                       part_h, nblk_rows / 4, nA, nB, nh_s, nb, m, s.Hraw, scb, red, hsb);
     GFCC_LAUNCH_CHECK();
   }
   void reduce_norms(double* out) {
@@ -1255,19 +1335,24 @@ struct GmresBlock {
 // gb.X holds the solutions (D-major block).
 // X0: optional initial guesses [nrhs][D] (device); the first cycle then starts from the
 // explicit residual b - M X0.
+// Solves the right-hand sides r0 .. r0 + nb - 1 (or, with cols, the right-hand sides cols[r]
+// of columns r, -1 for padding) of the block. X0: start iterates [nrhs][D]; x_ready: the
+// block's X already holds them (a compacted block). its0: iterations already done per column.
 static void solve_block(GmresBlock& gb, const double* omega, const int* pset, int np, int nrhs,
                         int r0, double eta, double tol, int maxit, std::vector<int>& its_out,
                         std::vector<double>& res_out, std::vector<int>& brk_out,
-                        const double2* X0) {
+                        const double2* X0, const int* cols = nullptr, const int* its0 = nullptr,
+                        bool x_ready = false) {
   gfcc_ctx* ctx = gb.ctx;
   const int nb = gb.nb, m = gb.m;
   const int64_t D = gb.D;
   hipStream_t st = ctx->stream;
+  auto gidx = [&](int r) { return cols ? cols[r] : (r0 + r < nrhs ? r0 + r : -1); };
   std::vector<double2> hz(nb);
   std::vector<int> hp(nb);
   for (int r = 0; r < nb; ++r) {
-    int gr = r0 + r;
-    if (gr < nrhs) {
+    const int gr = gidx(r);
+    if (gr >= 0) {
       hz[r] = make_double2(omega[gr / np], -eta);
       hp[r] = pset[gr % np];
     } else {
@@ -1281,19 +1366,23 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
   std::vector<double> bnorm(nb), rn(nb);
   gb.norms(gb.B, gb.nrm);
   GFCC_HIP(hipMemcpyAsync(bnorm.data(), gb.nrm, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
-  fill(ctx, reinterpret_cast<double*>(gb.X), D * nb * 2, 0.0);
-  if (X0) {
-    const int cnt = std::min(nb, nrhs - r0);
-    ctranspose(ctx, X0 + (int64_t)r0 * D, cnt, D, D, gb.X, nb);
+  if (!x_ready) {
+    fill(ctx, reinterpret_cast<double*>(gb.X), D * nb * 2, 0.0);
+    if (X0) {
+      const int cnt = std::min(nb, nrhs - r0);
+      ctranspose(ctx, X0 + (int64_t)r0 * D, cnt, D, D, gb.X, nb);
+    }
   }
   std::vector<int> zeros(nb, 0);
   GFCC_HIP(hipMemcpyAsync(gb.s.brk, zeros.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
   GFCC_HIP(hipStreamSynchronize(st));
 
   std::vector<int> its(nb, 0), act(nb), brk(nb, 0);
+  if (its0) std::copy(its0, its0 + nb, its.begin());
   std::vector<double> thr(nb), inv0(nb), rel(nb, 0.0);
   std::vector<double2> g0((size_t)nb * (m + 1));
-  bool first = X0 == nullptr;
+  bool first = X0 == nullptr && !x_ready;
+  bool handed = false;  // the active right-hand sides went on in a compacted block
   const bool mixed = gb.precision != GFCC_FP64;
   // small blocks (sigma work of a step below about 0.3 ms at 70 TF/s: 4 (ov)^2 o flops per
   // complex right-hand side in the ovvo product) read the convergence flags one step late
@@ -1334,7 +1423,7 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
       // stops; if another cycle is needed, every other one restarts from the explicit FP64
       // residual of its iterate (one sigma product per extra cycle; none when one cycle
       // suffices, as far from the poles).
-      bool more = false;
+      int more = 0;
       for (int r = 0; r < nb; ++r) {
         if (fin[r]) continue;
         const double rl = bnorm[r] > 0 ? rn[r] / bnorm[r] : 0.0;
@@ -1342,8 +1431,39 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
           fin[r] = 1;
           rel[r] = rl;
         } else {
-          more = true;
+          ++more;
         }
+      }
+      // When at most half the block's columns (in 64-column groups) go on, they go on in a
+      // compacted block carved from this block's Krylov basis: the next cycles sweep and
+      // multiply only their columns. The compacted block starts from their iterates with the
+      // explicit residual, as the restart here would.
+      const int nb2 = std::max(CW, (more + CW - 1) / CW * CW);
+      if (more && ctx->compact && 2 * nb2 <= nb &&
+          GmresBlock::bytes_for(D, nb2, m) <= D * nb * (int64_t)(m + 1) * 16) {
+        std::vector<int> cols2(nb2, -1), its2(nb2, 0), map(nb2, -1);
+        int j = 0;
+        for (int r = 0; r < nb; ++r) {
+          if (fin[r]) continue;
+          cols2[j] = gidx(r);
+          its2[j] = its[r];
+          map[j] = r;
+          ++j;
+        }
+        GmresBlock gb2;
+        gb2.setup(ctx, nb2, m, gb.precision, gb.transpose, reinterpret_cast<char*>(gb.V));
+        GFCC_HIP(hipMemcpyAsync(gb.used, map.data(), sizeof(int) * nb2, hipMemcpyHostToDevice,
+                                st));
+        hipLaunchKernelGGL(pick_cols_kernel, dim3(gridn(D * nb2)), dim3(256), 0, st, gb.X, nb,
+                           gb.used, nb2, D, gb2.X);
+        GFCC_LAUNCH_CHECK();
+        solve_block(gb2, omega, pset, np, nrhs, r0, eta, tol, maxit, its_out, res_out, brk_out,
+                    nullptr, cols2.data(), its2.data(), true);
+        hipLaunchKernelGGL(put_cols_kernel, dim3(gridn(D * nb2)), dim3(256), 0, st, gb2.X, nb2,
+                           gb.used, nb, D, gb.X);
+        GFCC_LAUNCH_CHECK();
+        handed = true;
+        break;
       }
       if (more) {
         explicit_residual();
@@ -1419,7 +1539,7 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
         } else {
           gb.apply_M(gb.U, gb.W, false, false);
         }
-        hipLaunchKernelGGL(Dcgs::dots[k], rgrid, dim3(CW), 0, st, gb.V, D * nb, gb.W, gb.U, gb.z,
+        hipLaunchKernelGGL(Dcgs::dots[k], ugrid, dim3(256), 0, st, gb.V, D * nb, gb.W, gb.U, gb.z,
                            D, nb, gb.part_h);
         GFCC_LAUNCH_CHECK();
         gb.dcgs_reduce(k + 1, k >= 1 ? k + 1 : 0, k >= 2 ? k : 0, k - 1);
@@ -1510,7 +1630,7 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
         } else {
           gb.apply_M(gb.U, gb.W, false, false);
         }
-        hipLaunchKernelGGL(Dcgs::dots[k], rgrid, dim3(CW), 0, st, gb.V, D * nb, gb.W, gb.U, gb.z,
+        hipLaunchKernelGGL(Dcgs::dots[k], ugrid, dim3(256), 0, st, gb.V, D * nb, gb.W, gb.U, gb.z,
                            D, nb, gb.part_h);
         GFCC_LAUNCH_CHECK();
         gb.dcgs_reduce(k + 1, 0, 0, 0);
@@ -1623,8 +1743,8 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
     GFCC_HIP(hipStreamSynchronize(st));
   }
   for (int r = 0; r < nb; ++r) {
-    int gr = r0 + r;
-    if (gr >= nrhs) continue;
+    const int gr = gidx(r);
+    if (gr < 0 || (handed && !fin[r])) continue;  // padding, or finished in the compacted block
     its_out[gr] = its[r];
     res_out[gr] = rel[r];
     brk_out[gr] = brk[r];

@@ -56,6 +56,7 @@ def _load():
         "gfcc_autotune_entry": (i32, [vp, i32, vp, vp]),
         "gfcc_autotune_pin": (i32, [vp, i32, i32, i32, i32]),
         "gfcc_graphs": (i32, [vp, i32]),
+        "gfcc_compact": (i32, [vp, i32]),
         "gfcc_grad_eps": (i32, [vp, i32, vp, i32, vp, vp, vp]),
         "mor_build": (i32, [vp, i32, vp, i32, vp, dbl, dbl, dbl, P(vp)]),
         "mor_build_diag": (i32, [vp, i32, vp, i32, vp, dbl, dbl, dbl, vp]),
@@ -80,7 +81,7 @@ def _load():
 lib = _load()
 SYMBOLS = ("gfcc_dim", "gfcc_create", "gfcc_destroy", "gfcc_last_error", "build_hbar_operands",
            "build_hbar_first_order", "sigma_apply", "gfcc_autotune", "gfcc_autotune_entry",
-           "gfcc_autotune_pin", "gfcc_graphs",
+           "gfcc_autotune_pin", "gfcc_graphs", "gfcc_compact",
            "gfcc_solve", "gfcc_solve_x0", "gfcc_solve_diis", "gfcc_grad_eps", "mor_build",
            "mor_build_diag", "mor_refine", "mor_eval", "mor_eval_noalloc", "mor_lift",
            "mor_info", "mor_destroy", "spectral_function", "spectral_weight", "gfcc_export",
@@ -290,6 +291,11 @@ class Context:
     def graphs(self, enable: bool = True):
         """Capture the Arnoldi steps of small blocks as HIP graphs (gfcc_graphs)."""
         self._check(lib.gfcc_graphs(self.h, int(enable)))
+
+    def compact(self, enable: bool = True):
+        """Continue the right-hand sides a GMRES restart leaves active in a compacted block
+        (gfcc_compact)."""
+        self._check(lib.gfcc_compact(self.h, int(enable)))
 
     def autotune_pin(self, kind: int, tile_m: int, tile_n: int, splits: int = 1):
         """Fix the choice of one of the sigma's fused product kinds (20/21); tile (0, 0) = the

@@ -40,8 +40,8 @@ def test_sigma_with_and_without_the_tuner(gpu_ctx, transpose):
                     assert e["K"] * 8 >= 4096 and e["tile"] == (0, 0)
                     assert e["splits"] == 0 or e["us"] <= e["generic_us"]
                 else:
-                    # a sigma product: the unfused route or a fused tile no slower than it
-                    assert e["kind"] in (20, 21)
+                    # a sigma or small product: its route or a segmented tile no slower than it
+                    assert e["kind"] in (20, 21, 22)
                     assert e["tile"] == (0, 0) or e["us"] <= e["generic_us"]
             if not transpose:
                 assert any(e["kind"] == 20 and e["M"] == o + v and e["K"] == D for e in ents)
@@ -50,6 +50,44 @@ def test_sigma_with_and_without_the_tuner(gpu_ctx, transpose):
     assert np.abs(ys[0] - ys[1]).max() <= 1e-13 * scale
     # a fresh tuning may pick another variant; both agree to rounding
     assert np.abs(ys[0] - ys[2]).max() <= 1e-13 * scale
+    gpu_ctx.autotune(True)
+
+
+def test_small_build_products_in_every_tuner_mode(gpu_ctx):
+    """o=10, v=20: every build product has fewer than 64 tiles of 128 x 128 (K6 is 200^3,
+    Woooo 100 x 100 x 400 with a transposed B), so the small-product route is tuned between the
+    plain routes and the segmented kernel's tiles and split counts. The blocks and the sigma
+    match the oracle with the tuner off, untimed at the most split candidates (mode 2) and
+    timed; the table names the small products."""
+    print("[autotune small build modes]", flush=True)
+    o, v = 10, 20
+    prob = synth.make_problem(o, v, 5)
+    prob.t1 = synth.normal(5, 9, o * v, 0.1).reshape(o, v)
+    hb = ohbar.build_hbar_from_problem(prob)
+    D = osig.dim(o, v)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((64, D)) + 1j * rng.standard_normal((64, D))
+    ref = osig.sigma(hb, x)
+    for mode in (0, 2, 1):
+        gpu_ctx.autotune(mode)
+        gpu_ctx.build_from_problem(prob)
+        for name in ("Foo", "Fvv", "Fov", "Woooo", "Wooov", "Wovvo", "Wovoo"):
+            g = gpu_ctx.export(name).cpu().numpy()
+            r = getattr(hb, name)
+            err = np.abs(g - r).max()
+            assert err <= 1e-13 * max(1.0, np.abs(r).max()), (mode, name, err)
+        y = gpu_ctx.sigma_apply(torch.from_numpy(x).cuda()).cpu().numpy()
+        assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max(), mode
+        ents = [e for e in gpu_ctx.autotune_entries() if e["kind"] == 22]
+        if mode == 0:
+            assert not ents
+        else:
+            assert ents, "no small product was tuned"
+            if mode == 2:
+                assert all(e["tile"] != (0, 0) for e in ents)
+                assert any(e["splits"] > 1 for e in ents)
+            else:
+                assert all(e["tile"] == (0, 0) or e["us"] <= e["generic_us"] for e in ents)
     gpu_ctx.autotune(True)
 
 
