@@ -281,9 +281,13 @@ void segmm_run(gfcc_ctx* ctx, const SegSpec<T>& s, int tm, int tn, int splits);
 template <typename T>
 void segmm_candidates(const SegSpec<T>& s, std::vector<std::array<int, 3>>& out);
 
-// Times each candidate (an untimed run, a timed warm-up run, then two timed runs, on the context
-// stream; a candidate whose warm-up run took more than twice the best time so far is not run
-// again) and
+// Grows the split-K workspace to what the most split of the candidates needs, before they are
+// timed (so that no candidate's time includes the allocation).
+template <typename T>
+void segmm_reserve(gfcc_ctx* ctx, const SegSpec<T>& s,
+                   const std::vector<std::array<int, 3>>& cands);
+// Times each candidate (one warm-up run, then two timed runs, on the context stream; a
+// candidate whose warm-up run took more than twice the best time so far is not run again) and
 // returns the index of the fastest; us[i] receives candidate i's time in microseconds.
 // Synchronises the stream. Candidates must be complete, idempotent computations.
 int time_candidates(gfcc_ctx* ctx, const std::vector<std::function<void()>>& cands,

@@ -439,11 +439,12 @@ const TuneChoice& tune_choice(gfcc_ctx* ctx, bool transA, int M, int N, int K, c
 
 }  // namespace
 
-// Products whose 128 x 128 tiles number under 64 while K is at least 128 (the small build
-// products: one to four workgroups on the 128 x 128 kernels, each walking all of K)
-inline bool small_product(int M, int N, int K) {
+// Products whose 128 x 128 tiles number under 64 with K from 128 up to the split-K products'
+// bound (the small build products: one to four workgroups on the 128 x 128 kernels, each
+// walking all of K; longer K is the split-K tuner's, whose products are bandwidth-bound)
+inline bool small_product(int M, int N, int K, size_t elem) {
   const int64_t tiles = (int64_t)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-  return tiles < 64 && K >= 128;
+  return tiles < 64 && K >= 128 && (int64_t)K * (int64_t)elem < 8 * 128 * 4;
 }
 
 template <typename T>
@@ -490,6 +491,7 @@ void gemm_small(gfcc_ctx* ctx, int M, int N, int K, T alpha, const T* A, int64_t
     } else if (ctx->tune_mode == 1) {
       DevBuf scratch;
       scratch.alloc(sizeof(T) * (size_t)M * N);
+      segmm_reserve(ctx, s, cand);
       SegSpec<T> t = s;
       t.C = scratch.as<T>();
       t.ldc = N;
@@ -535,14 +537,15 @@ void gemm(gfcc_ctx* ctx, bool transA, bool transB, int M, int N, int K, T alpha,
   // the product takes the row-major paths below (stream order protects the workspace until the
   // product has read it)
   if (transB && batch == 1 && sizeof(T) == 8 && ldb == K &&
-      ((int64_t)K * N >= (1 << 20) || (!transA && M > 0 && N > 0 && small_product(M, N, K))) &&
+      ((int64_t)K * N >= (1 << 20) ||
+       (!transA && M > 0 && N > 0 && small_product(M, N, K, sizeof(T)))) &&
       N < 65536 * 32) {
     ws_ensure(ctx, ctx->ws_trans, sizeof(T) * (size_t)K * N);
     transpose2d(ctx, reinterpret_cast<const double*>(B), N, K, ctx->ws_trans.as<double>());
     gemm<T>(ctx, transA, false, M, N, K, alpha, A, lda, ctx->ws_trans.as<T>(), N, beta, C, ldc);
     return;
   }
-  if (!transA && !transB && batch == 1 && M > 0 && N > 0 && small_product(M, N, K) &&
+  if (!transA && !transB && batch == 1 && M > 0 && N > 0 && small_product(M, N, K, sizeof(T)) &&
       ctx->tune_mode != 0) {
     gemm_small<T>(ctx, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
     return;
@@ -966,10 +969,7 @@ int time_candidates(gfcc_ctx* ctx, const std::vector<std::function<void()>>& can
     return ms * 1e3 / reps;
   };
   for (size_t i = 0; i < cands.size(); ++i) {
-    // an untimed first run takes any workspace growth (an allocation would otherwise count
-    // against the candidate); a candidate whose next run is already twice as slow as the best
-    // is not run again
-    cands[i]();
+    // the first run warms up; a candidate already twice as slow as the best is not run again
     const double warm = timed(cands[i], 1);
     if (i > 0 && warm > 2.0 * us[best]) {
       us[i] = warm;
@@ -983,6 +983,24 @@ int time_candidates(gfcc_ctx* ctx, const std::vector<std::function<void()>>& can
   return best;
 }
 
+template <typename T>
+void segmm_reserve(gfcc_ctx* ctx, const SegSpec<T>& s,
+                   const std::vector<std::array<int, 3>>& cands) {
+  size_t need = 0;
+  const int total = seg_slabs(s.K, s.nseg);
+  for (const auto& c : cands) {
+    if (c[2] <= 1 || s.batch != 1 || s.Zas || total <= 1) continue;
+    const int spz = (total + c[2] - 1) / c[2];
+    const int nz = (total + spz - 1) / spz;
+    if (nz > 1) need = std::max(need, sizeof(T) * (size_t)s.M * s.N * nz);
+  }
+  ws_ensure(ctx, ctx->ws_gemm, need);
+}
+
+template void segmm_reserve<double>(gfcc_ctx*, const SegSpec<double>&,
+                                    const std::vector<std::array<int, 3>>&);
+template void segmm_reserve<float>(gfcc_ctx*, const SegSpec<float>&,
+                                   const std::vector<std::array<int, 3>>&);
 template void segmm_run<double>(gfcc_ctx*, const SegSpec<double>&, int, int, int);
 template void segmm_run<float>(gfcc_ctx*, const SegSpec<float>&, int, int, int);
 template void segmm_candidates<double>(const SegSpec<double>&, std::vector<std::array<int, 3>>&);

@@ -125,6 +125,7 @@ bool tuned_route(gfcc_ctx* ctx, int64_t kind, const SegSpec<T>& fused,
       for (size_t i = 1; i < cand.size(); ++i)
         if (cand[i][2] > cand[pick - 1][2]) pick = (int)i + 1;
     } else if (ctx->tune_mode == 1) {
+      segmm_reserve(ctx, fused, cand);
       std::vector<std::function<void()>> fns{unfused};
       for (const auto& c : cand)
         fns.push_back([&, c] { segmm_run<T>(ctx, fused, c[0], c[1], c[2]); });
