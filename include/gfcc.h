@@ -143,8 +143,8 @@ gfcc_status sigma_apply(gfcc_ctx* ctx, int nrhs, const void* x, void* y, int tra
  * x_2h1p summed in one pass as a product batched over the virtual index) are timed as their
  * unfused route and as a segmented product on every candidate tile (32, 64 or 128 rows by 64
  * or 128 columns) and split count. Small row-major products (fewer than 64 tiles of 128 x 128
- * and K >= 128, chiefly the operator build's at small shapes; a transposed B is transposed
- * first) are timed, into a scratch output, as their route above and as a segmented product on
+ * and 128 <= K < 512 doubles or 1024 floats, chiefly the operator build's at small shapes; a
+ * transposed B is transposed first) are timed, into a scratch output, as their route above and as a segmented product on
  * every candidate tile and split count. Off: the generic kernel with its heuristic split count
  * for the first kind, the plain pipelined kernel for the second, the unfused route for the
  * sigma's products, the route above for small products. enable = 2 skips the timing and takes

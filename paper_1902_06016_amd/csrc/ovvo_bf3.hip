@@ -19,8 +19,9 @@
 //    takes 4 (o vp) (o nc) bytes (5.3 GB at o=70, v=260 and 512 right-hand sides) and its
 //    pass costs about 2% of the product.
 //
-// GEMM. Tile 256 x BN x 32 (BN = 128 or 256), 512 threads as 4 x 2 wavefronts of 64 x BN/2,
-// one workgroup per CU. LDS is double-buffered, so one barrier per slab: while a slab's MFMAs
+// GEMM. Column blocks of 256 (nc % 256 == 0) take pairs_gemm8_kernel (below: 256 x 256
+// tiles, direct global-to-LDS loads). Otherwise tile 256 x 128 x 32, 512 threads as 4 x 2
+// wavefronts of 64 x 64, one workgroup per CU. LDS is double-buffered, so one barrier per slab: while a slab's MFMAs
 // run, the next slab's global loads are in flight; they are stored to the other buffer after
 // the MFMAs. An LDS row of 128 bytes holds 32 k of one tile row (A) or column (B): the four
 // 16-byte chunks of the high parts, then the four of the remainders, chunk c stored at
@@ -631,7 +632,7 @@ bool ovvo_bf3(gfcc_ctx* ctx, int o, int v, int nc, const void* Wh, const void* W
   const int vp = (v + 7) / 8 * 8;
   const int64_t K8 = ldk / 8;
   if (OV >= (1LL << 30) || N >= (1LL << 31) || K8 * N >= (1LL << 40)) return false;
-  const int BN = 128;   // 256-column tiles need more than the 256 registers of a wavefront at two per SIMD
+  constexpr int BN = 128;  // 256-column tiles need more than the 256 registers of a wavefront at two per SIMD
   // the expanded operand, hi and lo chunks
   const size_t rbytes = sizeof(u4) * (size_t)(K8 * N);
   ws_ensure(ctx, ctx->ws_pairs, 2 * rbytes);
@@ -684,10 +685,7 @@ bool ovvo_bf3(gfcc_ctx* ctx, int o, int v, int nc, const void* Wh, const void* W
   const int64_t tiles = (int64_t)p.mtiles * p.ntiles;
   if (tiles >= (1LL << 31) - 8) return false;
   const dim3 grid((unsigned)((tiles + 7) / 8 * 8));
-  if (BN == 256)
-    hipLaunchKernelGGL(pairs_gemm_kernel<256>, grid, dim3(PNT), 0, ctx->stream, p);
-  else
-    hipLaunchKernelGGL(pairs_gemm_kernel<128>, grid, dim3(PNT), 0, ctx->stream, p);
+  hipLaunchKernelGGL(pairs_gemm_kernel<BN>, grid, dim3(PNT), 0, ctx->stream, p);
   GFCC_LAUNCH_CHECK();
   return true;
 }
