@@ -65,10 +65,19 @@ __global__ void transpose_kernel(const double* __restrict__ src, int64_t rows, i
   }
 }
 
-// per-block count of non-finite entries (grid-stride), reduced by a second one-block pass
-__global__ void nonfinite_kernel(const double* __restrict__ p, int64_t n,
-                                 unsigned long long* __restrict__ partial) {
+// Non-finite entries of up to NF_MAX arrays in two launches: blockIdx.y picks the array, whose
+// blocks count grid-stride into partial[y][blockIdx.x]; then one block per array adds its
+// partials in a fixed order.
+constexpr int NF_MAX = 16;
+struct NonfiniteArgs {
+  const double* p[NF_MAX];
+  int64_t n[NF_MAX];
+};
+
+__global__ void nonfinite_kernel(NonfiniteArgs a, unsigned long long* __restrict__ partial) {
   __shared__ unsigned long long red[256];
+  const double* p = a.p[blockIdx.y];
+  const int64_t n = a.n[blockIdx.y];
   unsigned long long local = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -79,21 +88,22 @@ __global__ void nonfinite_kernel(const double* __restrict__ p, int64_t n,
     if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
 }
 
 __global__ void sum_u64_kernel(const unsigned long long* __restrict__ partial, int n,
                                unsigned long long* __restrict__ out) {
   __shared__ unsigned long long red[256];
+  const unsigned long long* pp = partial + (int64_t)blockIdx.x * n;
   unsigned long long local = 0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) local += partial[i];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) local += pp[i];
   red[threadIdx.x] = local;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = red[0];
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 inline unsigned grid_for(int64_t n) {
@@ -156,27 +166,32 @@ void transpose2d(gfcc_ctx* ctx, const double* src, int64_t rows, int64_t cols, d
 
 std::vector<int64_t> count_nonfinite(gfcc_ctx* ctx,
                                      const std::vector<std::pair<const double*, int64_t>>& arrs) {
-  const int nb = 1024;
   const size_t na = arrs.size();
   std::vector<int64_t> out(na, 0);
   if (na == 0) return out;
-  // per-array partial counts, then one total per array; one copy and one wait for all
-  ws_ensure(ctx, ctx->ws_e, sizeof(unsigned long long) * (size_t)(nb + 1) * na);
-  auto* part = ctx->ws_e.as<unsigned long long>();
-  auto* tot = part + (size_t)nb * na;
-  for (size_t k = 0; k < na; ++k) {
-    const int64_t n = arrs[k].second;
-    hipLaunchKernelGGL(nonfinite_kernel, dim3(n > 0 ? nb : 1), dim3(256), 0, ctx->stream,
-                       arrs[k].first, n, part + (size_t)k * nb);
-    GFCC_LAUNCH_CHECK();
-    hipLaunchKernelGGL(sum_u64_kernel, dim3(1), dim3(256), 0, ctx->stream, part + (size_t)k * nb,
-                       n > 0 ? nb : 1, tot + k);
-    GFCC_LAUNCH_CHECK();
-  }
   std::vector<unsigned long long> h(na);
-  GFCC_HIP(hipMemcpyAsync(h.data(), tot, sizeof(unsigned long long) * na, hipMemcpyDeviceToHost,
-                          ctx->stream));
-  GFCC_HIP(hipStreamSynchronize(ctx->stream));
+  for (size_t k0 = 0; k0 < na; k0 += NF_MAX) {
+    const int cnt = (int)std::min<size_t>(NF_MAX, na - k0);
+    NonfiniteArgs a{};
+    int64_t nmax = 0;
+    for (int k = 0; k < cnt; ++k) {
+      a.p[k] = arrs[k0 + k].first;
+      a.n[k] = arrs[k0 + k].second;
+      nmax = std::max(nmax, a.n[k]);
+    }
+    // blocks per array: enough for the largest, at most 1024; one copy and one wait for all
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (nmax + 255) / 256));
+    ws_ensure(ctx, ctx->ws_e, sizeof(unsigned long long) * (size_t)(nb + 1) * cnt);
+    auto* part = ctx->ws_e.as<unsigned long long>();
+    auto* tot = part + (size_t)nb * cnt;
+    hipLaunchKernelGGL(nonfinite_kernel, dim3(nb, cnt), dim3(256), 0, ctx->stream, a, part);
+    GFCC_LAUNCH_CHECK();
+    hipLaunchKernelGGL(sum_u64_kernel, dim3(cnt), dim3(256), 0, ctx->stream, part, nb, tot);
+    GFCC_LAUNCH_CHECK();
+    GFCC_HIP(hipMemcpyAsync(h.data() + k0, tot, sizeof(unsigned long long) * cnt,
+                            hipMemcpyDeviceToHost, ctx->stream));
+    GFCC_HIP(hipStreamSynchronize(ctx->stream));
+  }
   for (size_t k = 0; k < na; ++k) out[k] = (int64_t)h[k];
   return out;
 }

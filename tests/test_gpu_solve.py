@@ -154,10 +154,21 @@ def test_errors(gpu_ctx):
     bad = [T.from_numpy(np.ascontiguousarray(a)).cuda() for a in
            (prob.eps, prob.t1, prob.t2, prob.l1, prob.l2, prob.block("oooo"), prob.block("ooov"),
             prob.block("oovv"), prob.block("ovvo"), prob.block("ovvv"))]
-    bad[8][0, 0, 0, 0] = float("nan")
-    with pytest.raises(gfcc.GfccError) as e:
-        gpu_ctx.build_hbar_operands(4, 3, *bad)
-    assert e.value.status == gfcc.GFCC_EINVAL
+    # one bad entry at a time, in every input (the last entry of each, and an infinity in the
+    # first): each is found and named in the error message
+    names = ("eps", "t1", "t2", "l1", "l2", "oooo", "ooov", "oovv", "ovvo", "ovvv")
+    o_, v_ = prob.o, prob.v
+    for k, t in enumerate(bad):
+        flat = t.view(-1)
+        for pos, val in ((flat.numel() - 1, float("nan")), (0, float("inf"))):
+            keep = flat[pos].item()
+            flat[pos] = val
+            with pytest.raises(gfcc.GfccError) as e:
+                gpu_ctx.build_hbar_operands(o_, v_, *bad)
+            assert e.value.status == gfcc.GFCC_EINVAL
+            assert names[k] in str(e.value), (k, str(e.value))
+            flat[pos] = keep
+    gpu_ctx.build_hbar_operands(o_, v_, *bad)  # all finite again
 
 
 def test_empty_inputs(gpu_ctx):
