@@ -206,7 +206,10 @@ static_assert(FJ == 32, "the launch tables cover NJ = 1 .. 32");
 // rho with g_j = (beta - s^H t) / rho, its preconditioned copy, and the dots s, alpha of
 // vt_{j+1}. The first-pass coefficients of column j are c_j = (g - Hbar s) / rho with
 // g = (t, g_j); Hbar s is formed by the next step's reduction. Two sweeps over the basis per
-// step instead of three, one reduction instead of three.
+// step instead of three, one reduction instead of three. The pending vector is stored only as
+// its preconditioned copy U = vt / (diag + z), which the operator product needs anyway; both
+// sweeps read U for the shift and recover vt = U (diag + z) from it, so a step moves the basis
+// twice plus 6 vectors (W and U read by each sweep; q_j and U written) instead of 9.
 constexpr int PB = FJ + 1;       // first partial row of pass B (pass A uses rows 0 .. j)
 constexpr int PSTR = PB + FJ + 2;  // partial rows per block
 
@@ -240,15 +243,18 @@ __device__ __forceinline__ void combine_partials(const double2 (&acc)[NA], doubl
   }
 }
 
-// pass A: partial[blk][jj][r] = sum_d conj(Q_jj[d][r]) w[d][r] (jj < NJ) and row NJ with
-// vt = V_NJ, w = W + z U; one workgroup of four wavefronts per block of rows
+// pass A: partial[blk][jj][r] = sum_d conj(Q_jj[d][r]) w[d][r] (jj < NJ) and row NJ with the
+// pending vector vt = U (diag + z), w = W + z U; one workgroup of four wavefronts per block of
+// rows
 template <int NJ>
 __global__ __launch_bounds__(256) void dcgs_dots_kernel(const double2* __restrict__ V,
                                                         int64_t vstride,
                                                         const double2* __restrict__ Wv,
                                                         const double2* __restrict__ U,
-                                                        const double2* __restrict__ z, int64_t D,
-                                                        int nb, double2* __restrict__ partial) {
+                                                        const double2* __restrict__ z,
+                                                        const double* __restrict__ diag,
+                                                        int64_t D, int nb,
+                                                        double2* __restrict__ partial) {
   constexpr int C = 8;
   __shared__ double2 buf[4 * C][CW];
   const int lane = threadIdx.x & (CW - 1), wave = threadIdx.x / CW;
@@ -265,9 +271,11 @@ __global__ __launch_bounds__(256) void dcgs_dots_kernel(const double2* __restric
     const int64_t idx = d * nb + r;
     double2 vj[NJ + 1];
 #pragma unroll
-    for (int jj = 0; jj <= NJ; ++jj) vj[jj] = V[(int64_t)jj * vstride + idx];
+    for (int jj = 0; jj < NJ; ++jj) vj[jj] = V[(int64_t)jj * vstride + idx];
     double2 w = Wv[idx];
-    const double2 p = cmul(zz, U[idx]);
+    const double2 u = U[idx];
+    vj[NJ] = cmul(u, make_double2(diag[d] + zz.x, zz.y));
+    const double2 p = cmul(zz, u);
     w.x += p.x;
     w.y += p.y;
 #pragma unroll
@@ -280,17 +288,18 @@ __global__ __launch_bounds__(256) void dcgs_dots_kernel(const double2* __restric
   combine_partials<NJ + 1, C>(acc, buf, partial + (int64_t)blockIdx.x * PSTR * nb, nb, nb);
 }
 
-// pass B over Q_0 .. Q_{NJ-1} and the pending vector in slot NJ:
+// pass B over Q_0 .. Q_{NJ-1} and the pending vector vt = U (diag + z):
 //   q = (vt - sum_i Q_i s_i) qscale          -> V slot NJ
-//   vn = (w - sum_i Q_i t_i - g q) vscale    -> V slot NJ + 1 (not when FINAL)
-//   U = vn / (diag + z); partial rows PB + i = conj(Q_i) vn, PB + NJ = conj(q) vn,
-//   PB + NJ + 1 = |vn|^2
+//   vn = (w - sum_i Q_i t_i - g q) vscale    (not when FINAL)
+//   U = vn / (diag + z), the next pending vector's only copy (the next sweeps recover
+//   vt' = U (diag + z) = vn to rounding); partial rows PB + i = conj(Q_i) vn,
+//   PB + NJ = conj(q) vn, PB + NJ + 1 = |vn|^2
 // s, t: [NJ][nb] (t row NJ holds g). FINAL (end of a cycle) only writes q. Four wavefronts
 // share the coefficients of their 64 RHS in LDS (registers hold the basis rows and the dots)
 // and take every fourth row of the workgroup's range; the workgroup writes one partial row per
 // sum (combine_partials).
 template <int NJ, bool FINAL>
-__global__ __launch_bounds__(256) void dcgs_update_kernel(
+__global__ __launch_bounds__(256, NJ <= 24 ? 2 : 1) void dcgs_update_kernel(
     double2* __restrict__ V, int64_t vstride, const double2* __restrict__ Wv,
     double2* __restrict__ U, const double2* __restrict__ z, const double* __restrict__ diag,
     const double2* __restrict__ sc, const double2* __restrict__ tc,
@@ -338,13 +347,11 @@ __global__ __launch_bounds__(256) void dcgs_update_kernel(
     double2 vj[NS];
 #pragma unroll
     for (int jj = 0; jj < NJ; ++jj) vj[jj] = V[(int64_t)jj * vstride + idx];
-    double2 q = V[(int64_t)NJ * vstride + idx];
+    const double2 u = U[idx];
+    const double2 dz = make_double2(diag[d] + zz.x, zz.y);
+    double2 q = cmul(u, dz);
     double2 w = make_double2(0.0, 0.0);
-    double2 u = make_double2(0.0, 0.0);
-    if (!FINAL) {
-      w = Wv[idx];
-      u = U[idx];
-    }
+    if (!FINAL) w = Wv[idx];
 #pragma unroll
     for (int jj = 0; jj < NJ; ++jj) {
       const double2 a = cmul(vj[jj], s_l[jj][li]);
@@ -371,8 +378,7 @@ __global__ __launch_bounds__(256) void dcgs_update_kernel(
       w.x = (w.x - a.x) * vs;
       w.y = (w.y - a.y) * vs;
     }
-    V[(int64_t)(NJ + 1) * vstride + idx] = w;
-    U[idx] = cdiv(w, make_double2(diag[d] + zz.x, zz.y));
+    U[idx] = cdiv(w, dz);
 #pragma unroll
     for (int jj = 0; jj < NJ; ++jj) {
       const double2 a = cconjmul(vj[jj], w);
@@ -448,7 +454,7 @@ __global__ __launch_bounds__(256) void dcgs_reduce_kernel(
 }
 
 typedef void (*DcgsDotsFn)(const double2*, int64_t, const double2*, const double2*,
-                           const double2*, int64_t, int, double2*);
+                           const double2*, const double*, int64_t, int, double2*);
 typedef void (*DcgsUpdateFn)(double2*, int64_t, const double2*, double2*, const double2*,
                              const double*, const double2*, const double2*, const double*,
                              const double*, int64_t, int, double2*);
@@ -1540,7 +1546,7 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
           gb.apply_M(gb.U, gb.W, false, false);
         }
         hipLaunchKernelGGL(Dcgs::dots[k], ugrid, dim3(256), 0, st, gb.V, D * nb, gb.W, gb.U, gb.z,
-                           D, nb, gb.part_h);
+                           ctx->op.diag.as<double>(), D, nb, gb.part_h);
         GFCC_LAUNCH_CHECK();
         gb.dcgs_reduce(k + 1, k >= 1 ? k + 1 : 0, k >= 2 ? k : 0, k - 1);
         finish(k, 0, fslot);
@@ -1631,7 +1637,7 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
           gb.apply_M(gb.U, gb.W, false, false);
         }
         hipLaunchKernelGGL(Dcgs::dots[k], ugrid, dim3(256), 0, st, gb.V, D * nb, gb.W, gb.U, gb.z,
-                           D, nb, gb.part_h);
+                           ctx->op.diag.as<double>(), D, nb, gb.part_h);
         GFCC_LAUNCH_CHECK();
         gb.dcgs_reduce(k + 1, 0, 0, 0);
         finish(k, k == 0 ? 0 : 2, nullptr);
