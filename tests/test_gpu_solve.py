@@ -65,6 +65,32 @@ def test_near_poles_and_transpose(gpu_ctx):
     assert np.abs(adj.G.cpu().numpy() - Gr).max() / np.abs(Gr).max() < 1e-9
 
 
+def test_small_preconditioner_entries(gpu_ctx):
+    """Frequencies where omega + diag(H-bar_N) nearly vanishes for some rows, with a broadening
+    of 1e-6: the Jacobi-preconditioned vectors U = v / (diag + omega - i eta) are then up to 1e6
+    times larger than v. The Arnoldi sweeps keep the pending vector only as U and recover it as
+    U (diag + omega - i eta); X and G must still match dense LU."""
+    print("[small preconditioner entries]", flush=True)
+    o, v, seed = 6, 10, 4
+    prob = synth.make_problem(o, v, seed)
+    hb = ohbar.build_hbar_from_problem(prob)
+    H = osolve.dense_hbar(hb)
+    dg = np.diag(H).real
+    # frequencies at minus four 1h diagonal entries, offset by a few eta (well-conditioned
+    # systems, cond 30-300, whose Jacobi-preconditioned Krylov spaces take 55-450 iterations)
+    eta = 1e-6
+    om = np.array([-dg[o - 1] + 3e-6, -dg[1] + 1e-5, -dg[2] - 5e-6, -dg[4] + 2e-6])
+    ps = np.arange(o)
+    _, _, _, _, Xr, Gr = _dense_ref(prob, om, ps, eta)
+    gpu_ctx.build_from_problem(prob)
+    r = gpu_ctx.gfcc_solve(om, ps, eta, tol=1e-12, restart=30, maxit=3000, want_x=True,
+                           allow_noconv=True)
+    assert r.resid.max() <= 1e-12, r.resid.max()
+    X = r.X.cpu().numpy()
+    assert np.abs(X - Xr).max() / np.abs(Xr).max() < 1e-8
+    assert np.abs(r.G.cpu().numpy() - Gr).max() / np.abs(Gr).max() < 1e-8
+
+
 @pytest.mark.parametrize("transpose", [False, True])
 def test_reported_residual_is_the_true_residual(gpu_ctx, transpose):
     """The FP64 solver forms the residual at the end of each restart cycle from the Arnoldi
