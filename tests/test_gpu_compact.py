@@ -86,3 +86,35 @@ def test_compacted_restart_from_a_start_iterate(gpu_ctx):
         assert r.resid.max() <= 1e-12
         assert np.abs(r.X.cpu().numpy().reshape(Xr.shape) - Xr).max() / np.abs(Xr).max() < 1e-10
     assert res[1].iters.max() > 6
+
+
+def test_compacted_blocks_share_captured_steps(gpu_ctx):
+    """A compacted block of 128 columns is laid out as a first-level block of 128 columns, so
+    the two share captured steps (same step shapes past step 0). Interleaving both kinds of
+    solve with graph capture on (eager, capture, replay) gives the bits of the same solves run
+    kernel by kernel."""
+    print("[compact graphs]", flush=True)
+    cfg = synth.WORKLOADS["o10v20"]
+    prob = synth.make_problem(cfg["o"], cfg["v"], cfg["seed"])
+    om = synth.omega_grid(cfg["omega"])
+    ps = synth.valence_p(cfg["o"], cfg["np"])
+    gpu_ctx.build_from_problem(prob)
+    kw = dict(tol=1e-10, restart=30, maxit=400)
+
+    def pair():
+        a = gpu_ctx.gfcc_solve(om, ps[:2], cfg["eta"], block=128, **kw)   # 128 columns
+        b = gpu_ctx.gfcc_solve(om, ps, cfg["eta"], block=640, **kw)       # compacts to 128
+        return a, b
+
+    try:
+        gpu_ctx.graphs(False)
+        ra, rb = pair()
+        assert rb.iters.max() > 30
+        gpu_ctx.graphs(True)
+        for rep in range(3):
+            a, b = pair()
+            for x, y in ((a, ra), (b, rb)):
+                assert np.array_equal(x.G.cpu().numpy(), y.G.cpu().numpy()), rep
+                assert np.array_equal(x.iters, y.iters) and np.array_equal(x.resid, y.resid)
+    finally:
+        gpu_ctx.graphs(True)
