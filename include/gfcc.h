@@ -144,12 +144,15 @@ gfcc_status sigma_apply(gfcc_ctx* ctx, int nrhs, const void* x, void* y, int tra
  * unfused route and as a segmented product on every candidate tile (32, 64 or 128 rows by 64
  * or 128 columns) and split count. Small row-major products (fewer than 64 tiles of 128 x 128
  * and 128 <= K < 512 doubles or 1024 floats, chiefly the operator build's at small shapes; a
- * transposed B is transposed first) are timed, into a scratch output, as their route above and as a segmented product on
- * every candidate tile and split count. Off: the generic kernel with its heuristic split count
- * for the first kind, the plain pipelined kernel for the second, the unfused route for the
- * sigma's products, the route above for small products. enable = 2 skips the timing and takes
- * the most split candidate of every class (the fused segmented product for the sigma's and the
- * small products), so that tests reach the split-K and segmented paths. Results agree to
+ * transposed B is transposed first) are timed, into a scratch output, as their route above and
+ * as a segmented product on every candidate tile and split count. The forward FP64 sigma's ovvo
+ * product, when its operand written out takes at most 64 MiB (small operators and blocks), is
+ * timed as the ovvo kernel and as the written-out operand on every segmented tile and split.
+ * Off: the generic kernel with its heuristic split count for the first kind, the plain
+ * pipelined kernel for the second, the unfused route for the sigma's products, the route above
+ * for small products, the ovvo kernel for small ovvo products. enable = 2 skips the timing and
+ * takes the most split candidate of every class (the segmented product for the sigma's, the
+ * small and the small ovvo products), so that tests reach the split-K and segmented paths. Results agree to
  * rounding in every mode. EINVAL for another value of enable.
  */
 gfcc_status gfcc_autotune(gfcc_ctx* ctx, int enable);
@@ -158,7 +161,7 @@ gfcc_status gfcc_autotune(gfcc_ctx* ctx, int enable);
  * gfcc_autotune_entry -- the tuner's choice number `index` (0-based, ordered by class):
  * desc[8] (host) receives {element bytes, kind, M, N, K, splits, tile rows, tile columns}.
  * kind: 0 or 1 a plain product (transA); 20 the sigma's [W1 ; 0 | Vp^T] . x; 21 the sigma's
- * linear 2h1p products; 22 a small product. M, N, K: the shape it was measured on (for kind 21 the fused
+ * linear 2h1p products; 22 a small product; 23 a small ovvo product. M, N, K: the shape it was measured on (for kind 21 the fused
  * product's: M = P pairs, N = columns, K = o + v + P, batched over the v virtual orbitals). splits: 0 for the generic kernel and,
  * for plain products of 256 tiles or more, 1 for the plain pipelined kernel. The tile is 0 x 0
  * for a plain product, for a sigma product that runs unfused and for a small product that

@@ -138,6 +138,7 @@ struct TuneChoice {
 constexpr int64_t TUNE_SIGMA_1H = 20;      // sigma's [W1 ; Vp^T] . X: fused (tile) or unfused
 constexpr int64_t TUNE_SIGMA_2H1P = 21;    // sigma's linear 2h1p products: fused or unfused
 constexpr int64_t TUNE_SMALL = 22;         // small products: segmented tile and split, or generic
+constexpr int64_t TUNE_OVVO = 23;          // small ovvo products: expanded operand on the segmented kernel, or the ovvo kernel
 using TuneKey = std::array<int64_t, 6>;
 
 struct TimerSlot {
@@ -160,6 +161,7 @@ struct gfcc_ctx {
   gfcc::DevBuf ws_trans;    // transposed B operands of the row-major product paths
   gfcc::DevBuf ws_io;       // sigma_apply: D-major copies of its input and output blocks
   gfcc::DevBuf ws_pairs;    // the expanded bf16-pair operand of the two-term ovvo product
+  gfcc::DevBuf ws_rexp;     // the expanded FP64 ovvo operand of small sigma products
   gfcc::DevBuf ws_solve, ws_solve_f32;  // GMRES block work arrays (Krylov basis, state)
   std::vector<gfcc::DevBuf> build_pool;  // operator-build buffers kept for the next build
   gfcc::DevBuf zrow;        // zeros (read for structurally zero rows of the ovvo operand)

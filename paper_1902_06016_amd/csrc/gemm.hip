@@ -593,14 +593,123 @@ template void gemm<float>(gfcc_ctx*, bool, bool, int, int, int, float, const flo
                           const float*, int64_t, float, float*, int64_t, int, int64_t, int64_t,
                           int64_t);
 
+namespace {
+// The ovvo operand written out: R[(m, e)][(j, c)] = r_mj^e[c] = sign X2[(pair, e)][c] with the
+// pair and sign of (m, j) from pairlut (+(pair+1) for m < j, -(pair+1) for m > j, 0 for m = j)
+__global__ void ovvo_expand_kernel(const double* __restrict__ X2, int64_t ldx,
+                                   const int* __restrict__ lut, int o, int v, int nc,
+                                   double* __restrict__ R) {
+  const int64_t N = (int64_t)o * nc, total = (int64_t)o * v * N;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = i / N, col = i - row * N;
+    const int m = (int)(row / v), e = (int)(row - (int64_t)m * v);
+    const int j = (int)(col / nc), c = (int)(col - (int64_t)j * nc);
+    const int l = lut[m * o + j];
+    double x = 0.0;
+    if (l != 0) {
+      const int pr = (l > 0 ? l : -l) - 1;
+      x = X2[((int64_t)pr * v + e) * ldx + c];
+      if (l < 0) x = -x;
+    }
+    R[i] = x;
+  }
+}
+}  // namespace
+
+// Small forward FP64 ovvo products (the written-out operand at most 64 MiB): the ovvo kernel
+// runs one 128 x 128 tile per CU at most, each walking all of K, so at the small case it is
+// bound by one CU's matrix throughput on 200 tiles. The alternative writes the operand out
+// (one HBM-bound pass) and runs the segmented kernel on small tiles; the tuner times the ovvo
+// kernel against every tile and split of it (class: TUNE_OVVO, o, v, 64-column groups).
+static bool ovvo_small(gfcc_ctx* ctx, int o, int v, int nc, const double* W, const double* X2,
+                       int64_t ldx, const int* pairlut, double* Z,
+                       const std::function<void()>& kernel_route) {
+  const int64_t OV = (int64_t)o * v, N = (int64_t)o * nc;
+  if (ctx->tune_mode == 0 || OV * N * 8 > (int64_t(64) << 20) || OV >= (1 << 20)) return false;
+  SegSpec<double> s;
+  s.M = (int)OV;
+  s.N = (int)N;
+  s.K[0] = (int)OV;
+  s.A[0] = W;
+  s.lda[0] = OV;
+  s.ldb[0] = N;
+  s.C = Z;
+  s.ldc = N;
+  auto expand = [&]() {
+    ws_ensure(ctx, ctx->ws_rexp, sizeof(double) * (size_t)(OV * N));
+    const int64_t nblk = std::min<int64_t>(16384, std::max<int64_t>(1, (OV * N + 255) / 256));
+    hipLaunchKernelGGL(ovvo_expand_kernel, dim3((unsigned)nblk), dim3(256), 0, ctx->stream,
+                       X2, ldx, pairlut, o, v, nc, ctx->ws_rexp.as<double>());
+    GFCC_LAUNCH_CHECK();
+  };
+  const TuneKey key{8, TUNE_OVVO, o, v, (nc + 63) / 64, 0};
+  auto it = ctx->tune.find(key);
+  if (it == ctx->tune.end()) {
+    ws_ensure(ctx, ctx->ws_rexp, sizeof(double) * (size_t)(OV * N));
+    s.B[0] = ctx->ws_rexp.as<double>();
+    std::vector<std::array<int, 3>> cand;
+    segmm_candidates(s, cand);
+    TuneChoice ch;
+    ch.M = s.M;
+    ch.N = s.N;
+    ch.K = s.K[0];
+    int pick = 0;
+    if (ctx->tune_mode == 2) {
+      pick = 1;
+      for (size_t i = 1; i < cand.size(); ++i)
+        if (cand[i][2] > cand[pick - 1][2]) pick = (int)i + 1;
+    } else {
+      segmm_reserve(ctx, s, cand);
+      std::vector<std::function<void()>> fns{kernel_route};
+      for (const auto& c : cand)
+        fns.push_back([&, c] {
+          expand();
+          segmm_run<double>(ctx, s, c[0], c[1], c[2]);
+        });
+      std::vector<double> us;
+      pick = time_candidates(ctx, fns, us);
+      ch.best_us = us[pick];
+      ch.generic_us = us[0];
+      if (std::getenv("GFCC_TUNE_LOG")) {
+        for (size_t i = 0; i < fns.size(); ++i)
+          std::fprintf(stderr, "[gfcc autotune] ovvo o=%d v=%d nc=%d %s %dx%d splits=%d: %.1f us\n",
+                       o, v, nc, i == 0 ? "kernel" : "expanded", i ? cand[i - 1][0] : 0,
+                       i ? cand[i - 1][1] : 0, i ? cand[i - 1][2] : 0, us[i]);
+      }
+    }
+    if (pick > 0) {
+      ch.tile_m = cand[pick - 1][0];
+      ch.tile_n = cand[pick - 1][1];
+      ch.splits = cand[pick - 1][2];
+    }
+    it = ctx->tune.emplace(key, ch).first;
+  }
+  const TuneChoice& ch = it->second;
+  if (ch.tile_m == 0) return false;
+  expand();
+  s.B[0] = ctx->ws_rexp.as<double>();
+  segmm_run<double>(ctx, s, ch.tile_m, ch.tile_n, ch.splits);
+  return true;
+}
+
 template <typename T>
 void gemm_ovvo(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, const T* X2,
                int64_t ldx, const int* pairlut, T* Z) {
   const T* zrow = static_cast<const T*>(zero_row(ctx, (size_t)nc * sizeof(T)));
-  if (ovvo_fast<T>(ctx, transW, o, v, nc, W, X2, ldx, Z, zrow)) return;
   const int OV = o * v;
-  gemm_impl<T>(ctx, transW, B_OVVO, OV, o * nc, OV, T(1), W, OV, X2, ldx, T(0), Z,
-               (int64_t)o * nc, 1, 0, 0, 0, pairlut, o, v, nc);
+  auto kernel_route = [&]() {
+    if (ovvo_fast<T>(ctx, transW, o, v, nc, W, X2, ldx, Z, zrow)) return;
+    gemm_impl<T>(ctx, transW, B_OVVO, OV, o * nc, OV, T(1), W, OV, X2, ldx, T(0), Z,
+                 (int64_t)o * nc, 1, 0, 0, 0, pairlut, o, v, nc);
+  };
+  if constexpr (sizeof(T) == 8) {
+    if (!transW && ovvo_small(ctx, o, v, nc, reinterpret_cast<const double*>(W),
+                              reinterpret_cast<const double*>(X2), ldx, pairlut,
+                              reinterpret_cast<double*>(Z), kernel_route))
+      return;
+  }
+  kernel_route();
 }
 
 template void gemm_ovvo<double>(gfcc_ctx*, bool, int, int, int, const double*, const double*,

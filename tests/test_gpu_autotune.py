@@ -40,8 +40,9 @@ def test_sigma_with_and_without_the_tuner(gpu_ctx, transpose):
                     assert e["K"] * 8 >= 4096 and e["tile"] == (0, 0)
                     assert e["splits"] == 0 or e["us"] <= e["generic_us"]
                 else:
-                    # a sigma or small product: its route or a segmented tile no slower than it
-                    assert e["kind"] in (20, 21, 22)
+                    # a sigma, small or small ovvo product: its route or a segmented tile no
+                    # slower than it
+                    assert e["kind"] in (20, 21, 22, 23)
                     assert e["tile"] == (0, 0) or e["us"] <= e["generic_us"]
             if not transpose:
                 assert any(e["kind"] == 20 and e["M"] == o + v and e["K"] == D for e in ents)
@@ -56,7 +57,8 @@ def test_sigma_with_and_without_the_tuner(gpu_ctx, transpose):
 def test_small_build_products_in_every_tuner_mode(gpu_ctx):
     """o=10, v=20: every build product has fewer than 64 tiles of 128 x 128 (K6 is 200^3,
     Woooo 100 x 100 x 400 with a transposed B), so the small-product route is tuned between the
-    plain routes and the segmented kernel's tiles and split counts. The blocks and the sigma
+    plain routes and the segmented kernel's tiles and split counts; the sigma's ovvo product is
+    small as well (the written-out operand against the ovvo kernel). The blocks and the sigma
     match the oracle with the tuner off, untimed at the most split candidates (mode 2) and
     timed; the table names the small products."""
     print("[autotune small build modes]", flush=True)
@@ -78,16 +80,21 @@ def test_small_build_products_in_every_tuner_mode(gpu_ctx):
             assert err <= 1e-13 * max(1.0, np.abs(r).max()), (mode, name, err)
         y = gpu_ctx.sigma_apply(torch.from_numpy(x).cuda()).cpu().numpy()
         assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max(), mode
-        ents = [e for e in gpu_ctx.autotune_entries() if e["kind"] == 22]
+        allents = gpu_ctx.autotune_entries()
+        ents = [e for e in allents if e["kind"] == 22]
+        ovvo = [e for e in allents if e["kind"] == 23]
         if mode == 0:
-            assert not ents
+            assert not ents and not ovvo
         else:
             assert ents, "no small product was tuned"
+            # the sigma's ovvo product (o v = 200 rows, o nc = 1280 columns) is small too
+            assert len(ovvo) == 1 and ovvo[0]["M"] == o * v and ovvo[0]["N"] == o * 128
             if mode == 2:
-                assert all(e["tile"] != (0, 0) for e in ents)
+                assert all(e["tile"] != (0, 0) for e in ents + ovvo)
                 assert any(e["splits"] > 1 for e in ents)
             else:
-                assert all(e["tile"] == (0, 0) or e["us"] <= e["generic_us"] for e in ents)
+                assert all(e["tile"] == (0, 0) or e["us"] <= e["generic_us"]
+                           for e in ents + ovvo)
     gpu_ctx.autotune(True)
 
 
