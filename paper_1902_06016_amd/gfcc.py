@@ -35,6 +35,11 @@ class GfccError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1902_06016_amd.build`")
+    # torch first: it loads the HIP runtime its wheel carries, and the library then binds to
+    # that one (same soname). Loaded first, the library would bring in the system runtime and
+    # torch a second copy of its own, and each would hold its own device state (contexts
+    # fail, torch's streams are foreign to the library).
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     P = ctypes.POINTER

@@ -52,3 +52,25 @@ def test_binding_constants_match_header():
     for name, val in found.items():
         py = getattr(gfcc, name, getattr(gfcc, "GFCC_" + name, None))
         assert py == val, (name, py, val)
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Importing the binding before torch still leaves one HIP runtime in the process: the
+    library binds to the runtime torch's wheel carries instead of loading the system's beside it
+    (two runtimes keep separate device state, and contexts fail)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1902_06016_amd import gfcc\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(sorted({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n"
+            "print(torch.__file__)\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    paths, torch_file = out.stdout.strip().splitlines()[-2:]
+    paths = eval(paths)
+    assert len(paths) == 1, paths
+    torch_dir = os.path.dirname(os.path.realpath(torch_file))
+    assert os.path.realpath(paths[0]).startswith(torch_dir), (paths, torch_dir)
