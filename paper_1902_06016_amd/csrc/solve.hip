@@ -23,9 +23,12 @@
 namespace gfcc {
 namespace {
 
-// basis vectors covered by one sweep of the fused Arnoldi kernels (restart lengths up to 32 run
-// every step on them; longer ones continue on dots_kernel and update_kernel)
+// basis vectors covered by one sweep of the fused Arnoldi kernels; restart lengths up to 2 FJ
+// run every step with delayed reorthogonalisation, in two sweeps per pass beyond FJ vectors,
+// and longer ones on the CGS2 kernels (fused up to FJ vectors, then dots_kernel and
+// update_kernel)
 constexpr int FJ = 32;
+constexpr int FD = 2 * FJ;
 
 
 // partial[blk][jj][r] = sum over this block's rows of conj(V_j[d][r]) * W[d][r], j = j0 + jj.
@@ -195,7 +198,7 @@ using Fused = FusedTables<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 
                           21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31>;
 static_assert(FJ == 32, "the launch tables cover NJ = 1 .. 32");
 
-// ---- Arnoldi with delayed reorthogonalisation (restart lengths up to FJ).
+// ---- Arnoldi with delayed reorthogonalisation (restart lengths up to FD).
 // Step j applies the operator to the pending vector vt_j (orthogonalised once against the
 // final basis Q_0 .. Q_{j-1}, not yet normalised). One sweep over the basis (pass A) gives
 // t = Q^H w and beta = vt_j^H w for w = M(omega) P^{-1} vt_j; one reduction also completes
@@ -210,8 +213,15 @@ static_assert(FJ == 32, "the launch tables cover NJ = 1 .. 32");
 // its preconditioned copy U = vt / (diag + z), which the operator product needs anyway; both
 // sweeps read U for the shift and recover vt = U (diag + z) from it, so a step moves the basis
 // twice plus 6 vectors (W and U read by each sweep; q_j and U written) instead of 9.
-constexpr int PB = FJ + 1;       // first partial row of pass B (pass A uses rows 0 .. j)
-constexpr int PSTR = PB + FJ + 2;  // partial rows per block
+// A register file holds the rows of at most FJ basis vectors; beyond that (j > FJ) each pass is
+// split at c = j - FJ. Pass A: one sweep over Q_0 .. Q_{c-1}, one over Q_c .. Q_{j-1} and the
+// pending vector (W and U read twice). Pass B: Q_0 .. Q_{c-1} form their shares of
+// vt_j - Q s and w - Q t (dcgs_lincomb_kernel; the first in the slot of q_j, the second in a
+// scratch vector), the sweep over Q_c .. Q_{j-1} completes both as above, and a last sweep forms
+// the dots of Q_0 .. Q_{c-1} with the new pending vector (dcgs_dots_kernel, VN): 3j - 19 vector
+// passes per step instead of 2j + 6.
+constexpr int PB = FD + 1;       // first partial row of pass B (pass A uses rows 0 .. j)
+constexpr int PSTR = PB + FD + 2;  // partial rows per block
 
 // The four wavefronts of a sweep workgroup take every fourth row of its range; their partial
 // sums are added in LDS, in a fixed order, C rows at a time (buf holds 4 C rows of CW values),
@@ -245,8 +255,8 @@ __device__ __forceinline__ void combine_partials(const double2 (&acc)[NA], doubl
 
 // pass A: partial[blk][jj][r] = sum_d conj(Q_jj[d][r]) w[d][r] (jj < NJ) and row NJ with the
 // pending vector vt = U (diag + z), w = W + z U; one workgroup of four wavefronts per block of
-// rows
-template <int NJ>
+// rows. VN: rows jj < NJ only, of the pending vector itself (w = U (diag + z); W is not read).
+template <int NJ, bool VN = false>
 __global__ __launch_bounds__(256) void dcgs_dots_kernel(const double2* __restrict__ V,
                                                         int64_t vstride,
                                                         const double2* __restrict__ Wv,
@@ -261,9 +271,10 @@ __global__ __launch_bounds__(256) void dcgs_dots_kernel(const double2* __restric
   const int r = blockIdx.y * CW + lane;
   const bool live = r < nb;
   const double2 zz = live ? z[r] : make_double2(0.0, 0.0);
-  double2 acc[NJ + 1];
+  constexpr int NA = VN ? NJ : NJ + 1;
+  double2 acc[NA];
 #pragma unroll
-  for (int jj = 0; jj <= NJ; ++jj) acc[jj] = make_double2(0.0, 0.0);
+  for (int jj = 0; jj < NA; ++jj) acc[jj] = make_double2(0.0, 0.0);
   const int64_t rows_per_blk = (D + gridDim.x - 1) / gridDim.x;
   const int64_t d0 = (int64_t)blockIdx.x * rows_per_blk;
   const int64_t d1 = live ? min(D, d0 + rows_per_blk) : d0;
@@ -272,20 +283,24 @@ __global__ __launch_bounds__(256) void dcgs_dots_kernel(const double2* __restric
     double2 vj[NJ + 1];
 #pragma unroll
     for (int jj = 0; jj < NJ; ++jj) vj[jj] = V[(int64_t)jj * vstride + idx];
-    double2 w = Wv[idx];
     const double2 u = U[idx];
-    vj[NJ] = cmul(u, make_double2(diag[d] + zz.x, zz.y));
-    const double2 p = cmul(zz, u);
-    w.x += p.x;
-    w.y += p.y;
+    const double2 vt = cmul(u, make_double2(diag[d] + zz.x, zz.y));
+    double2 w = vt;
+    if (!VN) {
+      w = Wv[idx];
+      vj[NJ] = vt;
+      const double2 p = cmul(zz, u);
+      w.x += p.x;
+      w.y += p.y;
+    }
 #pragma unroll
-    for (int jj = 0; jj <= NJ; ++jj) {
+    for (int jj = 0; jj < NA; ++jj) {
       const double2 q = cconjmul(vj[jj], w);
       acc[jj].x += q.x;
       acc[jj].y += q.y;
     }
   }
-  combine_partials<NJ + 1, C>(acc, buf, partial + (int64_t)blockIdx.x * PSTR * nb, nb, nb);
+  combine_partials<NA, C>(acc, buf, partial + (int64_t)blockIdx.x * PSTR * nb, nb, nb);
 }
 
 // pass B over Q_0 .. Q_{NJ-1} and the pending vector vt = U (diag + z):
@@ -297,14 +312,16 @@ __global__ __launch_bounds__(256) void dcgs_dots_kernel(const double2* __restric
 // s, t: [NJ][nb] (t row NJ holds g). FINAL (end of a cycle) only writes q. Four wavefronts
 // share the coefficients of their 64 RHS in LDS (registers hold the basis rows and the dots)
 // and take every fourth row of the workgroup's range; the workgroup writes one partial row per
-// sum (combine_partials).
-template <int NJ, bool FINAL>
+// sum (combine_partials). PRE (the later sweep of a split pass): the slot of q holds
+// sum_i Q_i s_i over the earlier basis vectors and T1 their sum_i Q_i t_i, which start the
+// two combinations.
+template <int NJ, bool FINAL, bool PRE = false>
 __global__ __launch_bounds__(256, NJ <= 24 ? 2 : 1) void dcgs_update_kernel(
     double2* __restrict__ V, int64_t vstride, const double2* __restrict__ Wv,
     double2* __restrict__ U, const double2* __restrict__ z, const double* __restrict__ diag,
     const double2* __restrict__ sc, const double2* __restrict__ tc,
     const double* __restrict__ qscale, const double* __restrict__ vscale, int64_t D, int nb,
-    double2* __restrict__ partial) {
+    double2* __restrict__ partial, const double2* __restrict__ T1) {
   constexpr int NS = NJ > 0 ? NJ : 1;
   // the coefficients s (rows 0 .. NS-1) and t (rows NS ..) of the workgroup's 64 RHS; after the
   // sweep the same buffer adds the four wavefronts' partial sums, C rows at a time
@@ -352,6 +369,16 @@ __global__ __launch_bounds__(256, NJ <= 24 ? 2 : 1) void dcgs_update_kernel(
     double2 q = cmul(u, dz);
     double2 w = make_double2(0.0, 0.0);
     if (!FINAL) w = Wv[idx];
+    if (PRE) {
+      const double2 s1 = V[(int64_t)NJ * vstride + idx];
+      q.x -= s1.x;
+      q.y -= s1.y;
+      if (!FINAL) {
+        const double2 t1 = T1[idx];
+        w.x -= t1.x;
+        w.y -= t1.y;
+      }
+    }
 #pragma unroll
     for (int jj = 0; jj < NJ; ++jj) {
       const double2 a = cmul(vj[jj], s_l[jj][li]);
@@ -394,6 +421,58 @@ __global__ __launch_bounds__(256, NJ <= 24 ? 2 : 1) void dcgs_update_kernel(
   }
   if (FINAL) return;
   combine_partials<NA, C>(acc, buf, partial + ((int64_t)blockIdx.x * PSTR + PB) * NB, NB, nb);
+}
+
+// The earlier NC basis vectors' share of pass B when the pass is split (see above):
+// S = sum_{i<NC} Q_i s_i and, unless FINAL, T = sum_{i<NC} Q_i t_i, with the coefficients of
+// the workgroup's 64 RHS in LDS and the rows taken as in dcgs_update_kernel.
+template <int NC, bool FINAL>
+__global__ __launch_bounds__(256) void dcgs_lincomb_kernel(const double2* __restrict__ V,
+                                                           int64_t vstride,
+                                                           const double2* __restrict__ sc,
+                                                           const double2* __restrict__ tc,
+                                                           int64_t D, int nb,
+                                                           double2* __restrict__ S,
+                                                           double2* __restrict__ T) {
+  __shared__ double2 s_l[NC][CW];
+  __shared__ double2 t_l[FINAL ? 1 : NC][CW];
+  const int lane = threadIdx.x & (CW - 1), wave = threadIdx.x / CW;
+  const int r = blockIdx.y * CW + lane;
+  const int64_t NB = nb;
+  for (int e = threadIdx.x; e < NC * CW; e += 256) {
+    const int jj = e / CW, l = e % CW;
+    const int rr = blockIdx.y * CW + l;
+    s_l[jj][l] = rr < nb ? sc[jj * NB + rr] : make_double2(0.0, 0.0);
+    if (!FINAL) t_l[jj][l] = rr < nb ? tc[jj * NB + rr] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  if (r >= nb) return;
+  const int64_t rows_per_blk = (D + gridDim.x - 1) / gridDim.x;
+  const int64_t d0 = (int64_t)blockIdx.x * rows_per_blk;
+  const int64_t d1 = min(D, d0 + rows_per_blk);
+  for (int64_t d = d0 + wave; d < d1; d += 4) {
+    const int64_t idx = d * nb + r;
+    int opq;  // an opaque zero, as in dcgs_update_kernel
+    asm volatile("v_mov_b32 %0, 0" : "=v"(opq));
+    const int li = lane + opq;
+    double2 vj[NC];
+#pragma unroll
+    for (int jj = 0; jj < NC; ++jj) vj[jj] = V[(int64_t)jj * vstride + idx];
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int jj = 0; jj < NC; ++jj) {
+      const double2 p = cmul(vj[jj], s_l[jj][li]);
+      a.x += p.x;
+      a.y += p.y;
+      if (!FINAL) {
+        const double2 q = cmul(vj[jj], t_l[jj][li]);
+        b.x += q.x;
+        b.y += q.y;
+      }
+    }
+    S[idx] = a;
+    if (!FINAL) T[idx] = b;
+  }
 }
 
 // The step's reduction, grid (ceil(nb/64), nA + nB + nH), 256 threads:
@@ -457,14 +536,20 @@ typedef void (*DcgsDotsFn)(const double2*, int64_t, const double2*, const double
                            const double2*, const double*, int64_t, int, double2*);
 typedef void (*DcgsUpdateFn)(double2*, int64_t, const double2*, double2*, const double2*,
                              const double*, const double2*, const double2*, const double*,
-                             const double*, int64_t, int, double2*);
-template <int... I> struct DcgsTables {
-  static constexpr DcgsDotsFn dots[] = {dcgs_dots_kernel<I>...};           // NJ = 0 .. FJ-1
-  static constexpr DcgsUpdateFn update[] = {dcgs_update_kernel<I, false>...};  // NJ = 0 .. FJ-1
-  static constexpr DcgsUpdateFn final_[] = {dcgs_update_kernel<I + 1, true>...};  // 1 .. FJ
+                             const double*, int64_t, int, double2*, const double2*);
+typedef void (*DcgsLincombFn)(const double2*, int64_t, const double2*, const double2*, int64_t,
+                              int, double2*, double2*);
+template <int... I> struct DcgsTables {  // I = 1 .. FJ
+  static constexpr DcgsDotsFn dots[] = {dcgs_dots_kernel<0>, dcgs_dots_kernel<I>...};  // NJ = 0 .. FJ
+  static constexpr DcgsUpdateFn update[] = {dcgs_update_kernel<0, false>,
+                                            dcgs_update_kernel<I, false>...};  // NJ = 0 .. FJ
+  static constexpr DcgsUpdateFn final_[] = {dcgs_update_kernel<I, true>...};  // NJ - 1, NJ = 1 .. FJ
+  static constexpr DcgsDotsFn vdots[] = {dcgs_dots_kernel<I, true>...};           // NC - 1
+  static constexpr DcgsLincombFn lin[] = {dcgs_lincomb_kernel<I, false>...};      // NC - 1
+  static constexpr DcgsLincombFn lin_final[] = {dcgs_lincomb_kernel<I, true>...};  // NC - 1
 };
-using Dcgs = DcgsTables<0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20,
-                        21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31>;
+using Dcgs = DcgsTables<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20,
+                        21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31, 32>;
 
 
 // W[d][r] -= sum_{j<=k} V_j[d][r] * h[j][r]
@@ -1165,6 +1250,11 @@ struct GmresBlock {
     const int n = (int)std::min<int64_t>(1024, std::max<int64_t>(1, D * nb / 4096));
     return (n + 3) / 4 * 4;
   }
+  // rows of nb partial dots: the fused CGS2 sweeps write FJ per block of rows, the delayed-
+  // reorthogonalisation sweeps PSTR per workgroup (nblk / 4 of them)
+  static int64_t part_rows(int nblk) {
+    return std::max<int64_t>((int64_t)nblk * FJ, (int64_t)(nblk / 4) * PSTR);
+  }
   // bytes of the work arrays of a block (each array 256-byte aligned)
   static int64_t bytes_for(int64_t D, int nb, int m) {
     const int64_t vec = D * nb;
@@ -1179,9 +1269,9 @@ struct GmresBlock {
     add(nb, 16);                                              // z
     add(nb, 8);                                               // nrm
     add((int64_t)nblk * nb, 8);                               // part_n
-    add((int64_t)nblk * PSTR * nb, 16);                       // part_h
-    add((int64_t)PSTR * nb, 16); add((int64_t)(FJ + 1) * nb, 16);    // red hsb
-    add((int64_t)(FJ + 1) * nb, 16); add((int64_t)(FJ + 2) * nb, 16);  // scb tcb
+    add(part_rows(nblk) * nb, 16);                            // part_h
+    add((int64_t)PSTR * nb, 16); add((int64_t)(FD + 1) * nb, 16);    // red hsb
+    add((int64_t)(FD + 1) * nb, 16); add((int64_t)(FD + 2) * nb, 16);  // scb tcb
     add(nb, 8); add(nb, 8);                                   // qsc vsc
     add(nb, 4); add(nb, 4);                                   // used prow
     add((int64_t)nb * m * (m + 1), 16);                       // H
@@ -1226,11 +1316,11 @@ struct GmresBlock {
     z = carve<double2>(cur, nb);
     nrm = carve<double>(cur, nb);
     part_n = carve<double>(cur, (int64_t)nblk_rows * nb);
-    part_h = carve<double2>(cur, (int64_t)nblk_rows * PSTR * nb);
+    part_h = carve<double2>(cur, part_rows(nblk_rows) * nb);
     red = carve<double2>(cur, (int64_t)PSTR * nb);
-    hsb = carve<double2>(cur, (int64_t)(FJ + 1) * nb);
-    scb = carve<double2>(cur, (int64_t)(FJ + 1) * nb);
-    tcb = carve<double2>(cur, (int64_t)(FJ + 2) * nb);
+    hsb = carve<double2>(cur, (int64_t)(FD + 1) * nb);
+    scb = carve<double2>(cur, (int64_t)(FD + 1) * nb);
+    tcb = carve<double2>(cur, (int64_t)(FD + 2) * nb);
     qsc = carve<double>(cur, nb);
     vsc = carve<double>(cur, nb);
     used = carve<int>(cur, nb);
@@ -1519,23 +1609,64 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
       for (int b = 0; b < gb.nbrows_y; ++b) any |= f[b];
       return any != 0;
     };
-    const bool delayed = m <= FJ;
+    const bool delayed = m <= FD;
     if (delayed) {
       // Arnoldi with delayed reorthogonalisation: step k finalises column k - 1 and basis
       // vector k; the end of the cycle finalises column m - 1 and vector m
       bool stopped = false;
+      const double* dg = ctx->op.diag.as<double>();
+      const int64_t vs = D * nb;
       auto finish = [&](int j, int mode, int* fslot) {
         hipLaunchKernelGGL(dcgs_finish_kernel, dim3(gb.nbrows_y), dim3(CW), 0, st, j, m, nb,
                            maxit, mode, gb.s, gb.red, gb.hsb, gb.scb, gb.tcb, gb.qsc, gb.vsc,
                            fslot);
         GFCC_LAUNCH_CHECK();
       };
-      auto final_vector = [&](int j) {  // q_j = (vt_j - Q s) / rho, no new pending vector
-        hipLaunchKernelGGL(Dcgs::final_[j - 1], ugrid, dim3(256), 0, st, gb.V, D * nb, gb.W,
-                           gb.U, gb.z, ctx->op.diag.as<double>(), gb.scb, gb.tcb, gb.qsc,
-                           gb.vsc, D, nb, gb.part_h);
+      // pass A of step k over Q_0 .. Q_{k-1}: beyond FJ vectors the older c = k - FJ first;
+      // that sweep's pending-vector row c is then rewritten by the second one
+      auto dots_sweep = [&](int k) {
+        if (k <= FJ) {
+          hipLaunchKernelGGL(Dcgs::dots[k], ugrid, dim3(256), 0, st, gb.V, vs, gb.W, gb.U, gb.z,
+                             dg, D, nb, gb.part_h);
+          GFCC_LAUNCH_CHECK();
+          return;
+        }
+        const int c = k - FJ;
+        hipLaunchKernelGGL(Dcgs::dots[c], ugrid, dim3(256), 0, st, gb.V, vs, gb.W, gb.U, gb.z,
+                           dg, D, nb, gb.part_h);
+        GFCC_LAUNCH_CHECK();
+        hipLaunchKernelGGL(Dcgs::dots[FJ], ugrid, dim3(256), 0, st, gb.V + c * vs, vs, gb.W,
+                           gb.U, gb.z, dg, D, nb, gb.part_h + (int64_t)c * nb);
         GFCC_LAUNCH_CHECK();
       };
+      // pass B of step k (fin: the end of a cycle, q_k only). Beyond FJ vectors: the shares of
+      // Q_0 .. Q_{c-1} go to the slot of q_k and to R (free between the start of a cycle and
+      // its solution update), the sweep over the last FJ vectors completes q_k and the next
+      // pending vector, and the dots of Q_0 .. Q_{c-1} with that vector follow
+      auto update_sweep = [&](int k, bool fin) {
+        if (k <= FJ) {
+          hipLaunchKernelGGL(fin ? Dcgs::final_[k - 1] : Dcgs::update[k], ugrid, dim3(256), 0, st,
+                             gb.V, vs, gb.W, gb.U, gb.z, dg, gb.scb, gb.tcb, gb.qsc, gb.vsc, D,
+                             nb, gb.part_h, nullptr);
+          GFCC_LAUNCH_CHECK();
+          return;
+        }
+        const int c = k - FJ;
+        hipLaunchKernelGGL(fin ? Dcgs::lin_final[c - 1] : Dcgs::lin[c - 1], ugrid, dim3(256), 0,
+                           st, gb.V, vs, gb.scb, gb.tcb, D, nb, gb.V + k * vs, gb.R);
+        GFCC_LAUNCH_CHECK();
+        const DcgsUpdateFn later = fin ? dcgs_update_kernel<FJ, true, true>
+                                       : dcgs_update_kernel<FJ, false, true>;
+        hipLaunchKernelGGL(later, ugrid, dim3(256), 0, st, gb.V + c * vs, vs, gb.W, gb.U, gb.z, dg,
+                           gb.scb + (int64_t)c * nb, gb.tcb + (int64_t)c * nb, gb.qsc, gb.vsc, D,
+                           nb, gb.part_h + (int64_t)c * nb, gb.R);
+        GFCC_LAUNCH_CHECK();
+        if (fin) return;
+        hipLaunchKernelGGL(Dcgs::vdots[c - 1], ugrid, dim3(256), 0, st, gb.V, vs, nullptr, gb.U,
+                           gb.z, dg, D, nb, gb.part_h + (int64_t)PB * nb);
+        GFCC_LAUNCH_CHECK();
+      };
+      auto final_vector = [&](int j) { update_sweep(j, true); };  // q_j = (vt_j - Q s) / rho
       // one step of a small block (flags read one step late): the operator product, pass A,
       // the reduction, the finishing kernel and pass B
       auto late_step = [&](int k) {
@@ -1545,15 +1676,10 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
         } else {
           gb.apply_M(gb.U, gb.W, false, false);
         }
-        hipLaunchKernelGGL(Dcgs::dots[k], ugrid, dim3(256), 0, st, gb.V, D * nb, gb.W, gb.U, gb.z,
-                           ctx->op.diag.as<double>(), D, nb, gb.part_h);
-        GFCC_LAUNCH_CHECK();
+        dots_sweep(k);
         gb.dcgs_reduce(k + 1, k >= 1 ? k + 1 : 0, k >= 2 ? k : 0, k - 1);
         finish(k, 0, fslot);
-        hipLaunchKernelGGL(Dcgs::update[k], ugrid, dim3(256), 0, st, gb.V, D * nb, gb.W, gb.U,
-                           gb.z, ctx->op.diag.as<double>(), gb.scb, gb.tcb, gb.qsc, gb.vsc, D,
-                           nb, gb.part_h);
-        GFCC_LAUNCH_CHECK();
+        update_sweep(k, false);
       };
       // The same step as a HIP graph, one per step shape, kept by the context: the first
       // sighting of a shape runs eagerly (it tunes products and sizes workspaces), the second
@@ -1636,15 +1762,10 @@ static void solve_block(GmresBlock& gb, const double* omega, const int* pset, in
         } else {
           gb.apply_M(gb.U, gb.W, false, false);
         }
-        hipLaunchKernelGGL(Dcgs::dots[k], ugrid, dim3(256), 0, st, gb.V, D * nb, gb.W, gb.U, gb.z,
-                           ctx->op.diag.as<double>(), D, nb, gb.part_h);
-        GFCC_LAUNCH_CHECK();
+        dots_sweep(k);
         gb.dcgs_reduce(k + 1, 0, 0, 0);
         finish(k, k == 0 ? 0 : 2, nullptr);
-        hipLaunchKernelGGL(Dcgs::update[k], ugrid, dim3(256), 0, st, gb.V, D * nb, gb.W, gb.U,
-                           gb.z, ctx->op.diag.as<double>(), gb.scb, gb.tcb, gb.qsc, gb.vsc, D,
-                           nb, gb.part_h);
-        GFCC_LAUNCH_CHECK();
+        update_sweep(k, false);
       }
       if (!stopped) {  // the end of the cycle: column m - 1 and basis vector m
         gb.dcgs_reduce(0, m + 1, m >= 2 ? m : 0, m - 1);
