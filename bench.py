@@ -128,18 +128,21 @@ def rows_report(o, v, D, nb, t_step, t_build, sig_ms_step, sig_calls_step, its, 
     t_sig = sig_ms_step * 1e-3
     # GMRES vector work: everything in the step but the build and the sigma products; bytes as
     # counted per iteration j and right-hand side: 16 D (2j+3) (one Gram-Schmidt pass over the
-    # basis plus the update), and as moved by this implementation (restart lengths up to 32:
+    # basis plus the update), and as moved by this implementation (restart lengths up to 64:
     # delayed reorthogonalisation, a dot sweep reading the basis, the sigma output and its
     # input, from which the pending vector is recovered, j + 2 vectors, and an update sweep
     # reading the same and writing the final basis vector and the next input, j + 4): 16 D (2j+6)
+    # up to 32 basis vectors, 16 D (3j-19) beyond (each pass in two sweeps)
     algo = 0.0
     moved = 0.0
     for n in its.reshape(-1):
         for it in range(int(n)):
             j = it % restart
             algo += 16.0 * D * (2 * j + 3)
-            moved += 16.0 * D * ((2 * j + 6) if restart <= 32 else
-                                 ((3 * j + 13) if j < 32 else (4 * j + 18)))
+            if restart <= 64:
+                moved += 16.0 * D * ((2 * j + 6) if j <= 32 else (3 * j - 19))
+            else:
+                moved += 16.0 * D * ((3 * j + 13) if j < 32 else (4 * j + 18))
     t_vec = max(t_step - t_build - t_sig, 1e-9)
     return {
         "a1_build": {"s": t_build, "flops": build_flops, "tflops": build_flops / t_build / 1e12,
