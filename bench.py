@@ -1063,7 +1063,9 @@ def main():
             "block": nb, "restart": args.restart, "seed": cfg["seed"],
         },
         "roofline": {
-            "bound": "mfma", "kernel": "ovvo contraction (ovvo_kernel<double>, column-block loader)",
+            "bound": "mfma", "kernel": ("ovvo contraction (ovvo_kernel<double>, column-block loader, "
+                                         "with ovvo_tail_kernel for the rows past the last full "
+                                         "128-row tile)"),
             "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(o, v, nb),
             "avg_launch_ms": avg_ms, "launches": ovvo_n, "flops_per_launch": flops_launch,

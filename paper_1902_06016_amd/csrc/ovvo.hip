@@ -522,6 +522,67 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
     }
 }
 
+// The last t <= TAIL rows of Z (rows r0 .. r0 + t - 1) with vector FMAs. When M = o v leaves
+// only a few rows for a last 128-row tile (o v = 7812 = 61 x 128 + 4 at the benzene shape),
+// that tile row costs the matrix cores a full tile per column tile for a handful of useful
+// rows: 1.6% of the contraction there. Here a thread owns one column (j, c) of Z and walks
+// k = (m, e), m != j, reading r_mj^e[c] = +-X2[pair][e][c] once (coalesced over c) against the
+// t rows of W staged in LDS one segment m at a time, EC values of e per stage.
+constexpr int TAIL = 8;
+template <typename T>
+__global__ __launch_bounds__(256) void ovvo_tail_kernel(const T* __restrict__ W, int64_t lda,
+                                                        int transW, int r0, int t,
+                                                        const T* __restrict__ X2, int64_t ldx,
+                                                        int o, int v, int nc, T* __restrict__ Z,
+                                                        int64_t ldc) {
+  constexpr int EC = 256, XB = 16;
+  static_assert(EC % XB == 0, "a batch stays inside a stage");
+  __shared__ __attribute__((aligned(16))) T a_s[EC][TAIL];  // the t rows of one e, contiguous
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  const bool live = c < nc;
+  T acc[TAIL];
+#pragma unroll
+  for (int rr = 0; rr < TAIL; ++rr) acc[rr] = T(0);
+  for (int m = 0; m < o; ++m) {
+    if (m == j) continue;  // r_jj = 0
+    const int lo = m < j ? m : j, hi = m < j ? j : m;
+    const int64_t pr = (int64_t)lo * o - ((int64_t)lo * (lo + 1) >> 1) + (hi - lo - 1);
+    const bool neg = m > j;
+    for (int e0 = 0; e0 < v; e0 += EC) {
+      const int ne = min(EC, v - e0);
+      __syncthreads();  // the previous stage has been read
+      for (int f = threadIdx.x; f < TAIL * EC; f += 256) {
+        const int rr = f % TAIL, ee = f / TAIL;
+        T a = T(0);
+        if (rr < t && ee < ne) {
+          const int64_t k = (int64_t)m * v + e0 + ee;
+          a = transW ? W[k * lda + r0 + rr] : W[(int64_t)(r0 + rr) * lda + k];
+        }
+        a_s[ee][rr] = neg ? -a : a;
+      }
+      __syncthreads();
+      if (!live) continue;
+      // XB loads in flight per batch (the kernel is bound by their latency: one thread per
+      // column keeps too few bytes in flight otherwise); a_s is zero past ne, and EC is a
+      // multiple of XB, so a batch never reads past a_s
+      const int lx = (int)ldx;  // v ldx < 2^30 (checked by the launcher)
+      for (int eb = 0; eb < ne; eb += XB) {
+        const T* x = X2 + (pr * v + e0 + eb) * ldx + c;
+        T xv[XB];
+#pragma unroll
+        for (int u = 0; u < XB; ++u) xv[u] = eb + u < ne ? x[u * lx] : T(0);
+#pragma unroll
+        for (int u = 0; u < XB; ++u)
+#pragma unroll
+          for (int rr = 0; rr < TAIL; ++rr) acc[rr] += a_s[eb + u][rr] * xv[u];
+      }
+    }
+  }
+  if (!live) return;
+  for (int rr = 0; rr < t; ++rr) Z[(int64_t)(r0 + rr) * ldc + (int64_t)j * nc + c] = acc[rr];
+}
+
 }  // namespace
 
 // Returns false when the shape is outside what the kernels support (the caller then uses the
@@ -540,6 +601,10 @@ bool ovvo_fast(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, con
   p.lda = transW ? p.M : p.K;
   p.ldb = 0; p.ldc = p.N;
   p.alpha = T(1); p.beta = T(0);
+  // a last tile row of at most TAIL rows goes to ovvo_tail_kernel (M stays a multiple of the
+  // 16-byte A chunk: o v - t = 128 (o v / 128))
+  const int tail = (p.M > BM && p.M % BM <= TAIL) ? p.M % BM : 0;
+  p.M -= tail;
   p.mtiles = (p.M + BM - 1) / BM;
   p.ntiles = (p.N + BN - 1) / BN;
   p.nslabs = (p.K + BK - 1) / BK;
@@ -563,6 +628,12 @@ bool ovvo_fast(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, con
     else hipLaunchKernelGGL((ovvo_kernel<T, false, B_GATHER, false>), grid, dim3(NT), 0, st, p);
   }
   GFCC_LAUNCH_CHECK();
+  if (tail) {
+    hipLaunchKernelGGL(ovvo_tail_kernel<T>, dim3((unsigned)((nc + 255) / 256), (unsigned)o),
+                       dim3(256), 0, st, W, p.lda, transW ? 1 : 0, p.M, tail, X2, ldx, o, v, nc,
+                       Z, p.ldc);
+    GFCC_LAUNCH_CHECK();
+  }
   return true;
 }
 

@@ -52,6 +52,41 @@ def test_sigma_fp64(gpu_ctx, o, v, seed, nrhs, transpose):
     assert err < 1e-13, err
 
 
+# o v = 260 = 2 x 128 + 4 and 264 = 2 x 128 + 8: the last rows of the ovvo contraction run on
+# the vector tail kernel instead of a nearly empty last 128-row tile (the benzene shape's
+# 7812 = 61 x 128 + 4); o v = 265 leaves 9 rows, one more than the tail kernel takes. The
+# tuner is off so that the small forward products take the ovvo kernel route, not the
+# written-out operand; 64 right-hand sides use the column-block loader, 70 the general one.
+@pytest.mark.parametrize("o,v,seed", [(13, 20, 5), (11, 24, 6), (5, 53, 7)])
+@pytest.mark.parametrize("nrhs", [64, 70])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_sigma_ovvo_tail_rows(gpu_ctx, o, v, seed, nrhs, transpose):
+    print(f"[sigma tail rows o={o} v={v} nrhs={nrhs} T={transpose}]", flush=True)
+    prob = synth.make_problem(o, v, seed)
+    prob.t1 = synth.normal(seed, 9, o * v, 0.1).reshape(o, v)
+    hb = ohbar.build_hbar_from_problem(prob)
+    D = osig.dim(o, v)
+    rng = np.random.default_rng(seed + 100 * nrhs)
+    x = rng.standard_normal((nrhs, D)) + 1j * rng.standard_normal((nrhs, D))
+    ref = osig.sigma_t(hb, x) if transpose else osig.sigma(hb, x)
+    try:
+        gpu_ctx.autotune(0)
+        gpu_ctx.build_from_problem(prob)
+        y = gpu_ctx.sigma_apply(torch.from_numpy(x).cuda(), transpose=transpose).cpu().numpy()
+    finally:
+        gpu_ctx.autotune(1)
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    assert err < 1e-13, err
+    # the entries that take the tail rows' terms: the rows (i, a) = (o - 1, a >= v - t) of the
+    # contraction enter sigma at the pairs (j, o - 1), with the same virtual a (the packed
+    # 2h1p entry of pair (j, l) and a sits at o + pair(j, l) v + a), relative to their own size
+    t = min((o * v) % 128, 8)
+    idx = [o + (j * o - j * (j + 1) // 2 + (o - 2 - j)) * v + a
+           for j in range(o - 1) for a in range(v - t, v)]
+    err_tail = np.abs(y[:, idx] - ref[:, idx]).max() / np.abs(ref[:, idx]).max()
+    assert err_tail < 1e-12, err_tail
+
+
 # FP32 and FP32 + two-term bf16 three-body: a few float32 roundings of the largest terms
 # (measured 2e-7 against FP64). BF16_PAIRS: every large contraction carries about 16 bits, and
 # sums over o v terms grow that by their cancellation (the oracle's emulation is 8e-6 off FP64
