@@ -528,7 +528,7 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
 // rows: 1.6% of the contraction there. Here a thread owns one column (j, c) of Z and walks
 // k = (m, e), m != j, reading r_mj^e[c] = +-X2[pair][e][c] once (coalesced over c) against the
 // t rows of W staged in LDS one segment m at a time, EC values of e per stage.
-constexpr int TAIL = 8;
+constexpr int TAIL = 8, TAIL_MIN_NC = 2048;
 template <typename T>
 __global__ __launch_bounds__(256) void ovvo_tail_kernel(const T* __restrict__ W, int64_t lda,
                                                         int transW, int r0, int t,
@@ -602,8 +602,11 @@ bool ovvo_fast(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, con
   p.ldb = 0; p.ldc = p.N;
   p.alpha = T(1); p.beta = T(0);
   // a last tile row of at most TAIL rows goes to ovvo_tail_kernel (M stays a multiple of the
-  // 16-byte A chunk: o v - t = 128 (o v / 128))
-  const int tail = (p.M > BM && p.M % BM <= TAIL) ? p.M % BM : 0;
+  // 16-byte A chunk: o v - t = 128 (o v / 128)) when the block has at least 2048 columns: each
+  // workgroup of the tail kernel walks all of k for 256 columns, so narrower blocks leave most
+  // of the chip idle for longer than the tile row it replaces would take (at 128 columns, 1 ms
+  // against 0.17)
+  const int tail = (p.M > BM && p.M % BM <= TAIL && nc >= TAIL_MIN_NC) ? p.M % BM : 0;
   p.M -= tail;
   p.mtiles = (p.M + BM - 1) / BM;
   p.ntiles = (p.N + BN - 1) / BN;

@@ -52,13 +52,15 @@ def test_sigma_fp64(gpu_ctx, o, v, seed, nrhs, transpose):
     assert err < 1e-13, err
 
 
-# o v = 260 = 2 x 128 + 4 and 264 = 2 x 128 + 8: the last rows of the ovvo contraction run on
-# the vector tail kernel instead of a nearly empty last 128-row tile (the benzene shape's
-# 7812 = 61 x 128 + 4); o v = 265 leaves 9 rows, one more than the tail kernel takes. The
-# tuner is off so that the small forward products take the ovvo kernel route, not the
-# written-out operand; 64 right-hand sides use the column-block loader, 70 the general one.
+# o v = 260 = 2 x 128 + 4 and 264 = 2 x 128 + 8: with at least 2048 columns (1024 complex
+# right-hand sides) the last rows of the ovvo contraction run on the vector tail kernel instead
+# of a nearly empty last 128-row tile (the benzene shape's 7812 = 61 x 128 + 4); o v = 265
+# leaves 9 rows, one more than the tail kernel takes, and 64 right-hand sides are below the
+# width it needs. The tuner is off so that the forward products take the ovvo kernel route,
+# not the written-out operand; 1024 and 64 right-hand sides use the column-block loader, 1030
+# the general one.
 @pytest.mark.parametrize("o,v,seed", [(13, 20, 5), (11, 24, 6), (5, 53, 7)])
-@pytest.mark.parametrize("nrhs", [64, 70])
+@pytest.mark.parametrize("nrhs", [1024, 1030, 64])
 @pytest.mark.parametrize("transpose", [False, True])
 def test_sigma_ovvo_tail_rows(gpu_ctx, o, v, seed, nrhs, transpose):
     print(f"[sigma tail rows o={o} v={v} nrhs={nrhs} T={transpose}]", flush=True)
