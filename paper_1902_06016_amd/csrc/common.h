@@ -238,9 +238,13 @@ inline int64_t ovvo_pad_bytes(int64_t M) { return 512 * M; }
 // false when the product has too few 128 x 128 tiles to fill the GPU.
 // a_padded: every row of A (its k dimension, or m when transposed) continues with finite
 // entries up to a multiple of 16 bytes inside lda, so that 16-byte loads may cover the tail.
+// Zas (with as_o, as_v, as_nc): C is the 2h1p block [P pairs][v nc] of the forward sigma and
+// the epilogue adds its antisymmetrised ovvo term Z[(i,a)][(j,c)] - Z[(j,a)][(i,c)] (row
+// pair(i, j), column a nc + c; Z [o v][o nc]).
 template <typename T>
 bool gemm_pipe(gfcc_ctx* ctx, bool transA, int M, int N, int K, T alpha, const T* A, int64_t lda,
-               const T* B, int64_t ldb, T beta, T* C, int64_t ldc, bool a_padded = false);
+               const T* B, int64_t ldb, T beta, T* C, int64_t ldc, bool a_padded = false,
+               const T* Zas = nullptr, int as_o = 0, int as_v = 0, int as_nc = 0);
 
 // Split-K partial products on the same kernel: part[y][M][N] = op(A) B over the k range
 // [y kchunk, (y+1) kchunk) for y < splits (kchunk a multiple of 128 bytes of k); the caller

@@ -84,10 +84,24 @@ template <typename T> struct OvvoArgs {
   int kchunk;        // dense split-K: k per split (a multiple of the slab), 0 without split
   int nsplit;        // dense split-K: number of splits (1 without split)
   int64_t sC;        // dense split-K: stride between the partial products
+  const T* Zas;      // dense: antisymmetrised ovvo term added in the epilogue (null: none)
+  int as_o, as_v, as_nc;
 };
 
 __device__ __forceinline__ int pair_index(int i, int j, int o) {  // i < j
   return i * o - (i * (i + 1) >> 1) + (j - i - 1);
+}
+
+// (i, j), i < j, of pair index q (the inverse of pair_index): the root of the quadratic in
+// double, then an exact integer correction
+__device__ __forceinline__ void pair_of(int q, int o, int& i, int& j) {
+  const double b = 2.0 * o - 1.0;
+  int ii = (int)floor((b - sqrt(b * b - 8.0 * q)) * 0.5);
+  ii = max(0, min(ii, o - 2));
+  while (ii > 0 && pair_index(ii, ii + 1, o) > q) --ii;
+  while (ii + 1 <= o - 2 && pair_index(ii + 1, ii + 2, o) <= q) ++ii;
+  i = ii;
+  j = q - pair_index(ii, ii + 1, o) + ii + 1;
 }
 
 template <int N> struct IC { static constexpr int value = N; };
@@ -505,6 +519,39 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
   }
 
   const int col_l = lane & 15;
+  if (DENSE && p.Zas) {
+    // C = Y2 [pair][a nc + c]: row mrow = pair(pi, pj), column nn = a nc + c gets
+    // Z[(pi,a)][(pj,c)] - Z[(pj,a)][(pi,c)]; the columns' (a, c) once per thread, the rows'
+    // pairs once per row
+    const int ao = p.as_o, av = p.as_v, anc = p.as_nc;
+    const int64_t ldz = (int64_t)ao * anc;
+    int ca[4], cc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int nn = min(n0 + wn * 64 + q * 16 + col_l, p.N - 1);
+      ca[q] = nn / anc;
+      cc[q] = nn - ca[q] * anc;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int mrow = m0 + wm * 64 + i * 16 + M4::row(lane, e);
+        if (mrow >= M) continue;
+        int pi, pj;
+        pair_of(mrow, ao, pi, pj);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int nn = n0 + wn * 64 + q * 16 + col_l;
+          if (nn >= p.N) continue;
+          T* cp = p.Z + (int64_t)ysplit * p.sC + (int64_t)mrow * p.ldc + nn;
+          const T zt = p.Zas[((int64_t)pi * av + ca[q]) * ldz + (int64_t)pj * anc + cc[q]] -
+                       p.Zas[((int64_t)pj * av + ca[q]) * ldz + (int64_t)pi * anc + cc[q]];
+          *cp = p.alpha * acc[i][q][e] + (p.beta != T(0) ? p.beta * *cp : T(0)) + zt;
+        }
+      }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -645,7 +692,8 @@ bool ovvo_fast(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, con
 // or too thin to fill the GPU with 128 x 128 tiles (the caller then uses the split-K kernel).
 template <typename T>
 bool gemm_pipe(gfcc_ctx* ctx, bool transA, int M, int N, int K, T alpha, const T* A, int64_t lda,
-               const T* B, int64_t ldb, T beta, T* C, int64_t ldc, bool a_padded) {
+               const T* B, int64_t ldb, T beta, T* C, int64_t ldc, bool a_padded, const T* Zas,
+               int as_o, int as_v, int as_nc) {
   constexpr int BK = 128 / (int)sizeof(T);
   constexpr int VPC = 16 / (int)sizeof(T);
   // thin products (vectors, a few rows or columns) would waste most of a 128 x 128 tile
@@ -663,6 +711,12 @@ bool gemm_pipe(gfcc_ctx* ctx, bool transA, int M, int N, int K, T alpha, const T
   p.alpha = alpha; p.beta = beta;
   p.nsplit = 1;
   p.nc = 1; p.o = 1; p.v = 1; p.ldx = 0;
+  if (Zas) {
+    GFCC_REQUIRE(as_o >= 2 && as_v >= 1 && as_nc >= 1 && M == as_o * (as_o - 1) / 2 &&
+                     (int64_t)N == (int64_t)as_v * as_nc && ldc == N,
+                 GFCC_EINVAL, "gemm_pipe: the antisymmetric term needs C = [pairs][v nc]");
+    p.Zas = Zas; p.as_o = as_o; p.as_v = as_v; p.as_nc = as_nc;
+  }
   p.zrow = static_cast<const T*>(zero_row(ctx, (size_t)N * sizeof(T)));
   // 16-byte A chunks need aligned rows and a chunked dimension that is a multiple of the chunk
   // (the clamp of the last chunk then stays inside the row), or rows padded with finite
@@ -733,8 +787,10 @@ template bool ovvo_fast<double>(gfcc_ctx*, bool, int, int, int, const double*, c
 template bool ovvo_fast<float>(gfcc_ctx*, bool, int, int, int, const float*, const float*,
                                int64_t, float*, const float*);
 template bool gemm_pipe<double>(gfcc_ctx*, bool, int, int, int, double, const double*, int64_t,
-                                const double*, int64_t, double, double*, int64_t, bool);
+                                const double*, int64_t, double, double*, int64_t, bool,
+                                const double*, int, int, int);
 template bool gemm_pipe<float>(gfcc_ctx*, bool, int, int, int, float, const float*, int64_t,
-                               const float*, int64_t, float, float*, int64_t, bool);
+                               const float*, int64_t, float, float*, int64_t, bool, const float*,
+                               int, int, int);
 
 }  // namespace gfcc

@@ -77,12 +77,17 @@ inline unsigned grid_for(int64_t n) {
 }
 
 // Y2 += (Woo (x) I_v) . X2 (or Woo^T): Woo's rows are padded with zeros to ldw, which lets the
-// pipelined kernel use 16-byte loads although P is odd
+// pipelined kernel use 16-byte loads although P is odd. With Z (forward sigma), antisym(Z) is
+// added in the epilogue of the pipelined kernel when that kernel takes the product; returns
+// whether it was.
 template <typename T>
-void woo_product(gfcc_ctx* ctx, bool transW, int64_t P, int64_t N, const T* Woo, int64_t ldw,
-                 const T* X2, T* Y2) {
-  if (!gemm_pipe<T>(ctx, transW, (int)P, (int)N, (int)P, T(1), Woo, ldw, X2, N, T(1), Y2, N, true))
-    gemm<T>(ctx, transW, false, (int)P, (int)N, (int)P, T(1), Woo, ldw, X2, N, T(1), Y2, N);
+bool woo_product(gfcc_ctx* ctx, bool transW, int64_t P, int64_t N, const T* Woo, int64_t ldw,
+                 const T* X2, T* Y2, const T* Z = nullptr, int o = 0, int v = 0, int nc = 0) {
+  if (gemm_pipe<T>(ctx, transW, (int)P, (int)N, (int)P, T(1), Woo, ldw, X2, N, T(1), Y2, N, true,
+                   Z, o, v, nc))
+    return Z != nullptr;
+  gemm<T>(ctx, transW, false, (int)P, (int)N, (int)P, T(1), Woo, ldw, X2, N, T(1), Y2, N);
+  return false;
 }
 
 template <typename T>
@@ -258,10 +263,12 @@ void sigma_block_f64(gfcc_ctx* ctx, int nc, const double* X, double* Y, bool tra
       copy_async<double>(ctx, S, X1, (int64_t)o * nc);
       gemm<double>(ctx, false, false, (int)PV, nc, o + v, 1.0, f.W4c.as<double>(), o + v, S, nc,
                    0.0, Y2, nc);
-      woo_product<double>(ctx, false, P, (int64_t)v * nc, f.Woo.as<double>(), op.ldwoo, X2, Y2);
-      hipLaunchKernelGGL(antisym_add_kernel<double>, dim3((unsigned)PV), dim3(256), 0,
-                         ctx->stream, Z, o, v, nc, Y2);
-      GFCC_LAUNCH_CHECK();
+      if (!woo_product<double>(ctx, false, P, (int64_t)v * nc, f.Woo.as<double>(), op.ldwoo,
+                               X2, Y2, Z, o, v, nc)) {
+        hipLaunchKernelGGL(antisym_add_kernel<double>, dim3((unsigned)PV), dim3(256), 0,
+                           ctx->stream, Z, o, v, nc, Y2);
+        GFCC_LAUNCH_CHECK();
+      }
     });
   } else {
     gemm<double>(ctx, true, false, (int)D, nc, o, 1.0, f.W1.as<double>(), D, X1, nc, 0.0, Y, nc);
