@@ -221,7 +221,9 @@ gfcc_status gfcc_compact(gfcc_ctx* ctx, int enable);
  *   an inner GMRES whose sigma product runs in that precision; the stopping test is always
  *   the FP64 true relative residual).
  * tol: relative residual ||b - M x|| / ||b||. maxit: max iterations per right-hand side
- *   (inner+outer). restart: Krylov restart length (1..200). block: number of right-hand
+ *   (inner+outer). restart: Krylov restart length (1..200; up to 64 the second Gram-Schmidt
+ *   pass is delayed by one step, so the basis is swept twice per step instead of four times,
+ *   which is the faster choice for long cycles). block: number of right-hand
  *   sides solved together (0 = library default, at most 2048). Multiples of 64 keep the
  *   fastest ovvo loader; a block that holds every right-hand side is padded with zero
  *   right-hand sides up to the next multiple of 64 when that adds at most a quarter; the last
