@@ -107,3 +107,31 @@ def test_large_block_against_oracle_residual(gpu_ctx, restart):
               f"{res.resid[w, k]:.2e} vs oracle {true:.2e} (rounding scale {fl:.1e})", flush=True)
         assert abs(true - res.resid[w, k]) <= 1e-13 + 16 * fl
         assert true <= tol + 16 * fl
+
+
+@pytest.mark.parametrize("restart,prec", [(33, gfcc.FP64), (48, gfcc.FP32), (48, gfcc.BF16_PAIRS)])
+def test_smallest_split_and_reduced_precision(gpu_ctx, restart, prec):
+    """Restart 33: every split has a single earlier basis vector (c = 1). Reduced-precision
+    GMRES-IR at restart 48: the inner cycles run the split sweeps on vectors whose sigma comes
+    in FP32 (or bf16 pairs), every cycle restarts from the explicit FP64 residual, and the
+    scratch vector of the split update sweep is that residual's buffer between restarts. Small
+    case next to the 1h poles, against dense LU (tol 1e-10 on the FP64 residual)."""
+    print(f"[long restart restart={restart} prec={prec}]", flush=True)
+    o, v, eta = 10, 20, 0.01
+    prob = synth.make_problem(o, v, 0)
+    hb = ohbar.build_hbar_from_problem(prob)
+    dg = osig.diagonal(hb)
+    om = np.concatenate([-dg[o - 1] + np.array([-3e-3, 2e-3, 6e-3]), np.linspace(-1.0, -0.3, 5)])
+    ps = np.array([o - 3, o - 2, o - 1], dtype=np.int32)
+    keep = gfcc.KEEP_FP64 | (gfcc.KEEP_FP32 if prec != gfcc.FP64 else 0)
+    gpu_ctx.build_from_problem(prob, keep=keep)
+    res = gpu_ctx.gfcc_solve(om, ps, eta, tol=1e-10, restart=restart, maxit=3000,
+                             precision=prec, want_x=True)
+    print(f"  iterations {res.iters.min()}..{res.iters.max()}", flush=True)
+    assert res.resid.max() <= 1e-10
+    assert res.iters.max() > 33
+    H = osolve.dense_hbar(hb)
+    B = np.stack([osig.b_vector(o, v, int(p)) for p in ps], 1)
+    Xr = osolve.dense_solve(H, om, B, eta)
+    err = np.abs(res.X.cpu().numpy() - Xr).max() / np.abs(Xr).max()
+    assert err < 1e-7, err
