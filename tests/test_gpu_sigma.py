@@ -124,6 +124,35 @@ def test_sigma_reduced_precision(gpu_ctx, prec, tol, tol_emu, nrhs):
         assert e9 < 1e-4, e9
 
 
+def test_sigma_fp32_wide_block_tail_rows(gpu_ctx):
+    """The FP32 ovvo contraction on a wide block (1024 right-hand sides) at o v = 260 = 2 x 128
+    + 4: its last 4 rows take the float tail kernel. Against FP64 at the FP32 tolerance of the
+    reduced-precision test and against the oracle's float32 emulation."""
+    o, v, seed, nrhs = 13, 20, 5, 1024
+    print(f"[sigma fp32 wide block o={o} v={v} nrhs={nrhs}]", flush=True)
+    prob = synth.make_problem(o, v, seed)
+    hb = ohbar.build_hbar_from_problem(prob)
+    from paper_1902_06016_amd import gfcc
+    from oracle import mixed as omix
+    D = osig.dim(o, v)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((nrhs, D)) + 1j * rng.standard_normal((nrhs, D))
+    try:
+        gpu_ctx.autotune(0)
+        gpu_ctx.build_from_problem(prob, keep=gfcc.KEEP_FP32)
+        y = gpu_ctx.sigma_apply(torch.from_numpy(x).cuda(), precision=gfcc.FP32).cpu().numpy()
+    finally:
+        gpu_ctx.autotune(1)
+    ref = osig.sigma(hb, x)
+    assert np.abs(y - ref).max() / np.abs(ref).max() < 2e-6
+    emu = omix.sigma_reduced(omix.f32_hbar(hb), x, bf16_3body=False, pairs=False)
+    assert np.abs(y - emu).max() <= 2e-6 * np.abs(ref).max()
+    # the entries the tail rows feed (pairs (j, o - 1), the last 4 virtuals), at the same bound
+    idx = [o + (j * o - j * (j + 1) // 2 + (o - 2 - j)) * v + a
+           for j in range(o - 1) for a in range(v - 4, v)]
+    assert np.abs(y[:, idx] - ref[:, idx]).max() < 2e-6 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("o,v,nrhs", [(5, 130, 64), (3, 64, 128)])
 def test_sigma_pairs_skip_and_tiles(gpu_ctx, o, v, nrhs):
     """The two-term bf16 ovvo where whole 64-row slabs lie inside a tile's zero segment m = j
