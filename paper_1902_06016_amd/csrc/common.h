@@ -162,6 +162,7 @@ struct gfcc_ctx {
   gfcc::DevBuf ws_io;       // sigma_apply: D-major copies of its input and output blocks
   gfcc::DevBuf ws_pairs;    // the expanded bf16-pair operand of the two-term ovvo product
   gfcc::DevBuf ws_rexp;     // the expanded FP64 ovvo operand of small sigma products
+  gfcc::DevBuf ws_tail;     // partial sums of the ovvo contraction's tail rows (split over m)
   gfcc::DevBuf ws_solve, ws_solve_f32;  // GMRES block work arrays (Krylov basis, state)
   std::vector<gfcc::DevBuf> build_pool;  // operator-build buffers kept for the next build
   gfcc::DevBuf zrow;        // zeros (read for structurally zero rows of the ovvo operand)

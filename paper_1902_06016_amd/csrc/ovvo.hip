@@ -574,14 +574,18 @@ __global__ __launch_bounds__(NT, 2) void ovvo_kernel(OvvoArgs<T> p) {
 // that tile row costs the matrix cores a full tile per column tile for a handful of useful
 // rows: 1.6% of the contraction there. Here a thread owns one column (j, c) of Z and walks
 // k = (m, e), m != j, reading r_mj^e[c] = +-X2[pair][e][c] once (coalesced over c) against the
-// t rows of W staged in LDS one segment m at a time, EC values of e per stage.
-constexpr int TAIL = 8, TAIL_MIN_NC = 2048;
+// t rows of W staged in LDS one segment m at a time, EC values of e per stage. Narrow blocks
+// split the segments m over blockIdx.z (mchunk each) so that the grid still fills the chip:
+// each split then writes its partial sums to part[z][rr][N] (N = o nc), which
+// ovvo_tail_reduce_kernel adds in split order; part null: one split, written to Z.
+constexpr int TAIL = 8, TAIL_MIN_NC = 256;
 template <typename T>
 __global__ __launch_bounds__(256) void ovvo_tail_kernel(const T* __restrict__ W, int64_t lda,
                                                         int transW, int r0, int t,
                                                         const T* __restrict__ X2, int64_t ldx,
                                                         int o, int v, int nc, T* __restrict__ Z,
-                                                        int64_t ldc) {
+                                                        int64_t ldc, int mchunk,
+                                                        T* __restrict__ part) {
   constexpr int EC = 256, XB = 16;
   static_assert(EC % XB == 0, "a batch stays inside a stage");
   __shared__ __attribute__((aligned(16))) T a_s[EC][TAIL];  // the t rows of one e, contiguous
@@ -591,7 +595,8 @@ __global__ __launch_bounds__(256) void ovvo_tail_kernel(const T* __restrict__ W,
   T acc[TAIL];
 #pragma unroll
   for (int rr = 0; rr < TAIL; ++rr) acc[rr] = T(0);
-  for (int m = 0; m < o; ++m) {
+  const int m_lo = blockIdx.z * mchunk, m_hi = min(o, m_lo + mchunk);
+  for (int m = m_lo; m < m_hi; ++m) {
     if (m == j) continue;  // r_jj = 0
     const int lo = m < j ? m : j, hi = m < j ? j : m;
     const int64_t pr = (int64_t)lo * o - ((int64_t)lo * (lo + 1) >> 1) + (hi - lo - 1);
@@ -627,7 +632,28 @@ __global__ __launch_bounds__(256) void ovvo_tail_kernel(const T* __restrict__ W,
     }
   }
   if (!live) return;
-  for (int rr = 0; rr < t; ++rr) Z[(int64_t)(r0 + rr) * ldc + (int64_t)j * nc + c] = acc[rr];
+  const int64_t N = (int64_t)o * nc;
+  for (int rr = 0; rr < t; ++rr) {
+    if (part)
+      part[((int64_t)blockIdx.z * TAIL + rr) * N + (int64_t)j * nc + c] = acc[rr];
+    else
+      Z[(int64_t)(r0 + rr) * ldc + (int64_t)j * nc + c] = acc[rr];
+  }
+}
+
+// Z rows r0 .. r0 + t - 1 = the sum of the ns splits' partial rows, in split order
+template <typename T>
+__global__ void ovvo_tail_reduce_kernel(const T* __restrict__ part, int ns, int t, int64_t N,
+                                        int r0, T* __restrict__ Z, int64_t ldc) {
+  const int64_t n = (int64_t)t * N;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int rr = (int)(idx / N);
+    const int64_t col = idx - (int64_t)rr * N;
+    T s = T(0);
+    for (int z = 0; z < ns; ++z) s += part[((int64_t)z * TAIL + rr) * N + col];
+    Z[(int64_t)(r0 + rr) * ldc + col] = s;
+  }
 }
 
 }  // namespace
@@ -649,10 +675,8 @@ bool ovvo_fast(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, con
   p.ldb = 0; p.ldc = p.N;
   p.alpha = T(1); p.beta = T(0);
   // a last tile row of at most TAIL rows goes to ovvo_tail_kernel (M stays a multiple of the
-  // 16-byte A chunk: o v - t = 128 (o v / 128)) when the block has at least 2048 columns: each
-  // workgroup of the tail kernel walks all of k for 256 columns, so narrower blocks leave most
-  // of the chip idle for longer than the tile row it replaces would take (at 128 columns, 1 ms
-  // against 0.17)
+  // 16-byte A chunk: o v - t = 128 (o v / 128)) when the block has at least 256 columns
+  // (below that the tile row it replaces costs next to nothing)
   const int tail = (p.M > BM && p.M % BM <= TAIL && nc >= TAIL_MIN_NC) ? p.M % BM : 0;
   p.M -= tail;
   p.mtiles = (p.M + BM - 1) / BM;
@@ -679,10 +703,30 @@ bool ovvo_fast(gfcc_ctx* ctx, bool transW, int o, int v, int nc, const T* W, con
   }
   GFCC_LAUNCH_CHECK();
   if (tail) {
-    hipLaunchKernelGGL(ovvo_tail_kernel<T>, dim3((unsigned)((nc + 255) / 256), (unsigned)o),
+    // splits of the segments m so that the tail grid has about 512 workgroups: one at the
+    // benchmark's 3200 columns (13 x 42 workgroups), five at 640
+    const int bx = (nc + 255) / 256;
+    int mchunk = o;
+    if (bx * o < 512) {
+      const int want = std::min(o, (512 + bx * o - 1) / (bx * o));
+      mchunk = (o + want - 1) / want;
+    }
+    const int ns = (o + mchunk - 1) / mchunk;
+    T* part = nullptr;
+    if (ns > 1) {
+      ws_ensure(ctx, ctx->ws_tail, sizeof(T) * (size_t)ns * TAIL * (size_t)p.N);
+      part = ctx->ws_tail.as<T>();
+    }
+    hipLaunchKernelGGL(ovvo_tail_kernel<T>, dim3((unsigned)bx, (unsigned)o, (unsigned)ns),
                        dim3(256), 0, st, W, p.lda, transW ? 1 : 0, p.M, tail, X2, ldx, o, v, nc,
-                       Z, p.ldc);
+                       Z, p.ldc, mchunk, part);
     GFCC_LAUNCH_CHECK();
+    if (part) {
+      hipLaunchKernelGGL(ovvo_tail_reduce_kernel<T>,
+                         dim3((unsigned)std::min<int64_t>(4096, ((int64_t)tail * p.N + 255) / 256)),
+                         dim3(256), 0, st, part, ns, tail, (int64_t)p.N, p.M, Z, p.ldc);
+      GFCC_LAUNCH_CHECK();
+    }
   }
   return true;
 }

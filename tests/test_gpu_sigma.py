@@ -52,17 +52,19 @@ def test_sigma_fp64(gpu_ctx, o, v, seed, nrhs, transpose):
     assert err < 1e-13, err
 
 
-# Wide blocks (1024 and 1030 complex right-hand sides, 2048 and 2060 columns), with the tuner
-# off so that the forward products take the ovvo kernel and the unfused linear route:
-# o v = 260 = 2 x 128 + 4 and 264 = 2 x 128 + 8 put the last rows of the ovvo contraction on
-# the vector tail kernel instead of a nearly empty last 128-row tile (the benzene shape's
-# 7812 = 61 x 128 + 4); o v = 265 leaves 9 rows, one more than the tail kernel takes, and 64
-# right-hand sides are below the width it needs. o = 13 and 16 (78 and 120 pairs) give the
-# Woo product enough tiles for the pipelined kernel, whose epilogue then adds the
-# antisymmetrised ovvo term (no separate pass). 1024 and 64 right-hand sides use the
-# column-block loader, 1030 the general one.
+# Wide blocks (1024 and 1030 complex right-hand sides, 2048 and 2060 columns; 160 right-hand
+# sides, 320 columns), with the tuner off so that the forward products take the ovvo kernel
+# and the unfused linear route: o v = 260 = 2 x 128 + 4 and 264 = 2 x 128 + 8 put the last
+# rows of the ovvo contraction on the vector tail kernel instead of a nearly empty last
+# 128-row tile (the benzene shape's 7812 = 61 x 128 + 4), its segments m split over 5 to 13
+# workgroup layers added in order (at 320 columns some layers hold only the skipped m = j);
+# o v = 265 leaves 9 rows, one more than the tail kernel takes, and 64 right-hand sides are
+# below the width it needs. o = 13 and 16 (78 and 120 pairs) give the Woo product enough tiles
+# for the pipelined kernel, whose epilogue then adds the antisymmetrised ovvo term (no
+# separate pass). 1024, 160 and 64 right-hand sides use the column-block loader, 1030 the
+# general one.
 @pytest.mark.parametrize("o,v,seed", [(13, 20, 5), (11, 24, 6), (5, 53, 7), (16, 30, 8)])
-@pytest.mark.parametrize("nrhs", [1024, 1030, 64])
+@pytest.mark.parametrize("nrhs", [1024, 1030, 160, 64])
 @pytest.mark.parametrize("transpose", [False, True])
 def test_sigma_wide_blocks(gpu_ctx, o, v, seed, nrhs, transpose):
     print(f"[sigma wide blocks o={o} v={v} nrhs={nrhs} T={transpose}]", flush=True)
