@@ -195,8 +195,9 @@ void sigma_block_f64(gfcc_ctx* ctx, int nc, const double* X, double* Y, bool tra
   double* Z = ctx->ws_b.as<double>();
   hipEvent_t e_all = nullptr, e_ovvo = nullptr;
   timer_begin(ctx, 1, &e_all);
-  // Z = Weff . r (the ovvo contraction), then the linear products; the fused 2h1p product adds
-  // antisym(Z) in its epilogue, the other routes with antisym_add_kernel
+  // Z = Weff . r (the ovvo contraction), then the linear products; the fused 2h1p product, or
+  // the Woo product when the pipelined kernel takes it, adds antisym(Z) in its epilogue,
+  // otherwise antisym_add_kernel does
   timer_begin(ctx, 0, &e_ovvo);
   gemm_ovvo<double>(ctx, transpose, o, v, nc, f.Weff.as<double>(), X2, nc,
                     op.pairlut.as<int>(), Z);
@@ -279,7 +280,8 @@ void sigma_block_f64(gfcc_ctx* ctx, int nc, const double* X, double* Y, bool tra
     GFCC_LAUNCH_CHECK();
     gemm<double>(ctx, false, false, (int)PV, nc, v, 1.0, f.Vp.as<double>(), v,
                  S + (int64_t)o * nc, nc, 1.0, Y2, nc);
-    woo_product<double>(ctx, true, P, (int64_t)v * nc, f.Woo.as<double>(), op.ldwoo, X2, Y2);
+    antisym_done = woo_product<double>(ctx, true, P, (int64_t)v * nc, f.Woo.as<double>(),
+                                       op.ldwoo, X2, Y2, Z, o, v, nc);
   }
   if (!antisym_done) {
     hipLaunchKernelGGL(antisym_add_kernel<double>, dim3((unsigned)PV), dim3(256), 0,
