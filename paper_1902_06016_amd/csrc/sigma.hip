@@ -329,7 +329,8 @@ void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, int precis
     gemm<float>(ctx, false, false, (int)PV, nc, o, 1.0f, f.W4.as<float>(), o, X1, nc, 0.0f, Y2, nc);
     pairs_gemm(ctx, op.T2p_bf16.p, op.T2p_bf16_lo.p, (int)PV, v, tau, nc, nc, Y2, nc, true);
   }
-  woo_product<float>(ctx, false, P, (int64_t)v * nc, f.Woo.as<float>(), op.ldwoo, X2, Y2);
+  // the ovvo contraction before the Woo product, whose epilogue then adds antisym(Z) when the
+  // pipelined kernel takes it
   timer_begin(ctx, 0, &e_ovvo);
   hipEvent_t e_bf3 = nullptr;
   timer_begin(ctx, 2, &e_bf3);
@@ -342,9 +343,12 @@ void sigma_block_f32(gfcc_ctx* ctx, int nc, const float* X, float* Y, int precis
   }
   timer_end(ctx, 0, e_ovvo);
   GFCC_REQUIRE(PV < (1LL << 31), GFCC_EINVAL, "sigma: too many 2h1p rows");
-  hipLaunchKernelGGL(antisym_add_kernel<float>, dim3((unsigned)PV), dim3(256), 0,
-                     ctx->stream, Z, o, v, nc, Y2);
-  GFCC_LAUNCH_CHECK();
+  if (!woo_product<float>(ctx, false, P, (int64_t)v * nc, f.Woo.as<float>(), op.ldwoo, X2, Y2,
+                          Z, o, v, nc)) {
+    hipLaunchKernelGGL(antisym_add_kernel<float>, dim3((unsigned)PV), dim3(256), 0,
+                       ctx->stream, Z, o, v, nc, Y2);
+    GFCC_LAUNCH_CHECK();
+  }
   timer_end(ctx, 1, e_all);
 }
 
